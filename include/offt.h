@@ -1,0 +1,163 @@
+/*
+ * offt.h -- C ABI of the MI355X (gfx950) 3-D complex-to-complex FFT library.
+ *
+ * The operation is the 3-D discrete Fourier transform of a grid A(a,b,c) with
+ * Na x Nb x Nc points (Duy & Ozaki, "Performance Tuning of a Parallel 3-D FFT
+ * Package OpenFFT", Sec. 2):
+ *
+ *   forward   X[ka,kb,kc] = sum_{a,b,c} x[a,b,c] W_Na^(a ka) W_Nb^(b kb) W_Nc^(c kc),
+ *             W_n = exp(-2 pi i / n)
+ *   backward  the same with W_n = exp(+2 pi i / n); unnormalised unless the plan
+ *             was created with normalize_inverse = 1, then scaled by 1/(Na Nb Nc).
+ *
+ * It is computed as in the paper's calculation flow (Sec. 3.1.1): batched 1-D
+ * transforms along one axis at a time, with the data rearranged between the
+ * axis passes (the transpose order abc -> cab -> cba of Sec. 2).  On one GPU the
+ * rearrangement is an in-HBM tile transpose through LDS rather than an MPI
+ * exchange.  The paper's three phases map to:
+ *   initialization  -> offt_plan / offt_plan_ex / offt_plan_many  (index math,
+ *                      one-time allocations (Sec. 3.2.4) and auto-tuning
+ *                      (Sec. 3.2.3) happen here)
+ *   execution       -> offt_exec_fwd / offt_exec_bwd / offt_exec_many_*  (may be
+ *                      repeated any number of times; never allocates)
+ *   finalization    -> offt_destroy
+ *
+ * Memory layout of every grid: row-major with c fastest, offset
+ * a*Nb*Nc + b*Nc + c (Sec. 2, Eq. 1); element = interleaved (re, im) of the
+ * plan's precision (binary64 for OFFT_C2C_F64, binary32 for OFFT_C2C_F32).
+ * A batch of grids is stored back to back: grid g starts at element g*N.
+ *
+ * Pointers passed to the exec calls are DEVICE pointers owned by the caller;
+ * `stream` is a hipStream_t (NULL = the null stream).  Exec calls are
+ * stream-ordered and asynchronous: device faults surface at the caller's next
+ * synchronisation, as usual in HIP.  A plan must not be executed concurrently
+ * on two streams.
+ *
+ * Errors: calls returning int return 0 (OFFT_SUCCESS) or a negative OFFT_ERR_*;
+ * calls returning a handle return NULL on error.  The last error code of the
+ * calling thread is kept and can be read with offt_last_error().
+ */
+#ifndef OFFT_H
+#define OFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct offt_plan_s* offt_plan_t;
+
+/* precision / transform kind */
+enum { OFFT_C2C_F64 = 0, OFFT_C2C_F32 = 1 };
+
+/* error codes */
+enum {
+    OFFT_SUCCESS = 0,
+    OFFT_ERR_INVALID_ARG = -1,      /* NULL handle/pointer, non-positive size, bad dtype/option */
+    OFFT_ERR_UNSUPPORTED_SIZE = -2, /* an axis has a prime factor > 5, or exceeds the supported length */
+    OFFT_ERR_OUT_OF_MEMORY = -3,    /* device allocation failed at plan time */
+    OFFT_ERR_NO_DEVICE = -4,        /* no HIP device visible */
+    OFFT_ERR_HIP = -5,              /* a HIP runtime call or kernel launch failed */
+    OFFT_ERR_BAD_PLAN = -6,         /* handle of the wrong kind, or a forced plan string that does not parse or fit */
+    OFFT_ERR_IO = -7                /* plan cache / weights file unreadable (non-fatal inside planning) */
+};
+
+/* plan selection modes (the paper's run-time auto-tuning, Sec. 3.2.3) */
+enum {
+    OFFT_TUNE_NONE = 0,       /* fixed heuristic plan (the default, like the paper's default method) */
+    OFFT_TUNE_EXHAUSTIVE = 1, /* time every candidate plan at init, keep the fastest */
+    OFFT_TUNE_LEARNED = 2,    /* rank candidates with the learned selector, no exhaustive timing */
+    OFFT_TUNE_FORCED = 3      /* use the plan string given in forced_plan (the paper's User-select) */
+};
+
+typedef struct offt_opts {
+    int tune;                 /* OFFT_TUNE_* (default NONE) */
+    int reps;                 /* timed runs per candidate when tuning (default 2, after 1 warm-up) */
+    int normalize_inverse;    /* 1: backward multiplies by 1/(Na Nb Nc) (default 0) */
+    const char* forced_plan;  /* plan string for OFFT_TUNE_FORCED (format of offt_plan_describe) */
+    const char* cache_path;   /* plan cache file for tuned plans, or NULL */
+    const char* weights_path; /* learned-selector weights for OFFT_TUNE_LEARNED, or NULL */
+    void* stream;             /* hipStream_t for tuning runs (NULL = null stream) */
+} offt_opts;
+
+/* Fill *o with the defaults listed above. */
+void offt_opts_default(offt_opts* o);
+
+/* Create a plan for `batch` grids of Na x Nb x Nc points of precision `dtype`
+ * with the heuristic plan.  Axis lengths must be >= 1, 2/3/5-smooth and at most
+ * OFFT_MAX_AXIS; batch >= 1.  Allocates the twiddle tables once.  Returns NULL
+ * on error (OFFT_ERR_INVALID_ARG, OFFT_ERR_UNSUPPORTED_SIZE,
+ * OFFT_ERR_NO_DEVICE, OFFT_ERR_OUT_OF_MEMORY, OFFT_ERR_HIP). */
+offt_plan_t offt_plan(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch);
+
+/* As offt_plan with options `o` (NULL = defaults).  Tuning runs here, on
+ * o->stream, with internally allocated temporary buffers that are freed before
+ * returning.  Errors as offt_plan, plus OFFT_ERR_BAD_PLAN for an unusable
+ * forced plan string. */
+offt_plan_t offt_plan_ex(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch,
+                         const offt_opts* o);
+
+#define OFFT_MAX_AXIS 1024
+
+/* Forward / backward transform of the plan's `batch` grids from `in` to `out`
+ * (device pointers, layout above).  in == out is allowed (in place); any other
+ * overlap is invalid.  Never allocates, never synchronises.
+ * Errors: OFFT_ERR_INVALID_ARG (NULL plan or pointer), OFFT_ERR_BAD_PLAN
+ * (plan made by offt_plan_many), OFFT_ERR_HIP (launch failure). */
+int offt_exec_fwd(offt_plan_t p, const void* in, void* out, void* stream);
+int offt_exec_bwd(offt_plan_t p, const void* in, void* out, void* stream);
+
+/* Free every plan-owned allocation.  NULL is a no-op.  The handle is invalid
+ * afterwards. */
+int offt_destroy(offt_plan_t p);
+
+/* Plan string (axis order, radix sequence, tile width and pass mode of each
+ * axis pass) written NUL-terminated into buf[0..n).  Returns the length of the
+ * full string, or a negative code; the string is truncated if n is too small. */
+int offt_plan_describe(offt_plan_t p, char* buf, size_t n);
+
+/* Bytes of device memory the plan owns (twiddle tables, scratch). */
+int64_t offt_workspace_bytes(offt_plan_t p);
+
+/* Last error code of the calling thread, and a static text for a code. */
+int offt_last_error(void);
+const char* offt_error_string(int code);
+
+/* Write the device-generated forward twiddle table W_n^m, m < n, of precision
+ * `dtype` to host memory `host_out` (n interleaved complex values).  The table
+ * is computed in binary64 on the GPU and rounded to nearest for OFFT_C2C_F32.
+ * For tests of the twiddle generator.  Errors: INVALID_ARG, NO_DEVICE, HIP. */
+int offt_twiddles(int64_t n, int dtype, void* host_out);
+
+/* ---- batches of grids of different sizes (uneven batch) ------------------
+ * `count` grids, grid i of dims[3i] x dims[3i+1] x dims[3i+2], all of precision
+ * `dtype`, packed back to back in one buffer; grid i starts at element offset
+ * offt_many_offset(p, i) (every grid starts on a 256-byte boundary).  With
+ * o->tune = OFFT_TUNE_EXHAUSTIVE each distinct grid shape gets its own tuned
+ * plan.  The execution is one persistent kernel launch over all (grid, axis
+ * pass, tile) work items, captured once into a HIP graph and replayed.
+ * Errors as offt_plan_ex. */
+offt_plan_t offt_plan_many(int count, const int64_t* dims, int dtype, const offt_opts* o);
+
+/* Element offset of grid i in the packed buffer, total elements of the
+ * packed buffer (i = count), or a negative code. */
+int64_t offt_many_offset(offt_plan_t p, int i);
+
+/* Transform every grid of the packed buffer.  in == out allowed.
+ * use_graph = 1 replays the captured graph (captured on first use on that
+ * stream), 0 launches the persistent kernel directly.  The separate-launch
+ * baseline (every grid's passes as ordinary launches) is use_graph = -1.
+ * Never allocates.  Errors: INVALID_ARG, BAD_PLAN (not a many-plan), HIP. */
+int offt_exec_many(offt_plan_t p, const void* in, void* out, int direction, int use_graph,
+                   void* stream);
+
+#define OFFT_FORWARD (-1)
+#define OFFT_BACKWARD (+1)
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OFFT_H */

@@ -1,0 +1,215 @@
+"""offt -- MI355X-native 3-D complex-to-complex FFT (Python binding).
+
+Python side of the C ABI in include/offt.h.  torch supplies device memory
+and streams only; the transform runs in the library's HIP kernels.
+
+    plan = Plan((Na, Nb, Nc), dtype=torch.complex128, batch=1)
+    y = plan.forward(x)            # x: contiguous cuda tensor (batch?, Na, Nb, Nc)
+    z = plan.backward(y)           # unnormalised unless normalize_inverse=True
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (BACKWARD, C2C_F32, C2C_F64, FORWARD, MAX_AXIS, OfftError, TUNE_EXHAUSTIVE,
+                   TUNE_FORCED, TUNE_LEARNED, TUNE_NONE)
+
+__all__ = ["Plan", "ManyPlan", "OfftError", "twiddles", "FORWARD", "BACKWARD", "MAX_AXIS"]
+
+_TUNE = {"none": TUNE_NONE, "exhaustive": TUNE_EXHAUSTIVE, "learned": TUNE_LEARNED,
+         "forced": TUNE_FORCED}
+
+
+def _dtype_code(dtype) -> int:
+    if dtype == torch.complex128:
+        return C2C_F64
+    if dtype == torch.complex64:
+        return C2C_F32
+    raise ValueError("dtype must be torch.complex128 or torch.complex64")
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _make_opts(tune="none", reps=2, normalize_inverse=False, forced_plan=None, cache_path=None,
+               weights_path=None, stream=None):
+    o = _lib.default_opts()
+    if tune not in _TUNE:
+        raise ValueError(f"tune must be one of {sorted(_TUNE)}")
+    o.tune = _TUNE[tune]
+    o.reps = int(reps)
+    o.normalize_inverse = 1 if normalize_inverse else 0
+    keep = []
+    for field, val in (("forced_plan", forced_plan), ("cache_path", cache_path),
+                       ("weights_path", weights_path)):
+        if val is not None:
+            b = str(val).encode()
+            keep.append(b)
+            setattr(o, field, b)
+    o.stream = ctypes.c_void_p(stream) if stream else None
+    return o, keep
+
+
+class Plan:
+    """Plan for `batch` grids of `shape` = (Na, Nb, Nc)."""
+
+    def __init__(self, shape, dtype=torch.complex128, batch: int = 1, tune: str = "none",
+                 normalize_inverse: bool = False, forced_plan: str | None = None,
+                 cache_path: str | None = None, weights_path: str | None = None, reps: int = 2):
+        lib = _lib.load()
+        if len(shape) != 3:
+            raise ValueError("shape must be (Na, Nb, Nc)")
+        self.shape = tuple(int(s) for s in shape)
+        self.dtype = dtype
+        self.batch = int(batch)
+        self.normalize_inverse = bool(normalize_inverse)
+        code = _dtype_code(dtype)
+        stream = _stream_handle() if torch.cuda.is_available() else None
+        opts, keep = _make_opts(tune, reps, normalize_inverse, forced_plan, cache_path, weights_path,
+                                stream)
+        h = lib.offt_plan_ex(self.shape[0], self.shape[1], self.shape[2], code, self.batch,
+                             ctypes.byref(opts))
+        del keep
+        if not h:
+            raise OfftError(_lib.last_error(), f"offt_plan_ex{self.shape}")
+        self._h = h
+
+    def _check_tensor(self, x: torch.Tensor, name: str):
+        if not isinstance(x, torch.Tensor) or not x.is_cuda:
+            raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+        if x.dtype != self.dtype:
+            raise ValueError(f"{name} has dtype {x.dtype}, plan expects {self.dtype}")
+        if not x.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        n = self.batch * self.shape[0] * self.shape[1] * self.shape[2]
+        if x.numel() != n or tuple(x.shape[-3:]) != self.shape:
+            raise ValueError(f"{name} has shape {tuple(x.shape)}, plan expects "
+                             f"{(self.batch,) + self.shape if self.batch > 1 else self.shape}")
+
+    def _run(self, fn, x, out):
+        self._check_tensor(x, "x")
+        if out is None:
+            out = torch.empty_like(x)
+        else:
+            self._check_tensor(out, "out")
+        _lib.check(fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                      ctypes.c_void_p(_stream_handle())), "exec")
+        return out
+
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        return self._run(_lib.load().offt_exec_fwd, x, out)
+
+    def backward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        return self._run(_lib.load().offt_exec_bwd, x, out)
+
+    def exec_ptr(self, direction: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+        """Raw-pointer execution (no tensor checks) for benchmarking loops."""
+        lib = _lib.load()
+        fn = lib.offt_exec_fwd if direction == FORWARD else lib.offt_exec_bwd
+        _lib.check(fn(self._h, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
+                      ctypes.c_void_p(stream)), "exec")
+
+    def describe(self) -> str:
+        lib = _lib.load()
+        n = _lib.check(lib.offt_plan_describe(self._h, None, 0), "describe")
+        buf = ctypes.create_string_buffer(n + 1)
+        lib.offt_plan_describe(self._h, buf, n + 1)
+        return buf.value.decode()
+
+    def workspace_bytes(self) -> int:
+        return _lib.check(_lib.load().offt_workspace_bytes(self._h), "workspace_bytes")
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.load().offt_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ManyPlan:
+    """Plan for an uneven batch: grid i has shape dims[i]; grids are packed
+    back to back in one buffer, grid i at element offset offset(i)."""
+
+    def __init__(self, dims, dtype=torch.complex64, tune: str = "none",
+                 normalize_inverse: bool = False, cache_path: str | None = None, reps: int = 2):
+        lib = _lib.load()
+        self.dims = [tuple(int(v) for v in d) for d in dims]
+        if not self.dims or any(len(d) != 3 for d in self.dims):
+            raise ValueError("dims must be a non-empty list of (Na, Nb, Nc)")
+        self.dtype = dtype
+        code = _dtype_code(dtype)
+        flat = (ctypes.c_int64 * (3 * len(self.dims)))(*[v for d in self.dims for v in d])
+        stream = _stream_handle() if torch.cuda.is_available() else None
+        opts, keep = _make_opts(tune, reps, normalize_inverse, None, cache_path, None, stream)
+        h = lib.offt_plan_many(len(self.dims), flat, code, ctypes.byref(opts))
+        del keep
+        if not h:
+            raise OfftError(_lib.last_error(), "offt_plan_many")
+        self._h = h
+        self.offsets = [_lib.check(lib.offt_many_offset(h, i)) for i in range(len(self.dims) + 1)]
+        self.total = self.offsets[-1]
+
+    def pack(self, grids) -> torch.Tensor:
+        buf = torch.zeros(self.total, dtype=self.dtype, device=grids[0].device)
+        for i, g in enumerate(grids):
+            n = g.numel()
+            buf[self.offsets[i]:self.offsets[i] + n] = g.reshape(-1)
+        return buf
+
+    def unpack(self, buf):
+        out = []
+        for i, d in enumerate(self.dims):
+            n = d[0] * d[1] * d[2]
+            out.append(buf[self.offsets[i]:self.offsets[i] + n].view(d))
+        return out
+
+    def execute(self, x: torch.Tensor, out: torch.Tensor | None = None, direction: int = FORWARD,
+                use_graph: int = 1) -> torch.Tensor:
+        if not x.is_cuda or x.dtype != self.dtype or not x.is_contiguous() or x.numel() < self.total:
+            raise ValueError("x must be a contiguous CUDA tensor holding the packed grids")
+        if out is None:
+            out = torch.empty_like(x)
+        lib = _lib.load()
+        _lib.check(lib.offt_exec_many(self._h, ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), int(direction), int(use_graph),
+                                      ctypes.c_void_p(_stream_handle())), "exec_many")
+        return out
+
+    def describe(self) -> str:
+        lib = _lib.load()
+        n = _lib.check(lib.offt_plan_describe(self._h, None, 0), "describe")
+        buf = ctypes.create_string_buffer(n + 1)
+        lib.offt_plan_describe(self._h, buf, n + 1)
+        return buf.value.decode()
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.load().offt_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def twiddles(n: int, dtype=torch.complex128):
+    """Device-generated forward twiddle table W_n^m, m < n, copied to the host."""
+    import numpy as np
+    code = _dtype_code(dtype)
+    out = np.empty(n, dtype=np.complex128 if code == C2C_F64 else np.complex64)
+    _lib.check(_lib.load().offt_twiddles(n, code, out.ctypes.data_as(ctypes.c_void_p)), "twiddles")
+    return out

@@ -1,0 +1,114 @@
+"""ctypes binding of libofft.so (the C ABI declared in include/offt.h).
+
+Argument marshalling only: every step of the transform runs in the library's
+HIP kernels.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libofft.so")
+
+C2C_F64 = 0
+C2C_F32 = 1
+
+SUCCESS = 0
+ERR_INVALID_ARG = -1
+ERR_UNSUPPORTED_SIZE = -2
+ERR_OUT_OF_MEMORY = -3
+ERR_NO_DEVICE = -4
+ERR_HIP = -5
+ERR_BAD_PLAN = -6
+ERR_IO = -7
+
+TUNE_NONE = 0
+TUNE_EXHAUSTIVE = 1
+TUNE_LEARNED = 2
+TUNE_FORCED = 3
+
+FORWARD = -1
+BACKWARD = +1
+MAX_AXIS = 1024
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("tune", ctypes.c_int),
+        ("reps", ctypes.c_int),
+        ("normalize_inverse", ctypes.c_int),
+        ("forced_plan", ctypes.c_char_p),
+        ("cache_path", ctypes.c_char_p),
+        ("weights_path", ctypes.c_char_p),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+# name -> (restype, argtypes); every symbol the header declares
+_i64 = ctypes.c_int64
+_vp = ctypes.c_void_p
+_ci = ctypes.c_int
+SIGNATURES = {
+    "offt_opts_default": (None, [ctypes.POINTER(Opts)]),
+    "offt_plan": (_vp, [_i64, _i64, _i64, _ci, _i64]),
+    "offt_plan_ex": (_vp, [_i64, _i64, _i64, _ci, _i64, ctypes.POINTER(Opts)]),
+    "offt_exec_fwd": (_ci, [_vp, _vp, _vp, _vp]),
+    "offt_exec_bwd": (_ci, [_vp, _vp, _vp, _vp]),
+    "offt_destroy": (_ci, [_vp]),
+    "offt_plan_describe": (_ci, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
+    "offt_workspace_bytes": (_i64, [_vp]),
+    "offt_last_error": (_ci, []),
+    "offt_error_string": (ctypes.c_char_p, [_ci]),
+    "offt_twiddles": (_ci, [_i64, _ci, _vp]),
+    "offt_plan_many": (_vp, [_ci, ctypes.POINTER(_i64), _ci, ctypes.POINTER(Opts)]),
+    "offt_many_offset": (_i64, [_vp, _ci]),
+    "offt_exec_many": (_ci, [_vp, _vp, _vp, _ci, _ci, _vp]),
+}
+
+_lib = None
+
+
+class OfftError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = error_string(code) if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+def load():
+    """Load libofft.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it first (python -m paper_1501_07350_amd.build "
+            "or __graft_entry__.build()); there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def error_string(code: int) -> str:
+    return load().offt_error_string(code).decode()
+
+
+def last_error() -> int:
+    return load().offt_last_error()
+
+
+def check(rc: int, what: str = ""):
+    if rc < 0:
+        raise OfftError(rc, what)
+    return rc
+
+
+def default_opts() -> Opts:
+    o = Opts()
+    load().offt_opts_default(ctypes.byref(o))
+    return o

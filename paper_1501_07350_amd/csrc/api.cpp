@@ -1,0 +1,254 @@
+// api.cpp -- the C ABI: plan (initialization), exec (execution), destroy
+// (finalization), following the three phases of the paper's calculation flow
+// (Sec. 3.1.1).  All device allocations happen at plan time (Sec. 3.2.4);
+// exec only launches kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/offt.h"
+#include "offt_internal.h"
+#include "plan_impl.h"
+
+namespace offt {
+
+static thread_local int g_last_error = OFFT_SUCCESS;
+void set_error(int code) { g_last_error = code; }
+
+int check_device() {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return OFFT_ERR_NO_DEVICE;
+    }
+    return OFFT_SUCCESS;
+}
+
+int validate_dims(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch) {
+    if (dtype != OFFT_C2C_F64 && dtype != OFFT_C2C_F32) return OFFT_ERR_INVALID_ARG;
+    if (Na < 1 || Nb < 1 || Nc < 1 || batch < 1) return OFFT_ERR_INVALID_ARG;
+    const int64_t d[3] = {Na, Nb, Nc};
+    for (int64_t n : d)
+        if (!smooth235(n) || n > OFFT_MAX_AXIS) return OFFT_ERR_UNSUPPORTED_SIZE;
+    // batch * N * elem must not overflow a signed 64-bit byte count
+    const long double bytes = (long double)Na * Nb * Nc * batch * elem_size(dtype);
+    if (bytes > 9.0e18L) return OFFT_ERR_INVALID_ARG;
+    return OFFT_SUCCESS;
+}
+
+// Allocate and fill the twiddle table for every distinct pass length.
+int attach_twiddles(offt_plan_s* p, PassPlan* passes, int npass, hipStream_t s) {
+    for (int i = 0; i < npass; ++i) {
+        const int L = passes[i].L;
+        auto it = p->tw.find(L);
+        if (it == p->tw.end()) {
+            void* d = nullptr;
+            const size_t bytes = (size_t)L * elem_size(p->dtype);
+            if (hipMalloc(&d, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return OFFT_ERR_OUT_OF_MEMORY;
+            }
+            p->allocs.push_back(d);
+            p->alloc_bytes.push_back(bytes);
+            if (launch_twiddles(d, L, p->dtype, s) != hipSuccess) return OFFT_ERR_HIP;
+            it = p->tw.emplace(L, d).first;
+        }
+        passes[i].tw = it->second;
+    }
+    return OFFT_SUCCESS;
+}
+
+int set_choice(offt_plan_s* p, const PlanChoice& c, hipStream_t s) {
+    p->choice = c;
+    p->npass = build_passes(c, p->dims, p->batch, p->passes);
+    for (int i = 0; i < p->npass; ++i)
+        if (!p->passes[i].k) return OFFT_ERR_UNSUPPORTED_SIZE;
+    return attach_twiddles(p, p->passes, p->npass, s);
+}
+
+int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const void* in, void* out,
+                int dir, hipStream_t s) {
+    const int64_t N = p->dims[0] * p->dims[1] * p->dims[2];
+    if (npass == 0) {
+        if (in != out) {
+            const size_t bytes = (size_t)(N * p->batch) * elem_size(p->dtype);
+            if (hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return OFFT_ERR_HIP;
+        }
+        return OFFT_SUCCESS;
+    }
+    const bool bwd = dir > 0;
+    for (int i = 0; i < npass; ++i) {
+        const bool last = i == npass - 1;
+        const double scale = (bwd && last && p->normalize) ? 1.0 / (double)N : 1.0;
+        if (launch_pass(passes[i], i == 0 ? in : out, out, bwd && i == 0, bwd && last, scale, s) !=
+            hipSuccess)
+            return OFFT_ERR_HIP;
+    }
+    return OFFT_SUCCESS;
+}
+
+}  // namespace offt
+
+int64_t offt_plan_s::workspace_bytes() const {
+    int64_t b = 0;
+    for (size_t x : alloc_bytes) b += (int64_t)x;
+    return b;
+}
+
+namespace offt {
+
+void free_plan(offt_plan_s* p) {
+    if (!p) return;
+    release_many(p);
+    for (void* d : p->allocs) (void)hipFree(d);
+    delete p;
+}
+
+}  // namespace offt
+
+using namespace offt;
+
+extern "C" {
+
+void offt_opts_default(offt_opts* o) {
+    if (!o) return;
+    o->tune = OFFT_TUNE_NONE;
+    o->reps = 2;
+    o->normalize_inverse = 0;
+    o->forced_plan = nullptr;
+    o->cache_path = nullptr;
+    o->weights_path = nullptr;
+    o->stream = nullptr;
+}
+
+int offt_last_error(void) { return g_last_error; }
+
+const char* offt_error_string(int code) {
+    switch (code) {
+        case OFFT_SUCCESS: return "success";
+        case OFFT_ERR_INVALID_ARG: return "invalid argument";
+        case OFFT_ERR_UNSUPPORTED_SIZE: return "unsupported size (axis not 2/3/5-smooth or too long)";
+        case OFFT_ERR_OUT_OF_MEMORY: return "device out of memory";
+        case OFFT_ERR_NO_DEVICE: return "no HIP device";
+        case OFFT_ERR_HIP: return "HIP runtime error";
+        case OFFT_ERR_BAD_PLAN: return "bad plan";
+        case OFFT_ERR_IO: return "plan cache or weights file I/O error";
+        default: return "unknown error";
+    }
+}
+
+offt_plan_t offt_plan(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch) {
+    return offt_plan_ex(Na, Nb, Nc, dtype, batch, nullptr);
+}
+
+offt_plan_t offt_plan_ex(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch,
+                         const offt_opts* o) {
+    offt_opts opts;
+    offt_opts_default(&opts);
+    if (o) opts = *o;
+    int rc = validate_dims(Na, Nb, Nc, dtype, batch);
+    if (rc == OFFT_SUCCESS && (opts.tune < OFFT_TUNE_NONE || opts.tune > OFFT_TUNE_FORCED))
+        rc = OFFT_ERR_INVALID_ARG;
+    if (rc == OFFT_SUCCESS && opts.tune == OFFT_TUNE_FORCED && !opts.forced_plan)
+        rc = OFFT_ERR_INVALID_ARG;
+    if (rc == OFFT_SUCCESS && opts.reps < 1) rc = OFFT_ERR_INVALID_ARG;
+    if (rc != OFFT_SUCCESS) { set_error(rc); return nullptr; }
+    const int64_t dims[3] = {Na, Nb, Nc};
+    PlanChoice forced;
+    if (opts.tune == OFFT_TUNE_FORCED && !choice_from_string(opts.forced_plan, dtype, dims, &forced)) {
+        set_error(OFFT_ERR_BAD_PLAN);
+        return nullptr;
+    }
+    rc = check_device();
+    if (rc != OFFT_SUCCESS) { set_error(rc); return nullptr; }
+
+    offt_plan_s* p = new offt_plan_s();
+    p->kind = 1;
+    p->dtype = dtype;
+    p->dims[0] = Na; p->dims[1] = Nb; p->dims[2] = Nc;
+    p->batch = batch;
+    p->normalize = opts.normalize_inverse ? 1 : 0;
+    hipStream_t s = static_cast<hipStream_t>(opts.stream);
+
+    PlanChoice choice = default_choice(dtype, dims);
+    if (opts.tune == OFFT_TUNE_FORCED) {
+        choice = forced;
+    } else if (opts.tune == OFFT_TUNE_EXHAUSTIVE || opts.tune == OFFT_TUNE_LEARNED) {
+        rc = select_plan(p, opts, &choice);
+        if (rc != OFFT_SUCCESS) { free_plan(p); set_error(rc); return nullptr; }
+    }
+    rc = set_choice(p, choice, s);
+    if (rc == OFFT_SUCCESS && hipStreamSynchronize(s) != hipSuccess) rc = OFFT_ERR_HIP;
+    if (rc != OFFT_SUCCESS) { free_plan(p); set_error(rc); return nullptr; }
+    set_error(OFFT_SUCCESS);
+    return p;
+}
+
+static int exec_checked(offt_plan_t p, const void* in, void* out, void* stream, int dir) {
+    if (!p || !in || !out) { set_error(OFFT_ERR_INVALID_ARG); return OFFT_ERR_INVALID_ARG; }
+    if (p->kind != 1) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
+    const int rc = exec_passes(p, p->passes, p->npass, in, out, dir, static_cast<hipStream_t>(stream));
+    set_error(rc);
+    return rc;
+}
+
+int offt_exec_fwd(offt_plan_t p, const void* in, void* out, void* stream) {
+    return exec_checked(p, in, out, stream, OFFT_FORWARD);
+}
+
+int offt_exec_bwd(offt_plan_t p, const void* in, void* out, void* stream) {
+    return exec_checked(p, in, out, stream, OFFT_BACKWARD);
+}
+
+int offt_destroy(offt_plan_t p) {
+    free_plan(p);
+    set_error(OFFT_SUCCESS);
+    return OFFT_SUCCESS;
+}
+
+int offt_plan_describe(offt_plan_t p, char* buf, size_t n) {
+    if (!p || (!buf && n)) { set_error(OFFT_ERR_INVALID_ARG); return OFFT_ERR_INVALID_ARG; }
+    std::string s = describe_plan(p);
+    if (n) {
+        const size_t m = std::min(n - 1, s.size());
+        memcpy(buf, s.data(), m);
+        buf[m] = 0;
+    }
+    set_error(OFFT_SUCCESS);
+    return (int)s.size();
+}
+
+int64_t offt_workspace_bytes(offt_plan_t p) {
+    if (!p) { set_error(OFFT_ERR_INVALID_ARG); return OFFT_ERR_INVALID_ARG; }
+    set_error(OFFT_SUCCESS);
+    return p->workspace_bytes();
+}
+
+int offt_twiddles(int64_t n, int dtype, void* host_out) {
+    if (n < 1 || !host_out || (dtype != OFFT_C2C_F64 && dtype != OFFT_C2C_F32)) {
+        set_error(OFFT_ERR_INVALID_ARG);
+        return OFFT_ERR_INVALID_ARG;
+    }
+    int rc = check_device();
+    if (rc != OFFT_SUCCESS) { set_error(rc); return rc; }
+    void* d = nullptr;
+    const size_t bytes = (size_t)n * elem_size(dtype);
+    if (hipMalloc(&d, bytes) != hipSuccess) { set_error(OFFT_ERR_OUT_OF_MEMORY); return OFFT_ERR_OUT_OF_MEMORY; }
+    rc = OFFT_SUCCESS;
+    if (launch_twiddles(d, n, dtype, nullptr) != hipSuccess ||
+        hipMemcpy(host_out, d, bytes, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = OFFT_ERR_HIP;
+    (void)hipFree(d);
+    set_error(rc);
+    return rc;
+}
+
+}  // extern "C"

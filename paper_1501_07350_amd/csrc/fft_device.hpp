@@ -1,0 +1,320 @@
+// fft_device.hpp -- device code of one axis pass of the 3-D transform.
+//
+// One axis pass applies a length-L 1-D DFT to every "line" of a [M1][L][M2]
+// view of the data (the paper's step "transform in a particular dimension",
+// Sec. 3.1.1).  With the grid stored row-major (Sec. 2, Eq. 1):
+//   c axis: M1 = batch*Na*Nb, M2 = 1          (lines contiguous)
+//   b axis: M1 = batch*Na,    M2 = Nc         (lines strided by Nc)
+//   a axis: M1 = batch,       M2 = Nb*Nc      (lines strided by Nb*Nc)
+// A workgroup owns W lines.  It stages them from HBM into LDS with coalesced
+// accesses (W consecutive columns per row for strided lines: this is where
+// the paper's pack/transpose step happens on one GPU), runs the radix stages
+// out of LDS, and writes the tile back the same way.  Each pass reads and
+// writes the grid exactly once.
+//
+// The 1-D DFT is a Stockham autosort FFT: stage s with radix R and span Ns
+// (product of the previous radices) takes butterfly b in [0, L/R), reads
+// x[b + r*L/R] for r < R, multiplies element r by W_{Ns R}^(r (b mod Ns)),
+// applies the R-point DFT and writes element r to
+// (b div Ns)*Ns*R + (b mod Ns) + r*Ns.  After the last stage the result is in
+// natural order.  Only forward butterflies exist: the backward transform is
+// conj(F(conj(x))), folded into the first load and the last store.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace offt {
+
+template <typename S> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+    V r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { V r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+// multiply by -i
+template <typename V> __device__ __forceinline__ V mul_mi(V a) { V r; r.x = a.y; r.y = -a.x; return r; }
+// multiply by +i
+template <typename V> __device__ __forceinline__ V mul_pi(V a) { V r; r.x = -a.y; r.y = a.x; return r; }
+template <typename V, typename S> __device__ __forceinline__ V cscale(V a, S s) { V r; r.x = a.x * s; r.y = a.y * s; return r; }
+
+// ---- small forward DFTs on registers (W_R = exp(-2 pi i / R)) -----------------
+// Each is derived from the definition y_k = sum_j x_j W_R^(jk) by pairing
+// x_j with x_{R-j} (radix 3, 5) or by one even/odd split (radix 4, 8, 16).
+
+template <typename V> __device__ __forceinline__ void dft2(V& a, V& b) {
+    V t = a; a = cadd(t, b); b = csub(t, b);
+}
+
+template <typename V> __device__ __forceinline__ void dft3(V* v) {
+    using S = decltype(v[0].x);
+    const S c = S(-0.5);                                   // cos(2pi/3)
+    const S s = S(-0.86602540378443864676372317075294);    // -sin(2pi/3)
+    V a = cadd(v[1], v[2]);
+    V d = csub(v[1], v[2]);
+    V t = cadd(v[0], cscale(a, c));
+    V u = cscale(d, s);          // y1 = t + i u, y2 = t - i u
+    v[0] = cadd(v[0], a);
+    v[1] = cadd(t, mul_pi(u));
+    v[2] = csub(t, mul_pi(u));
+}
+
+template <typename V> __device__ __forceinline__ void dft4(V* v) {
+    V s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    V s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, mul_mi(d13));
+    v[3] = csub(d02, mul_mi(d13));
+}
+
+template <typename V> __device__ __forceinline__ void dft5(V* v) {
+    using S = decltype(v[0].x);
+    const S c1 = S(0.30901699437494742410229341718282);    // cos(2pi/5)
+    const S c2 = S(-0.80901699437494742410229341718282);   // cos(4pi/5)
+    const S s1 = S(-0.95105651629515357211643933337938);   // -sin(2pi/5)
+    const S s2 = S(-0.58778525229247312916870595463907);   // -sin(4pi/5)
+    V a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    V a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    V t1 = cadd(v[0], cadd(cscale(a1, c1), cscale(a2, c2)));
+    V t2 = cadd(v[0], cadd(cscale(a1, c2), cscale(a2, c1)));
+    V u1 = cadd(cscale(b1, s1), cscale(b2, s2));   // y1 = t1 + i u1, y4 = t1 - i u1
+    V u2 = csub(cscale(b1, s2), cscale(b2, s1));   // y2 = t2 + i u2, y3 = t2 - i u2
+    v[0] = cadd(v[0], cadd(a1, a2));
+    v[1] = cadd(t1, mul_pi(u1));
+    v[4] = csub(t1, mul_pi(u1));
+    v[2] = cadd(t2, mul_pi(u2));
+    v[3] = csub(t2, mul_pi(u2));
+}
+
+// y_k = E_k + W_8^k O_k, y_{k+4} = E_k - W_8^k O_k with E, O the 4-point DFTs
+// of the even and odd samples.
+template <typename V> __device__ __forceinline__ void dft8(V* v) {
+    using S = decltype(v[0].x);
+    const S h = S(0.70710678118654752440084436210485);     // sqrt(2)/2
+    V e[4] = {v[0], v[2], v[4], v[6]};
+    V o[4] = {v[1], v[3], v[5], v[7]};
+    dft4(e);
+    dft4(o);
+    V o1; o1.x = h * (o[1].x + o[1].y); o1.y = h * (o[1].y - o[1].x);     // W8^1 = h(1 - i)
+    V o2 = mul_mi(o[2]);                                                // W8^2 = -i
+    V o3; o3.x = h * (o[3].y - o[3].x); o3.y = -h * (o[3].x + o[3].y);  // W8^3 = h(-1 - i)
+    v[0] = cadd(e[0], o[0]); v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);   v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);   v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);   v[7] = csub(e[3], o3);
+}
+
+template <typename V> __device__ __forceinline__ void dft16(V* v) {
+    using S = decltype(v[0].x);
+    // W16^k = cos(k pi/8) - i sin(k pi/8), k = 1..7
+    const S c1 = S(0.92387953251128675612818318939679);
+    const S s1 = S(0.38268343236508977172845998403040);
+    const S h = S(0.70710678118654752440084436210485);
+    V e[8], o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { e[k] = v[2 * k]; o[k] = v[2 * k + 1]; }
+    dft8(e);
+    dft8(o);
+    V w[8];
+    w[0] = o[0];
+    { V t; t.x = c1 * o[1].x + s1 * o[1].y; t.y = c1 * o[1].y - s1 * o[1].x; w[1] = t; }   // (c1 - i s1)
+    { V t; t.x = h * (o[2].x + o[2].y); t.y = h * (o[2].y - o[2].x); w[2] = t; }          // h(1 - i)
+    { V t; t.x = s1 * o[3].x + c1 * o[3].y; t.y = s1 * o[3].y - c1 * o[3].x; w[3] = t; }   // (s1 - i c1)
+    w[4] = mul_mi(o[4]);                                                                  // -i
+    { V t; t.x = -s1 * o[5].x + c1 * o[5].y; t.y = -s1 * o[5].y - c1 * o[5].x; w[5] = t; } // (-s1 - i c1)
+    { V t; t.x = h * (o[6].y - o[6].x); t.y = -h * (o[6].x + o[6].y); w[6] = t; }         // h(-1 - i)
+    { V t; t.x = -c1 * o[7].x + s1 * o[7].y; t.y = -c1 * o[7].y - s1 * o[7].x; w[7] = t; } // (-c1 - i s1)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { v[k] = cadd(e[k], w[k]); v[k + 8] = csub(e[k], w[k]); }
+}
+
+template <int R, typename V> __device__ __forceinline__ void dft(V* v) {
+    if constexpr (R == 2) dft2(v[0], v[1]);
+    else if constexpr (R == 3) dft3(v);
+    else if constexpr (R == 4) dft4(v);
+    else if constexpr (R == 5) dft5(v);
+    else if constexpr (R == 8) dft8(v);
+    else if constexpr (R == 16) dft16(v);
+    else static_assert(R == 2, "unsupported radix");
+}
+
+// ---- one Stockham stage out of LDS ------------------------------------------
+// `line` points at the LDS copy of this thread's line; t in [0, TPL) is the
+// thread's rank within the line.  tw holds W_L^m, m < L.
+template <typename V, int L, int TPL, int NS, int R>
+__device__ __forceinline__ void fft_stage(V* __restrict__ line, const V* __restrict__ tw, int t) {
+    constexpr int B = L / R;                 // butterflies in this stage
+    constexpr int NB = (B + TPL - 1) / TPL;  // butterflies per thread
+    constexpr bool EXACT = (B % TPL) == 0;
+    constexpr int STEP = L / (NS * R);       // W_{Ns R}^e = W_L^(e STEP)
+    V v[NB][R];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = t + i * TPL;
+        if (EXACT || b < B) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = line[b + r * B];
+            if constexpr (NS > 1) {
+                const int k = b % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[r * k * STEP]);
+            }
+            dft<R>(v[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = t + i * TPL;
+        if (EXACT || b < B) {
+            const int base = (b / NS) * NS * R + (b % NS);
+#pragma unroll
+            for (int r = 0; r < R; ++r) line[base + r * NS] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename V, int L, int TPL, int NS, int R, int... Rest>
+__device__ __forceinline__ void run_stages(V* __restrict__ line, const V* __restrict__ tw, int t) {
+    fft_stage<V, L, TPL, NS, R>(line, tw, t);
+    if constexpr (sizeof...(Rest) > 0) run_stages<V, L, TPL, NS * R, Rest...>(line, tw, t);
+}
+
+template <int... Rs> struct RadixProduct;
+template <> struct RadixProduct<> { static constexpr int value = 1; };
+template <int R, int... Rest> struct RadixProduct<R, Rest...> {
+    static constexpr int value = R * RadixProduct<Rest...>::value;
+};
+
+// ---- pass arguments --------------------------------------------------------
+struct PassArgs {
+    const void* in;
+    void* out;
+    const void* tw;     // W_L^m, m < L, in the pass precision
+    int64_t nlines;     // M1 * M2
+    int64_t M2;         // element stride of the axis (1: contiguous lines)
+    int logW;           // log2 of lines per workgroup
+    int mode;           // 0: contiguous lines (M2 == 1), 1: strided lines
+    int conj_in;        // negate imaginary parts on load
+    int conj_out;       // negate imaginary parts on store
+    double scale;       // multiply on store
+};
+
+template <typename V> __device__ __forceinline__ V fix_in(V x, int conj) {
+    if (conj) x.y = -x.y;
+    return x;
+}
+template <typename V, typename S> __device__ __forceinline__ V fix_out(V x, int conj, S scale) {
+    if (conj) x.y = -x.y;
+    x.x *= scale;
+    x.y *= scale;
+    return x;
+}
+
+// LDS line pitch: one extra element keeps the W lines of a column tile on
+// different banks.
+__host__ __device__ constexpr int Pitch_value(int L) { return L + 1; }
+template <int L> struct Pitch { static constexpr int value = Pitch_value(L); };
+
+// Device body of one axis pass for one tile of W = 2^logW lines starting at
+// line l0.  Threads: W * TPL.  lds: W * Pitch<L> elements.
+template <typename V, int L, int TPL, int... Rs>
+__device__ __forceinline__ void pass_tile(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
+    using S = decltype(V{}.x);
+    static_assert(RadixProduct<Rs...>::value == L, "radix sequence must multiply to L");
+    constexpr int LP = Pitch<L>::value;
+    const int W = 1 << a.logW;
+    const int NT = W * TPL;
+    const int tid = threadIdx.x;
+    const int64_t rem = a.nlines - l0;
+    const int nl = rem < W ? (int)rem : W;
+    const V* __restrict__ in = static_cast<const V*>(a.in);
+    V* __restrict__ out = static_cast<V*>(a.out);
+    const V* __restrict__ tw = static_cast<const V*>(a.tw);
+    const int cin = a.conj_in, cout = a.conj_out;
+    const S scale = (S)a.scale;
+
+    if (a.mode == 0) {
+        // contiguous lines: the tile is one block of nl*L elements
+        const V* g = in + l0 * L;
+        if (nl == W) {
+#pragma unroll
+            for (int k = 0; k < L / TPL; ++k) {
+                const int f = tid + k * NT;
+                const int w = f / L, j = f - w * L;
+                lds[w * LP + j] = fix_in(g[f], cin);
+            }
+        } else {
+            for (int f = tid; f < nl * L; f += NT) {
+                const int w = f / L, j = f - w * L;
+                lds[w * LP + j] = fix_in(g[f], cin);
+            }
+        }
+    } else {
+        // strided lines: lanes walk W consecutive lines (columns) of one row
+        const int w = tid & (W - 1);
+        const int jj = tid >> a.logW;
+        if (w < nl) {
+            const int64_t l = l0 + w;
+            const int64_t m1 = l / a.M2, m2 = l - m1 * a.M2;
+            const V* g = in + m1 * (int64_t)L * a.M2 + m2;
+#pragma unroll
+            for (int k = 0; k < L / TPL; ++k) {
+                const int j = jj + k * TPL;
+                lds[w * LP + j] = fix_in(g[(int64_t)j * a.M2], cin);
+            }
+        }
+    }
+    __syncthreads();
+    {
+        const int w = tid / TPL, t = tid - (tid / TPL) * TPL;
+        run_stages<V, L, TPL, 1, Rs...>(lds + w * LP, tw, t);
+    }
+    if (a.mode == 0) {
+        V* g = out + l0 * L;
+        if (nl == W) {
+#pragma unroll
+            for (int k = 0; k < L / TPL; ++k) {
+                const int f = tid + k * NT;
+                const int w = f / L, j = f - w * L;
+                g[f] = fix_out(lds[w * LP + j], cout, scale);
+            }
+        } else {
+            for (int f = tid; f < nl * L; f += NT) {
+                const int w = f / L, j = f - w * L;
+                g[f] = fix_out(lds[w * LP + j], cout, scale);
+            }
+        }
+    } else {
+        const int w = tid & (W - 1);
+        const int jj = tid >> a.logW;
+        if (w < nl) {
+            const int64_t l = l0 + w;
+            const int64_t m1 = l / a.M2, m2 = l - m1 * a.M2;
+            V* g = out + m1 * (int64_t)L * a.M2 + m2;
+#pragma unroll
+            for (int k = 0; k < L / TPL; ++k) {
+                const int j = jj + k * TPL;
+                g[(int64_t)j * a.M2] = fix_out(lds[w * LP + j], cout, scale);
+            }
+        }
+    }
+}
+
+template <typename V, int L, int TPL, int... Rs>
+__global__ void __launch_bounds__(512) fft_pass_kernel(PassArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V* lds = reinterpret_cast<V*>(smem_raw);
+    const int64_t l0 = (int64_t)blockIdx.x << a.logW;
+    pass_tile<V, L, TPL, Rs...>(a, lds, l0);
+}
+
+}  // namespace offt

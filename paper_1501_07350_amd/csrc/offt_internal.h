@@ -1,0 +1,73 @@
+// offt_internal.h -- host-side types shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "fft_device.hpp"
+
+namespace offt {
+
+constexpr int kMaxStages = 8;
+constexpr int kMaxLds = 64 * 1024;   // bytes of LDS a pass tile may use
+
+using LaunchFn = hipError_t (*)(const PassArgs& a, int64_t nblocks, int threads, size_t lds,
+                                hipStream_t s);
+
+// One compiled length-L pass kernel: radix sequence (in stage order), threads
+// per line, and its launcher.
+struct KernelEntry {
+    int dtype;                 // OFFT_C2C_F64 / OFFT_C2C_F32
+    int L;
+    int nstages;
+    int radices[kMaxStages];
+    int tpl;                   // threads per line
+    LaunchFn launch;
+};
+
+// Registry of all compiled pass kernels (generated tables).
+const std::vector<const KernelEntry*>& registry();
+// All kernels for (dtype, L), default first.
+std::vector<const KernelEntry*> kernels_for(int dtype, int L);
+
+// One axis pass of a plan.
+struct PassPlan {
+    int axis;                  // 0 = a, 1 = b, 2 = c
+    int L;
+    int64_t M1, M2;
+    const KernelEntry* k;
+    int logW;                  // lines per workgroup = 2^logW
+    int mode;                  // 0 contiguous lines, 1 strided lines
+    const void* tw;            // device twiddle table for L
+};
+
+// Plan choice for one grid shape, independent of device memory.
+struct PlanChoice {
+    int order[3];              // axis order of the passes (axis ids)
+    const KernelEntry* k[3];   // per axis id (a, b, c); nullptr for L == 1
+    int logW[3];               // per axis id
+};
+
+size_t elem_size(int dtype);
+bool smooth235(int64_t n);
+std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]);
+// Parses a plan string; returns false if it does not parse or does not fit dims/dtype.
+bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanChoice* out);
+PlanChoice default_choice(int dtype, const int64_t dims[3]);
+// Candidate plans for tuning (deterministic order, default first).
+std::vector<PlanChoice> candidate_choices(int dtype, const int64_t dims[3]);
+// Pass descriptors (M1, M2, mode, W) for a grid + batch under a choice.
+int build_passes(const PlanChoice& c, const int64_t dims[3], int64_t batch, PassPlan out[3]);
+// Clamp logW so the tile fits LDS and the thread limit; returns the adjusted value.
+int fit_logW(const KernelEntry* k, int logW, int dtype);
+
+hipError_t launch_twiddles(void* out, int64_t n, int dtype, hipStream_t s);
+hipError_t launch_pass(const PassPlan& p, const void* in, void* out, int conj_in, int conj_out,
+                       double scale, hipStream_t s);
+
+void set_error(int code);
+
+}  // namespace offt

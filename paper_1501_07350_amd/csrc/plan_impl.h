@@ -1,0 +1,53 @@
+// plan_impl.h -- the plan object behind offt_plan_t.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/offt.h"
+#include "offt_internal.h"
+
+namespace offt {
+struct ManyState;
+}
+
+struct offt_plan_s {
+    int kind = 0;                 // 1: one grid shape (+batch), 2: uneven batch
+    int dtype = 0;
+    int64_t dims[3] = {1, 1, 1};
+    int64_t batch = 1;
+    int normalize = 0;
+    offt::PlanChoice choice{};
+    offt::PassPlan passes[3]{};
+    int npass = 0;
+    std::map<int, void*> tw;      // twiddle table per pass length
+    std::vector<void*> allocs;    // every device allocation owned by the plan
+    std::vector<size_t> alloc_bytes;
+    std::string tune_log;         // how the plan was chosen (for describe)
+    offt::ManyState* many = nullptr;
+
+    int64_t workspace_bytes() const;
+};
+
+namespace offt {
+
+int check_device();
+int validate_dims(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch);
+int attach_twiddles(offt_plan_s* p, PassPlan* passes, int npass, hipStream_t s);
+int set_choice(offt_plan_s* p, const PlanChoice& c, hipStream_t s);
+int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const void* in, void* out,
+                int dir, hipStream_t s);
+void free_plan(offt_plan_s* p);
+
+// Tuning (tuner.cpp): fills *choice for EXHAUSTIVE / LEARNED modes.
+int select_plan(offt_plan_s* p, const offt_opts& o, PlanChoice* choice);
+std::string describe_plan(const offt_plan_s* p);
+
+// Uneven batches (many.hip).
+void release_many(offt_plan_s* p);
+std::string describe_many(const offt_plan_s* p);
+
+}  // namespace offt

@@ -1,0 +1,272 @@
+// planner.cpp -- kernel registry lookup, heuristic plan, candidate plans for
+// tuning, plan strings, and the [M1][L][M2] pass descriptors of a plan.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <sstream>
+
+#include "offt_internal.h"
+#include "../../include/offt.h"
+
+namespace offt {
+
+#include "_gen/registry_parts.inc"
+
+namespace {
+struct Table {
+    const KernelEntry* p;
+    int n;
+};
+}  // namespace
+
+const std::vector<const KernelEntry*>& registry() {
+    static const std::vector<const KernelEntry*> all = [] {
+        std::vector<const KernelEntry*> v;
+        const Table tables[] = {OFFT_REGISTRY_TABLES};
+        for (const Table& t : tables)
+            for (int i = 0; i < t.n; ++i) v.push_back(&t.p[i]);
+        return v;
+    }();
+    return all;
+}
+
+// Default-first order: the generator emits the default sequence of a length
+// first; tables are interleaved across files, so sort by the sequence's rank
+// within its length, recovered from the generator's ordering rule
+// (balanced <= 16 first, then balanced <= 8, then greedy 16).
+std::vector<const KernelEntry*> kernels_for(int dtype, int L) {
+    std::vector<const KernelEntry*> v;
+    for (const KernelEntry* e : registry())
+        if (e->dtype == dtype && e->L == L) v.push_back(e);
+    auto rank = [](const KernelEntry* e) {
+        // fewest stages first; among equal counts, smallest max radix first
+        int maxr = 0;
+        for (int i = 0; i < e->nstages; ++i) maxr = std::max(maxr, e->radices[i]);
+        return e->nstages * 100 + maxr;
+    };
+    std::stable_sort(v.begin(), v.end(),
+                     [&](const KernelEntry* x, const KernelEntry* y) { return rank(x) < rank(y); });
+    return v;
+}
+
+size_t elem_size(int dtype) { return dtype == OFFT_C2C_F64 ? 16 : 8; }
+
+bool smooth235(int64_t n) {
+    if (n < 1) return false;
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+static int ilog2(int64_t v) {
+    int k = 0;
+    while ((int64_t(1) << (k + 1)) <= v) ++k;
+    return k;
+}
+
+int fit_logW(const KernelEntry* k, int logW, int dtype) {
+    if (!k) return 0;
+    const size_t es = elem_size(dtype);
+    while (logW > 0) {
+        const int64_t W = int64_t(1) << logW;
+        const int64_t threads = W * k->tpl;
+        const int64_t lds = W * (int64_t)Pitch_value(k->L) * (int64_t)es;
+        if (threads <= 512 && lds <= kMaxLds) break;
+        --logW;
+    }
+    return logW;
+}
+
+// Heuristic tile width: strided lines get enough columns per row for >= 128 B
+// contiguous segments; contiguous lines get ~256 threads per workgroup.
+static int default_logW(const KernelEntry* k, int dtype, bool strided) {
+    if (!k) return 0;
+    int logW;
+    if (strided)
+        logW = dtype == OFFT_C2C_F64 ? 3 : 4;
+    else
+        logW = ilog2(std::max<int64_t>(1, 256 / k->tpl));
+    return fit_logW(k, logW, dtype);
+}
+
+static bool axis_strided(int axis, const int64_t dims[3]) {
+    // M2 of an axis: product of the later axes' lengths
+    int64_t m2 = 1;
+    for (int j = axis + 1; j < 3; ++j) m2 *= dims[j];
+    return m2 > 1;
+}
+
+PlanChoice default_choice(int dtype, const int64_t dims[3]) {
+    PlanChoice c;
+    c.order[0] = 2; c.order[1] = 1; c.order[2] = 0;   // c, then b, then a
+    for (int ax = 0; ax < 3; ++ax) {
+        c.k[ax] = nullptr;
+        c.logW[ax] = 0;
+        if (dims[ax] > 1) {
+            std::vector<const KernelEntry*> ks = kernels_for(dtype, (int)dims[ax]);
+            if (!ks.empty()) {
+                c.k[ax] = ks[0];
+                c.logW[ax] = default_logW(ks[0], dtype, axis_strided(ax, dims));
+            }
+        }
+    }
+    return c;
+}
+
+std::vector<PlanChoice> candidate_choices(int dtype, const int64_t dims[3]) {
+    std::vector<PlanChoice> out;
+    const PlanChoice base = default_choice(dtype, dims);
+    out.push_back(base);
+    // per-axis variants with the default order: other radix sequences and
+    // tile widths one step either side of the heuristic
+    for (int ax = 0; ax < 3; ++ax) {
+        if (dims[ax] <= 1) continue;
+        std::vector<const KernelEntry*> ks = kernels_for(dtype, (int)dims[ax]);
+        for (const KernelEntry* k : ks) {
+            const int l0 = default_logW(k, dtype, axis_strided(ax, dims));
+            for (int dl = -1; dl <= 1; ++dl) {
+                const int lw = l0 + dl;
+                if (lw < 0 || fit_logW(k, lw, dtype) != lw) continue;
+                if (k == base.k[ax] && lw == base.logW[ax]) continue;
+                PlanChoice c = base;
+                c.k[ax] = k;
+                c.logW[ax] = lw;
+                out.push_back(c);
+            }
+        }
+    }
+    // other axis orders with the default kernels
+    const int perms[5][3] = {{2, 0, 1}, {1, 2, 0}, {1, 0, 2}, {0, 2, 1}, {0, 1, 2}};
+    for (const auto& pm : perms) {
+        PlanChoice c = base;
+        for (int i = 0; i < 3; ++i) c.order[i] = pm[i];
+        out.push_back(c);
+    }
+    return out;
+}
+
+static const char kAxisName[] = "abc";
+
+std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]) {
+    std::ostringstream os;
+    os << "order=" << kAxisName[c.order[0]] << kAxisName[c.order[1]] << kAxisName[c.order[2]];
+    for (int ax = 0; ax < 3; ++ax) {
+        os << ";" << kAxisName[ax] << "=";
+        if (!c.k[ax] || dims[ax] <= 1) {
+            os << "1";
+            continue;
+        }
+        for (int i = 0; i < c.k[ax]->nstages; ++i) os << (i ? "x" : "") << c.k[ax]->radices[i];
+        os << "/" << (1 << c.logW[ax]);
+    }
+    return os.str();
+}
+
+bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanChoice* out) {
+    if (!s) return false;
+    PlanChoice c = default_choice(dtype, dims);
+    std::string str(s);
+    std::stringstream ss(str);
+    std::string item;
+    bool have_order = false;
+    while (std::getline(ss, item, ';')) {
+        const size_t eq = item.find('=');
+        if (eq == std::string::npos) return false;
+        const std::string key = item.substr(0, eq), val = item.substr(eq + 1);
+        if (key == "order") {
+            if (val.size() != 3) return false;
+            bool seen[3] = {false, false, false};
+            for (int i = 0; i < 3; ++i) {
+                const char* p = strchr(kAxisName, val[i]);
+                if (!p || val[i] == 0) return false;
+                const int ax = int(p - kAxisName);
+                if (seen[ax]) return false;
+                seen[ax] = true;
+                c.order[i] = ax;
+            }
+            have_order = true;
+        } else if (key.size() == 1 && strchr(kAxisName, key[0]) && key[0]) {
+            const int ax = int(strchr(kAxisName, key[0]) - kAxisName);
+            if (dims[ax] <= 1) {
+                if (val != "1") return false;
+                continue;
+            }
+            const size_t slash = val.find('/');
+            if (slash == std::string::npos) return false;
+            std::vector<int> rad;
+            std::stringstream rs(val.substr(0, slash));
+            std::string tok;
+            while (std::getline(rs, tok, 'x')) {
+                char* end = nullptr;
+                const long r = strtol(tok.c_str(), &end, 10);
+                if (!end || *end || r < 2) return false;
+                rad.push_back((int)r);
+            }
+            char* end = nullptr;
+            const long W = strtol(val.c_str() + slash + 1, &end, 10);
+            if (!end || *end || W < 1 || (W & (W - 1))) return false;
+            const KernelEntry* found = nullptr;
+            for (const KernelEntry* k : kernels_for(dtype, (int)dims[ax])) {
+                if (k->nstages != (int)rad.size()) continue;
+                bool eq2 = true;
+                for (int i = 0; i < k->nstages; ++i) eq2 = eq2 && k->radices[i] == rad[i];
+                if (eq2) { found = k; break; }
+            }
+            if (!found) return false;
+            const int lw = ilog2(W);
+            if (fit_logW(found, lw, dtype) != lw) return false;
+            c.k[ax] = found;
+            c.logW[ax] = lw;
+        } else {
+            return false;
+        }
+    }
+    if (!have_order) return false;
+    *out = c;
+    return true;
+}
+
+int build_passes(const PlanChoice& c, const int64_t dims[3], int64_t batch, PassPlan out[3]) {
+    int n = 0;
+    for (int i = 0; i < 3; ++i) {
+        const int ax = c.order[i];
+        if (dims[ax] <= 1) continue;
+        PassPlan p;
+        p.axis = ax;
+        p.L = (int)dims[ax];
+        int64_t m1 = batch, m2 = 1;
+        for (int j = 0; j < ax; ++j) m1 *= dims[j];
+        for (int j = ax + 1; j < 3; ++j) m2 *= dims[j];
+        p.M1 = m1;
+        p.M2 = m2;
+        p.k = c.k[ax];
+        p.logW = c.logW[ax];
+        p.mode = m2 > 1 ? 1 : 0;
+        p.tw = nullptr;
+        out[n++] = p;
+    }
+    return n;
+}
+
+hipError_t launch_pass(const PassPlan& p, const void* in, void* out, int conj_in, int conj_out,
+                       double scale, hipStream_t s) {
+    PassArgs a;
+    a.in = in;
+    a.out = out;
+    a.tw = p.tw;
+    a.nlines = p.M1 * p.M2;
+    a.M2 = p.M2;
+    a.logW = p.logW;
+    a.mode = p.mode;
+    a.conj_in = conj_in;
+    a.conj_out = conj_out;
+    a.scale = scale;
+    const int64_t W = int64_t(1) << p.logW;
+    const int64_t nblocks = (a.nlines + W - 1) / W;
+    const int threads = (int)(W * p.k->tpl);
+    const size_t lds = (size_t)(W * Pitch_value(p.L)) * (p.k->dtype == OFFT_C2C_F64 ? 16 : 8);
+    return p.k->launch(a, nblocks, threads, lds, s);
+}
+
+}  // namespace offt

@@ -1,0 +1,153 @@
+// tuner.cpp -- run-time plan selection at plan time, the GPU counterpart of
+// the paper's auto-tuning of communication methods (Sec. 3.2.3): every
+// candidate plan is executed a few times during initialization and the
+// fastest is kept; a plan cache plays the role of the paper's "User-select
+// after tuning once".  Candidates: radix sequence and tile width per axis,
+// and the axis order of the passes.
+//
+// Protocol: 1 warm-up + `reps` timed executions per candidate (hipEvents on the
+// tuning stream), score = minimum; ties go to the earlier candidate in the
+// deterministic enumeration (the heuristic default is candidate 0).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/offt.h"
+#include "offt_internal.h"
+#include "plan_impl.h"
+#include "selector.h"
+
+namespace offt {
+
+static std::string device_name() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "unknown";
+    }
+    std::string n = prop.gcnArchName;
+    for (char& ch : n)
+        if (ch == ' ' || ch == '\t') ch = '_';
+    return n;
+}
+
+std::string cache_key(int dtype, const int64_t dims[3], int64_t batch) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "dtype=%d dims=%lldx%lldx%lld batch=%lld dev=%s", dtype, (long long)dims[0],
+             (long long)dims[1], (long long)dims[2], (long long)batch, device_name().c_str());
+    return buf;
+}
+
+// Returns OFFT_SUCCESS and fills *c when the cache holds a usable entry.
+static int cache_lookup(const char* path, int dtype, const int64_t dims[3], int64_t batch, PlanChoice* c) {
+    std::ifstream f(path);
+    if (!f) return OFFT_ERR_IO;
+    const std::string key = cache_key(dtype, dims, batch);
+    std::string line;
+    int rc = OFFT_ERR_IO;
+    while (std::getline(f, line)) {
+        const size_t t1 = line.find('\t');
+        if (t1 == std::string::npos || line.compare(0, t1, key) != 0 || t1 != key.size()) continue;
+        const size_t t2 = line.find('\t', t1 + 1);
+        const std::string plan = line.substr(t1 + 1, t2 == std::string::npos ? std::string::npos : t2 - t1 - 1);
+        PlanChoice pc;
+        if (choice_from_string(plan.c_str(), dtype, dims, &pc)) {
+            *c = pc;   // the latest valid entry wins
+            rc = OFFT_SUCCESS;
+        }
+    }
+    return rc;
+}
+
+static void cache_store(const char* path, int dtype, const int64_t dims[3], int64_t batch,
+                        const PlanChoice& c, float ms) {
+    std::ofstream f(path, std::ios::app);
+    if (!f) return;
+    f << cache_key(dtype, dims, batch) << '\t' << choice_to_string(c, dims) << '\t' << ms << '\n';
+}
+
+// Times one candidate on buffer `buf` (in place).  Returns OFFT_SUCCESS and
+// the minimum time in *ms.
+int time_choice(offt_plan_s* p, const PlanChoice& c, void* buf, hipStream_t s, int reps, float* ms) {
+    PassPlan passes[3];
+    const int n = build_passes(c, p->dims, p->batch, passes);
+    for (int i = 0; i < n; ++i)
+        if (!passes[i].k) return OFFT_ERR_UNSUPPORTED_SIZE;
+    int rc = attach_twiddles(p, passes, n, s);
+    if (rc != OFFT_SUCCESS) return rc;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return OFFT_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OFFT_ERR_HIP; }
+    rc = exec_passes(p, passes, n, buf, buf, OFFT_FORWARD, s);   // warm-up
+    float best = 1e30f;
+    for (int r = 0; r < reps && rc == OFFT_SUCCESS; ++r) {
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = OFFT_ERR_HIP; break; }
+        rc = exec_passes(p, passes, n, buf, buf, OFFT_FORWARD, s);
+        if (rc != OFFT_SUCCESS) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = OFFT_ERR_HIP; break; }
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) { rc = OFFT_ERR_HIP; break; }
+        if (t < best) best = t;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = best;
+    return rc;
+}
+
+static int exhaustive(offt_plan_s* p, const offt_opts& o, PlanChoice* choice) {
+    hipStream_t s = static_cast<hipStream_t>(o.stream);
+    const std::vector<PlanChoice> cands = candidate_choices(p->dtype, p->dims);
+    const size_t bytes = (size_t)(p->dims[0] * p->dims[1] * p->dims[2] * p->batch) * elem_size(p->dtype);
+    void* buf = nullptr;
+    if (hipMalloc(&buf, bytes) != hipSuccess) { (void)hipGetLastError(); return OFFT_ERR_OUT_OF_MEMORY; }
+    int rc = hipMemsetAsync(buf, 0, bytes, s) == hipSuccess ? OFFT_SUCCESS : OFFT_ERR_HIP;
+    int best_i = -1;
+    float best_ms = 1e30f;
+    for (size_t i = 0; i < cands.size() && rc == OFFT_SUCCESS; ++i) {
+        float ms = 0.f;
+        rc = time_choice(p, cands[i], buf, s, o.reps, &ms);
+        if (rc == OFFT_SUCCESS && ms < best_ms) { best_ms = ms; best_i = (int)i; }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    if (rc != OFFT_SUCCESS) return rc;
+    *choice = cands[best_i];
+    char buf2[128];
+    snprintf(buf2, sizeof buf2, "exhaustive: %zu candidates, best #%d %.4f ms", cands.size(), best_i, best_ms);
+    p->tune_log = buf2;
+    if (o.cache_path) cache_store(o.cache_path, p->dtype, p->dims, p->batch, *choice, best_ms);
+    return OFFT_SUCCESS;
+}
+
+int select_plan(offt_plan_s* p, const offt_opts& o, PlanChoice* choice) {
+    if (o.cache_path && cache_lookup(o.cache_path, p->dtype, p->dims, p->batch, choice) == OFFT_SUCCESS) {
+        p->tune_log = "cache";
+        return OFFT_SUCCESS;
+    }
+    if (o.tune == OFFT_TUNE_LEARNED) {
+        std::string why;
+        if (learned_choice(p->dtype, p->dims, p->batch, o.weights_path, choice, &why) == OFFT_SUCCESS) {
+            p->tune_log = "learned";
+            return OFFT_SUCCESS;
+        }
+        // weights missing / unreadable / no feasible prediction: fall back
+        const int rc = exhaustive(p, o, choice);
+        p->tune_log = "learned-fallback(" + why + ") " + p->tune_log;
+        return rc;
+    }
+    return exhaustive(p, o, choice);
+}
+
+std::string describe_plan(const offt_plan_s* p) {
+    if (p->kind == 2) return describe_many(p);
+    return choice_to_string(p->choice, p->dims);
+}
+
+}  // namespace offt

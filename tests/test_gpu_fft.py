@@ -1,0 +1,280 @@
+"""GPU parity of the HIP transform against the CPU oracle (through the C ABI).
+
+Tolerances (relative L2 over the compared values): 1e-12 for complex128,
+2e-6 * log2(N) for complex64 with N the grid's element count.  complex64
+inputs are binary64 values rounded to binary32; the oracle consumes those
+binary32 values widened exactly, so the error measured is the transform's.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1501_07350_amd as offt
+import synth
+
+pytestmark = pytest.mark.gpu
+
+C128, C64 = torch.complex128, torch.complex64
+
+
+def tol(n, dtype):
+    return oracle.tolerance(n, dtype == C64)
+
+
+def gen(shape, dtype, key=synth.SEED, dev="cuda"):
+    return synth.complex_grid(shape, dtype, key=key, device=dev)
+
+
+def host(x):
+    return x.detach().cpu().numpy().astype(np.complex128)
+
+
+def run(shape, dtype, batch=1, inplace=False, forced=None, key=synth.SEED, normalize=False):
+    full = (batch,) + tuple(shape) if batch > 1 else tuple(shape)
+    x = gen(full, dtype, key)
+    plan = offt.Plan(shape, dtype=dtype, batch=batch, tune="forced" if forced else "none",
+                     forced_plan=forced, normalize_inverse=normalize)
+    if inplace:
+        y = x.clone()
+        plan.forward(y, out=y)
+    else:
+        y = plan.forward(x)
+    torch.cuda.synchronize()
+    return plan, x, y
+
+
+def ref3(xh, sign=oracle.FORWARD):
+    if xh.ndim == 4:
+        return np.stack([oracle.fft3(g, sign) for g in xh])
+    return oracle.fft3(xh, sign)
+
+
+# ------------------------------------------------------------ small workload ----
+def test_config1_32cubed_complex128_vs_brute_force():
+    """32x32x32 complex128 forward vs the brute-force definition, then the
+    inverse; round trip with 1/N."""
+    plan, x, y = run((32, 32, 32), C128, normalize=True)
+    xh = host(x)
+    e_brute = oracle.rel_l2(host(y), oracle.dft3_brute(xh))
+    e_axes = oracle.rel_l2(host(y), oracle.dft3_axes(xh))
+    z = plan.backward(y)
+    torch.cuda.synchronize()
+    e_rt = oracle.rel_l2(host(z), xh)
+    print(f"32^3 c128: brute {e_brute:.2e} axes {e_axes:.2e} roundtrip {e_rt:.2e}")
+    assert e_brute <= 1e-12 and e_axes <= 1e-12 and e_rt <= 1e-12
+
+
+TINY = [(1, 1, 1), (2, 3, 5), (5, 3, 2), (4, 4, 4), (8, 6, 10), (1, 9, 1), (3, 1, 16), (16, 1, 1),
+        (1, 1, 2), (2, 1, 1), (6, 5, 4), (15, 12, 10), (9, 25, 27)]
+
+
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("shape", TINY, ids=lambda s: "x".join(map(str, s)))
+def test_tiny_grids_vs_brute_force(shape, dtype):
+    plan, x, y = run(shape, dtype)
+    xh = host(x)
+    ref = oracle.dft3_brute(xh)
+    assert oracle.rel_l2(host(y), ref) <= tol(x.numel(), dtype)
+    # backward, unnormalised
+    z = plan.backward(x)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(host(z), oracle.dft3_brute(xh, oracle.BACKWARD)) <= tol(x.numel(), dtype)
+
+
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+def test_batched_ragged_and_inplace(dtype):
+    # batch of 5 grids, lines not a multiple of any tile width
+    shape = (6, 10, 15)
+    plan, x, y = run(shape, dtype, batch=5, key=synth.SEED + 9)
+    ref = ref3(host(x))
+    assert oracle.rel_l2(host(y), ref) <= tol(np.prod(shape), dtype)
+    _, x2, y2 = run(shape, dtype, batch=5, inplace=True, key=synth.SEED + 9)
+    assert torch.equal(y, y2), "in-place result differs from out-of-place"
+
+
+# ------------------------------------------------------ every 1-D length ----
+LENGTHS = [n for n in range(2, 1025) if synth.smooth_lengths(n, n)]
+
+
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+def test_every_length_contiguous_lines(dtype):
+    """Every 2/3/5-smooth length 2..1024 along the contiguous axis, 37 lines
+    (ragged tile), against the 1-D oracle on each line."""
+    bad = []
+    for L in LENGTHS:
+        plan, x, y = run((1, 1, L), dtype, batch=37, key=synth.SEED + L)
+        xh = host(x).reshape(37, L)
+        ref = oracle.fft1_lines(xh)
+        e = oracle.rel_l2(host(y).reshape(37, L), ref)
+        if e > tol(L, dtype):
+            bad.append((L, e))
+        plan.close()
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+def test_every_length_strided_lines(dtype):
+    """Every length along a strided axis: shape (L, 1, 20) puts L on axis a
+    with stride 20 (not a multiple of the tile width: straddling tiles)."""
+    bad = []
+    for L in LENGTHS:
+        plan, x, y = run((L, 1, 20), dtype, key=synth.SEED + 2 * L)
+        xh = host(x)
+        ref = np.moveaxis(oracle.fft1_lines(np.moveaxis(xh[:, 0, :], 0, 1)), 1, 0)
+        # c axis (20) is transformed too: apply it to the reference
+        ref = oracle.fft1_lines(ref)
+        e = oracle.rel_l2(host(y)[:, 0, :], ref)
+        if e > tol(20 * L, dtype):
+            bad.append((L, e))
+        plan.close()
+    assert not bad, bad
+
+
+def _gen_kernels():
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(offt.__file__), "csrc", "gen_kernels.py")
+    spec = importlib.util.spec_from_file_location("gen_kernels", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _all_forced_plans(shape, dtype):
+    """Plan strings of every radix sequence per axis (default tile width)."""
+    base = offt.Plan(shape, dtype=dtype).describe()
+    fields = dict(kv.split("=") for kv in base.split(";"))
+    plans = [base]
+    gk = _gen_kernels()
+    for ax, L in zip("abc", shape):
+        if L <= 1:
+            continue
+        W = fields[ax].split("/")[1]
+        for seq in gk.radix_seqs(L):
+            f2 = dict(fields)
+            f2[ax] = "x".join(map(str, seq)) + "/" + W
+            s = ";".join(f"{k}={v}" for k, v in f2.items())
+            if s not in plans:
+                plans.append(s)
+    return plans
+
+
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("shape", [(32, 32, 32), (48, 60, 80), (128, 16, 256), (1024, 2, 12)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_every_radix_sequence_and_order(shape, dtype):
+    x = gen(shape, dtype, synth.SEED + 77)
+    ref = oracle.fft3(host(x))
+    plans = _all_forced_plans(shape, dtype)
+    for order in ("abc", "acb", "bac", "bca", "cab"):
+        plans.append(plans[0].replace("order=cba", "order=" + order))
+    for ps in plans:
+        p = offt.Plan(shape, dtype=dtype, tune="forced", forced_plan=ps)
+        assert p.describe() == ps
+        y = p.forward(x)
+        torch.cuda.synchronize()
+        e = oracle.rel_l2(host(y), ref)
+        assert e <= tol(x.numel(), dtype), (ps, e)
+        p.close()
+
+
+def test_tile_widths_forced():
+    shape = (64, 40, 96)
+    for dtype in (C128, C64):
+        x = gen(shape, dtype, synth.SEED + 5)
+        ref = oracle.fft3(host(x))
+        for W in (1, 2, 4, 8, 16):
+            ps = f"order=cba;a=8x8/{W};b=8x5/{W};c=8x4x3/{W}"
+            try:
+                p = offt.Plan(shape, dtype=dtype, tune="forced", forced_plan=ps)
+            except offt.OfftError:
+                continue   # tile does not fit LDS / thread limit for this precision
+            y = p.forward(x)
+            torch.cuda.synchronize()
+            assert oracle.rel_l2(host(y), ref) <= tol(x.numel(), dtype), (dtype, ps)
+            p.close()
+
+
+# ------------------------------------------------------------- twiddles ----
+def roots_extended(n):
+    """exp(-2 pi i m / n) in x87 extended precision (independent of both the
+    GPU generator and the oracle's binary64 table)."""
+    pi = np.arctan(np.longdouble(1)) * 4
+    m = np.arange(n, dtype=np.longdouble)
+    ang = 2 * pi * m / np.longdouble(n)
+    c, s = np.cos(ang), -np.sin(ang)
+    # the quarter points are exact: 1, -i, -1, +i
+    q = (4 * np.arange(n)) % n == 0
+    k = (4 * np.arange(n))[q] // n
+    c[q] = np.array([1, 0, -1, 0], dtype=np.longdouble)[k]
+    s[q] = np.array([0, -1, 0, 1], dtype=np.longdouble)[k]
+    return c, s
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 12, 60, 150, 512, 1000, 1024])
+def test_twiddles_fp64_and_rounded_fp32(n):
+    t64 = offt.twiddles(n, C128)
+    cr, ci = roots_extended(n)
+    # binary64 table within ~1 ulp of the extended-precision value
+    err = np.maximum(np.abs(t64.real - cr), np.abs(t64.imag - ci)).astype(np.float64)
+    assert np.max(err) <= 2.3e-16
+    # and within the oracle table's own accuracy of the oracle
+    assert np.max(np.abs(t64 - oracle.root_table(n))) <= 2e-15   # oracle: cos(2 pi m/n) in binary64
+    # exact quarter points
+    assert t64[0] == 1
+    if n % 4 == 0:
+        assert t64[n // 4] == -1j and t64[n // 2] == -1 and t64[3 * n // 4] == 1j
+    # binary32: the binary64 value rounded to nearest; within one binary32 ulp
+    # of RN(extended value), and equal to it almost everywhere
+    t32 = offt.twiddles(n, C64)
+    rr, ri = cr.astype(np.float32), ci.astype(np.float32)
+    ulp_r = np.spacing(np.abs(rr)).astype(np.float64)
+    ulp_i = np.spacing(np.abs(ri)).astype(np.float64)
+    assert np.all(np.abs(t32.real.astype(np.float64) - rr) <= ulp_r)
+    assert np.all(np.abs(t32.imag.astype(np.float64) - ri) <= ulp_i)
+    assert np.mean((t32.real == rr) & (t32.imag == ri)) >= 0.99
+    # and exactly RN of the device's own binary64 table
+    assert np.array_equal(t32, t64.astype(np.complex64))
+
+
+# ------------------------------------------------------- determinism etc ----
+def test_bitwise_deterministic_and_stream_ordered():
+    shape = (64, 64, 64)
+    x = gen(shape, C64)
+    plan = offt.Plan(shape, dtype=C64)
+    y1 = plan.forward(x)
+    y2 = plan.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        y3 = plan.forward(x)
+    s.synchronize()
+    assert torch.equal(y1, y3)
+
+
+def test_normalized_inverse_and_linearity():
+    shape = (20, 24, 30)
+    for dtype in (C128, C64):
+        a = gen(shape, dtype, synth.SEED + 1)
+        b = gen(shape, dtype, synth.SEED + 2)
+        plan = offt.Plan(shape, dtype=dtype, normalize_inverse=True)
+        z = plan.backward(plan.forward(a))
+        torch.cuda.synchronize()
+        assert oracle.rel_l2(host(z), host(a)) <= tol(a.numel(), dtype)
+        fa, fb, fab = plan.forward(a), plan.forward(b), plan.forward(a + b)
+        torch.cuda.synchronize()
+        assert oracle.rel_l2(host(fab), host(fa) + host(fb)) <= tol(a.numel(), dtype)
+
+
+def test_tensor_checks():
+    plan = offt.Plan((8, 8, 8), dtype=C64)
+    with pytest.raises(ValueError):
+        plan.forward(torch.zeros((8, 8, 8), dtype=C128, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.forward(torch.zeros((8, 8, 16), dtype=C64, device="cuda")[:, :, :8])
+    with pytest.raises(ValueError):
+        plan.forward(torch.zeros((8, 8, 8), dtype=C64))
