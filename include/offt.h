@@ -109,6 +109,19 @@ offt_plan_t offt_plan_ex(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t 
 int offt_exec_fwd(offt_plan_t p, const void* in, void* out, void* stream);
 int offt_exec_bwd(offt_plan_t p, const void* in, void* out, void* stream);
 
+/* Number of axis passes of a plan (0..3: axes of length 1 need none), or a
+ * negative code. */
+int offt_plan_passes(offt_plan_t p);
+
+/* Launch only axis pass i (0-based, plan order) of the forward
+ * (direction = OFFT_FORWARD) or backward (OFFT_BACKWARD) transform.  Launching
+ * passes 0..n-1 in order on one stream with the same in/out is exactly
+ * offt_exec_fwd / offt_exec_bwd (pass 0 reads `in`, later passes work in place
+ * on `out`); it exists so that each pass can be timed on its own.
+ * Errors: INVALID_ARG (NULL plan/pointer, i out of range, bad direction),
+ * BAD_PLAN, HIP. */
+int offt_exec_pass(offt_plan_t p, int i, int direction, const void* in, void* out, void* stream);
+
 /* Free every plan-owned allocation.  NULL is a no-op.  The handle is invalid
  * afterwards. */
 int offt_destroy(offt_plan_t p);

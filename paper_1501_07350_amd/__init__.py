@@ -114,6 +114,15 @@ class Plan:
         _lib.check(fn(self._h, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
                       ctypes.c_void_p(stream)), "exec")
 
+    def npasses(self) -> int:
+        return _lib.check(_lib.load().offt_plan_passes(self._h), "plan_passes")
+
+    def exec_pass(self, i: int, direction: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+        """Launch only axis pass i (plan order); passes 0..n-1 in order equal exec."""
+        _lib.check(_lib.load().offt_exec_pass(self._h, int(i), int(direction), ctypes.c_void_p(in_ptr),
+                                              ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream)),
+                   "exec_pass")
+
     def describe(self) -> str:
         lib = _lib.load()
         n = _lib.check(lib.offt_plan_describe(self._h, None, 0), "describe")

@@ -56,6 +56,8 @@ SIGNATURES = {
     "offt_exec_fwd": (_ci, [_vp, _vp, _vp, _vp]),
     "offt_exec_bwd": (_ci, [_vp, _vp, _vp, _vp]),
     "offt_destroy": (_ci, [_vp]),
+    "offt_plan_passes": (_ci, [_vp]),
+    "offt_exec_pass": (_ci, [_vp, _ci, _ci, _vp, _vp, _vp]),
     "offt_plan_describe": (_ci, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "offt_workspace_bytes": (_i64, [_vp]),
     "offt_last_error": (_ci, []),

@@ -208,6 +208,30 @@ int offt_exec_bwd(offt_plan_t p, const void* in, void* out, void* stream) {
     return exec_checked(p, in, out, stream, OFFT_BACKWARD);
 }
 
+int offt_plan_passes(offt_plan_t p) {
+    if (!p) { set_error(OFFT_ERR_INVALID_ARG); return OFFT_ERR_INVALID_ARG; }
+    if (p->kind != 1) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
+    set_error(OFFT_SUCCESS);
+    return p->npass;
+}
+
+int offt_exec_pass(offt_plan_t p, int i, int direction, const void* in, void* out, void* stream) {
+    if (!p || !in || !out || (direction != OFFT_FORWARD && direction != OFFT_BACKWARD)) {
+        set_error(OFFT_ERR_INVALID_ARG);
+        return OFFT_ERR_INVALID_ARG;
+    }
+    if (p->kind != 1) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
+    if (i < 0 || i >= p->npass) { set_error(OFFT_ERR_INVALID_ARG); return OFFT_ERR_INVALID_ARG; }
+    const int64_t N = p->dims[0] * p->dims[1] * p->dims[2];
+    const bool bwd = direction == OFFT_BACKWARD;
+    const bool last = i == p->npass - 1;
+    const double scale = (bwd && last && p->normalize) ? 1.0 / (double)N : 1.0;
+    const int rc = launch_pass(p->passes[i], i == 0 ? in : out, out, bwd && i == 0, bwd && last, scale,
+                               static_cast<hipStream_t>(stream)) == hipSuccess ? OFFT_SUCCESS : OFFT_ERR_HIP;
+    set_error(rc);
+    return rc;
+}
+
 int offt_destroy(offt_plan_t p) {
     free_plan(p);
     set_error(OFFT_SUCCESS);

@@ -145,47 +145,119 @@ template <int R, typename V> __device__ __forceinline__ void dft(V* v) {
     else static_assert(R == 2, "unsupported radix");
 }
 
-// ---- one Stockham stage out of LDS ------------------------------------------
-// `line` points at the LDS copy of this thread's line; t in [0, TPL) is the
-// thread's rank within the line.  tw holds W_L^m, m < L.
-template <typename V, int L, int TPL, int NS, int R>
-__device__ __forceinline__ void fft_stage(V* __restrict__ line, const V* __restrict__ tw, int t) {
-    constexpr int B = L / R;                 // butterflies in this stage
-    constexpr int NB = (B + TPL - 1) / TPL;  // butterflies per thread
-    constexpr bool EXACT = (B % TPL) == 0;
-    constexpr int STEP = L / (NS * R);       // W_{Ns R}^e = W_L^(e STEP)
-    V v[NB][R];
+// ---- LDS layout of a tile ----------------------------------------------------
+// Element j of a line sits at lds_idx(j): one pad slot per 16 elements keeps
+// the stride-R scatter of the early Stockham stages off a single bank.  The
+// line pitch is odd so the W lines of a column tile fall on different banks.
+__host__ __device__ constexpr int lds_idx(int j) { return j + (j >> 4); }
+__host__ __device__ constexpr int Pitch_value(int L) { return (lds_idx(L - 1) + 1) | 1; }
+
+// ---- Stockham stages ---------------------------------------------------------
+// A thread of rank t (0 <= t < TPL) within its line owns butterflies
+// b = t + i*TPL of every stage.  The first stage reads its inputs from `src`
+// (HBM or LDS), the last stage hands its outputs to `sink`; the stages in
+// between exchange through the LDS copy `line` of the thread's line.
+template <typename V, int L, int TPL, int R>
+struct StageShape {
+    static constexpr int B = L / R;                 // butterflies in the stage
+    static constexpr int NB = (B + TPL - 1) / TPL;  // butterflies per thread
+    static constexpr bool EXACT = (B % TPL) == 0;
+};
+
+// Stage with span NS (product of earlier radices) and radix R whose input is
+// in LDS.  If it is the last stage (NS*R == L), its outputs go to `sink`
+// (natural order index j = b + r*L/R); otherwise they are written back to LDS
+// at the Stockham positions and the next stage follows.
+template <typename V, int L, int TPL, bool OUT_LDS, int NS, int R, int... Rest, typename Sink>
+__device__ __forceinline__ void stages_from_lds(V* __restrict__ line, const V* __restrict__ tw, int t,
+                                                Sink& sink) {
+    using SH = StageShape<V, L, TPL, R>;
+    constexpr int STEP = L / (NS * R);   // W_{Ns R}^e = W_L^(e STEP)
+    V v[SH::NB][R];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
+    for (int i = 0; i < SH::NB; ++i) {
         const int b = t + i * TPL;
-        if (EXACT || b < B) {
+        if (SH::EXACT || b < SH::B) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = line[b + r * B];
-            if constexpr (NS > 1) {
-                const int k = b % NS;
+            for (int r = 0; r < R; ++r) v[i][r] = line[lds_idx(b + r * SH::B)];
+            const int k = b % NS;
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[r * k * STEP]);
-            }
+            for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[r * k * STEP]);
             dft<R>(v[i]);
         }
     }
-    __syncthreads();
+    if constexpr (sizeof...(Rest) == 0) {
+        static_assert(NS * R == L, "last stage must complete the transform");
+        if constexpr (OUT_LDS) __syncthreads();   // every read of the stage precedes the writes
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const int b = t + i * TPL;
-        if (EXACT || b < B) {
-            const int base = (b / NS) * NS * R + (b % NS);
+        for (int i = 0; i < SH::NB; ++i) {
+            const int b = t + i * TPL;
+            if (SH::EXACT || b < SH::B) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) line[base + r * NS] = v[i][r];
+                for (int r = 0; r < R; ++r) sink(b + r * SH::B, v[i][r]);
+            }
         }
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < SH::NB; ++i) {
+            const int b = t + i * TPL;
+            if (SH::EXACT || b < SH::B) {
+                const int base = (b / NS) * NS * R + (b % NS);
+#pragma unroll
+                for (int r = 0; r < R; ++r) line[lds_idx(base + r * NS)] = v[i][r];
+            }
+        }
+        __syncthreads();
+        stages_from_lds<V, L, TPL, OUT_LDS, NS * R, Rest...>(line, tw, t, sink);
     }
-    __syncthreads();
 }
 
-template <typename V, int L, int TPL, int NS, int R, int... Rest>
-__device__ __forceinline__ void run_stages(V* __restrict__ line, const V* __restrict__ tw, int t) {
-    fft_stage<V, L, TPL, NS, R>(line, tw, t);
-    if constexpr (sizeof...(Rest) > 0) run_stages<V, L, TPL, NS * R, Rest...>(line, tw, t);
+// Whole 1-D FFT of the thread's line.  IN_LDS: `src` reads LDS (so the first
+// stage's writes wait for every read); OUT_LDS: `sink` writes LDS.
+template <typename V, int L, int TPL, bool IN_LDS, bool OUT_LDS, int R, int... Rest, typename Src,
+          typename Sink>
+__device__ __forceinline__ void run_fft(V* __restrict__ line, const V* __restrict__ tw, int t, Src& src,
+                                        Sink& sink) {
+    using SH = StageShape<V, L, TPL, R>;
+    V v[SH::NB][R];
+#pragma unroll
+    for (int i = 0; i < SH::NB; ++i) {
+        const int b = t + i * TPL;
+        if (SH::EXACT || b < SH::B) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = src(b + r * SH::B);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < SH::NB; ++i) {
+        const int b = t + i * TPL;
+        if (SH::EXACT || b < SH::B) dft<R>(v[i]);   // span 1: no twiddles
+    }
+    if constexpr (sizeof...(Rest) == 0) {
+        // a single stage: output j = r (one butterfly, b = 0)
+        if constexpr (OUT_LDS || IN_LDS) __syncthreads();
+#pragma unroll
+        for (int i = 0; i < SH::NB; ++i) {
+            const int b = t + i * TPL;
+            if (SH::EXACT || b < SH::B) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) sink(b + r * SH::B, v[i][r]);
+            }
+        }
+    } else {
+        if constexpr (IN_LDS) __syncthreads();
+#pragma unroll
+        for (int i = 0; i < SH::NB; ++i) {
+            const int b = t + i * TPL;
+            if (SH::EXACT || b < SH::B) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) line[lds_idx(b * R + r)] = v[i][r];
+            }
+        }
+        __syncthreads();
+        stages_from_lds<V, L, TPL, OUT_LDS, R, Rest...>(line, tw, t, sink);
+    }
 }
 
 template <int... Rs> struct RadixProduct;
@@ -219,20 +291,24 @@ template <typename V, typename S> __device__ __forceinline__ V fix_out(V x, int 
     return x;
 }
 
-// LDS line pitch: one extra element keeps the W lines of a column tile on
-// different banks.
-__host__ __device__ constexpr int Pitch_value(int L) { return L + 1; }
-template <int L> struct Pitch { static constexpr int value = Pitch_value(L); };
+// Contiguous lines with fewer than this many threads per line are staged
+// through LDS with a flat coalesced copy (direct loads would touch one
+// element per line per lane).
+constexpr int kDirectRowMinTpl = 16;
 
 // Device body of one axis pass for one tile of W = 2^logW lines starting at
-// line l0.  Threads: W * TPL.  lds: W * Pitch<L> elements.
+// line l0.  Threads: W * TPL.  lds: W * Pitch_value(L) elements.
+//   strided lines:     lanes walk the W lines (consecutive columns of a row),
+//                      first/last stage straight from/to HBM.
+//   contiguous lines:  lanes walk along the line; first/last stage straight
+//                      from/to HBM when TPL >= kDirectRowMinTpl, else the tile
+//                      is staged through LDS as one contiguous block.
 template <typename V, int L, int TPL, int... Rs>
 __device__ __forceinline__ void pass_tile(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
     using S = decltype(V{}.x);
     static_assert(RadixProduct<Rs...>::value == L, "radix sequence must multiply to L");
-    constexpr int LP = Pitch<L>::value;
+    constexpr int LP = Pitch_value(L);
     const int W = 1 << a.logW;
-    const int NT = W * TPL;
     const int tid = threadIdx.x;
     const int64_t rem = a.nlines - l0;
     const int nl = rem < W ? (int)rem : W;
@@ -242,69 +318,51 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, V* __restrict__ lds
     const int cin = a.conj_in, cout = a.conj_out;
     const S scale = (S)a.scale;
 
-    if (a.mode == 0) {
-        // contiguous lines: the tile is one block of nl*L elements
+    if (a.mode == 1) {
+        const int w = tid & (W - 1);
+        const int t = tid >> a.logW;
+        const bool ok = w < nl;
+        const int64_t l = l0 + (ok ? w : 0);   // rows beyond the tail read line l0, store nothing
+        const int64_t m1 = l / a.M2, m2 = l - m1 * a.M2;
+        const int64_t base = m1 * (int64_t)L * a.M2 + m2;
+        const int64_t M2 = a.M2;
+        const V* g = in + base;
+        V* go = out + base;
+        auto src = [&](int j) { return fix_in(g[(int64_t)j * M2], cin); };
+        auto sink = [&](int j, V x) {
+            if (ok) go[(int64_t)j * M2] = fix_out(x, cout, scale);
+        };
+        run_fft<V, L, TPL, false, false, Rs...>(lds + w * LP, tw, t, src, sink);
+        return;
+    }
+    const int t = tid % TPL, w = tid / TPL;
+    V* line = lds + w * LP;
+    if constexpr (TPL >= kDirectRowMinTpl) {
+        const bool ok = w < nl;
+        const V* g = in + (l0 + (ok ? w : 0)) * L;
+        V* go = out + (l0 + w) * L;
+        auto src = [&](int j) { return fix_in(g[j], cin); };
+        auto sink = [&](int j, V x) {
+            if (ok) go[j] = fix_out(x, cout, scale);
+        };
+        run_fft<V, L, TPL, false, false, Rs...>(line, tw, t, src, sink);
+    } else {
+        // stage the contiguous block of nl*L elements through LDS
+        const int NT = W * TPL;
         const V* g = in + l0 * L;
-        if (nl == W) {
-#pragma unroll
-            for (int k = 0; k < L / TPL; ++k) {
-                const int f = tid + k * NT;
-                const int w = f / L, j = f - w * L;
-                lds[w * LP + j] = fix_in(g[f], cin);
-            }
-        } else {
-            for (int f = tid; f < nl * L; f += NT) {
-                const int w = f / L, j = f - w * L;
-                lds[w * LP + j] = fix_in(g[f], cin);
-            }
+        V* go = out + l0 * L;
+        for (int f = tid; f < nl * L; f += NT) {
+            const int lw = f / L, j = f - lw * L;
+            lds[lw * LP + lds_idx(j)] = fix_in(g[f], cin);
         }
-    } else {
-        // strided lines: lanes walk W consecutive lines (columns) of one row
-        const int w = tid & (W - 1);
-        const int jj = tid >> a.logW;
-        if (w < nl) {
-            const int64_t l = l0 + w;
-            const int64_t m1 = l / a.M2, m2 = l - m1 * a.M2;
-            const V* g = in + m1 * (int64_t)L * a.M2 + m2;
-#pragma unroll
-            for (int k = 0; k < L / TPL; ++k) {
-                const int j = jj + k * TPL;
-                lds[w * LP + j] = fix_in(g[(int64_t)j * a.M2], cin);
-            }
-        }
-    }
-    __syncthreads();
-    {
-        const int w = tid / TPL, t = tid - (tid / TPL) * TPL;
-        run_stages<V, L, TPL, 1, Rs...>(lds + w * LP, tw, t);
-    }
-    if (a.mode == 0) {
-        V* g = out + l0 * L;
-        if (nl == W) {
-#pragma unroll
-            for (int k = 0; k < L / TPL; ++k) {
-                const int f = tid + k * NT;
-                const int w = f / L, j = f - w * L;
-                g[f] = fix_out(lds[w * LP + j], cout, scale);
-            }
-        } else {
-            for (int f = tid; f < nl * L; f += NT) {
-                const int w = f / L, j = f - w * L;
-                g[f] = fix_out(lds[w * LP + j], cout, scale);
-            }
-        }
-    } else {
-        const int w = tid & (W - 1);
-        const int jj = tid >> a.logW;
-        if (w < nl) {
-            const int64_t l = l0 + w;
-            const int64_t m1 = l / a.M2, m2 = l - m1 * a.M2;
-            V* g = out + m1 * (int64_t)L * a.M2 + m2;
-#pragma unroll
-            for (int k = 0; k < L / TPL; ++k) {
-                const int j = jj + k * TPL;
-                g[(int64_t)j * a.M2] = fix_out(lds[w * LP + j], cout, scale);
-            }
+        __syncthreads();
+        auto src = [&](int j) { return line[lds_idx(j)]; };
+        auto sink = [&](int j, V x) { line[lds_idx(j)] = x; };
+        run_fft<V, L, TPL, true, true, Rs...>(line, tw, t, src, sink);
+        __syncthreads();
+        for (int f = tid; f < nl * L; f += NT) {
+            const int lw = f / L, j = f - lw * L;
+            go[f] = fix_out(lds[lw * LP + lds_idx(j)], cout, scale);
         }
     }
 }

@@ -12,7 +12,9 @@
 namespace offt {
 
 constexpr int kMaxStages = 8;
-constexpr int kMaxLds = 64 * 1024;   // bytes of LDS a pass tile may use
+// Bytes of LDS a pass tile may use: the device's per-workgroup limit (160 KiB
+// on gfx950), 64 KiB when no device is visible.
+int64_t lds_limit();
 
 using LaunchFn = hipError_t (*)(const PassArgs& a, int64_t nblocks, int threads, size_t lds,
                                 hipStream_t s);

@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <sstream>
+#include <tuple>
 
 #include "offt_internal.h"
 #include "../../include/offt.h"
@@ -31,23 +32,27 @@ const std::vector<const KernelEntry*>& registry() {
     return all;
 }
 
-// Default-first order: the generator emits the default sequence of a length
-// first; tables are interleaved across files, so sort by the sequence's rank
-// within its length, recovered from the generator's ordering rule
-// (balanced <= 16 first, then balanced <= 8, then greedy 16).
+// Kernels of one length, default first: fewest stages, then largest leading
+// radix, then the most threads per line (one butterfly of the largest radix
+// per thread).
 std::vector<const KernelEntry*> kernels_for(int dtype, int L) {
     std::vector<const KernelEntry*> v;
     for (const KernelEntry* e : registry())
         if (e->dtype == dtype && e->L == L) v.push_back(e);
-    auto rank = [](const KernelEntry* e) {
-        // fewest stages first; among equal counts, smallest max radix first
+    auto key = [](const KernelEntry* e) {
         int maxr = 0;
         for (int i = 0; i < e->nstages; ++i) maxr = std::max(maxr, e->radices[i]);
-        return e->nstages * 100 + maxr;
+        return std::make_tuple(e->nstages, -maxr, -e->tpl);
     };
     std::stable_sort(v.begin(), v.end(),
-                     [&](const KernelEntry* x, const KernelEntry* y) { return rank(x) < rank(y); });
+                     [&](const KernelEntry* x, const KernelEntry* y) { return key(x) < key(y); });
     return v;
+}
+
+static int default_tpl(const KernelEntry* k) {
+    int maxr = 0;
+    for (int i = 0; i < k->nstages; ++i) maxr = std::max(maxr, k->radices[i]);
+    return k->L / maxr;
 }
 
 size_t elem_size(int dtype) { return dtype == OFFT_C2C_F64 ? 16 : 8; }
@@ -65,6 +70,19 @@ static int ilog2(int64_t v) {
     return k;
 }
 
+int64_t lds_limit() {
+    static const int64_t lim = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
+            (void)hipGetLastError();
+            return int64_t(64 * 1024);
+        }
+        return int64_t(v);
+    }();
+    return lim;
+}
+
 int fit_logW(const KernelEntry* k, int logW, int dtype) {
     if (!k) return 0;
     const size_t es = elem_size(dtype);
@@ -72,22 +90,35 @@ int fit_logW(const KernelEntry* k, int logW, int dtype) {
         const int64_t W = int64_t(1) << logW;
         const int64_t threads = W * k->tpl;
         const int64_t lds = W * (int64_t)Pitch_value(k->L) * (int64_t)es;
-        if (threads <= 512 && lds <= kMaxLds) break;
+        if (threads <= 512 && lds <= lds_limit()) break;
         --logW;
     }
     return logW;
 }
 
-// Heuristic tile width: strided lines get enough columns per row for >= 128 B
-// contiguous segments; contiguous lines get ~256 threads per workgroup.
+// Heuristic tile width: strided lines get 256-byte row segments (16 columns
+// of complex128, 32 of complex64) when the tile fits, contiguous lines ~512
+// threads per workgroup for complex128 and ~128 for complex64.
 static int default_logW(const KernelEntry* k, int dtype, bool strided) {
     if (!k) return 0;
     int logW;
     if (strided)
-        logW = dtype == OFFT_C2C_F64 ? 3 : 4;
+        logW = dtype == OFFT_C2C_F64 ? 4 : 5;
     else
-        logW = ilog2(std::max<int64_t>(1, 256 / k->tpl));
+        logW = ilog2(std::max<int64_t>(1, (dtype == OFFT_C2C_F64 ? 512 : 128) / k->tpl));
     return fit_logW(k, logW, dtype);
+}
+
+// Default kernel of an axis: the first in kernels_for() order whose tile at the
+// heuristic width reaches 256-byte rows for strided lines; otherwise the first.
+static const KernelEntry* default_kernel(int dtype, int L, bool strided) {
+    std::vector<const KernelEntry*> ks = kernels_for(dtype, L);
+    if (ks.empty()) return nullptr;
+    if (!strided) return ks[0];
+    const int want = dtype == OFFT_C2C_F64 ? 4 : 5;
+    for (const KernelEntry* k : ks)
+        if (default_logW(k, dtype, true) >= want) return k;
+    return ks[0];
 }
 
 static bool axis_strided(int axis, const int64_t dims[3]) {
@@ -104,10 +135,11 @@ PlanChoice default_choice(int dtype, const int64_t dims[3]) {
         c.k[ax] = nullptr;
         c.logW[ax] = 0;
         if (dims[ax] > 1) {
-            std::vector<const KernelEntry*> ks = kernels_for(dtype, (int)dims[ax]);
-            if (!ks.empty()) {
-                c.k[ax] = ks[0];
-                c.logW[ax] = default_logW(ks[0], dtype, axis_strided(ax, dims));
+            const bool strided = axis_strided(ax, dims);
+            const KernelEntry* k = default_kernel(dtype, (int)dims[ax], strided);
+            if (k) {
+                c.k[ax] = k;
+                c.logW[ax] = default_logW(k, dtype, strided);
             }
         }
     }
@@ -159,6 +191,7 @@ std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]) {
         }
         for (int i = 0; i < c.k[ax]->nstages; ++i) os << (i ? "x" : "") << c.k[ax]->radices[i];
         os << "/" << (1 << c.logW[ax]);
+        if (c.k[ax]->tpl != default_tpl(c.k[ax])) os << "/" << c.k[ax]->tpl;
     }
     return os.str();
 }
@@ -205,13 +238,21 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
             }
             char* end = nullptr;
             const long W = strtol(val.c_str() + slash + 1, &end, 10);
-            if (!end || *end || W < 1 || (W & (W - 1))) return false;
+            if (!end || W < 1 || (W & (W - 1))) return false;
+            long tpl = 0;   // 0: the sequence's default thread count
+            if (*end == '/') {
+                char* end2 = nullptr;
+                tpl = strtol(end + 1, &end2, 10);
+                if (!end2 || *end2 || tpl < 1) return false;
+            } else if (*end) {
+                return false;
+            }
             const KernelEntry* found = nullptr;
             for (const KernelEntry* k : kernels_for(dtype, (int)dims[ax])) {
                 if (k->nstages != (int)rad.size()) continue;
                 bool eq2 = true;
                 for (int i = 0; i < k->nstages; ++i) eq2 = eq2 && k->radices[i] == rad[i];
-                if (eq2) { found = k; break; }
+                if (eq2 && k->tpl == (tpl ? (int)tpl : default_tpl(k))) { found = k; break; }
             }
             if (!found) return false;
             const int lw = ilog2(W);

@@ -152,11 +152,20 @@ def _all_forced_plans(shape, dtype):
     for ax, L in zip("abc", shape):
         if L <= 1:
             continue
-        W = fields[ax].split("/")[1]
+        W0 = int(fields[ax].split("/")[1])
         for seq in gk.radix_seqs(L):
-            f2 = dict(fields)
-            f2[ax] = "x".join(map(str, seq)) + "/" + W
-            s = ";".join(f"{k}={v}" for k, v in f2.items())
+            # largest tile width <= the default one that fits this kernel
+            W = W0
+            while True:
+                f2 = dict(fields)
+                f2[ax] = "x".join(map(str, seq)) + f"/{W}"
+                s = ";".join(f"{k}={v}" for k, v in f2.items())
+                try:
+                    offt.Plan(shape, dtype=dtype, tune="forced", forced_plan=s).close()
+                    break
+                except offt.OfftError as e:
+                    assert e.code == -6 and W > 1, (s, e)
+                    W //= 2
             if s not in plans:
                 plans.append(s)
     return plans
