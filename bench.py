@@ -140,15 +140,135 @@ def cpu_baseline(n: int):
 
     x = synth.complex_grid((n, n, n), torch.complex128).numpy()
     cores = oracle.max_threads()
-    t0 = time.perf_counter()
-    y = oracle.fft3(x)
-    dt = time.perf_counter() - t0
+    # repeat whole transforms until about 10 s of CPU work (at most 16)
+    times = []
+    while sum(times) < 10.0 and len(times) < 16:
+        t0 = time.perf_counter()
+        y = oracle.fft3(x)
+        times.append(time.perf_counter() - t0)
+        del y
+    dt = sum(times) / len(times)
     N = x.size
-    del x, y
+    del x
     return {"value": round(5.0 * N * math.log2(N) / (dt * 1e9), 3), "unit": "GFLOP/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"one forward {n}^3 complex128 transform (the whole workload, one execution), "
-                      f"recursive radix-2/3/5 FFT along c, b, a in binary64; {dt:.2f} s"}
+            "sample": f"{len(times)} forward {n}^3 complex128 transforms of the same synthetic grid (the "
+                      f"whole workload per execution), recursive radix-2/3/5 FFT along c, b, a in "
+                      f"binary64, mean {dt:.2f} s each"}
+
+
+# ---------------------------------------------------------------- profiling ----
+# rocprofv3 runs of this script (commands in profiles/README.md) are reduced to
+# short text summaries and to profiles/pmc_traffic.json with the modes below.
+
+CALIB_BYTES = 1 << 31   # bytes read (and written) by one calibration copy
+
+
+def calibrate_copy(reps: int = 3):
+    """Plain device-to-device copies of a known size (torch's copy kernel):
+    HBM counters of a kernel that moves exactly CALIB_BYTES in and out."""
+    import torch
+
+    a = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _find(d, suffix):
+    for root, _, files in os.walk(d):
+        for fn in files:
+            if fn.endswith(suffix):
+                return os.path.join(root, fn)
+    raise FileNotFoundError(f"no *{suffix} under {d}")
+
+
+def summarize_stats(d: str, command: str, n: int, steps: int, warmup: int) -> str:
+    rows = _read_csv(_find(d, "kernel_stats.csv"))
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}",
+             f"{'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total%':>7}  kernel"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"{int(r['Calls']):>6} {float(r['AverageNs'])/1e3:>10.2f} {float(r['MinNs'])/1e3:>10.2f} "
+                     f"{float(r['MaxNs'])/1e3:>10.2f} {float(r['Percentage']):>7.2f}  {r['Name'][:150]}")
+    # per-pass durations from the dispatch trace: the transforms launch pass
+    # 0, 1, 2 per step, complex128 first, then complex64
+    trace = _read_csv(_find(d, "kernel_trace.csv"))
+    trace.sort(key=lambda r: int(r["Dispatch_Id"]))
+    disp = [r for r in trace if "fft_pass_kernel" in r["Kernel_Name"]]
+    lines.append("")
+    lines.append("# per-pass mean duration over the timed steps (from the dispatch trace)")
+    k = 0
+    for tag in (f"{n}^3 complex128", f"{n}^3 complex64"):
+        dur = [[] for _ in range(3)]
+        for st in range(steps + warmup):
+            for i in range(3):
+                r = disp[k]
+                k += 1
+                if st >= warmup:
+                    dur[i].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        for i in range(3):
+            name = disp[k - 3 + i]["Kernel_Name"]
+            mean = sum(dur[i]) / len(dur[i])
+            lines.append(f"{tag} pass {i}: mean {mean:9.2f} us over {len(dur[i])} dispatches  {name[:110]}")
+    return "\n".join(lines) + "\n"
+
+
+def _pmc_per_dispatch(d: str, counter: str):
+    """[(kernel_name, value_KiB)] in dispatch order for one counter."""
+    rows = _read_csv(_find(d, "counter_collection.csv"))
+    per = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter:
+            continue
+        did = int(r["Dispatch_Id"])
+        name, val = r["Kernel_Name"], float(r["Counter_Value"])
+        prev = per.get(did)
+        per[did] = (name, val + (prev[1] if prev else 0.0))
+    return [per[k] for k in sorted(per)]
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, n: int, steps: int, warmup: int, command: str):
+    """Per-pass HBM bytes of the transforms, scaled by the copy calibration:
+    factor = CALIB_BYTES / (counter bytes of one calibration copy)."""
+    out = {"kernel_hash": kernel_source_hash(), "command": command, "workloads": {}}
+    text = [f"# HBM traffic per dispatch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE",
+            f"# command: {command}"]
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        disp = _pmc_per_dispatch(d, counter)
+        passes = [x for x in disp if "fft_pass_kernel" in x[0]]
+        copies = [x for x in disp if "copyBuffer" in x[0]]
+        calib_kib = copies[-1][1]
+        factor = CALIB_BYTES / (calib_kib * 1024.0)
+        text.append(f"{counter}: calibration copy of {CALIB_BYTES} B in and out counted {calib_kib:.0f} KiB -> factor {factor:.4f}")
+        per_step = (steps + warmup)
+        k = 0
+        for tag in (f"{n}_f64", f"{n}_f32"):
+            npass = 3
+            vals = [[] for _ in range(npass)]
+            for _ in range(per_step):
+                for i in range(npass):
+                    vals[i].append(passes[k][1]); k += 1
+            w = out["workloads"].setdefault(tag, {"pass_bytes": [0.0] * npass, "raw": {}})
+            for i in range(npass):
+                kib = sum(vals[i][warmup:]) / max(1, len(vals[i][warmup:]))
+                w["raw"].setdefault(counter, []).append(kib)
+                w["pass_bytes"][i] += kib * 1024.0 * factor
+                text.append(f"{tag} pass {i} {counter}: {kib:.0f} KiB/dispatch -> {kib*1024*factor/1e9:.4f} GB scaled")
+    for tag, w in out["workloads"].items():
+        s = 16 if tag.endswith("f64") else 8
+        alg = 2 * n ** 3 * s
+        w["pass_bytes"] = [round(v) for v in w["pass_bytes"]]
+        w["algorithmic_bytes"] = alg
+        text.append(f"{tag}: measured bytes per pass {[round(v/1e9, 4) for v in w['pass_bytes']]} GB, "
+                    f"algorithmic {alg/1e9:.4f} GB, amplification {[round(v/alg, 3) for v in w['pass_bytes']]}")
+    return out, "\n".join(text) + "\n"
 
 
 def main():
@@ -159,7 +279,24 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled-line parity check")
+    ap.add_argument("--calibrate", action="store_true", help="also run the copy-kernel calibration")
+    ap.add_argument("--summarize-stats", metavar="DIR", help="reduce a rocprofv3 --stats output dir")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="reduce two rocprofv3 --pmc output dirs to profiles/pmc_traffic.json")
+    ap.add_argument("--command", default="", help="profiling command recorded in the summary")
+    ap.add_argument("--out", help="summary text file")
     args = ap.parse_args()
+    if args.summarize_stats:
+        txt = summarize_stats(args.summarize_stats, args.command, args.n, args.steps, args.warmup)
+        open(args.out, "w").write(txt) if args.out else print(txt)
+        return
+    if args.summarize_pmc:
+        d, txt = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.n, args.steps, args.warmup,
+                               args.command)
+        with open(TRAFFIC_FILE, "w") as f:
+            json.dump(d, f, indent=1)
+        open(args.out, "w").write(txt) if args.out else print(txt)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the 3-D FFT is measured on a single MI355X)", file=sys.stderr)
@@ -202,6 +339,8 @@ def main():
         if "check_rel_l2_sampled_lines" in r:
             out[key] = {"rel_l2_sampled_lines": r["check_rel_l2_sampled_lines"],
                         "tolerance": r["check_tolerance"]}
+    if args.calibrate:
+        calibrate_copy()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out), flush=True)
