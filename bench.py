@@ -118,6 +118,81 @@ def time_transform(n: int, dtype, steps: int, warmup: int, check: bool):
     return res
 
 
+def time_batch(steps: int, warmup: int, check: bool, count: int = 64):
+    """Uneven batch of `count` complex64 grids (axes drawn from
+    {48,...,160}): persistent launch replayed from a HIP graph vs every grid's
+    passes launched separately on the same stream."""
+    import numpy as np
+    import torch
+
+    import paper_1501_07350_amd as offt
+    import synth
+
+    dims = synth.uneven_batch_dims(count)
+    dtype = torch.complex64
+    heur = offt.ManyPlan(dims, dtype=dtype, tune="none")
+    t0 = time.perf_counter()
+    tuned = offt.ManyPlan(dims, dtype=dtype, tune="exhaustive")
+    tune_s = time.perf_counter() - t0
+    grids = synth.batch_grids(dims, dtype, device="cuda")
+    x = heur.pack(grids)
+    y = torch.empty_like(x)
+    h = int(torch.cuda.current_stream().cuda_stream)
+    xp, yp = x.data_ptr(), y.data_ptr()
+    variants = {
+        "separate_heuristic": (heur, offt.MANY_SEPARATE_HEURISTIC),
+        "separate_tuned": (tuned, offt.MANY_SEPARATE_TUNED),
+        "persistent_tuned": (tuned, offt.MANY_PERSISTENT),
+        "graph_tuned": (tuned, offt.MANY_PERSISTENT_GRAPH),
+        "graph_heuristic": (heur, offt.MANY_PERSISTENT_GRAPH),
+        "levels_tuned": (tuned, offt.MANY_LEVELS),
+        "levels_graph_tuned": (tuned, offt.MANY_LEVELS_GRAPH),
+    }
+    ms = {}
+    for name, (pl, mode) in variants.items():
+        for _ in range(warmup):
+            pl.exec_ptr(xp, yp, offt.FORWARD, mode, h)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            pl.exec_ptr(xp, yp, offt.FORWARD, mode, h)
+        e1.record()
+        torch.cuda.synchronize()
+        ms[name] = e0.elapsed_time(e1) / steps
+        if mode >= 0 and pl.status() != 0:
+            raise RuntimeError(f"persistent executor reported a dependency timeout ({name})")
+    flop = sum(5.0 * a * b * c * math.log2(a * b * c) for a, b, c in dims)
+    nbytes = sum(6.0 * a * b * c * 8 for a, b, c in dims)
+    out = {
+        "workload": f"{count} complex64 grids, axes uniform over {list(synth.BATCH_AXIS_LENGTHS)}",
+        "elements": int(sum(a * b * c for a, b, c in dims)),
+        "tune_seconds": round(tune_s, 3),
+        "executor": tuned.describe().splitlines()[0],
+        "ms": {k: round(v, 4) for k, v in ms.items()},
+        "gflops": {k: round(flop / (v * 1e6), 1) for k, v in ms.items()},
+        "eff_gbs": {k: round(nbytes / (v * 1e6), 1) for k, v in ms.items()},
+        "speedup_graph_tuned_vs_separate_heuristic": round(ms["separate_heuristic"] / ms["graph_tuned"], 3),
+        "speedup_levels_graph_tuned_vs_separate_heuristic": round(
+            ms["separate_heuristic"] / ms["levels_graph_tuned"], 3),
+    }
+    if check:
+        import oracle
+        tuned.exec_ptr(xp, yp, offt.FORWARD, 1, h)
+        torch.cuda.synchronize()
+        worst = 0.0
+        ys = tuned.unpack(y)
+        for g in (0, 1, count // 2, count - 1):
+            ref = oracle.fft3(grids[g].cpu().numpy().astype(np.complex128))
+            e = oracle.rel_l2(ys[g].cpu().numpy(), ref)
+            worst = max(worst, e / oracle.tolerance(grids[g].numel(), True))
+        out["check_worst_error_over_tolerance_4_grids"] = worst
+    heur.close()
+    tuned.close()
+    return out
+
+
 def roofline(res, tag):
     i = max(range(len(res["pass_ms"])), key=lambda j: res["pass_ms"][j])
     dur_ms = res["pass_ms"][i]
@@ -280,6 +355,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled-line parity check")
     ap.add_argument("--calibrate", action="store_true", help="also run the copy-kernel calibration")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch (64 grids) timing")
     ap.add_argument("--summarize-stats", metavar="DIR", help="reduce a rocprofv3 --stats output dir")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="reduce two rocprofv3 --pmc output dirs to profiles/pmc_traffic.json")
@@ -339,6 +415,8 @@ def main():
         if "check_rel_l2_sampled_lines" in r:
             out[key] = {"rel_l2_sampled_lines": r["check_rel_l2_sampled_lines"],
                         "tolerance": r["check_tolerance"]}
+    if not args.no_batch:
+        out["batch"] = time_batch(args.steps, args.warmup, not args.no_check)
     if args.calibrate:
         calibrate_copy()
     if not args.no_cpu:

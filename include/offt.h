@@ -138,6 +138,12 @@ int64_t offt_workspace_bytes(offt_plan_t p);
 int offt_last_error(void);
 const char* offt_error_string(int code);
 
+/* Plan string of the heuristic plan (OFFT_TUNE_NONE) for one grid shape,
+ * written like offt_plan_describe.  Needs no device: the per-workgroup LDS
+ * limit is the current device's when one is visible, 64 KiB otherwise.
+ * Returns the full string length or INVALID_ARG / UNSUPPORTED_SIZE. */
+int offt_default_plan_string(int64_t Na, int64_t Nb, int64_t Nc, int dtype, char* buf, size_t n);
+
 /* Write the device-generated forward twiddle table W_n^m, m < n, of precision
  * `dtype` to host memory `host_out` (n interleaved complex values).  The table
  * is computed in binary64 on the GPU and rounded to nearest for OFFT_C2C_F32.
@@ -158,13 +164,39 @@ offt_plan_t offt_plan_many(int count, const int64_t* dims, int dtype, const offt
  * packed buffer (i = count), or a negative code. */
 int64_t offt_many_offset(offt_plan_t p, int i);
 
-/* Transform every grid of the packed buffer.  in == out allowed.
- * use_graph = 1 replays the captured graph (captured on first use on that
- * stream), 0 launches the persistent kernel directly.  The separate-launch
- * baseline (every grid's passes as ordinary launches) is use_graph = -1.
- * Never allocates.  Errors: INVALID_ARG, BAD_PLAN (not a many-plan), HIP. */
+/* Transform every grid of the packed buffer (direction OFFT_FORWARD or
+ * OFFT_BACKWARD; the plan's normalize_inverse scales each grid by 1/its N).
+ * in == out allowed.  `use_graph` selects the launch (OFFT_MANY_*):
+ *    1  PERSISTENT_GRAPH: one persistent kernel over every (grid, pass, tile)
+ *       work item, after a counter-reset kernel, replayed from a HIP graph
+ *       built on the first call; later calls with other buffers or direction
+ *       update the graph's kernel arguments;
+ *    0  PERSISTENT: the same two kernels launched directly;
+ *    2  LEVELS_GRAPH: one kernel per pass level (all grids' first passes, then
+ *       all second, then all third), one workgroup per tile, replayed from a
+ *       HIP graph built on the first call;
+ *    3  LEVELS: the same kernels launched directly;
+ *   -1  SEPARATE_HEURISTIC: every grid's passes as ordinary launches with the
+ *       heuristic plans;
+ *   -2  SEPARATE_TUNED: the same with the plans chosen at plan time.
+ * Never allocates device memory.  Errors: INVALID_ARG, BAD_PLAN (not a
+ * many-plan), UNSUPPORTED_SIZE (use_graph >= 0 when an axis length of the
+ * batch is outside the batch executor's set {48, 60, 64, 80, 96, 120, 128,
+ * 150, 160}; lengths 1 are fine), HIP. */
 int offt_exec_many(offt_plan_t p, const void* in, void* out, int direction, int use_graph,
                    void* stream);
+
+/* After the stream that ran offt_exec_many has been synchronised: 0 if the
+ * last persistent run completed every dependency wait normally, OFFT_ERR_HIP
+ * if a wait hit its bounded spin limit (results then invalid). */
+int offt_many_status(offt_plan_t p);
+
+#define OFFT_MANY_SEPARATE_TUNED (-2)
+#define OFFT_MANY_SEPARATE_HEURISTIC (-1)
+#define OFFT_MANY_PERSISTENT 0
+#define OFFT_MANY_PERSISTENT_GRAPH 1
+#define OFFT_MANY_LEVELS_GRAPH 2
+#define OFFT_MANY_LEVELS 3
 
 #define OFFT_FORWARD (-1)
 #define OFFT_BACKWARD (+1)

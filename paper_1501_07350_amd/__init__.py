@@ -14,10 +14,12 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (BACKWARD, C2C_F32, C2C_F64, FORWARD, MAX_AXIS, OfftError, TUNE_EXHAUSTIVE,
-                   TUNE_FORCED, TUNE_LEARNED, TUNE_NONE)
+from ._lib import (BACKWARD, C2C_F32, C2C_F64, FORWARD, MANY_LEVELS, MANY_LEVELS_GRAPH, MANY_PERSISTENT,
+                   MANY_PERSISTENT_GRAPH, MANY_SEPARATE_HEURISTIC, MANY_SEPARATE_TUNED, MAX_AXIS, OfftError,
+                   TUNE_EXHAUSTIVE, TUNE_FORCED, TUNE_LEARNED, TUNE_NONE)
 
-__all__ = ["Plan", "ManyPlan", "OfftError", "twiddles", "FORWARD", "BACKWARD", "MAX_AXIS"]
+__all__ = ["Plan", "ManyPlan", "OfftError", "twiddles", "default_plan_string", "FORWARD", "BACKWARD",
+           "MAX_AXIS"]
 
 _TUNE = {"none": TUNE_NONE, "exhaustive": TUNE_EXHAUSTIVE, "learned": TUNE_LEARNED,
          "forced": TUNE_FORCED}
@@ -195,6 +197,17 @@ class ManyPlan:
                                       ctypes.c_void_p(_stream_handle())), "exec_many")
         return out
 
+    def exec_ptr(self, in_ptr: int, out_ptr: int, direction: int = FORWARD, use_graph: int = 1,
+                 stream: int = 0) -> None:
+        _lib.check(_lib.load().offt_exec_many(self._h, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
+                                              int(direction), int(use_graph), ctypes.c_void_p(stream)),
+                   "exec_many")
+
+    def status(self) -> int:
+        """0, or the error code of a persistent run whose dependency wait timed out
+        (synchronise the stream first)."""
+        return _lib.load().offt_many_status(self._h)
+
     def describe(self) -> str:
         lib = _lib.load()
         n = _lib.check(lib.offt_plan_describe(self._h, None, 0), "describe")
@@ -213,6 +226,16 @@ class ManyPlan:
             self.close()
         except Exception:
             pass
+
+
+def default_plan_string(shape, dtype=torch.complex128) -> str:
+    """Heuristic plan string of a grid shape (no device needed)."""
+    lib = _lib.load()
+    code = _dtype_code(dtype)
+    n = _lib.check(lib.offt_default_plan_string(shape[0], shape[1], shape[2], code, None, 0), "plan string")
+    buf = ctypes.create_string_buffer(n + 1)
+    lib.offt_default_plan_string(shape[0], shape[1], shape[2], code, buf, n + 1)
+    return buf.value.decode()
 
 
 def twiddles(n: int, dtype=torch.complex128):

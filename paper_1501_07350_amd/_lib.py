@@ -30,6 +30,14 @@ TUNE_FORCED = 3
 
 FORWARD = -1
 BACKWARD = +1
+
+# launch forms of offt_exec_many
+MANY_SEPARATE_TUNED = -2
+MANY_SEPARATE_HEURISTIC = -1
+MANY_PERSISTENT = 0
+MANY_PERSISTENT_GRAPH = 1
+MANY_LEVELS_GRAPH = 2
+MANY_LEVELS = 3
 MAX_AXIS = 1024
 
 
@@ -63,9 +71,11 @@ SIGNATURES = {
     "offt_last_error": (_ci, []),
     "offt_error_string": (ctypes.c_char_p, [_ci]),
     "offt_twiddles": (_ci, [_i64, _ci, _vp]),
+    "offt_default_plan_string": (_ci, [_i64, _i64, _i64, _ci, ctypes.c_char_p, ctypes.c_size_t]),
     "offt_plan_many": (_vp, [_ci, ctypes.POINTER(_i64), _ci, ctypes.POINTER(Opts)]),
     "offt_many_offset": (_i64, [_vp, _ci]),
     "offt_exec_many": (_ci, [_vp, _vp, _vp, _ci, _ci, _vp]),
+    "offt_many_status": (_ci, [_vp]),
 }
 
 _lib = None

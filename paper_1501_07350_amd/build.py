@@ -37,7 +37,7 @@ def sources():
         import gen_kernels  # noqa: E402
     finally:
         sys.path.pop(0)
-    gen = gen_kernels.emit(GEN)
+    gen = gen_kernels.emit(GEN) + gen_kernels.emit_many(GEN)
     own = sorted(
         os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp"))
     )

@@ -256,6 +256,24 @@ int64_t offt_workspace_bytes(offt_plan_t p) {
     return p->workspace_bytes();
 }
 
+int offt_default_plan_string(int64_t Na, int64_t Nb, int64_t Nc, int dtype, char* buf, size_t n) {
+    const int rc = validate_dims(Na, Nb, Nc, dtype, 1);
+    if (rc != OFFT_SUCCESS || (!buf && n)) {
+        const int e = rc != OFFT_SUCCESS ? rc : OFFT_ERR_INVALID_ARG;
+        set_error(e);
+        return e;
+    }
+    const int64_t dims[3] = {Na, Nb, Nc};
+    const std::string s = choice_to_string(default_choice(dtype, dims), dims);
+    if (n) {
+        const size_t m = std::min(n - 1, s.size());
+        memcpy(buf, s.data(), m);
+        buf[m] = 0;
+    }
+    set_error(OFFT_SUCCESS);
+    return (int)s.size();
+}
+
 int offt_twiddles(int64_t n, int dtype, void* host_out) {
     if (n < 1 || !host_out || (dtype != OFFT_C2C_F64 && dtype != OFFT_C2C_F32)) {
         set_error(OFFT_ERR_INVALID_ARG);

@@ -170,14 +170,14 @@ struct StageShape {
 // at the Stockham positions and the next stage follows.
 template <typename V, int L, int TPL, bool OUT_LDS, int NS, int R, int... Rest, typename Sink>
 __device__ __forceinline__ void stages_from_lds(V* __restrict__ line, const V* __restrict__ tw, int t,
-                                                Sink& sink) {
+                                                bool active, Sink& sink) {
     using SH = StageShape<V, L, TPL, R>;
     constexpr int STEP = L / (NS * R);   // W_{Ns R}^e = W_L^(e STEP)
     V v[SH::NB][R];
 #pragma unroll
     for (int i = 0; i < SH::NB; ++i) {
         const int b = t + i * TPL;
-        if (SH::EXACT || b < SH::B) {
+        if (active && (SH::EXACT || b < SH::B)) {
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = line[lds_idx(b + r * SH::B)];
             const int k = b % NS;
@@ -192,7 +192,7 @@ __device__ __forceinline__ void stages_from_lds(V* __restrict__ line, const V* _
 #pragma unroll
         for (int i = 0; i < SH::NB; ++i) {
             const int b = t + i * TPL;
-            if (SH::EXACT || b < SH::B) {
+            if (active && (SH::EXACT || b < SH::B)) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) sink(b + r * SH::B, v[i][r]);
             }
@@ -202,29 +202,30 @@ __device__ __forceinline__ void stages_from_lds(V* __restrict__ line, const V* _
 #pragma unroll
         for (int i = 0; i < SH::NB; ++i) {
             const int b = t + i * TPL;
-            if (SH::EXACT || b < SH::B) {
+            if (active && (SH::EXACT || b < SH::B)) {
                 const int base = (b / NS) * NS * R + (b % NS);
 #pragma unroll
                 for (int r = 0; r < R; ++r) line[lds_idx(base + r * NS)] = v[i][r];
             }
         }
         __syncthreads();
-        stages_from_lds<V, L, TPL, OUT_LDS, NS * R, Rest...>(line, tw, t, sink);
+        stages_from_lds<V, L, TPL, OUT_LDS, NS * R, Rest...>(line, tw, t, active, sink);
     }
 }
 
 // Whole 1-D FFT of the thread's line.  IN_LDS: `src` reads LDS (so the first
-// stage's writes wait for every read); OUT_LDS: `sink` writes LDS.
+// stage's writes wait for every read); OUT_LDS: `sink` writes LDS.  Threads
+// with active == false only take part in the barriers.
 template <typename V, int L, int TPL, bool IN_LDS, bool OUT_LDS, int R, int... Rest, typename Src,
           typename Sink>
-__device__ __forceinline__ void run_fft(V* __restrict__ line, const V* __restrict__ tw, int t, Src& src,
-                                        Sink& sink) {
+__device__ __forceinline__ void run_fft(V* __restrict__ line, const V* __restrict__ tw, int t, bool active,
+                                        Src& src, Sink& sink) {
     using SH = StageShape<V, L, TPL, R>;
     V v[SH::NB][R];
 #pragma unroll
     for (int i = 0; i < SH::NB; ++i) {
         const int b = t + i * TPL;
-        if (SH::EXACT || b < SH::B) {
+        if (active && (SH::EXACT || b < SH::B)) {
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = src(b + r * SH::B);
         }
@@ -232,7 +233,7 @@ __device__ __forceinline__ void run_fft(V* __restrict__ line, const V* __restric
 #pragma unroll
     for (int i = 0; i < SH::NB; ++i) {
         const int b = t + i * TPL;
-        if (SH::EXACT || b < SH::B) dft<R>(v[i]);   // span 1: no twiddles
+        if (active && (SH::EXACT || b < SH::B)) dft<R>(v[i]);   // span 1: no twiddles
     }
     if constexpr (sizeof...(Rest) == 0) {
         // a single stage: output j = r (one butterfly, b = 0)
@@ -240,7 +241,7 @@ __device__ __forceinline__ void run_fft(V* __restrict__ line, const V* __restric
 #pragma unroll
         for (int i = 0; i < SH::NB; ++i) {
             const int b = t + i * TPL;
-            if (SH::EXACT || b < SH::B) {
+            if (active && (SH::EXACT || b < SH::B)) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) sink(b + r * SH::B, v[i][r]);
             }
@@ -250,13 +251,13 @@ __device__ __forceinline__ void run_fft(V* __restrict__ line, const V* __restric
 #pragma unroll
         for (int i = 0; i < SH::NB; ++i) {
             const int b = t + i * TPL;
-            if (SH::EXACT || b < SH::B) {
+            if (active && (SH::EXACT || b < SH::B)) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) line[lds_idx(b * R + r)] = v[i][r];
             }
         }
         __syncthreads();
-        stages_from_lds<V, L, TPL, OUT_LDS, R, Rest...>(line, tw, t, sink);
+        stages_from_lds<V, L, TPL, OUT_LDS, R, Rest...>(line, tw, t, active, sink);
     }
 }
 
@@ -291,6 +292,26 @@ template <typename V, typename S> __device__ __forceinline__ V fix_out(V x, int 
     return x;
 }
 
+// Store of one element to HBM.  COHERENT stores are agent-scope relaxed
+// atomics: they write through the XCD's L2, so data another workgroup will
+// read after a release/acquire handshake never sits dirty in one L2 and the
+// release has nothing to write back.
+template <bool COHERENT, typename V> __device__ __forceinline__ void store_elem(V* p, V x);
+template <> __device__ __forceinline__ void store_elem<false, float2>(float2* p, float2 x) { *p = x; }
+template <> __device__ __forceinline__ void store_elem<false, double2>(double2* p, double2 x) { *p = x; }
+template <> __device__ __forceinline__ void store_elem<true, float2>(float2* p, float2 x) {
+    uint64_t bits;
+    __builtin_memcpy(&bits, &x, sizeof bits);
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <> __device__ __forceinline__ void store_elem<true, double2>(double2* p, double2 x) {
+    uint64_t bx, by;
+    __builtin_memcpy(&bx, &x.x, sizeof bx);
+    __builtin_memcpy(&by, &x.y, sizeof by);
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), bx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p) + 1, by, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Contiguous lines with fewer than this many threads per line are staged
 // through LDS with a flat coalesced copy (direct loads would touch one
 // element per line per lane).
@@ -303,8 +324,10 @@ constexpr int kDirectRowMinTpl = 16;
 //   contiguous lines:  lanes walk along the line; first/last stage straight
 //                      from/to HBM when TPL >= kDirectRowMinTpl, else the tile
 //                      is staged through LDS as one contiguous block.
-template <typename V, int L, int TPL, int... Rs>
-__device__ __forceinline__ void pass_tile(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
+// Threads beyond W*TPL (possible when a larger workgroup runs this tile, as in
+// the persistent batch executor) only take part in the barriers.
+template <typename V, bool COHERENT, int L, int TPL, int... Rs>
+__device__ __forceinline__ void pass_tile_impl(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
     using S = decltype(V{}.x);
     static_assert(RadixProduct<Rs...>::value == L, "radix sequence must multiply to L");
     constexpr int LP = Pitch_value(L);
@@ -317,11 +340,12 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, V* __restrict__ lds
     const V* __restrict__ tw = static_cast<const V*>(a.tw);
     const int cin = a.conj_in, cout = a.conj_out;
     const S scale = (S)a.scale;
+    const bool active = tid < W * TPL;
 
     if (a.mode == 1) {
         const int w = tid & (W - 1);
         const int t = tid >> a.logW;
-        const bool ok = w < nl;
+        const bool ok = active && w < nl;
         const int64_t l = l0 + (ok ? w : 0);   // rows beyond the tail read line l0, store nothing
         const int64_t m1 = l / a.M2, m2 = l - m1 * a.M2;
         const int64_t base = m1 * (int64_t)L * a.M2 + m2;
@@ -330,49 +354,58 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, V* __restrict__ lds
         V* go = out + base;
         auto src = [&](int j) { return fix_in(g[(int64_t)j * M2], cin); };
         auto sink = [&](int j, V x) {
-            if (ok) go[(int64_t)j * M2] = fix_out(x, cout, scale);
+            if (ok) store_elem<COHERENT>(go + (int64_t)j * M2, fix_out(x, cout, scale));
         };
-        run_fft<V, L, TPL, false, false, Rs...>(lds + w * LP, tw, t, src, sink);
+        run_fft<V, L, TPL, false, false, Rs...>(lds + w * LP, tw, t, active, src, sink);
         return;
     }
-    const int t = tid % TPL, w = tid / TPL;
+    const int t = tid % TPL, w = active ? tid / TPL : 0;
     V* line = lds + w * LP;
     if constexpr (TPL >= kDirectRowMinTpl) {
-        const bool ok = w < nl;
+        const bool ok = active && tid / TPL < nl;
         const V* g = in + (l0 + (ok ? w : 0)) * L;
         V* go = out + (l0 + w) * L;
         auto src = [&](int j) { return fix_in(g[j], cin); };
         auto sink = [&](int j, V x) {
-            if (ok) go[j] = fix_out(x, cout, scale);
+            if (ok) store_elem<COHERENT>(go + j, fix_out(x, cout, scale));
         };
-        run_fft<V, L, TPL, false, false, Rs...>(line, tw, t, src, sink);
+        run_fft<V, L, TPL, false, false, Rs...>(line, tw, t, active, src, sink);
     } else {
         // stage the contiguous block of nl*L elements through LDS
         const int NT = W * TPL;
         const V* g = in + l0 * L;
         V* go = out + l0 * L;
-        for (int f = tid; f < nl * L; f += NT) {
-            const int lw = f / L, j = f - lw * L;
-            lds[lw * LP + lds_idx(j)] = fix_in(g[f], cin);
+        if (active) {
+            for (int f = tid; f < nl * L; f += NT) {
+                const int lw = f / L, j = f - lw * L;
+                lds[lw * LP + lds_idx(j)] = fix_in(g[f], cin);
+            }
         }
         __syncthreads();
         auto src = [&](int j) { return line[lds_idx(j)]; };
         auto sink = [&](int j, V x) { line[lds_idx(j)] = x; };
-        run_fft<V, L, TPL, true, true, Rs...>(line, tw, t, src, sink);
+        run_fft<V, L, TPL, true, true, Rs...>(line, tw, t, active, src, sink);
         __syncthreads();
-        for (int f = tid; f < nl * L; f += NT) {
-            const int lw = f / L, j = f - lw * L;
-            go[f] = fix_out(lds[lw * LP + lds_idx(j)], cout, scale);
+        if (active) {
+            for (int f = tid; f < nl * L; f += NT) {
+                const int lw = f / L, j = f - lw * L;
+                store_elem<COHERENT>(go + f, fix_out(lds[lw * LP + lds_idx(j)], cout, scale));
+            }
         }
     }
 }
 
+// One tile of an axis pass with ordinary stores (stand-alone pass kernels).
 template <typename V, int L, int TPL, int... Rs>
-__global__ void __launch_bounds__(512) fft_pass_kernel(PassArgs a) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    V* lds = reinterpret_cast<V*>(smem_raw);
-    const int64_t l0 = (int64_t)blockIdx.x << a.logW;
-    pass_tile<V, L, TPL, Rs...>(a, lds, l0);
+__device__ __forceinline__ void pass_tile(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
+    pass_tile_impl<V, false, L, TPL, Rs...>(a, lds, l0);
+}
+
+// One tile with write-through stores (batch executors, whose tiles are read
+// by other workgroups of the same launch).
+template <typename V, int L, int TPL, int... Rs>
+__device__ __forceinline__ void pass_tile_coherent(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
+    pass_tile_impl<V, true, L, TPL, Rs...>(a, lds, l0);
 }
 
 }  // namespace offt

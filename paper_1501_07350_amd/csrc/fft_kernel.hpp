@@ -1,0 +1,17 @@
+// fft_kernel.hpp -- the stand-alone axis-pass kernel: one workgroup per tile
+// of W lines (device body in fft_device.hpp).
+#pragma once
+
+#include "fft_device.hpp"
+
+namespace offt {
+
+template <typename V, int L, int TPL, int... Rs>
+__global__ void __launch_bounds__(512) fft_pass_kernel(PassArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V* lds = reinterpret_cast<V*>(smem_raw);
+    const int64_t l0 = (int64_t)blockIdx.x << a.logW;
+    pass_tile<V, L, TPL, Rs...>(a, lds, l0);
+}
+
+}  // namespace offt

@@ -1,0 +1,180 @@
+// many_device.hpp -- persistent executor for a batch of grids of different
+// sizes.
+//
+// One launch runs every (grid, axis pass, tile) work item of the batch.  Work
+// items are ordered pass level by pass level: all first passes of all grids,
+// then all second passes, then all third passes; a "segment" is the run of
+// tiles of one (level, grid).  Workgroups pop items from one queue counter in
+// increasing order.  An item of level p > 0 may start only when every tile of
+// the same grid's level p-1 segment has been published.
+//
+// Progress: when a workgroup takes item i, every item < i has already been
+// taken by a workgroup that is resident and running, and an item depends only
+// on items of a lower level, i.e. smaller indices.  So the smallest unfinished
+// item never waits, by induction every wait ends, and the number of resident
+// workgroups does not matter.  Each wait is still bounded: after spin_limit
+// polls the error flag is raised and the workgroup goes on, so the grid
+// always drains.
+//
+// A work item covers tiles_per_item consecutive tiles of one segment, so the
+// publish/wait cost is paid once per several tiles.
+//
+// Visibility across XCDs (each XCD has its own L2): tiles are written with
+// agent-scope (write-through) stores, and every thread waits until its
+// stores have completed (vmcnt 0) before the workgroup barrier; then one
+// thread publishes with an agent-scope release atomic.  Because the executor
+// leaves no dirty tile data in any L2, that release's L2 write-back is cheap.
+// The consumer polls the counter with relaxed agent-scope loads, then one
+// thread performs an agent-scope acquire (L1/L2 invalidate) before the
+// workgroup barrier that releases the other threads onto the data.  Tiles of
+// a grid's last pass publish nothing (nothing depends on them) and
+// first-pass tiles wait for nothing.
+#pragma once
+
+#include "fft_device.hpp"
+
+namespace offt {
+
+struct ManySeg {
+    int64_t elem_off;    // element offset of the grid in the packed buffer
+    int64_t nlines;      // lines of this pass
+    int64_t M2;          // element stride of the pass axis
+    int64_t item_base;   // first work item of the segment (items, not tiles)
+    const void* tw;      // twiddle table of the pass length
+    double scale_bwd;    // scale of the grid's last pass in a backward transform
+    int kid;             // kernel case in the executor's dispatch table
+    int logW;            // lines per tile = 2^logW
+    int mode;            // 0 contiguous lines, 1 strided lines
+    int ntiles;          // tiles of W lines
+    int nitems;          // work items = ceil(ntiles / tiles_per_item)
+    int first;           // the grid's first pass: reads the input buffer
+    int last;            // the grid's last pass
+    int dep;             // segment that must complete first, or -1
+    int tiles_per_item;  // consecutive tiles one work item covers
+};
+
+struct ManyArgs {
+    const void* in;
+    void* out;
+    const ManySeg* segs;
+    unsigned* counters;  // [0] queue head, [1] error flag, [2 + s] items done in segment s
+    int64_t total_items;
+    int nseg;
+    int dir;             // -1 forward, +1 backward
+    int spin_limit;
+    int pad_;
+};
+
+constexpr int kManyCounterBase = 2;
+
+// Waits until this thread's outstanding memory operations have completed
+// (stores acknowledged by L2).
+__device__ __forceinline__ void wait_own_stores() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);   // keep the compiler from moving stores past the wait
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// The tiles of work item `item` of segment `sg`, one after the other.
+template <typename V, typename Dispatch>
+__device__ __forceinline__ void run_item(const ManySeg& sg, const PassArgs& p, int64_t item, V* __restrict__ lds,
+                                         const Dispatch& dispatch) {
+    const int64_t t0 = (item - sg.item_base) * sg.tiles_per_item;
+    for (int k = 0; k < sg.tiles_per_item; ++k) {
+        const int64_t tile = t0 + k;
+        if (tile >= sg.ntiles) break;   // uniform across the workgroup
+        if (k > 0) __syncthreads();     // the previous tile is done with LDS
+        dispatch(sg.kid, p, lds, tile << sg.logW);
+    }
+}
+
+// Segment of work item `item`: the last segment with item_base <= item.
+__device__ __forceinline__ int find_segment(const ManySeg* segs, int nseg, int64_t item) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].item_base <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename V>
+__device__ __forceinline__ PassArgs segment_pass_args(const ManyArgs& a, const ManySeg& sg) {
+    const bool bwd = a.dir > 0;
+    PassArgs p;
+    p.in = static_cast<const V*>(sg.first ? a.in : a.out) + sg.elem_off;
+    p.out = static_cast<V*>(a.out) + sg.elem_off;
+    p.tw = sg.tw;
+    p.nlines = sg.nlines;
+    p.M2 = sg.M2;
+    p.logW = sg.logW;
+    p.mode = sg.mode;
+    p.conj_in = bwd && sg.first;
+    p.conj_out = bwd && sg.last;
+    p.scale = (bwd && sg.last) ? sg.scale_bwd : 1.0;
+    return p;
+}
+
+template <typename V, typename Dispatch>
+__device__ __forceinline__ void many_body(const ManyArgs& a, V* __restrict__ lds, const Dispatch& dispatch) {
+    __shared__ int64_t s_item;
+    __shared__ int s_seg;
+    const int tid = threadIdx.x;
+    for (;;) {
+        __syncthreads();   // the previous tile is done with LDS and the broadcast slots
+        if (tid == 0) {
+            const int64_t item = (int64_t)__hip_atomic_fetch_add(&a.counters[0], 1u, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+            int seg = -1;
+            if (item < a.total_items) {
+                seg = find_segment(a.segs, a.nseg, item);
+                const int dep = a.segs[seg].dep;
+                if (dep >= 0) {
+                    const unsigned target = (unsigned)a.segs[dep].nitems;
+                    int polls = 0;
+                    while (__hip_atomic_load(&a.counters[kManyCounterBase + dep], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) < target) {
+                        if (++polls > a.spin_limit) {
+                            __hip_atomic_store(&a.counters[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(4);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                }
+            }
+            s_item = item;
+            s_seg = seg;
+        }
+        __syncthreads();
+        const int64_t item = s_item;
+        const int seg = s_seg;
+        if (item >= a.total_items) break;
+        const ManySeg sg = a.segs[seg];
+        const PassArgs p = segment_pass_args<V>(a, sg);
+        run_item(sg, p, item, lds, dispatch);
+        if (!sg.last) {
+            wait_own_stores();
+            __syncthreads();
+            if (tid == 0)
+                __hip_atomic_fetch_add(&a.counters[kManyCounterBase + seg], 1u, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Non-persistent form: one workgroup per work item of items
+// [item_begin, item_begin + gridDim.x), all of one pass level, so the kernel
+// boundary between levels orders the passes and no counters are used.
+template <typename V, typename Dispatch>
+__device__ __forceinline__ void many_level_body(const ManyArgs& a, int64_t item_begin, V* __restrict__ lds,
+                                                const Dispatch& dispatch) {
+    const int64_t item = item_begin + (int64_t)blockIdx.x;
+    const int seg = find_segment(a.segs, a.nseg, item);
+    const ManySeg sg = a.segs[seg];
+    const PassArgs p = segment_pass_args<V>(a, sg);
+    run_item(sg, p, item, lds, dispatch);
+}
+
+}  // namespace offt

@@ -30,6 +30,25 @@ struct KernelEntry {
     LaunchFn launch;
 };
 
+// One kernel case compiled into the persistent batch executor.
+struct ManyCase {
+    int dtype;
+    int L;
+    int nstages;
+    int radices[kMaxStages];
+    int tpl;
+};
+
+// A persistent batch executor: its kernel and the cases it dispatches.
+struct ManyExecutor {
+    const char* name;
+    int dtype;
+    const ManyCase* cases;
+    int ncases;
+    const void* kernel;        // persistent kernel (ManyArgs)
+    const void* level_kernel;  // one work item per workgroup (ManyArgs, int64_t item_begin)
+};
+
 // Registry of all compiled pass kernels (generated tables).
 const std::vector<const KernelEntry*>& registry();
 // All kernels for (dtype, L), default first.

@@ -1,0 +1,167 @@
+// emu_driver.cpp -- runs the library's tile code (pass_tile) and the
+// persistent batch loop (many_body) for one workgroup on CPU threads.
+//
+//   emu_driver pass <dtype 0|1> <L> <TPL> <r1,r2,..> <nlines> <M2> <logW> <tile> <threads>
+//       one tile of an axis pass, input from stdin-free synthetic data; prints
+//       the tile's output lines (forward transform) as text
+//   emu_driver many <dtype> <nwg> <threads> <nseg> <segments...> <total>
+//       the persistent loop over a segment table, run by nwg workgroups at
+//       once: each workgroup is a forked process of `threads` CPU threads;
+//       buffers and counters live in shared memory
+//
+// Built by tests/test_emu.py with g++ -fsanitize=address.
+#include "hip_emu.h"
+
+#include <sys/mman.h>
+#include <sys/wait.h>
+#include <unistd.h>
+
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "fft_device.hpp"
+#include "many_device.hpp"
+#include "emu_cases.inc"
+
+thread_local EmuDim threadIdx;
+EmuDim blockIdx, blockDim, gridDim;
+EmuBarrier g_emu_barrier;
+thread_local long g_emu_barrier_count = 0;
+
+using namespace offt;
+
+template <typename V> static void twiddles(std::vector<V>& tw, int L) {
+    tw.resize(L);
+    for (int m = 0; m < L; ++m) {
+        const double a = 2.0 * M_PI * (double)m / (double)L;
+        tw[m].x = (decltype(tw[m].x))std::cos(a);
+        tw[m].y = (decltype(tw[m].y))(-std::sin(a));
+    }
+}
+
+// Runs fn(tid) on `threads` CPU threads that share one barrier; returns false
+// if the threads passed different numbers of barriers or a barrier broke.
+static bool run_block(int threads, const std::function<void(int)>& fn) {
+    g_emu_barrier.reset(threads);
+    std::vector<long> counts(threads);
+    std::vector<std::thread> ts;
+    for (int t = 0; t < threads; ++t)
+        ts.emplace_back([&, t] {
+            threadIdx.x = (unsigned)t;
+            g_emu_barrier_count = 0;
+            fn(t);
+            counts[t] = g_emu_barrier_count;
+        });
+    for (auto& th : ts) th.join();
+    bool ok = !g_emu_barrier.broken;
+    for (int t = 1; t < threads; ++t)
+        if (counts[t] != counts[0]) ok = false;
+    if (!ok) std::fprintf(stderr, "EMU: barrier counts differ (thread 0: %ld)\n", counts[0]);
+    return ok;
+}
+
+template <typename V>
+static int do_many(int argc, char** argv) {
+    // many <dtype> <nwg> <threads> <nseg> then per segment:
+    //   L kid logW mode nlines M2 ntiles first last dep elem_off tiles_per_item
+    // then <total_elems>
+    int k = 3;
+    const int nwg = atoi(argv[k++]);
+    const int threads = atoi(argv[k++]);
+    const int nseg = atoi(argv[k++]);
+    std::vector<ManySeg> segs(nseg);
+    std::vector<std::vector<V>> tws(nseg);
+    int64_t items = 0;
+    size_t lds_elems = 0;
+    for (int s = 0; s < nseg; ++s) {
+        ManySeg& g = segs[s];
+        memset(&g, 0, sizeof g);
+        const int L = atoi(argv[k++]);
+        g.kid = atoi(argv[k++]);
+        g.logW = atoi(argv[k++]);
+        g.mode = atoi(argv[k++]);
+        g.nlines = atoll(argv[k++]);
+        g.M2 = atoll(argv[k++]);
+        g.ntiles = atoi(argv[k++]);
+        g.first = atoi(argv[k++]);
+        g.last = atoi(argv[k++]);
+        g.dep = atoi(argv[k++]);
+        g.elem_off = atoll(argv[k++]);
+        g.tiles_per_item = atoi(argv[k++]);
+        g.nitems = (g.ntiles + g.tiles_per_item - 1) / g.tiles_per_item;
+        g.scale_bwd = 1.0;
+        g.item_base = items;
+        items += g.nitems;
+        twiddles(tws[s], L);
+        g.tw = tws[s].data();
+        lds_elems = std::max(lds_elems, (size_t)(1 << g.logW) * (size_t)Pitch_value(L));
+    }
+    const int64_t total = atoll(argv[k++]);
+    // shared between the workgroup processes
+    const size_t bytes = sizeof(V) * 2 * (size_t)total + sizeof(unsigned) * (kManyCounterBase + nseg);
+    void* shm = mmap(nullptr, bytes, PROT_READ | PROT_WRITE, MAP_SHARED | MAP_ANONYMOUS, -1, 0);
+    if (shm == MAP_FAILED) return 3;
+    V* in = static_cast<V*>(shm);
+    V* out = in + total;
+    unsigned* counters = reinterpret_cast<unsigned*>(out + total);
+    for (int64_t i = 0; i < total; ++i) {
+        in[i].x = (decltype(in[i].x))std::sin(0.37 * (double)i + 0.1);
+        in[i].y = (decltype(in[i].y))std::cos(0.91 * (double)i);
+        out[i].x = out[i].y = 0;
+    }
+    for (int i = 0; i < kManyCounterBase + nseg; ++i) counters[i] = 0u;
+    ManyArgs a;
+    memset(&a, 0, sizeof a);
+    a.in = in;
+    a.out = out;
+    a.segs = segs.data();
+    a.counters = counters;
+    a.total_items = items;
+    a.nseg = nseg;
+    a.dir = -1;
+    a.spin_limit = 1 << 22;
+    blockDim.x = threads;
+    std::vector<pid_t> kids;
+    for (int wg = 1; wg < nwg; ++wg) {
+        const pid_t pid = fork();
+        if (pid == 0) {
+            blockIdx.x = (unsigned)wg;
+            std::vector<V> lds(lds_elems + 64);
+            const bool okc = run_block(threads, [&](int) { many_body<V>(a, lds.data(), EmuDispatch<V>{}); });
+            _exit(okc ? 0 : 1);
+        }
+        kids.push_back(pid);
+    }
+    blockIdx.x = 0;
+    std::vector<V> lds(lds_elems + 64);
+    bool ok = run_block(threads, [&](int) { many_body<V>(a, lds.data(), EmuDispatch<V>{}); });
+    for (pid_t pid : kids) {
+        int st = 0;
+        waitpid(pid, &st, 0);
+        if (!WIFEXITED(st) || WEXITSTATUS(st) != 0) ok = false;
+    }
+    if (!ok || counters[1]) {
+        std::printf("FAIL barrier_ok=%d err=%u\n", (int)ok, counters[1]);
+        return 1;
+    }
+    for (int s = 0; s < nseg; ++s)   // a grid's last pass publishes nothing
+        if (counters[kManyCounterBase + s] != (segs[s].last ? 0u : (unsigned)segs[s].nitems)) {
+            std::printf("FAIL segment %d done %u of %d\n", s, counters[kManyCounterBase + s], segs[s].nitems);
+            return 1;
+        }
+    std::printf("OK %lld items\n", (long long)items);
+    for (int64_t i = 0; i < total; ++i) std::printf("%.17g %.17g\n", (double)out[i].x, (double)out[i].y);
+    return 0;
+}
+
+int main(int argc, char** argv) {
+    if (argc < 3) return 2;
+    const std::string mode = argv[1];
+    const int dtype = atoi(argv[2]);
+    if (mode == "many") return dtype == 0 ? do_many<double2>(argc, argv) : do_many<float2>(argc, argv);
+    return 2;
+}

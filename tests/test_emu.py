@@ -1,0 +1,187 @@
+"""CPU emulation of the library's device code (no GPU).
+
+tests/emu/hip_emu.h supplies just enough of HIP for fft_device.hpp and
+many_device.hpp to compile as host C++; one workgroup runs as CPU threads
+sharing a barrier that reports threads reaching different numbers of
+__syncthreads() instead of hanging.  Built with AddressSanitizer and
+UBSan, so an out-of-bounds LDS or global access in the tile code fails the
+test.  The persistent batch loop runs as a single workgroup, which takes the
+work items in order, so every dependency is met by construction; the check is
+on the tile code, the barrier structure and the bookkeeping.
+"""
+import importlib.util
+import os
+import subprocess
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1501_07350_amd as offt
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+EMU = os.path.join(HERE, "emu")
+CSRC = os.path.join(os.path.dirname(HERE), "paper_1501_07350_amd", "csrc")
+BUILD = os.path.join(EMU, "_build")
+THREADS = 512          # workgroup size of the persistent executor
+LDS_LIMIT = 160 * 1024  # gfx950 per-workgroup LDS
+
+
+def gen_kernels():
+    spec = importlib.util.spec_from_file_location("gen_kernels_emu", os.path.join(CSRC, "gen_kernels.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.fixture(scope="module")
+def emu_binary():
+    gk = gen_kernels()
+    os.makedirs(BUILD, exist_ok=True)
+    lines = ["template <typename V> struct EmuDispatch;"]
+    for vt, prec in (("double2", "f64"), ("float2", "f32")):
+        lines.append(f"template <> struct EmuDispatch<{vt}> {{")
+        lines.append(f"  void operator()(int kid, const PassArgs& a, {vt}* lds, int64_t l0) const {{")
+        lines.append("    switch (kid) {")
+        for i, (L, seq, tpl) in enumerate(gk.many_cases(prec, "all")):
+            lines.append(f"      case {i}: pass_tile_coherent<{vt}, {L}, {tpl}, {', '.join(map(str, seq))}>(a, lds, l0); break;")
+        lines.append("      default: break;\n    }\n  }\n};")
+    with open(os.path.join(BUILD, "emu_cases.inc"), "w") as f:
+        f.write("namespace offt {\n" + "\n".join(lines) + "\n}\n")
+    exe = os.path.join(BUILD, "emu_driver")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-pthread", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-I", EMU, "-I", BUILD, "-I", CSRC,
+           os.path.join(EMU, "emu_driver.cpp"), "-o", exe]
+    subprocess.run(cmd, check=True)
+    return exe
+
+
+def lds_idx(j):
+    return j + (j >> 4)
+
+
+def pitch(L):
+    return (lds_idx(L - 1) + 1) | 1
+
+
+def plan_passes(dims, dtype):
+    """Passes of the heuristic plan, parsed from the library's plan string."""
+    s = offt.default_plan_string(dims, dtype)
+    fields = dict(kv.split("=") for kv in s.split(";"))
+    out = []
+    for ch in fields["order"]:
+        ax = "abc".index(ch)
+        L = dims[ax]
+        if L <= 1:
+            continue
+        rad_s, *rest = fields[ch].split("/")
+        seq = [int(r) for r in rad_s.split("x")]
+        W = int(rest[0])
+        tpl = int(rest[1]) if len(rest) > 1 else L // max(seq)
+        M2 = int(np.prod(dims[ax + 1:])) if ax < 2 else 1
+        M1 = int(np.prod(dims[:ax])) if ax > 0 else 1
+        out.append(dict(L=L, seq=seq, W=W, tpl=tpl, M1=M1, M2=M2, mode=1 if M2 > 1 else 0))
+    return out
+
+
+def many_logW(p, es):
+    """Tile width inside the batch executors: fill THREADS threads within an
+    80 KiB LDS budget."""
+    lw = 0
+    while (2 << lw) * p["tpl"] <= THREADS and (2 << lw) * pitch(p["L"]) * es <= min(80 * 1024, LDS_LIMIT):
+        lw += 1
+    return lw
+
+
+TILES_PER_ITEM = 4
+
+
+def segment_args(dims_list, dtype):
+    """The persistent executor's segment table, built as the library does
+    (pass levels in order, grids in order within a level)."""
+    gk = gen_kernels()
+    prec = "f64" if dtype == torch.complex128 else "f32"
+    es = 16 if prec == "f64" else 8
+    cases = gk.many_cases(prec, "all")
+    align = 256 // es
+    offs, off = [], 0
+    for d in dims_list:
+        offs.append(off)
+        off += int(np.prod(d))
+        off = (off + align - 1) // align * align
+    total = off
+    passes = [plan_passes(d, dtype) for d in dims_list]
+    segs, seg_of = [], {}
+    for lvl in range(3):
+        for g, ps in enumerate(passes):
+            if lvl >= len(ps):
+                continue
+            p = ps[lvl]
+            kid = cases.index((p["L"], p["seq"], p["tpl"]))
+            lw = many_logW(p, es)
+            nlines = p["M1"] * p["M2"]
+            ntiles = -(-nlines // (1 << lw))
+            dep = seg_of[(lvl - 1, g)] if lvl > 0 else -1
+            seg_of[(lvl, g)] = len(segs)
+            segs.append([p["L"], kid, lw, p["mode"], nlines, p["M2"], ntiles, int(lvl == 0),
+                         int(lvl == len(ps) - 1), dep, offs[g], TILES_PER_ITEM])
+    args = [str(THREADS), str(len(segs))] + [str(v) for s in segs for v in s] + [str(total)]
+    return args, offs, total
+
+
+def run_many(exe, dims_list, dtype, nwg=1):
+    args, offs, total = segment_args(dims_list, dtype)
+    code = "0" if dtype == torch.complex128 else "1"
+    r = subprocess.run([exe, "many", code, str(nwg)] + args, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, (r.stdout[:500], r.stderr[-3000:])
+    lines = r.stdout.splitlines()
+    assert lines[0].startswith("OK"), lines[0]
+    vals = np.array([[float(a) for a in ln.split()] for ln in lines[1:]])
+    out = vals[:, 0] + 1j * vals[:, 1]
+    assert out.size == total
+    # the driver's input: in[i] = sin(0.37 i + 0.1) + i cos(0.91 i), rounded to the precision
+    i = np.arange(total)
+    xin = np.sin(0.37 * i + 0.1) + 1j * np.cos(0.91 * i)
+    if dtype == torch.complex64:
+        xin = xin.astype(np.complex64).astype(np.complex128)
+    for g, d in enumerate(dims_list):
+        n = int(np.prod(d))
+        if n == 1:
+            continue   # a one-point grid has no pass (the library copies it)
+        x = xin[offs[g]:offs[g] + n].reshape(d)
+        y = out[offs[g]:offs[g] + n].reshape(d)
+        e = oracle.rel_l2(y, oracle.fft3(x))
+        assert e <= oracle.tolerance(n, dtype == torch.complex64), (d, e)
+
+
+MIXED = [(2, 3, 5), (1, 1, 1), (9, 25, 27), (100, 4, 6), (48, 60, 64), (16, 1, 8), (5, 5, 5)]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
+def test_emulated_persistent_loop_mixed_batch(emu_binary, dtype):
+    run_many(emu_binary, MIXED, dtype)
+
+
+@pytest.mark.parametrize("nwg", [2, 4])
+def test_emulated_concurrent_workgroups_mixed_batch(emu_binary, nwg):
+    """Several workgroups (one process each) race on the queue and the
+    dependency counters in shared memory."""
+    run_many(emu_binary, MIXED, torch.complex64, nwg=nwg)
+
+
+def test_emulated_persistent_loop_batch_lengths(emu_binary):
+    dims = synth.uneven_batch_dims(4, key=synth.KEY_DIMS + 99)
+    dims = [tuple(min(v, 64) for v in d) for d in dims]   # small enough for CPU threads
+    run_many(emu_binary, dims, torch.complex64)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
+def test_emulated_every_case_once(emu_binary, dtype):
+    """Every kernel case of the executor on a small strided and contiguous pass."""
+    gk = gen_kernels()
+    prec = "f64" if dtype == torch.complex128 else "f32"
+    lengths = sorted({L for L, _, _ in gk.many_cases(prec, "all")})
+    for L in lengths:
+        run_many(emu_binary, [(L, 1, 3), (1, 2, L)], dtype)
