@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
+#include <thread>
 
 #define __global__
 #define __device__
@@ -47,7 +48,7 @@ struct EmuBarrier {
             cv.notify_all();
             return;
         }
-        if (!cv.wait_for(lk, std::chrono::seconds(20), [&] { return generation != gen || broken; })) {
+        if (!cv.wait_for(lk, std::chrono::seconds(180), [&] { return generation != gen || broken; })) {
             broken = true;
             std::fprintf(stderr, "EMU: barrier mismatch: %d of %d threads waiting at generation %ld\n", waiting, n,
                          gen);
@@ -68,5 +69,5 @@ inline void __syncthreads() {
 #define __hip_atomic_load(p, o, s) __atomic_load_n((p), (o))
 #define __hip_atomic_store(p, v, o, s) __atomic_store_n((p), (v), (o))
 #define __builtin_amdgcn_fence(o, scope) __atomic_thread_fence(o)
-#define __builtin_amdgcn_s_sleep(n) ((void)0)
+#define __builtin_amdgcn_s_sleep(n) std::this_thread::sleep_for(std::chrono::microseconds(20))
 #define __builtin_amdgcn_s_waitcnt(n) ((void)0)
