@@ -191,6 +191,81 @@ int offt_exec_many(offt_plan_t p, const void* in, void* out, int direction, int 
  * if a wait hit its bounded spin limit (results then invalid). */
 int offt_many_status(offt_plan_t p);
 
+/* ---- plan selection internals: candidates, features, timings -------------
+ * The tuners choose among a deterministic list of candidate plans per grid
+ * shape (the heuristic plan first; then other radix sequences and tile widths
+ * per axis; then the other five axis orders).  These calls expose that list
+ * for building and using the learned selector. */
+
+/* Length of one plan feature vector. */
+int offt_feature_dim(void);
+
+/* Candidate plans of a grid: returns their number n; the first min(n, max)
+ * plan strings are written NUL-separated into plans[0..plans_bytes) and their
+ * feature vectors (offt_feature_dim() floats each) into features.  Host only,
+ * no device needed.  Errors: INVALID_ARG (buffers too small), UNSUPPORTED_SIZE. */
+int offt_candidates(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch, char* plans,
+                    size_t plans_bytes, float* features, int max);
+
+/* Times every candidate plan of a grid as the exhaustive tuner does
+ * (1 warm-up + reps timed forward transforms, minimum, HIP events on
+ * `stream`), in place on the caller's device buffer `buf` of at least
+ * batch*Na*Nb*Nc elements (its contents are destroyed).  times_ms[i] is
+ * candidate i's time for i < min(n, max).  Returns n.  Synchronises the
+ * stream.  Errors: INVALID_ARG, UNSUPPORTED_SIZE, NO_DEVICE, HIP. */
+int offt_tune_table(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch, int reps, void* buf,
+                    size_t buf_bytes, void* stream, float* times_ms, int max);
+
+/* Feature vector (offt_feature_dim() floats) of one plan string for a grid.
+ * Host only; the plan string is not checked against this device's tile
+ * limits.  Errors: INVALID_ARG, UNSUPPORTED_SIZE, BAD_PLAN. */
+int offt_plan_features(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch, const char* plan,
+                       float* out);
+
+/* Predicted ln(time in ms) of n feature vectors with the network in the
+ * weights file.  Host only.  Errors: INVALID_ARG, IO. */
+int offt_selector_scores(const char* weights_path, const float* features, int n, float* scores);
+
+/* The plan the learned selector picks for a grid, from the weights file at
+ * weights_path (format: offt-selector 1 text; see paper_1501_07350_amd/
+ * selector.py), written like offt_plan_describe.  Host only.  Errors:
+ * INVALID_ARG, UNSUPPORTED_SIZE, IO (missing or corrupt weights). */
+int offt_selector_choose(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch,
+                         const char* weights_path, char* buf, size_t n);
+
+/* ---- the selector's network: MLP with two hidden ReLU layers -------------
+ *   a1 = relu(W1 x + b1), a2 = relu(W2 a1 + b2), y = w3 . a2 + b3,
+ *   loss = mean over the minibatch of (y - t)^2.
+ * Parameters: one float vector W1[H][D], b1[H], W2[H][H], b2[H], w3[H], b3. */
+typedef struct offt_mlp_s* offt_mlp_t;
+
+/* Number of parameters for input width D and hidden width H (1..256). */
+int64_t offt_mlp_nparams(int in_dim, int hidden);
+
+/* Seeded initial parameters (He-uniform weights, zero biases) into host_out. */
+void offt_mlp_init_params(int in_dim, int hidden, uint64_t seed, float* host_out);
+
+/* Network on the device with room for minibatches of up to max_batch;
+ * parameters from host_params (NULL: offt_mlp_init_params(seed)).  Adam
+ * moments start at zero.  Errors: INVALID_ARG, NO_DEVICE, OUT_OF_MEMORY, HIP. */
+offt_mlp_t offt_mlp_create(int in_dim, int hidden, int max_batch, const float* host_params, uint64_t seed);
+int offt_mlp_destroy(offt_mlp_t m);
+int offt_mlp_get_params(offt_mlp_t m, float* host_out);
+int offt_mlp_set_params(offt_mlp_t m, const float* host_in);   /* also resets Adam */
+
+/* y[b] = network(X[row_b]) for b < B, row_b = idx[b] (idx == NULL: b).  X is
+ * a device array of rows of D floats; y a device array of B floats. */
+int offt_mlp_forward(offt_mlp_t m, const float* X, const int32_t* idx, int B, float* y, void* stream);
+
+/* Gradient of the mean squared error over the minibatch rows idx[0..B)
+ * (B <= max_batch) with targets T[row]: grad (device, nparams floats) and,
+ * if loss != NULL, the loss (device float). */
+int offt_mlp_gradient(offt_mlp_t m, const float* X, const float* T, const int32_t* idx, int B, float* grad,
+                      float* loss, void* stream);
+
+/* One Adam step (Kingma & Ba) with bias correction on the device parameters. */
+int offt_mlp_adam(offt_mlp_t m, const float* grad, float lr, float beta1, float beta2, float eps, void* stream);
+
 #define OFFT_MANY_SEPARATE_TUNED (-2)
 #define OFFT_MANY_SEPARATE_HEURISTIC (-1)
 #define OFFT_MANY_PERSISTENT 0

@@ -72,6 +72,25 @@ SIGNATURES = {
     "offt_error_string": (ctypes.c_char_p, [_ci]),
     "offt_twiddles": (_ci, [_i64, _ci, _vp]),
     "offt_default_plan_string": (_ci, [_i64, _i64, _i64, _ci, ctypes.c_char_p, ctypes.c_size_t]),
+    "offt_feature_dim": (_ci, []),
+    "offt_candidates": (_ci, [_i64, _i64, _i64, _ci, _i64, ctypes.c_char_p, ctypes.c_size_t,
+                              ctypes.POINTER(ctypes.c_float), _ci]),
+    "offt_tune_table": (_ci, [_i64, _i64, _i64, _ci, _i64, _ci, _vp, ctypes.c_size_t, _vp,
+                              ctypes.POINTER(ctypes.c_float), _ci]),
+    "offt_selector_choose": (_ci, [_i64, _i64, _i64, _ci, _i64, ctypes.c_char_p, ctypes.c_char_p,
+                                   ctypes.c_size_t]),
+    "offt_plan_features": (_ci, [_i64, _i64, _i64, _ci, _i64, ctypes.c_char_p, ctypes.POINTER(ctypes.c_float)]),
+    "offt_selector_scores": (_ci, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_float), _ci,
+                                   ctypes.POINTER(ctypes.c_float)]),
+    "offt_mlp_nparams": (_i64, [_ci, _ci]),
+    "offt_mlp_init_params": (None, [_ci, _ci, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float)]),
+    "offt_mlp_create": (_vp, [_ci, _ci, _ci, ctypes.POINTER(ctypes.c_float), ctypes.c_uint64]),
+    "offt_mlp_destroy": (_ci, [_vp]),
+    "offt_mlp_get_params": (_ci, [_vp, ctypes.POINTER(ctypes.c_float)]),
+    "offt_mlp_set_params": (_ci, [_vp, ctypes.POINTER(ctypes.c_float)]),
+    "offt_mlp_forward": (_ci, [_vp, _vp, _vp, _ci, _vp, _vp]),
+    "offt_mlp_gradient": (_ci, [_vp, _vp, _vp, _vp, _ci, _vp, _vp, _vp]),
+    "offt_mlp_adam": (_ci, [_vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp]),
     "offt_plan_many": (_vp, [_ci, ctypes.POINTER(_i64), _ci, ctypes.POINTER(Opts)]),
     "offt_many_offset": (_i64, [_vp, _ci]),
     "offt_exec_many": (_ci, [_vp, _vp, _vp, _ci, _ci, _vp]),

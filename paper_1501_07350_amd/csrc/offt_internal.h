@@ -75,8 +75,9 @@ struct PlanChoice {
 size_t elem_size(int dtype);
 bool smooth235(int64_t n);
 std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]);
-// Parses a plan string; returns false if it does not parse or does not fit dims/dtype.
-bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanChoice* out);
+// Parses a plan string; returns false if it does not parse or does not fit
+// dims/dtype (with check_fit, also when a tile exceeds this device's limits).
+bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanChoice* out, bool check_fit = true);
 PlanChoice default_choice(int dtype, const int64_t dims[3]);
 // Candidate plans for tuning (deterministic order, default first).
 std::vector<PlanChoice> candidate_choices(int dtype, const int64_t dims[3]);

@@ -196,7 +196,7 @@ std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]) {
     return os.str();
 }
 
-bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanChoice* out) {
+bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanChoice* out, bool check_fit) {
     if (!s) return false;
     PlanChoice c = default_choice(dtype, dims);
     std::string str(s);
@@ -256,7 +256,7 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
             }
             if (!found) return false;
             const int lw = ilog2(W);
-            if (fit_logW(found, lw, dtype) != lw) return false;
+            if (check_fit && fit_logW(found, lw, dtype) != lw) return false;
             c.k[ax] = found;
             c.logW[ax] = lw;
         } else {

@@ -12,6 +12,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <fstream>
 #include <sstream>
 #include <string>
@@ -144,6 +145,35 @@ int select_plan(offt_plan_s* p, const offt_opts& o, PlanChoice* choice) {
     }
     return exhaustive(p, o, choice);
 }
+
+}  // namespace offt
+
+extern "C" int offt_tune_table(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch, int reps, void* buf,
+                               size_t buf_bytes, void* stream, float* times_ms, int max) {
+    using namespace offt;
+    int rc = validate_dims(Na, Nb, Nc, dtype, batch);
+    const size_t need = (size_t)(Na * Nb * Nc * batch) * elem_size(dtype);
+    if (rc == OFFT_SUCCESS && (!buf || buf_bytes < need || reps < 1 || max < 0 || (max > 0 && !times_ms)))
+        rc = OFFT_ERR_INVALID_ARG;
+    if (rc == OFFT_SUCCESS) rc = check_device();
+    if (rc != OFFT_SUCCESS) { set_error(rc); return rc; }
+    offt_plan_s tmp;
+    tmp.kind = 1;
+    tmp.dtype = dtype;
+    tmp.dims[0] = Na; tmp.dims[1] = Nb; tmp.dims[2] = Nc;
+    tmp.batch = batch;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const std::vector<PlanChoice> cands = candidate_choices(dtype, tmp.dims);
+    for (int i = 0; i < std::min((int)cands.size(), max) && rc == OFFT_SUCCESS; ++i)
+        rc = time_choice(&tmp, cands[i], buf, s, reps, &times_ms[i]);
+    (void)hipStreamSynchronize(s);
+    for (void* d : tmp.allocs) (void)hipFree(d);
+    if (rc != OFFT_SUCCESS) { set_error(rc); return rc; }
+    set_error(OFFT_SUCCESS);
+    return (int)cands.size();
+}
+
+namespace offt {
 
 std::string describe_plan(const offt_plan_s* p) {
     if (p->kind == 2) return describe_many(p);
