@@ -4,6 +4,9 @@
 Workload (default): one forward 3-D transform of a 512x512x512 grid, complex128
 (the headline value) and, measured in the same run, complex64; uniform [-1, 1)
 synthetic entries from the seeded generator, resident in HBM before timing.
+Plans are tuned at plan time (exhaustive tuning, excluded from the timed
+region like the paper's initialization phase); the heuristic plan's times are
+reported beside them.
 
 A "step" is one forward transform: all axis passes with their fused
 rearrangements.  W warm-up steps, then K timed steps; each pass is bracketed
@@ -56,7 +59,8 @@ def load_traffic(tag: str):
     return d.get("workloads", {}).get(tag)
 
 
-def time_transform(n: int, dtype, steps: int, warmup: int, check: bool):
+def time_transform(n: int, dtype, steps: int, warmup: int, check: bool, tune: str = "exhaustive",
+                   forced: str | None = None):
     import numpy as np
     import torch
 
@@ -66,7 +70,9 @@ def time_transform(n: int, dtype, steps: int, warmup: int, check: bool):
     shape = (n, n, n)
     x = synth.complex_grid(shape, dtype, device="cuda")
     y = torch.empty_like(x)
-    plan = offt.Plan(shape, dtype=dtype)
+    t0 = time.perf_counter()
+    plan = offt.Plan(shape, dtype=dtype, tune=tune, forced_plan=forced)
+    plan_s = time.perf_counter() - t0
     npass = plan.npasses()
     stream = torch.cuda.current_stream()
     h = int(stream.cuda_stream)
@@ -99,6 +105,7 @@ def time_transform(n: int, dtype, steps: int, warmup: int, check: bool):
         "eff_gbs": 6.0 * N * s / (ms * 1e6),
         "wall_ms_per_step": 1e3 * wall / steps,
         "plan": plan.describe(),
+        "plan_seconds": plan_s,
         "pass_ms": pass_ms,
         "pass_bytes": 2 * N * s,
     }
@@ -356,6 +363,11 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the sampled-line parity check")
     ap.add_argument("--calibrate", action="store_true", help="also run the copy-kernel calibration")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch (64 grids) timing")
+    ap.add_argument("--tune", default="exhaustive", choices=["exhaustive", "none", "learned", "forced"],
+                    help="plan selection of the timed transforms")
+    ap.add_argument("--plan64", help="plan string for --tune forced (complex128)")
+    ap.add_argument("--plan32", help="plan string for --tune forced (complex64)")
+    ap.add_argument("--no-heuristic", action="store_true", help="skip the heuristic-plan comparison runs")
     ap.add_argument("--summarize-stats", metavar="DIR", help="reduce a rocprofv3 --stats output dir")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="reduce two rocprofv3 --pmc output dirs to profiles/pmc_traffic.json")
@@ -383,8 +395,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     n = args.n
-    r64 = time_transform(n, torch.complex128, args.steps, args.warmup, not args.no_check)
-    r32 = time_transform(n, torch.complex64, args.steps, args.warmup, not args.no_check)
+    # plans tuned at init (excluded from the timing, as the paper excludes its
+    # initialization phase with auto-tuning); the heuristic plan beside them
+    r64 = time_transform(n, torch.complex128, args.steps, args.warmup, not args.no_check, args.tune, args.plan64)
+    r32 = time_transform(n, torch.complex64, args.steps, args.warmup, not args.no_check, args.tune, args.plan32)
+    if args.no_heuristic:
+        h64 = h32 = {"ms": float("nan"), "gflops": float("nan"), "plan": None}
+    else:
+        h64 = time_transform(n, torch.complex128, args.steps, args.warmup, False, tune="none")
+        h32 = time_transform(n, torch.complex64, args.steps, args.warmup, False, tune="none")
     out = {
         "metric": METRIC,
         "value": round(r64["gflops"], 1),
@@ -403,10 +422,16 @@ def main():
         "hbm_gbs_effective": round(r64["eff_gbs"], 1),
         "frac_of_peak_effective": round(r64["eff_gbs"] / PEAK_HBM_GBS, 4),
         "plan": r64["plan"],
+        "plan_tuning_seconds": round(r64["plan_seconds"], 3),
         "pass_ms": [round(v, 4) for v in r64["pass_ms"]],
+        "heuristic_plan": {"f64": {"ms_per_step": round(h64["ms"], 4), "gflops": round(h64["gflops"], 1),
+                                   "plan": h64["plan"]},
+                           "f32": {"ms_per_step": round(h32["ms"], 4), "gflops": round(h32["gflops"], 1),
+                                   "plan": h32["plan"]}},
         "f32": {"dtype": "f32", "value": round(r32["gflops"], 1), "unit": "GFLOP/s",
                 "ms_per_step": round(r32["ms"], 4), "hbm_gbs_effective": round(r32["eff_gbs"], 1),
                 "frac_of_peak_effective": round(r32["eff_gbs"] / PEAK_HBM_GBS, 4), "plan": r32["plan"],
+                "plan_tuning_seconds": round(r32["plan_seconds"], 3),
                 "pass_ms": [round(v, 4) for v in r32["pass_ms"]],
                 "roofline": roofline(r32, f"{n}_f32")},
         "roofline": roofline(r64, f"{n}_f64"),

@@ -151,6 +151,10 @@ template <int R, typename V> __device__ __forceinline__ void dft(V* v) {
 // line pitch is odd so the W lines of a column tile fall on different banks.
 __host__ __device__ constexpr int lds_idx(int j) { return j + (j >> 4); }
 __host__ __device__ constexpr int Pitch_value(int L) { return (lds_idx(L - 1) + 1) | 1; }
+// LDS of a tile of W lines: the lines, then the twiddle table W_L^m (m < L),
+// copied in at the start of the tile so the radix stages read twiddles from
+// LDS instead of waiting on global memory after each barrier.
+__host__ __device__ constexpr int64_t tile_lds_elems(int W, int L) { return (int64_t)W * Pitch_value(L) + L; }
 
 // ---- Stockham stages ---------------------------------------------------------
 // A thread of rank t (0 <= t < TPL) within its line owns butterflies
@@ -318,7 +322,7 @@ template <> __device__ __forceinline__ void store_elem<true, double2>(double2* p
 constexpr int kDirectRowMinTpl = 16;
 
 // Device body of one axis pass for one tile of W = 2^logW lines starting at
-// line l0.  Threads: W * TPL.  lds: W * Pitch_value(L) elements.
+// line l0.  Threads: W * TPL.  lds: tile_lds_elems(W, L) elements.
 //   strided lines:     lanes walk the W lines (consecutive columns of a row),
 //                      first/last stage straight from/to HBM.
 //   contiguous lines:  lanes walk along the line; first/last stage straight
@@ -337,10 +341,17 @@ __device__ __forceinline__ void pass_tile_impl(const PassArgs& a, V* __restrict_
     const int nl = rem < W ? (int)rem : W;
     const V* __restrict__ in = static_cast<const V*>(a.in);
     V* __restrict__ out = static_cast<V*>(a.out);
-    const V* __restrict__ tw = static_cast<const V*>(a.tw);
+    const V* tw = static_cast<const V*>(a.tw);
     const int cin = a.conj_in, cout = a.conj_out;
     const S scale = (S)a.scale;
     const bool active = tid < W * TPL;
+    if constexpr (sizeof...(Rs) > 1) {
+        // stage the twiddle table; the first barrier inside run_fft (after the
+        // first stage, which needs no twiddles) orders it before any use
+        V* twl = lds + W * LP;
+        for (int i = tid; i < L; i += (int)blockDim.x) twl[i] = tw[i];
+        tw = twl;
+    }
 
     if (a.mode == 1) {
         const int w = tid & (W - 1);

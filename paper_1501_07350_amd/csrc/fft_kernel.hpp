@@ -6,8 +6,9 @@
 
 namespace offt {
 
-template <typename V, int L, int TPL, int... Rs>
-__global__ void __launch_bounds__(512) fft_pass_kernel(PassArgs a) {
+// MAXT: the largest workgroup the kernel is compiled for (launch bound).
+template <typename V, int MAXT, int L, int TPL, int... Rs>
+__global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* lds = reinterpret_cast<V*>(smem_raw);
     const int64_t l0 = (int64_t)blockIdx.x << a.logW;

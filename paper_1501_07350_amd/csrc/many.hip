@@ -132,7 +132,7 @@ static int many_logW(const PassPlan& pp, int dtype) {
     const int64_t es = (int64_t)elem_size(dtype);
     int lw = 0;
     while ((int64_t(2) << lw) * pp.k->tpl <= kManyThreads &&
-           (int64_t(2) << lw) * Pitch_value(pp.L) * es <= std::min(kManyLdsBudget, lds_limit()))
+           tile_lds_elems(2 << lw, pp.L) * es <= std::min(kManyLdsBudget, lds_limit()))
         ++lw;
     return lw;
 }
@@ -171,7 +171,7 @@ static int build_many(offt_plan_s* p, hipStream_t s) {
             sg.last = lvl == G.ntuned - 1;
             sg.dep = lvl > 0 ? seg_of[(lvl - 1) * m->count + g] : -1;
             seg_of[lvl * m->count + g] = (int)segs.size();
-            lds_max = std::max(lds_max, (size_t)(W * Pitch_value(pp.L)) * es);
+            lds_max = std::max(lds_max, (size_t)tile_lds_elems((int)W, pp.L) * es);
             segs.push_back(sg);
         }
     }

@@ -27,6 +27,7 @@ struct KernelEntry {
     int nstages;
     int radices[kMaxStages];
     int tpl;                   // threads per line
+    int max_threads;           // launch bound the kernel is compiled for
     LaunchFn launch;
 };
 

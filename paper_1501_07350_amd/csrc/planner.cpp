@@ -89,8 +89,8 @@ int fit_logW(const KernelEntry* k, int logW, int dtype) {
     while (logW > 0) {
         const int64_t W = int64_t(1) << logW;
         const int64_t threads = W * k->tpl;
-        const int64_t lds = W * (int64_t)Pitch_value(k->L) * (int64_t)es;
-        if (threads <= 512 && lds <= lds_limit()) break;
+        const int64_t lds = tile_lds_elems((int)W, k->L) * (int64_t)es;
+        if (threads <= k->max_threads && lds <= lds_limit()) break;
         --logW;
     }
     return logW;
@@ -306,7 +306,7 @@ hipError_t launch_pass(const PassPlan& p, const void* in, void* out, int conj_in
     const int64_t W = int64_t(1) << p.logW;
     const int64_t nblocks = (a.nlines + W - 1) / W;
     const int threads = (int)(W * p.k->tpl);
-    const size_t lds = (size_t)(W * Pitch_value(p.L)) * (p.k->dtype == OFFT_C2C_F64 ? 16 : 8);
+    const size_t lds = (size_t)tile_lds_elems((int)W, p.L) * (p.k->dtype == OFFT_C2C_F64 ? 16 : 8);
     return p.k->launch(a, nblocks, threads, lds, s);
 }
 

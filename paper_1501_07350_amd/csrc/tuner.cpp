@@ -6,8 +6,8 @@
 // and the axis order of the passes.
 //
 // Protocol: 1 warm-up + `reps` timed executions per candidate (hipEvents on the
-// tuning stream), score = minimum; ties go to the earlier candidate in the
-// deterministic enumeration (the heuristic default is candidate 0).
+// tuning stream), score = minimum; ties go to the earlier candidate (the
+// heuristic's choices come first).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -102,28 +102,98 @@ int time_choice(offt_plan_s* p, const PlanChoice& c, void* buf, hipStream_t s, i
     return rc;
 }
 
+// Times one axis pass of a plan alone (in place on buf): 1 warm-up + reps runs, minimum.
+static int time_pass(offt_plan_s* p, const PlanChoice& c, int axis, void* buf, hipStream_t s, int reps, float* ms) {
+    PassPlan passes[3];
+    const int n = build_passes(c, p->dims, p->batch, passes);
+    int i = 0;
+    while (i < n && passes[i].axis != axis) ++i;
+    if (i == n || !passes[i].k) return OFFT_ERR_UNSUPPORTED_SIZE;
+    int rc = attach_twiddles(p, &passes[i], 1, s);
+    if (rc != OFFT_SUCCESS) return rc;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return OFFT_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OFFT_ERR_HIP; }
+    if (launch_pass(passes[i], buf, buf, 0, 0, 1.0, s) != hipSuccess) rc = OFFT_ERR_HIP;   // warm-up
+    float best = 1e30f;
+    for (int r = 0; r < reps && rc == OFFT_SUCCESS; ++r) {
+        float t = 0.f;
+        if (hipEventRecord(e0, s) != hipSuccess || launch_pass(passes[i], buf, buf, 0, 0, 1.0, s) != hipSuccess ||
+            hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+            rc = OFFT_ERR_HIP;
+            break;
+        }
+        best = std::min(best, t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = best;
+    return rc;
+}
+
+// Exhaustive search over a factorised space: the passes are independent
+// kernels, so every (radix sequence, threads per line, tile width) of each
+// axis is timed as a single pass and the fastest kept per axis; then the six
+// pass orders are timed as whole transforms with those kernels.  Ties keep
+// the earlier candidate (the heuristic's kernels and order come first).
 static int exhaustive(offt_plan_s* p, const offt_opts& o, PlanChoice* choice) {
     hipStream_t s = static_cast<hipStream_t>(o.stream);
-    const std::vector<PlanChoice> cands = candidate_choices(p->dtype, p->dims);
     const size_t bytes = (size_t)(p->dims[0] * p->dims[1] * p->dims[2] * p->batch) * elem_size(p->dtype);
     void* buf = nullptr;
     if (hipMalloc(&buf, bytes) != hipSuccess) { (void)hipGetLastError(); return OFFT_ERR_OUT_OF_MEMORY; }
     int rc = hipMemsetAsync(buf, 0, bytes, s) == hipSuccess ? OFFT_SUCCESS : OFFT_ERR_HIP;
-    int best_i = -1;
-    float best_ms = 1e30f;
-    for (size_t i = 0; i < cands.size() && rc == OFFT_SUCCESS; ++i) {
+    PlanChoice best = default_choice(p->dtype, p->dims);
+    int timed = 0;
+    for (int ax = 0; ax < 3 && rc == OFFT_SUCCESS; ++ax) {
+        if (p->dims[ax] <= 1) continue;
+        float best_ms = 1e30f;
+        PlanChoice cur = best;
+        const int lw0 = best.logW[ax];
+        // the heuristic's kernel first, so ties keep it
+        std::vector<const KernelEntry*> ks = kernels_for(p->dtype, (int)p->dims[ax]);
+        std::stable_partition(ks.begin(), ks.end(), [&](const KernelEntry* k) { return k == best.k[ax]; });
+        const KernelEntry* best_k = best.k[ax];
+        int best_lw = lw0;
+        for (const KernelEntry* k : ks) {
+            const int top = fit_logW(k, 10, p->dtype);
+            for (int lw = top; lw >= 0 && rc == OFFT_SUCCESS; --lw) {
+                if (top - lw > 4) break;   // widths below 1/16 of the widest that fits: never competitive
+                cur.k[ax] = k;
+                cur.logW[ax] = lw;
+                float ms = 0.f;
+                rc = time_pass(p, cur, ax, buf, s, o.reps, &ms);
+                ++timed;
+                if (rc == OFFT_SUCCESS && ms < best_ms) {
+                    best_ms = ms;
+                    best_k = k;
+                    best_lw = lw;
+                }
+            }
+        }
+        best.k[ax] = best_k;
+        best.logW[ax] = best_lw;
+    }
+    static const int orders[6][3] = {{2, 1, 0}, {2, 0, 1}, {1, 2, 0}, {1, 0, 2}, {0, 2, 1}, {0, 1, 2}};
+    PlanChoice winner = best;
+    float win_ms = 1e30f;
+    for (int i = 0; i < 6 && rc == OFFT_SUCCESS; ++i) {
+        PlanChoice c = best;
+        for (int j = 0; j < 3; ++j) c.order[j] = orders[i][j];
         float ms = 0.f;
-        rc = time_choice(p, cands[i], buf, s, o.reps, &ms);
-        if (rc == OFFT_SUCCESS && ms < best_ms) { best_ms = ms; best_i = (int)i; }
+        rc = time_choice(p, c, buf, s, o.reps, &ms);
+        ++timed;
+        if (rc == OFFT_SUCCESS && ms < win_ms) { win_ms = ms; winner = c; }
     }
     (void)hipStreamSynchronize(s);
     (void)hipFree(buf);
     if (rc != OFFT_SUCCESS) return rc;
-    *choice = cands[best_i];
-    char buf2[128];
-    snprintf(buf2, sizeof buf2, "exhaustive: %zu candidates, best #%d %.4f ms", cands.size(), best_i, best_ms);
+    *choice = winner;
+    char buf2[160];
+    snprintf(buf2, sizeof buf2, "exhaustive: %d timings (per-axis kernels and widths, then 6 orders), best %.4f ms",
+             timed, win_ms);
     p->tune_log = buf2;
-    if (o.cache_path) cache_store(o.cache_path, p->dtype, p->dims, p->batch, *choice, best_ms);
+    if (o.cache_path) cache_store(o.cache_path, p->dtype, p->dims, p->batch, *choice, win_ms);
     return OFFT_SUCCESS;
 }
 

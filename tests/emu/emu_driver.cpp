@@ -98,7 +98,7 @@ static int do_many(int argc, char** argv) {
         items += g.nitems;
         twiddles(tws[s], L);
         g.tw = tws[s].data();
-        lds_elems = std::max(lds_elems, (size_t)(1 << g.logW) * (size_t)Pitch_value(L));
+        lds_elems = std::max(lds_elems, (size_t)tile_lds_elems(1 << g.logW, L));
     }
     const int64_t total = atoll(argv[k++]);
     // shared between the workgroup processes

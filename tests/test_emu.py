@@ -66,6 +66,10 @@ def pitch(L):
     return (lds_idx(L - 1) + 1) | 1
 
 
+def tile_lds_elems(W, L):
+    return W * pitch(L) + L
+
+
 def plan_passes(dims, dtype):
     """Passes of the heuristic plan, parsed from the library's plan string."""
     s = offt.default_plan_string(dims, dtype)
@@ -90,7 +94,7 @@ def many_logW(p, es):
     """Tile width inside the batch executors: fill THREADS threads within an
     80 KiB LDS budget."""
     lw = 0
-    while (2 << lw) * p["tpl"] <= THREADS and (2 << lw) * pitch(p["L"]) * es <= min(80 * 1024, LDS_LIMIT):
+    while (2 << lw) * p["tpl"] <= THREADS and tile_lds_elems(2 << lw, p["L"]) * es <= min(80 * 1024, LDS_LIMIT):
         lw += 1
     return lw
 
