@@ -80,6 +80,8 @@ typedef struct offt_opts {
     const char* cache_path;   /* plan cache file for tuned plans, or NULL */
     const char* weights_path; /* learned-selector weights for OFFT_TUNE_LEARNED, or NULL */
     void* stream;             /* hipStream_t for tuning runs (NULL = null stream) */
+    int tune_inplace;         /* 1: time whole transforms in place (in == out) when tuning;
+                                 0 (default): out of place, with a second temporary buffer */
 } offt_opts;
 
 /* Fill *o with the defaults listed above. */

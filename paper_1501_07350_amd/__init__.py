@@ -39,7 +39,7 @@ def _stream_handle(stream=None) -> int:
 
 
 def _make_opts(tune="none", reps=2, normalize_inverse=False, forced_plan=None, cache_path=None,
-               weights_path=None, stream=None):
+               weights_path=None, stream=None, tune_inplace=False):
     o = _lib.default_opts()
     if tune not in _TUNE:
         raise ValueError(f"tune must be one of {sorted(_TUNE)}")
@@ -54,6 +54,7 @@ def _make_opts(tune="none", reps=2, normalize_inverse=False, forced_plan=None, c
             keep.append(b)
             setattr(o, field, b)
     o.stream = ctypes.c_void_p(stream) if stream else None
+    o.tune_inplace = 1 if tune_inplace else 0
     return o, keep
 
 
@@ -62,7 +63,8 @@ class Plan:
 
     def __init__(self, shape, dtype=torch.complex128, batch: int = 1, tune: str = "none",
                  normalize_inverse: bool = False, forced_plan: str | None = None,
-                 cache_path: str | None = None, weights_path: str | None = None, reps: int = 2):
+                 cache_path: str | None = None, weights_path: str | None = None, reps: int = 2,
+                 tune_inplace: bool = False):
         lib = _lib.load()
         if len(shape) != 3:
             raise ValueError("shape must be (Na, Nb, Nc)")
@@ -73,7 +75,7 @@ class Plan:
         code = _dtype_code(dtype)
         stream = _stream_handle() if torch.cuda.is_available() else None
         opts, keep = _make_opts(tune, reps, normalize_inverse, forced_plan, cache_path, weights_path,
-                                stream)
+                                stream, tune_inplace)
         h = lib.offt_plan_ex(self.shape[0], self.shape[1], self.shape[2], code, self.batch,
                              ctypes.byref(opts))
         del keep

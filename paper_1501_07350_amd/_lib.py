@@ -50,6 +50,7 @@ class Opts(ctypes.Structure):
         ("cache_path", ctypes.c_char_p),
         ("weights_path", ctypes.c_char_p),
         ("stream", ctypes.c_void_p),
+        ("tune_inplace", ctypes.c_int),
     ]
 
 

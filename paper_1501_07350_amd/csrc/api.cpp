@@ -127,6 +127,7 @@ void offt_opts_default(offt_opts* o) {
     o->cache_path = nullptr;
     o->weights_path = nullptr;
     o->stream = nullptr;
+    o->tune_inplace = 0;
 }
 
 int offt_last_error(void) { return g_last_error; }

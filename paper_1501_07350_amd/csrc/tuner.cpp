@@ -73,9 +73,9 @@ static void cache_store(const char* path, int dtype, const int64_t dims[3], int6
     f << cache_key(dtype, dims, batch) << '\t' << choice_to_string(c, dims) << '\t' << ms << '\n';
 }
 
-// Times one candidate on buffer `buf` (in place).  Returns OFFT_SUCCESS and
-// the minimum time in *ms.
-int time_choice(offt_plan_s* p, const PlanChoice& c, void* buf, hipStream_t s, int reps, float* ms) {
+// Times one candidate from `src` to `dst` (equal: in place).  Returns
+// OFFT_SUCCESS and the minimum time in *ms.
+int time_choice(offt_plan_s* p, const PlanChoice& c, void* src, void* dst, hipStream_t s, int reps, float* ms) {
     PassPlan passes[3];
     const int n = build_passes(c, p->dims, p->batch, passes);
     for (int i = 0; i < n; ++i)
@@ -85,11 +85,11 @@ int time_choice(offt_plan_s* p, const PlanChoice& c, void* buf, hipStream_t s, i
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return OFFT_ERR_HIP;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OFFT_ERR_HIP; }
-    rc = exec_passes(p, passes, n, buf, buf, OFFT_FORWARD, s);   // warm-up
+    rc = exec_passes(p, passes, n, src, dst, OFFT_FORWARD, s);   // warm-up
     float best = 1e30f;
     for (int r = 0; r < reps && rc == OFFT_SUCCESS; ++r) {
         if (hipEventRecord(e0, s) != hipSuccess) { rc = OFFT_ERR_HIP; break; }
-        rc = exec_passes(p, passes, n, buf, buf, OFFT_FORWARD, s);
+        rc = exec_passes(p, passes, n, src, dst, OFFT_FORWARD, s);
         if (rc != OFFT_SUCCESS) break;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = OFFT_ERR_HIP; break; }
         float t = 0.f;
@@ -140,9 +140,20 @@ static int time_pass(offt_plan_s* p, const PlanChoice& c, int axis, void* buf, h
 static int exhaustive(offt_plan_s* p, const offt_opts& o, PlanChoice* choice) {
     hipStream_t s = static_cast<hipStream_t>(o.stream);
     const size_t bytes = (size_t)(p->dims[0] * p->dims[1] * p->dims[2] * p->batch) * elem_size(p->dtype);
+    // two buffers: whole transforms are timed out of place (src -> buf) unless
+    // the caller tunes for in-place use; single passes run in place on buf
     void* buf = nullptr;
+    void* src = nullptr;
     if (hipMalloc(&buf, bytes) != hipSuccess) { (void)hipGetLastError(); return OFFT_ERR_OUT_OF_MEMORY; }
+    if (o.tune_inplace) {
+        src = buf;
+    } else if (hipMalloc(&src, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(buf);
+        return OFFT_ERR_OUT_OF_MEMORY;
+    }
     int rc = hipMemsetAsync(buf, 0, bytes, s) == hipSuccess ? OFFT_SUCCESS : OFFT_ERR_HIP;
+    if (rc == OFFT_SUCCESS && src != buf && hipMemsetAsync(src, 0, bytes, s) != hipSuccess) rc = OFFT_ERR_HIP;
     PlanChoice best = default_choice(p->dtype, p->dims);
     int timed = 0;
     for (int ax = 0; ax < 3 && rc == OFFT_SUCCESS; ++ax) {
@@ -181,17 +192,18 @@ static int exhaustive(offt_plan_s* p, const offt_opts& o, PlanChoice* choice) {
         PlanChoice c = best;
         for (int j = 0; j < 3; ++j) c.order[j] = orders[i][j];
         float ms = 0.f;
-        rc = time_choice(p, c, buf, s, o.reps, &ms);
+        rc = time_choice(p, c, src, buf, s, o.reps, &ms);
         ++timed;
         if (rc == OFFT_SUCCESS && ms < win_ms) { win_ms = ms; winner = c; }
     }
     (void)hipStreamSynchronize(s);
     (void)hipFree(buf);
+    if (src != buf) (void)hipFree(src);
     if (rc != OFFT_SUCCESS) return rc;
     *choice = winner;
     char buf2[160];
-    snprintf(buf2, sizeof buf2, "exhaustive: %d timings (per-axis kernels and widths, then 6 orders), best %.4f ms",
-             timed, win_ms);
+    snprintf(buf2, sizeof buf2, "exhaustive: %d timings (per-axis kernels and widths, then 6 orders %s), best %.4f ms",
+             timed, o.tune_inplace ? "in place" : "out of place", win_ms);
     p->tune_log = buf2;
     if (o.cache_path) cache_store(o.cache_path, p->dtype, p->dims, p->batch, *choice, win_ms);
     return OFFT_SUCCESS;
@@ -235,7 +247,7 @@ extern "C" int offt_tune_table(int64_t Na, int64_t Nb, int64_t Nc, int dtype, in
     hipStream_t s = static_cast<hipStream_t>(stream);
     const std::vector<PlanChoice> cands = candidate_choices(dtype, tmp.dims);
     for (int i = 0; i < std::min((int)cands.size(), max) && rc == OFFT_SUCCESS; ++i)
-        rc = time_choice(&tmp, cands[i], buf, s, reps, &times_ms[i]);
+        rc = time_choice(&tmp, cands[i], buf, buf, s, reps, &times_ms[i]);
     (void)hipStreamSynchronize(s);
     for (void* d : tmp.allocs) (void)hipFree(d);
     if (rc != OFFT_SUCCESS) { set_error(rc); return rc; }
