@@ -46,8 +46,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(tag: str):
-    """Measured HBM bytes per launch of each pass (from rocprofv3 PMC runs),
+def pass_keys(plan: str):
+    """Per-pass keys "axis=spec" of a plan string such as
+    order=bca;a=16x16x2/16;b=16x16x2/16;c=16x16x2/2 (pass i transforms the
+    axis order[i])."""
+    fields = dict(f.split("=", 1) for f in plan.strip().split(";"))
+    return [f"{ax}={fields[ax]}" for ax in fields["order"]]
+
+
+def load_traffic(tag: str, key: str):
+    """Measured HBM bytes per launch of one pass (from rocprofv3 PMC runs),
     only if they were taken on the current kernel sources."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -56,7 +64,7 @@ def load_traffic(tag: str):
         return None
     if d.get("kernel_hash") != kernel_source_hash():
         return None
-    return d.get("workloads", {}).get(tag)
+    return d.get("workloads", {}).get(tag, {}).get("pass_bytes", {}).get(key)
 
 
 def time_transform(n: int, dtype, steps: int, warmup: int, check: bool, tune: str = "exhaustive",
@@ -204,13 +212,10 @@ def roofline(res, tag):
     i = max(range(len(res["pass_ms"])), key=lambda j: res["pass_ms"][j])
     dur_ms = res["pass_ms"][i]
     achieved = res["pass_bytes"] / (dur_ms * 1e6)
-    tr = load_traffic(tag)
-    traffic = None
-    if tr and len(tr.get("pass_bytes", [])) == len(res["pass_ms"]):
-        traffic = tr["pass_bytes"][i]
+    key = pass_keys(res["plan"])[i]
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel_pass": i,
-            "kernel_ms": round(dur_ms, 4), "algorithmic_bytes_per_launch": res["pass_bytes"]}
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": load_traffic(tag, key), "kernel_pass": i,
+            "kernel": key, "kernel_ms": round(dur_ms, 4), "algorithmic_bytes_per_launch": res["pass_bytes"]}
 
 
 def cpu_baseline(n: int):
@@ -240,7 +245,7 @@ def cpu_baseline(n: int):
 
 
 # ---------------------------------------------------------------- profiling ----
-# rocprofv3 runs of this script (commands in profiles/README.md) are reduced to
+# rocprofv3 runs of this script (their commands head each summary under profiles/) are reduced to
 # short text summaries and to profiles/pmc_traffic.json with the modes below.
 
 CALIB_BYTES = 1 << 31   # bytes read (and written) by one calibration copy
@@ -272,33 +277,57 @@ def _find(d, suffix):
     raise FileNotFoundError(f"no *{suffix} under {d}")
 
 
-def summarize_stats(d: str, command: str, n: int, steps: int, warmup: int) -> str:
+def _profiled_runs(log: str, n: int):
+    """The transforms a profiled bench.py run timed, in launch order, from the
+    JSON line it printed: [(tag, dtype label, plan)].  The run must use forced
+    (or heuristic) plans so that no tuning dispatches sit among them."""
+    line = [l for l in open(log) if l.startswith("{")][-1]
+    d = json.loads(line)
+    runs = [(f"{n}_f64", "complex128", d["plan"]), (f"{n}_f32", "complex64", d["f32"]["plan"])]
+    h = d.get("heuristic_plan", {})
+    if h.get("f64", {}).get("plan"):
+        runs += [(f"{n}_f64", "complex128", h["f64"]["plan"]), (f"{n}_f32", "complex64", h["f32"]["plan"])]
+    return runs
+
+
+def _pass_dispatches(names, runs, steps, warmup):
+    """Split the fft_pass_kernel dispatches (in dispatch order) into
+    runs x steps x passes; yields (run index, pass index, step, position)."""
+    k = 0
+    for r, (_, _, plan) in enumerate(runs):
+        npass = len(pass_keys(plan))
+        for st in range(steps + warmup):
+            for i in range(npass):
+                yield r, i, st, k
+                k += 1
+    if k != len(names):
+        raise RuntimeError(f"expected {k} pass dispatches, the trace holds {len(names)}")
+
+
+def summarize_stats(d: str, log: str, command: str, n: int, steps: int, warmup: int) -> str:
     rows = _read_csv(_find(d, "kernel_stats.csv"))
     lines = [f"# rocprofv3 kernel statistics", f"# command: {command}",
              f"{'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total%':>7}  kernel"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
         lines.append(f"{int(r['Calls']):>6} {float(r['AverageNs'])/1e3:>10.2f} {float(r['MinNs'])/1e3:>10.2f} "
                      f"{float(r['MaxNs'])/1e3:>10.2f} {float(r['Percentage']):>7.2f}  {r['Name'][:150]}")
-    # per-pass durations from the dispatch trace: the transforms launch pass
-    # 0, 1, 2 per step, complex128 first, then complex64
+    runs = _profiled_runs(log, n)
     trace = _read_csv(_find(d, "kernel_trace.csv"))
     trace.sort(key=lambda r: int(r["Dispatch_Id"]))
     disp = [r for r in trace if "fft_pass_kernel" in r["Kernel_Name"]]
+    dur = {}
+    for r, i, st, k in _pass_dispatches(disp, runs, steps, warmup):
+        if st >= warmup:
+            x = disp[k]
+            dur.setdefault((r, i), ([], x["Kernel_Name"])).__getitem__(0).append(
+                (int(x["End_Timestamp"]) - int(x["Start_Timestamp"])) / 1e3)
     lines.append("")
     lines.append("# per-pass mean duration over the timed steps (from the dispatch trace)")
-    k = 0
-    for tag in (f"{n}^3 complex128", f"{n}^3 complex64"):
-        dur = [[] for _ in range(3)]
-        for st in range(steps + warmup):
-            for i in range(3):
-                r = disp[k]
-                k += 1
-                if st >= warmup:
-                    dur[i].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-        for i in range(3):
-            name = disp[k - 3 + i]["Kernel_Name"]
-            mean = sum(dur[i]) / len(dur[i])
-            lines.append(f"{tag} pass {i}: mean {mean:9.2f} us over {len(dur[i])} dispatches  {name[:110]}")
+    for r, (tag, label, plan) in enumerate(runs):
+        lines.append(f"{n}^3 {label}, plan {plan}")
+        for i, key in enumerate(pass_keys(plan)):
+            v, name = dur[(r, i)]
+            lines.append(f"  pass {i} {key:<18} mean {sum(v)/len(v):9.2f} us over {len(v)} dispatches  {name[:100]}")
     return "\n".join(lines) + "\n"
 
 
@@ -316,40 +345,41 @@ def _pmc_per_dispatch(d: str, counter: str):
     return [per[k] for k in sorted(per)]
 
 
-def summarize_pmc(fetch_dir: str, write_dir: str, n: int, steps: int, warmup: int, command: str):
+def summarize_pmc(fetch_dir: str, write_dir: str, log: str, n: int, steps: int, warmup: int, command: str):
     """Per-pass HBM bytes of the transforms, scaled by the copy calibration:
-    factor = CALIB_BYTES / (counter bytes of one calibration copy)."""
+    factor = CALIB_BYTES / (counter bytes of one calibration copy).  Passes are
+    keyed by "axis=spec" of their plan, per precision."""
+    runs = _profiled_runs(log, n)
     out = {"kernel_hash": kernel_source_hash(), "command": command, "workloads": {}}
     text = [f"# HBM traffic per dispatch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE",
             f"# command: {command}"]
+    acc = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         disp = _pmc_per_dispatch(d, counter)
         passes = [x for x in disp if "fft_pass_kernel" in x[0]]
         copies = [x for x in disp if "copyBuffer" in x[0]]
         calib_kib = copies[-1][1]
         factor = CALIB_BYTES / (calib_kib * 1024.0)
-        text.append(f"{counter}: calibration copy of {CALIB_BYTES} B in and out counted {calib_kib:.0f} KiB -> factor {factor:.4f}")
-        per_step = (steps + warmup)
-        k = 0
-        for tag in (f"{n}_f64", f"{n}_f32"):
-            npass = 3
-            vals = [[] for _ in range(npass)]
-            for _ in range(per_step):
-                for i in range(npass):
-                    vals[i].append(passes[k][1]); k += 1
-            w = out["workloads"].setdefault(tag, {"pass_bytes": [0.0] * npass, "raw": {}})
-            for i in range(npass):
-                kib = sum(vals[i][warmup:]) / max(1, len(vals[i][warmup:]))
-                w["raw"].setdefault(counter, []).append(kib)
-                w["pass_bytes"][i] += kib * 1024.0 * factor
-                text.append(f"{tag} pass {i} {counter}: {kib:.0f} KiB/dispatch -> {kib*1024*factor/1e9:.4f} GB scaled")
-    for tag, w in out["workloads"].items():
+        text.append(f"{counter}: calibration copy of {CALIB_BYTES} B in and out counted {calib_kib:.0f} KiB "
+                    f"-> factor {factor:.4f}")
+        vals = {}
+        for r, i, st, k in _pass_dispatches(passes, runs, steps, warmup):
+            if st >= warmup:
+                vals.setdefault((r, i), []).append(passes[k][1])
+        for (r, i), v in sorted(vals.items()):
+            tag, label, plan = runs[r]
+            key = pass_keys(plan)[i]
+            kib = sum(v) / len(v)
+            acc.setdefault((tag, key), {})[counter] = kib * 1024.0 * factor
+            text.append(f"{tag} {key:<18} {counter}: {kib:.0f} KiB/dispatch -> {kib*1024*factor/1e9:.4f} GB scaled")
+    for (tag, key), c in sorted(acc.items()):
         s = 16 if tag.endswith("f64") else 8
         alg = 2 * n ** 3 * s
-        w["pass_bytes"] = [round(v) for v in w["pass_bytes"]]
-        w["algorithmic_bytes"] = alg
-        text.append(f"{tag}: measured bytes per pass {[round(v/1e9, 4) for v in w['pass_bytes']]} GB, "
-                    f"algorithmic {alg/1e9:.4f} GB, amplification {[round(v/alg, 3) for v in w['pass_bytes']]}")
+        w = out["workloads"].setdefault(tag, {"algorithmic_bytes": alg, "pass_bytes": {}, "raw_bytes": {}})
+        w["pass_bytes"][key] = round(c["FETCH_SIZE"] + c["WRITE_SIZE"])
+        w["raw_bytes"][key] = {k: round(v) for k, v in c.items()}
+        text.append(f"{tag} {key:<18} measured {w['pass_bytes'][key]/1e9:.4f} GB, algorithmic {alg/1e9:.4f} GB, "
+                    f"amplification {w['pass_bytes'][key]/alg:.3f}")
     return out, "\n".join(text) + "\n"
 
 
@@ -368,19 +398,20 @@ def main():
     ap.add_argument("--plan64", help="plan string for --tune forced (complex128)")
     ap.add_argument("--plan32", help="plan string for --tune forced (complex64)")
     ap.add_argument("--no-heuristic", action="store_true", help="skip the heuristic-plan comparison runs")
-    ap.add_argument("--summarize-stats", metavar="DIR", help="reduce a rocprofv3 --stats output dir")
-    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+    ap.add_argument("--summarize-stats", nargs=2, metavar=("DIR", "LOG"),
+                    help="reduce a rocprofv3 --stats output dir (LOG: the profiled run's stdout)")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "LOG"),
                     help="reduce two rocprofv3 --pmc output dirs to profiles/pmc_traffic.json")
     ap.add_argument("--command", default="", help="profiling command recorded in the summary")
     ap.add_argument("--out", help="summary text file")
     args = ap.parse_args()
     if args.summarize_stats:
-        txt = summarize_stats(args.summarize_stats, args.command, args.n, args.steps, args.warmup)
+        txt = summarize_stats(args.summarize_stats[0], args.summarize_stats[1], args.command, args.n,
+                              args.steps, args.warmup)
         open(args.out, "w").write(txt) if args.out else print(txt)
         return
     if args.summarize_pmc:
-        d, txt = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.n, args.steps, args.warmup,
-                               args.command)
+        d, txt = summarize_pmc(*args.summarize_pmc, args.n, args.steps, args.warmup, args.command)
         with open(TRAFFIC_FILE, "w") as f:
             json.dump(d, f, indent=1)
         open(args.out, "w").write(txt) if args.out else print(txt)
