@@ -153,14 +153,19 @@ __host__ __device__ constexpr int lds_idx(int j) { return j + (j >> 4); }
 __host__ __device__ constexpr int Pitch_value(int L) { return (lds_idx(L - 1) + 1) | 1; }
 // LDS of a tile of W lines: the lines, then the twiddle table W_L^m (m < L),
 // copied in at the start of the tile so the radix stages read twiddles from
-// LDS instead of waiting on global memory after each barrier.
-__host__ __device__ constexpr int64_t tile_lds_elems(int W, int L) { return (int64_t)W * Pitch_value(L) + L; }
+// LDS instead of waiting on global memory after each barrier.  A tile whose
+// exchanges run in P parts holds only L/P positions of each line.
+__host__ __device__ constexpr int line_pitch(int L, int P) { return Pitch_value(L / P); }
+__host__ __device__ constexpr int64_t tile_lds_elems(int W, int L, int P = 1) {
+    return (int64_t)W * line_pitch(L, P) + L;
+}
 
 // ---- Stockham stages ---------------------------------------------------------
 // A thread of rank t (0 <= t < TPL) within its line owns butterflies
 // b = t + i*TPL of every stage.  The first stage reads its inputs from `src`
-// (HBM or LDS), the last stage hands its outputs to `sink`; the stages in
-// between exchange through the LDS copy `line` of the thread's line.
+// (HBM or LDS), the last stage hands its outputs to `sink`; between stages
+// the values pass through the LDS copy `line` of the thread's line, and the
+// stage functions hand their register arrays on explicitly.
 template <typename V, int L, int TPL, int R>
 struct StageShape {
     static constexpr int B = L / R;                 // butterflies in the stage
@@ -168,22 +173,89 @@ struct StageShape {
     static constexpr bool EXACT = (B % TPL) == 0;
 };
 
-// Stage with span NS (product of earlier radices) and radix R whose input is
-// in LDS.  If it is the last stage (NS*R == L), its outputs go to `sink`
-// (natural order index j = b + r*L/R); otherwise they are written back to LDS
-// at the Stockham positions and the next stage follows.
-template <typename V, int L, int TPL, bool OUT_LDS, int NS, int R, int... Rest, typename Sink>
-__device__ __forceinline__ void stages_from_lds(V* __restrict__ line, const V* __restrict__ tw, int t,
-                                                bool active, Sink& sink) {
+template <int R, int... Rest> struct FirstRadix { static constexpr int value = R; };
+
+// The register array of one thread in a stage of radix R: R values for each
+// of its butterflies.
+template <typename V, int L, int TPL, int R>
+using StageRegs = V[StageShape<V, L, TPL, R>::NB][R];
+
+// LDS exchange between a stage with span NS and radix R (outputs v) and the
+// next stage of radix R2 (inputs u).  The outputs go to their Stockham
+// positions (b div NS)*NS*R + (b mod NS) + r*NS; the next stage reads
+// b2 + r2*L/R2.
+//
+// Parts: the exchange may run in P phases over the positions [p*L/P,
+// (p+1)*L/P) of every line, so LDS holds only L/P positions per line.  The
+// output block of butterfly b, NS*R consecutive positions, lies in part
+// b div (L/(R*P)) when NS*R divides L/P, and the next stage's element r2
+// lies in part r2 div (R2/P) when P divides R2.  Phase p writes the
+// butterflies of part p and reads elements r2 of part p; every thread takes
+// part in every phase, so each exchange is 2*P barriers for all threads.
+template <typename V, int L, int TPL, int NS, int R, int R2, int P>
+__device__ __forceinline__ void exchange_parts(V* __restrict__ line, int t, bool act,
+                                               const StageRegs<V, L, TPL, R>& v, StageRegs<V, L, TPL, R2>& u) {
+    using S1 = StageShape<V, L, TPL, R>;
+    using S2 = StageShape<V, L, TPL, R2>;
+    constexpr int PART = L / P;      // positions per part
+    constexpr int BP = S1::B / P;    // writing butterflies per part
+    constexpr int RP = R2 / P;       // reading elements per part
+    // b = t + i*TPL with t < TPL: when TPL divides BP the part of butterfly b
+    // is (i*TPL) div BP, known per register slot at compile time, so each
+    // slot's outputs are dead after its own phase
+    constexpr bool BY_SLOT = BP % TPL == 0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+#pragma unroll
+        for (int i = 0; i < S1::NB; ++i) {
+            const int b = t + i * TPL;
+            const bool in_part = P == 1 || (BY_SLOT ? (i * TPL) / BP == p : b / BP == p);
+            if (act && (S1::EXACT || b < S1::B) && in_part) {
+                const int base = (b / NS) * NS * R + (b % NS) - p * PART;
+#pragma unroll
+                for (int r = 0; r < R; ++r) line[lds_idx(base + r * NS)] = v[i][r];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < S2::NB; ++i) {
+            const int b = t + i * TPL;
+            if (act && (S2::EXACT || b < S2::B)) {
+#pragma unroll
+                for (int r = p * RP; r < (p + 1) * RP; ++r) u[i][r] = line[lds_idx(b + r * S2::B - p * PART)];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Whether an exchange after a stage of span NS and radix R, before a stage
+// of radix R2, can run in P parts (the host checks the same for a kernel).
+template <int L, int NS, int R, int R2, int P>
+__host__ __device__ constexpr bool exchange_splits() {
+    return P == 1 || (L % P == 0 && R2 % P == 0 && (L / P) % (NS * R) == 0);
+}
+
+template <typename V, int L, int TPL, int P, int NS, int R, int R2>
+__device__ __forceinline__ void exchange(V* __restrict__ line, int t, bool act, const StageRegs<V, L, TPL, R>& v,
+                                         StageRegs<V, L, TPL, R2>& u) {
+    static_assert(exchange_splits<L, NS, R, R2, P>(), "exchange cannot run in P parts");
+    exchange_parts<V, L, TPL, NS, R, R2, P>(line, t, act, v, u);
+}
+
+// Stage with span NS > 1 and radix R on the register inputs v: twiddles
+// W_{Ns R}^(r (b mod Ns)) from the table W_L^m, the R-point DFT, then either
+// the sink (last stage: natural-order index j = b + r*L/R) or the exchange
+// into the next stage.
+template <typename V, int L, int TPL, int P, int NS, int R, int... Rest, typename Sink>
+__device__ __forceinline__ void stage_regs(StageRegs<V, L, TPL, R>& v, V* __restrict__ line,
+                                           const V* __restrict__ tw, int t, bool act, Sink& sink) {
     using SH = StageShape<V, L, TPL, R>;
     constexpr int STEP = L / (NS * R);   // W_{Ns R}^e = W_L^(e STEP)
-    V v[SH::NB][R];
 #pragma unroll
     for (int i = 0; i < SH::NB; ++i) {
         const int b = t + i * TPL;
-        if (active && (SH::EXACT || b < SH::B)) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = line[lds_idx(b + r * SH::B)];
+        if (act && (SH::EXACT || b < SH::B)) {
             const int k = b % NS;
 #pragma unroll
             for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[r * k * STEP]);
@@ -192,52 +264,49 @@ __device__ __forceinline__ void stages_from_lds(V* __restrict__ line, const V* _
     }
     if constexpr (sizeof...(Rest) == 0) {
         static_assert(NS * R == L, "last stage must complete the transform");
-        if constexpr (OUT_LDS) __syncthreads();   // every read of the stage precedes the writes
 #pragma unroll
         for (int i = 0; i < SH::NB; ++i) {
             const int b = t + i * TPL;
-            if (active && (SH::EXACT || b < SH::B)) {
+            if (act && (SH::EXACT || b < SH::B)) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) sink(b + r * SH::B, v[i][r]);
             }
         }
     } else {
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < SH::NB; ++i) {
-            const int b = t + i * TPL;
-            if (active && (SH::EXACT || b < SH::B)) {
-                const int base = (b / NS) * NS * R + (b % NS);
-#pragma unroll
-                for (int r = 0; r < R; ++r) line[lds_idx(base + r * NS)] = v[i][r];
-            }
-        }
-        __syncthreads();
-        stages_from_lds<V, L, TPL, OUT_LDS, NS * R, Rest...>(line, tw, t, active, sink);
+        constexpr int R2 = FirstRadix<Rest...>::value;
+        StageRegs<V, L, TPL, R2> u;
+        exchange<V, L, TPL, P, NS, R, R2>(line, t, act, v, u);
+        stage_regs<V, L, TPL, P, NS * R, Rest...>(u, line, tw, t, act, sink);
     }
 }
 
-// Whole 1-D FFT of the thread's line.  IN_LDS: `src` reads LDS (so the first
-// stage's writes wait for every read); OUT_LDS: `sink` writes LDS.  Threads
-// with active == false only take part in the barriers.
-template <typename V, int L, int TPL, bool IN_LDS, bool OUT_LDS, int R, int... Rest, typename Src,
-          typename Sink>
-__device__ __forceinline__ void run_fft(V* __restrict__ line, const V* __restrict__ tw, int t, bool active,
-                                        Src& src, Sink& sink) {
+// First-stage inputs of the thread's butterflies: v[i][r] = src(b + r*L/R).
+template <typename V, int L, int TPL, int R, typename Src>
+__device__ __forceinline__ void load_first(StageRegs<V, L, TPL, R>& v, int t, bool act, Src& src) {
     using SH = StageShape<V, L, TPL, R>;
-    V v[SH::NB][R];
 #pragma unroll
     for (int i = 0; i < SH::NB; ++i) {
         const int b = t + i * TPL;
-        if (active && (SH::EXACT || b < SH::B)) {
+        if (act && (SH::EXACT || b < SH::B)) {
 #pragma unroll
             for (int r = 0; r < R; ++r) v[i][r] = src(b + r * SH::B);
         }
     }
+}
+
+// The 1-D FFT of the thread's line from its first-stage inputs v (already
+// loaded).  IN_LDS: the inputs came from LDS (so the first exchange's writes
+// wait for every read); OUT_LDS: `sink` writes LDS (the last exchange ends
+// with a barrier, so every LDS read precedes it).  Lanes with act == false
+// only take part in the barriers.
+template <typename V, int L, int TPL, int P, bool IN_LDS, bool OUT_LDS, int R, int... Rest, typename Sink>
+__device__ __forceinline__ void fft_from_regs(StageRegs<V, L, TPL, R>& v, V* __restrict__ line,
+                                              const V* __restrict__ tw, int t, bool act, Sink& sink) {
+    using SH = StageShape<V, L, TPL, R>;
 #pragma unroll
     for (int i = 0; i < SH::NB; ++i) {
         const int b = t + i * TPL;
-        if (active && (SH::EXACT || b < SH::B)) dft<R>(v[i]);   // span 1: no twiddles
+        if (act && (SH::EXACT || b < SH::B)) dft<R>(v[i]);   // span 1: no twiddles
     }
     if constexpr (sizeof...(Rest) == 0) {
         // a single stage: output j = r (one butterfly, b = 0)
@@ -245,24 +314,29 @@ __device__ __forceinline__ void run_fft(V* __restrict__ line, const V* __restric
 #pragma unroll
         for (int i = 0; i < SH::NB; ++i) {
             const int b = t + i * TPL;
-            if (active && (SH::EXACT || b < SH::B)) {
+            if (act && (SH::EXACT || b < SH::B)) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) sink(b + r * SH::B, v[i][r]);
             }
         }
     } else {
         if constexpr (IN_LDS) __syncthreads();
-#pragma unroll
-        for (int i = 0; i < SH::NB; ++i) {
-            const int b = t + i * TPL;
-            if (active && (SH::EXACT || b < SH::B)) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) line[lds_idx(b * R + r)] = v[i][r];
-            }
-        }
-        __syncthreads();
-        stages_from_lds<V, L, TPL, OUT_LDS, R, Rest...>(line, tw, t, active, sink);
+        constexpr int R2 = FirstRadix<Rest...>::value;
+        StageRegs<V, L, TPL, R2> u;
+        exchange<V, L, TPL, P, 1, R, R2>(line, t, act, v, u);
+        stage_regs<V, L, TPL, P, R, Rest...>(u, line, tw, t, act, sink);
     }
+}
+
+// Whole 1-D FFT of the thread's line: first-stage loads from `src`, then
+// fft_from_regs.  P: the parts every LDS exchange runs in.
+template <typename V, int L, int TPL, int P, bool IN_LDS, bool OUT_LDS, int R, int... Rest, typename Src,
+          typename Sink>
+__device__ __forceinline__ void run_fft(V* __restrict__ line, const V* __restrict__ tw, int t, bool act, Src& src,
+                                        Sink& sink) {
+    StageRegs<V, L, TPL, R> v;
+    load_first<V, L, TPL, R>(v, t, act, src);
+    fft_from_regs<V, L, TPL, P, IN_LDS, OUT_LDS, R, Rest...>(v, line, tw, t, act, sink);
 }
 
 template <int... Rs> struct RadixProduct;
@@ -330,11 +404,11 @@ constexpr int kDirectRowMinTpl = 16;
 //                      is staged through LDS as one contiguous block.
 // Threads beyond W*TPL (possible when a larger workgroup runs this tile, as in
 // the persistent batch executor) only take part in the barriers.
-template <typename V, bool COHERENT, int L, int TPL, int... Rs>
+template <typename V, bool COHERENT, int L, int TPL, int P, int... Rs>
 __device__ __forceinline__ void pass_tile_impl(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
     using S = decltype(V{}.x);
     static_assert(RadixProduct<Rs...>::value == L, "radix sequence must multiply to L");
-    constexpr int LP = Pitch_value(L);
+    constexpr int LP = line_pitch(L, P);
     const int W = 1 << a.logW;
     const int tid = threadIdx.x;
     const int64_t rem = a.nlines - l0;
@@ -367,40 +441,43 @@ __device__ __forceinline__ void pass_tile_impl(const PassArgs& a, V* __restrict_
         auto sink = [&](int j, V x) {
             if (ok) store_elem<COHERENT>(go + (int64_t)j * M2, fix_out(x, cout, scale));
         };
-        run_fft<V, L, TPL, false, false, Rs...>(lds + w * LP, tw, t, active, src, sink);
+        run_fft<V, L, TPL, P, false, false, Rs...>(lds + w * LP, tw, t, active, src, sink);
         return;
     }
-    const int t = tid % TPL, w = active ? tid / TPL : 0;
-    V* line = lds + w * LP;
-    if constexpr (TPL >= kDirectRowMinTpl) {
-        const bool ok = active && tid / TPL < nl;
-        const V* g = in + (l0 + (ok ? w : 0)) * L;
-        V* go = out + (l0 + w) * L;
-        auto src = [&](int j) { return fix_in(g[j], cin); };
-        auto sink = [&](int j, V x) {
-            if (ok) store_elem<COHERENT>(go + j, fix_out(x, cout, scale));
-        };
-        run_fft<V, L, TPL, false, false, Rs...>(line, tw, t, active, src, sink);
-    } else {
-        // stage the contiguous block of nl*L elements through LDS
-        const int NT = W * TPL;
-        const V* g = in + l0 * L;
-        V* go = out + l0 * L;
-        if (active) {
-            for (int f = tid; f < nl * L; f += NT) {
-                const int lw = f / L, j = f - lw * L;
-                lds[lw * LP + lds_idx(j)] = fix_in(g[f], cin);
+    // contiguous lines keep whole lines in LDS: kernels with parts serve strided lines only
+    if constexpr (P == 1) {
+        const int t = tid % TPL, w = active ? tid / TPL : 0;
+        V* line = lds + w * LP;
+        if constexpr (TPL >= kDirectRowMinTpl) {
+            const bool ok = active && tid / TPL < nl;
+            const V* g = in + (l0 + (ok ? w : 0)) * L;
+            V* go = out + (l0 + w) * L;
+            auto src = [&](int j) { return fix_in(g[j], cin); };
+            auto sink = [&](int j, V x) {
+                if (ok) store_elem<COHERENT>(go + j, fix_out(x, cout, scale));
+            };
+            run_fft<V, L, TPL, 1, false, false, Rs...>(line, tw, t, active, src, sink);
+        } else {
+            // stage the contiguous block of nl*L elements through LDS
+            const int NT = W * TPL;
+            const V* g = in + l0 * L;
+            V* go = out + l0 * L;
+            if (active) {
+                for (int f = tid; f < nl * L; f += NT) {
+                    const int lw = f / L, j = f - lw * L;
+                    lds[lw * LP + lds_idx(j)] = fix_in(g[f], cin);
+                }
             }
-        }
-        __syncthreads();
-        auto src = [&](int j) { return line[lds_idx(j)]; };
-        auto sink = [&](int j, V x) { line[lds_idx(j)] = x; };
-        run_fft<V, L, TPL, true, true, Rs...>(line, tw, t, active, src, sink);
-        __syncthreads();
-        if (active) {
-            for (int f = tid; f < nl * L; f += NT) {
-                const int lw = f / L, j = f - lw * L;
-                store_elem<COHERENT>(go + f, fix_out(lds[lw * LP + lds_idx(j)], cout, scale));
+            __syncthreads();
+            auto src = [&](int j) { return line[lds_idx(j)]; };
+            auto sink = [&](int j, V x) { line[lds_idx(j)] = x; };
+            run_fft<V, L, TPL, 1, true, true, Rs...>(line, tw, t, active, src, sink);
+            __syncthreads();
+            if (active) {
+                for (int f = tid; f < nl * L; f += NT) {
+                    const int lw = f / L, j = f - lw * L;
+                    store_elem<COHERENT>(go + f, fix_out(lds[lw * LP + lds_idx(j)], cout, scale));
+                }
             }
         }
     }
@@ -409,14 +486,21 @@ __device__ __forceinline__ void pass_tile_impl(const PassArgs& a, V* __restrict_
 // One tile of an axis pass with ordinary stores (stand-alone pass kernels).
 template <typename V, int L, int TPL, int... Rs>
 __device__ __forceinline__ void pass_tile(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
-    pass_tile_impl<V, false, L, TPL, Rs...>(a, lds, l0);
+    pass_tile_impl<V, false, L, TPL, 1, Rs...>(a, lds, l0);
+}
+
+// One tile of a strided pass whose LDS exchanges run in P parts (stand-alone
+// pass kernels of lengths whose radix sequence allows it).
+template <typename V, int L, int TPL, int P, int... Rs>
+__device__ __forceinline__ void pass_tile_parts(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
+    pass_tile_impl<V, false, L, TPL, P, Rs...>(a, lds, l0);
 }
 
 // One tile with write-through stores (batch executors, whose tiles are read
 // by other workgroups of the same launch).
 template <typename V, int L, int TPL, int... Rs>
 __device__ __forceinline__ void pass_tile_coherent(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
-    pass_tile_impl<V, true, L, TPL, Rs...>(a, lds, l0);
+    pass_tile_impl<V, true, L, TPL, 1, Rs...>(a, lds, l0);
 }
 
 }  // namespace offt

@@ -7,12 +7,13 @@
 namespace offt {
 
 // MAXT: the largest workgroup the kernel is compiled for (launch bound).
-template <typename V, int MAXT, int L, int TPL, int... Rs>
+// P: the parts its LDS exchanges run in (P > 1: strided lines only).
+template <typename V, int MAXT, int L, int TPL, int P, int... Rs>
 __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* lds = reinterpret_cast<V*>(smem_raw);
     const int64_t l0 = (int64_t)blockIdx.x << a.logW;
-    pass_tile<V, L, TPL, Rs...>(a, lds, l0);
+    pass_tile_parts<V, L, TPL, P, Rs...>(a, lds, l0);
 }
 
 }  // namespace offt

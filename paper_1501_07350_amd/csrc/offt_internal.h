@@ -28,6 +28,7 @@ struct KernelEntry {
     int radices[kMaxStages];
     int tpl;                   // threads per line
     int max_threads;           // launch bound the kernel is compiled for
+    int nparts;                // parts each LDS exchange runs in (> 1: strided lines only)
     LaunchFn launch;
 };
 
@@ -84,6 +85,9 @@ PlanChoice default_choice(int dtype, const int64_t dims[3]);
 std::vector<PlanChoice> candidate_choices(int dtype, const int64_t dims[3]);
 // Pass descriptors (M1, M2, mode, W) for a grid + batch under a choice.
 int build_passes(const PlanChoice& c, const int64_t dims[3], int64_t batch, PassPlan out[3]);
+// Whether a tile of 2^logW lines of kernel k can be launched: thread limit
+// and LDS limit.
+bool tile_fits(const KernelEntry* k, int logW, int dtype);
 // Clamp logW so the tile fits LDS and the thread limit; returns the adjusted value.
 int fit_logW(const KernelEntry* k, int logW, int dtype);
 

@@ -34,7 +34,7 @@ const std::vector<const KernelEntry*>& registry() {
 
 // Kernels of one length, default first: fewest stages, then largest leading
 // radix, then the most threads per line (one butterfly of the largest radix
-// per thread).
+// per thread), then whole-line exchanges before exchanges in parts.
 std::vector<const KernelEntry*> kernels_for(int dtype, int L) {
     std::vector<const KernelEntry*> v;
     for (const KernelEntry* e : registry())
@@ -42,7 +42,7 @@ std::vector<const KernelEntry*> kernels_for(int dtype, int L) {
     auto key = [](const KernelEntry* e) {
         int maxr = 0;
         for (int i = 0; i < e->nstages; ++i) maxr = std::max(maxr, e->radices[i]);
-        return std::make_tuple(e->nstages, -maxr, -e->tpl);
+        return std::make_tuple(e->nstages, -maxr, -e->tpl, e->nparts);
     };
     std::stable_sort(v.begin(), v.end(),
                      [&](const KernelEntry* x, const KernelEntry* y) { return key(x) < key(y); });
@@ -83,16 +83,18 @@ int64_t lds_limit() {
     return lim;
 }
 
+bool tile_fits(const KernelEntry* k, int logW, int dtype) {
+    if (!k || logW < 0) return false;
+    const int64_t W = int64_t(1) << logW;
+    const int64_t threads = W * k->tpl;
+    if (threads > k->max_threads) return false;
+    const int64_t lds = tile_lds_elems((int)W, k->L, k->nparts) * (int64_t)elem_size(dtype);
+    return lds <= lds_limit();
+}
+
 int fit_logW(const KernelEntry* k, int logW, int dtype) {
     if (!k) return 0;
-    const size_t es = elem_size(dtype);
-    while (logW > 0) {
-        const int64_t W = int64_t(1) << logW;
-        const int64_t threads = W * k->tpl;
-        const int64_t lds = tile_lds_elems((int)W, k->L) * (int64_t)es;
-        if (threads <= k->max_threads && lds <= lds_limit()) break;
-        --logW;
-    }
+    while (logW > 0 && !tile_fits(k, logW, dtype)) --logW;
     return logW;
 }
 
@@ -112,7 +114,9 @@ static int default_logW(const KernelEntry* k, int dtype, bool strided) {
 // Default kernel of an axis: the first in kernels_for() order whose tile at the
 // heuristic width reaches 256-byte rows for strided lines; otherwise the first.
 static const KernelEntry* default_kernel(int dtype, int L, bool strided) {
-    std::vector<const KernelEntry*> ks = kernels_for(dtype, L);
+    std::vector<const KernelEntry*> ks;
+    for (const KernelEntry* k : kernels_for(dtype, L))
+        if (k->nparts == 1) ks.push_back(k);
     if (ks.empty()) return nullptr;
     if (!strided) return ks[0];
     const int want = dtype == OFFT_C2C_F64 ? 4 : 5;
@@ -156,6 +160,7 @@ std::vector<PlanChoice> candidate_choices(int dtype, const int64_t dims[3]) {
         if (dims[ax] <= 1) continue;
         std::vector<const KernelEntry*> ks = kernels_for(dtype, (int)dims[ax]);
         for (const KernelEntry* k : ks) {
+            if (k->nparts > 1) continue;   // the exhaustive tuner covers exchanges in parts
             const int l0 = default_logW(k, dtype, axis_strided(ax, dims));
             for (int dl = -1; dl <= 1; ++dl) {
                 const int lw = l0 + dl;
@@ -192,6 +197,7 @@ std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]) {
         for (int i = 0; i < c.k[ax]->nstages; ++i) os << (i ? "x" : "") << c.k[ax]->radices[i];
         os << "/" << (1 << c.logW[ax]);
         if (c.k[ax]->tpl != default_tpl(c.k[ax])) os << "/" << c.k[ax]->tpl;
+        if (c.k[ax]->nparts > 1) os << "/p" << c.k[ax]->nparts;
     }
     return os.str();
 }
@@ -240,23 +246,31 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
             const long W = strtol(val.c_str() + slash + 1, &end, 10);
             if (!end || W < 1 || (W & (W - 1))) return false;
             long tpl = 0;   // 0: the sequence's default thread count
-            if (*end == '/') {
+            long P = 1;     // parts of each LDS exchange ("/p<P>", strided axes)
+            if (*end == '/' && end[1] != 'p') {
                 char* end2 = nullptr;
                 tpl = strtol(end + 1, &end2, 10);
-                if (!end2 || *end2 || tpl < 1) return false;
-            } else if (*end) {
-                return false;
+                if (!end2 || tpl < 1) return false;
+                end = end2;
             }
+            if (*end == '/' && end[1] == 'p') {
+                char* end2 = nullptr;
+                P = strtol(end + 2, &end2, 10);
+                if (!end2 || (P != 1 && P != 2 && P != 4)) return false;
+                end = end2;
+            }
+            if (*end) return false;
+            if (P > 1 && !axis_strided(ax, dims)) return false;
             const KernelEntry* found = nullptr;
             for (const KernelEntry* k : kernels_for(dtype, (int)dims[ax])) {
                 if (k->nstages != (int)rad.size()) continue;
                 bool eq2 = true;
                 for (int i = 0; i < k->nstages; ++i) eq2 = eq2 && k->radices[i] == rad[i];
-                if (eq2 && k->tpl == (tpl ? (int)tpl : default_tpl(k))) { found = k; break; }
+                if (eq2 && k->tpl == (tpl ? (int)tpl : default_tpl(k)) && k->nparts == (int)P) { found = k; break; }
             }
             if (!found) return false;
             const int lw = ilog2(W);
-            if (check_fit && fit_logW(found, lw, dtype) != lw) return false;
+            if (check_fit && !tile_fits(found, lw, dtype)) return false;
             c.k[ax] = found;
             c.logW[ax] = lw;
         } else {
@@ -303,10 +317,13 @@ hipError_t launch_pass(const PassPlan& p, const void* in, void* out, int conj_in
     a.conj_in = conj_in;
     a.conj_out = conj_out;
     a.scale = scale;
+    // a kernel with exchanges in parts keeps only part of each line in LDS:
+    // strided lines only
+    if (p.k->nparts > 1 && p.mode != 1) return hipErrorInvalidValue;
     const int64_t W = int64_t(1) << p.logW;
     const int64_t nblocks = (a.nlines + W - 1) / W;
     const int threads = (int)(W * p.k->tpl);
-    const size_t lds = (size_t)tile_lds_elems((int)W, p.L) * (p.k->dtype == OFFT_C2C_F64 ? 16 : 8);
+    const size_t lds = (size_t)tile_lds_elems((int)W, p.L, p.k->nparts) * (p.k->dtype == OFFT_C2C_F64 ? 16 : 8);
     return p.k->launch(a, nblocks, threads, lds, s);
 }
 

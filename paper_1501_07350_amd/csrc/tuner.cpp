@@ -2,8 +2,9 @@
 // the paper's auto-tuning of communication methods (Sec. 3.2.3): every
 // candidate plan is executed a few times during initialization and the
 // fastest is kept; a plan cache plays the role of the paper's "User-select
-// after tuning once".  Candidates: radix sequence and tile width per axis,
-// and the axis order of the passes.
+// after tuning once".  Candidates: radix sequence (with the parts its LDS
+// exchanges run in) and tile width per axis, and the axis order of the
+// passes.
 //
 // Protocol: 1 warm-up + `reps` timed executions per candidate (hipEvents on the
 // tuning stream), score = minimum; ties go to the earlier candidate (the
@@ -166,10 +167,17 @@ static int exhaustive(offt_plan_s* p, const offt_opts& o, PlanChoice* choice) {
         std::stable_partition(ks.begin(), ks.end(), [&](const KernelEntry* k) { return k == best.k[ax]; });
         const KernelEntry* best_k = best.k[ax];
         int best_lw = lw0;
+        int64_t m2 = 1;
+        for (int j = ax + 1; j < 3; ++j) m2 *= p->dims[j];
         for (const KernelEntry* k : ks) {
+            // kernels whose LDS exchanges run in parts serve strided axes only
+            if (k->nparts > 1 && m2 == 1) continue;
             const int top = fit_logW(k, 10, p->dtype);
-            for (int lw = top; lw >= 0 && rc == OFFT_SUCCESS; --lw) {
-                if (top - lw > 4) break;   // widths below 1/16 of the widest that fits: never competitive
+            // widths below 1/16 of the widest that fits are never competitive;
+            // of a kernel with exchanges in parts only the two widest are tried
+            const int span = k->nparts == 1 ? 4 : 1;
+            for (int lw = top; lw >= 0 && top - lw <= span && rc == OFFT_SUCCESS; --lw) {
+                if (!tile_fits(k, lw, p->dtype)) continue;
                 cur.k[ax] = k;
                 cur.logW[ax] = lw;
                 float ms = 0.f;

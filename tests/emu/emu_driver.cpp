@@ -1,9 +1,11 @@
 // emu_driver.cpp -- runs the library's tile code (pass_tile) and the
 // persistent batch loop (many_body) for one workgroup on CPU threads.
 //
-//   emu_driver pass <dtype 0|1> <L> <TPL> <r1,r2,..> <nlines> <M2> <logW> <tile> <threads>
-//       one tile of an axis pass, input from stdin-free synthetic data; prints
-//       the tile's output lines (forward transform) as text
+//   emu_driver pass <dtype 0|1> <kid> <L> <M1> <M2> <logW> <logP> <TPL>
+//       one stand-alone axis pass (kernel case kid of the executor's table,
+//       plain stores) over a [M1][L][M2] view of synthetic data, tile by tile
+//       with W*TPL threads each (strided lines with LDS exchanges in 2^logP
+//       parts when M2 > 1); prints the forward-transformed data as text
 //   emu_driver many <dtype> <nwg> <threads> <nseg> <segments...> <total>
 //       the persistent loop over a segment table, run by nwg workgroups at
 //       once: each workgroup is a forked process of `threads` CPU threads;
@@ -158,10 +160,57 @@ static int do_many(int argc, char** argv) {
     return 0;
 }
 
+template <typename V>
+static int do_pass(int argc, char** argv) {
+    if (argc < 10) return 2;
+    const int kid = atoi(argv[3]);
+    const int L = atoi(argv[4]);
+    const int64_t M1 = atoll(argv[5]), M2 = atoll(argv[6]);
+    const int logW = atoi(argv[7]), logP = atoi(argv[8]);
+    const int tpl = atoi(argv[9]);
+    const int64_t total = M1 * L * M2;
+    std::vector<V> in(total), out(total);
+    for (int64_t i = 0; i < total; ++i) {
+        in[i].x = (decltype(in[i].x))std::sin(0.37 * (double)i + 0.1);
+        in[i].y = (decltype(in[i].y))std::cos(0.91 * (double)i);
+        out[i].x = out[i].y = 0;
+    }
+    std::vector<V> tw;
+    twiddles(tw, L);
+    PassArgs a;
+    memset(&a, 0, sizeof a);
+    a.in = in.data();
+    a.out = out.data();
+    a.tw = tw.data();
+    a.nlines = M1 * M2;
+    a.M2 = M2;
+    a.logW = logW;
+    a.mode = M2 > 1 ? 1 : 0;
+    a.scale = 1.0;
+    const int W = 1 << logW;
+    const int threads = W * tpl;
+    // exactly the LDS the host launches the tile with: ASan flags any access beyond it
+    const int P = M2 > 1 ? 1 << logP : 1;
+    std::vector<V> lds((size_t)tile_lds_elems(W, L, P));
+    blockDim.x = threads;
+    const int64_t nblocks = (a.nlines + W - 1) / W;
+    for (int64_t blk = 0; blk < nblocks; ++blk) {
+        blockIdx.x = (unsigned)blk;
+        if (!run_block(threads, [&](int) { EmuDispatchPlain<V>{}(kid, P, a, lds.data(), blk << logW); })) {
+            std::printf("FAIL barrier in tile %lld\n", (long long)blk);
+            return 1;
+        }
+    }
+    std::printf("OK %lld tiles\n", (long long)nblocks);
+    for (int64_t i = 0; i < total; ++i) std::printf("%.17g %.17g\n", (double)out[i].x, (double)out[i].y);
+    return 0;
+}
+
 int main(int argc, char** argv) {
     if (argc < 3) return 2;
     const std::string mode = argv[1];
     const int dtype = atoi(argv[2]);
     if (mode == "many") return dtype == 0 ? do_many<double2>(argc, argv) : do_many<float2>(argc, argv);
+    if (mode == "pass") return dtype == 0 ? do_pass<double2>(argc, argv) : do_pass<float2>(argc, argv);
     return 2;
 }

@@ -48,6 +48,17 @@ def emu_binary():
         for i, (L, seq, tpl) in enumerate(gk.many_cases(prec, "all")):
             lines.append(f"      case {i}: pass_tile_coherent<{vt}, {L}, {tpl}, {', '.join(map(str, seq))}>(a, lds, l0); break;")
         lines.append("      default: break;\n    }\n  }\n};")
+    lines.append("template <typename V> struct EmuDispatchPlain;")
+    for vt, prec in (("double2", "f64"), ("float2", "f32")):
+        lines.append(f"template <> struct EmuDispatchPlain<{vt}> {{")
+        lines.append(f"  void operator()(int kid, int P, const PassArgs& a, {vt}* lds, int64_t l0) const {{")
+        lines.append("    switch (kid) {")
+        for i, (L, seq, tpl) in enumerate(gk.many_cases(prec, "all")):
+            rad = ", ".join(map(str, seq))
+            body = " else ".join(f"if (P == {P}) pass_tile_parts<{vt}, {L}, {tpl}, {P}, {rad}>(a, lds, l0);"
+                                 for P in (1, 2, 4) if gk.splits(L, seq, P))
+            lines.append(f"      case {i}: {body} break;")
+        lines.append("      default: break;\n    }\n  }\n};")
     with open(os.path.join(BUILD, "emu_cases.inc"), "w") as f:
         f.write("namespace offt {\n" + "\n".join(lines) + "\n}\n")
     exe = os.path.join(BUILD, "emu_driver")
@@ -189,3 +200,52 @@ def test_emulated_every_case_once(emu_binary, dtype):
     lengths = sorted({L for L, _, _ in gk.many_cases(prec, "all")})
     dims = [d for L in lengths for d in ((L, 1, 3), (1, 2, L))]
     run_many(emu_binary, dims, dtype)
+
+
+def run_pass(exe, dtype, L, seq, tpl, M1, M2, logW, logP):
+    """One stand-alone axis pass through the emulated tile code, checked line
+    by line against the oracle's naive DFT."""
+    gk = gen_kernels()
+    prec = "f64" if dtype == torch.complex128 else "f32"
+    kid = gk.many_cases(prec, "all").index((L, seq, tpl))
+    code = "0" if dtype == torch.complex128 else "1"
+    args = [exe, "pass", code] + [str(v) for v in (kid, L, M1, M2, logW, logP, tpl)]
+    r = subprocess.run(args, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, (r.stdout[:500], r.stderr[-3000:])
+    lines = r.stdout.splitlines()
+    assert lines[0].startswith("OK"), lines[0]
+    vals = np.array([[float(a) for a in ln.split()] for ln in lines[1:]])
+    out = (vals[:, 0] + 1j * vals[:, 1]).reshape(M1, L, M2)
+    i = np.arange(M1 * L * M2)
+    x = np.sin(0.37 * i + 0.1) + 1j * np.cos(0.91 * i)
+    if dtype == torch.complex64:
+        x = x.astype(np.complex64).astype(np.complex128)
+    x = x.reshape(M1, L, M2)
+    lines_in = x.transpose(0, 2, 1).reshape(M1 * M2, L)        # every line along the pass axis
+    want = oracle.fft1_lines(lines_in, method=0)               # naive DFT of each line
+    got = out.transpose(0, 2, 1).reshape(M1 * M2, L)
+    worst = max(oracle.rel_l2(got[i], want[i]) for i in range(M1 * M2))
+    assert worst <= oracle.tolerance(L, dtype == torch.complex64), worst
+
+
+# (L, radix sequence, threads per line, M1, M2, logW, logP): strided passes
+# whose LDS exchanges run in 2 and 4 parts, with a ragged last tile (M1*M2
+# not a multiple of W); the 2-stage and 3-stage sequences cover butterflies
+# per thread of 1 and several, where the part of a butterfly is decided per
+# thread and per register slot.
+PART_CASES = [
+    (64, [8, 8], 8, 2, 24, 4, 1),
+    (64, [8, 8], 8, 2, 24, 4, 2),
+    (128, [16, 8], 8, 1, 40, 5, 1),
+    (128, [16, 8], 8, 1, 72, 5, 2),
+    (128, [8, 4, 4], 16, 3, 20, 4, 1),
+    (128, [8, 4, 4], 16, 3, 20, 3, 2),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
+@pytest.mark.parametrize("case", PART_CASES, ids=lambda c: f"L{c[0]}-{'x'.join(map(str, c[1]))}-M2_{c[4]}-W{1 << c[5]}-P{1 << c[6]}")
+def test_emulated_strided_pass_exchange_parts(emu_binary, dtype, case):
+    L, seq, tpl, M1, M2, logW, logP = case
+    assert gen_kernels().splits(L, seq, 1 << logP)
+    run_pass(emu_binary, dtype, L, seq, tpl, M1, M2, logW, logP)

@@ -207,6 +207,70 @@ def test_tile_widths_forced():
             p.close()
 
 
+def _kernel_spec(L, seq, tpl, P, W):
+    spec = "x".join(map(str, seq)) + f"/{W}"
+    if tpl != L // max(seq):
+        spec += f"/{tpl}"
+    if P > 1:
+        spec += f"/p{P}"
+    return spec
+
+
+# strided axes of power-of-two length >= 256 (the kernels with LDS exchanges
+# in parts); lines per pass not a multiple of the tile width, so the last
+# tile is ragged
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("shape,axis", [((256, 12, 10), "a"), ((6, 512, 9), "b"), ((1024, 3, 5), "a")],
+                         ids=["a256", "b512", "a1024"])
+def test_strided_exchange_parts(shape, axis, dtype):
+    """Every kernel whose LDS exchanges run in 2 or 4 parts, at every tile
+    width that fits: within tolerance of the oracle, and bit-identical across
+    tile widths (the width changes which threads and LDS slots carry a line,
+    not the arithmetic).  Kernels of different part counts are separate
+    compilations whose multiply-adds may be contracted differently, so they
+    agree to rounding only."""
+    gk = _gen_kernels()
+    prec = "f64" if dtype == C128 else "f32"
+    x = gen(shape, dtype, synth.SEED + 31)
+    ref = oracle.fft3(host(x))
+    base = offt.Plan(shape, dtype=dtype).describe()
+    fields = dict(kv.split("=") for kv in base.split(";"))
+    L = shape["abc".index(axis)]
+    ents = [e for e in gk.entries(prec) if e[0] == L]
+    tried = 0
+    for (_, seq, tpl, P) in ents:
+        if P == 1:
+            continue
+        whole = None
+        for W in (64, 32, 16, 8, 4, 2, 1):
+            f2 = dict(fields)
+            f2[axis] = _kernel_spec(L, seq, tpl, P, W)
+            ps = ";".join(f"{k}={v}" for k, v in f2.items())
+            try:
+                p = offt.Plan(shape, dtype=dtype, tune="forced", forced_plan=ps)
+            except offt.OfftError:
+                continue   # tile does not fit the thread or LDS limit
+            assert p.describe() == ps
+            y = p.forward(x)
+            p.close()
+            torch.cuda.synchronize()
+            if whole is None:
+                whole = y   # the widest tile of this kernel
+            assert torch.equal(y, whole), ps
+            e = oracle.rel_l2(host(y), ref)
+            assert e <= tol(x.numel(), dtype), (ps, e)
+            tried += 1
+    assert tried > 0
+
+
+def test_exchange_parts_rejected_for_contiguous_axes():
+    """Kernels with exchanges in parts keep only part of each line in LDS:
+    plan strings that put one on the contiguous axis are refused."""
+    shape = (4, 4, 512)
+    with pytest.raises(offt.OfftError):
+        offt.Plan(shape, dtype=C128, tune="forced", forced_plan="order=cba;a=4/16;b=4/16;c=16x16x2/1/p2")
+
+
 # ------------------------------------------------------------- twiddles ----
 def roots_extended(n):
     """exp(-2 pi i m / n) in x87 extended precision (independent of both the
