@@ -59,6 +59,7 @@ struct ManyState {
     size_t lds = 0;
     const void* kernel = nullptr;
     int64_t level_begin[4] = {0, 0, 0, 0};   // work items of pass level l: [level_begin[l], level_begin[l+1])
+    int64_t level_tile_begin[4] = {0, 0, 0, 0};   // tiles of pass level l (level kernels, one per workgroup)
     // graph of the persistent launch: reset node -> persistent node
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -180,13 +181,24 @@ static int build_many(offt_plan_s* p, hipStream_t s) {
     for (int lvl = 0; lvl < 3; ++lvl)
         for (int g = 0; g < m->count; ++g)
             if (seg_of[lvl * m->count + g] >= 0) seg_level.push_back(lvl);
+    int64_t tiles = 0;
     int lv = 0;
     for (size_t i = 0; i < segs.size(); ++i) {
-        while (lv < seg_level[i]) m->level_begin[++lv] = items;
+        while (lv < seg_level[i]) {
+            ++lv;
+            m->level_begin[lv] = items;
+            m->level_tile_begin[lv] = tiles;
+        }
         segs[i].item_base = items;
+        segs[i].tile_base = tiles;
         items += segs[i].nitems;
+        tiles += segs[i].ntiles;
     }
-    while (lv < 3) m->level_begin[++lv] = items;
+    while (lv < 3) {
+        ++lv;
+        m->level_begin[lv] = items;
+        m->level_tile_begin[lv] = tiles;
+    }
     m->nseg = (int)segs.size();
     m->total_items = items;
     if (items >= (int64_t(1) << 31)) { m->persistent_ok = false; m->why_not = "too many work items"; }
@@ -236,8 +248,8 @@ static ManyArgs make_args(const ManyState* m, const void* in, void* out, int dir
 static int launch_levels(ManyState* m, const void* in, void* out, int dir, hipStream_t s) {
     ManyArgs a = make_args(m, in, out, dir);
     for (int l = 0; l < 3; ++l) {
-        int64_t begin = m->level_begin[l];
-        const int64_t n = m->level_begin[l + 1] - begin;
+        int64_t begin = m->level_tile_begin[l];
+        const int64_t n = m->level_tile_begin[l + 1] - begin;
         if (n <= 0) continue;
         void* params[] = {&a, &begin};
         if (hipLaunchKernel(m->exec->level_kernel, dim3((unsigned)n), dim3(kManyThreads), params, m->lds, s) !=
@@ -256,7 +268,7 @@ static int level_graph_launch(ManyState* m, const void* in, void* out, int dir, 
         params[0] = &m->largs;
         params[1] = &m->lbegin[l];
         kp->func = const_cast<void*>(m->exec->level_kernel);
-        kp->gridDim = dim3((unsigned)(m->level_begin[l + 1] - m->level_begin[l]));
+        kp->gridDim = dim3((unsigned)(m->level_tile_begin[l + 1] - m->level_tile_begin[l]));
         kp->blockDim = dim3(kManyThreads);
         kp->sharedMemBytes = (unsigned)m->lds;
         kp->kernelParams = params;
@@ -266,9 +278,9 @@ static int level_graph_launch(ManyState* m, const void* in, void* out, int dir, 
         m->largs = a;
         hipGraphNode_t prev = nullptr;
         for (int l = 0; l < 3; ++l) {
-            m->lbegin[l] = m->level_begin[l];
+            m->lbegin[l] = m->level_tile_begin[l];
             m->lnodes[l] = nullptr;
-            if (m->level_begin[l + 1] <= m->level_begin[l]) continue;
+            if (m->level_tile_begin[l + 1] <= m->level_tile_begin[l]) continue;
             hipKernelNodeParams kp;
             void* params[2];
             node_params(l, &kp, params);

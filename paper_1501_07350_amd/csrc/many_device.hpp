@@ -40,6 +40,7 @@ struct ManySeg {
     int64_t nlines;      // lines of this pass
     int64_t M2;          // element stride of the pass axis
     int64_t item_base;   // first work item of the segment (items, not tiles)
+    int64_t tile_base;   // first tile of the segment in the level kernels' tile numbering
     const void* tw;      // twiddle table of the pass length
     double scale_bwd;    // scale of the grid's last pass in a backward transform
     int kid;             // kernel case in the executor's dispatch table
@@ -164,17 +165,29 @@ __device__ __forceinline__ void many_body(const ManyArgs& a, V* __restrict__ lds
     }
 }
 
-// Non-persistent form: one workgroup per work item of items
-// [item_begin, item_begin + gridDim.x), all of one pass level, so the kernel
+// Segment of tile `tile` in the level kernels' numbering: the last segment
+// with tile_base <= tile.
+__device__ __forceinline__ int find_segment_by_tile(const ManySeg* segs, int nseg, int64_t tile) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].tile_base <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Non-persistent form: one workgroup per tile of tiles
+// [tile_begin, tile_begin + gridDim.x), all of one pass level, so the kernel
 // boundary between levels orders the passes and no counters are used.
 template <typename V, typename Dispatch>
-__device__ __forceinline__ void many_level_body(const ManyArgs& a, int64_t item_begin, V* __restrict__ lds,
+__device__ __forceinline__ void many_level_body(const ManyArgs& a, int64_t tile_begin, V* __restrict__ lds,
                                                 const Dispatch& dispatch) {
-    const int64_t item = item_begin + (int64_t)blockIdx.x;
-    const int seg = find_segment(a.segs, a.nseg, item);
+    const int64_t tile = tile_begin + (int64_t)blockIdx.x;
+    const int seg = find_segment_by_tile(a.segs, a.nseg, tile);
     const ManySeg sg = a.segs[seg];
     const PassArgs p = segment_pass_args<V>(a, sg);
-    run_item(sg, p, item, lds, dispatch);
+    dispatch(sg.kid, p, lds, (tile - sg.tile_base) << sg.logW);
 }
 
 }  // namespace offt

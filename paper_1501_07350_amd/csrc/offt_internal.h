@@ -48,7 +48,7 @@ struct ManyExecutor {
     const ManyCase* cases;
     int ncases;
     const void* kernel;        // persistent kernel (ManyArgs)
-    const void* level_kernel;  // one work item per workgroup (ManyArgs, int64_t item_begin)
+    const void* level_kernel;  // one tile per workgroup (ManyArgs, int64_t tile_begin)
 };
 
 // Registry of all compiled pass kernels (generated tables).
