@@ -124,11 +124,14 @@ static int dev_alloc(offt_plan_s* p, size_t bytes, void** out) {
     return OFFT_SUCCESS;
 }
 
-constexpr int64_t kManyLdsBudget = 80 * 1024;   // per workgroup: two fit in a CU's 160 KiB
+// LDS per workgroup of the batch executors: three fit in a CU's 160 KiB (the
+// level kernels' 65 registers allow three 512-thread workgroups per CU; on 64
+// uneven complex64 grids 52 KiB beat 80 KiB by 16% and 40 KiB by 2%)
+constexpr int64_t kManyLdsBudget = 52 * 1024;
 constexpr int kTilesPerItem = 4;
 
 // Tile width of a pass inside the batch executors: as many lines as fill the
-// kManyThreads threads, within the LDS budget (two workgroups per CU).
+// kManyThreads threads, within the LDS budget (three workgroups per CU).
 static int many_logW(const PassPlan& pp, int dtype) {
     const int64_t es = (int64_t)elem_size(dtype);
     int lw = 0;

@@ -113,8 +113,15 @@ static int default_logW(const KernelEntry* k, int dtype, bool strided) {
 
 // Default kernel of an axis: the first in kernels_for() order whose tile at the
 // heuristic width reaches 256-byte rows for strided lines; otherwise the first.
+// Strided axes of length >= 512 look at the kernels whose LDS exchanges run in
+// 2 parts first: their tiles need half the LDS (two workgroups per CU, or 32
+// columns of complex64 at L = 1024), which was faster in every measured case
+// (512^3 and 1024^3 on MI355X).  Contiguous axes use whole-line exchanges.
 static const KernelEntry* default_kernel(int dtype, int L, bool strided) {
     std::vector<const KernelEntry*> ks;
+    if (strided && L >= 512)
+        for (const KernelEntry* k : kernels_for(dtype, L))
+            if (k->nparts == 2) ks.push_back(k);
     for (const KernelEntry* k : kernels_for(dtype, L))
         if (k->nparts == 1) ks.push_back(k);
     if (ks.empty()) return nullptr;
@@ -122,6 +129,8 @@ static const KernelEntry* default_kernel(int dtype, int L, bool strided) {
     const int want = dtype == OFFT_C2C_F64 ? 4 : 5;
     for (const KernelEntry* k : ks)
         if (default_logW(k, dtype, true) >= want) return k;
+    for (const KernelEntry* k : ks)
+        if (k->nparts == 1) return k;
     return ks[0];
 }
 
@@ -160,7 +169,7 @@ std::vector<PlanChoice> candidate_choices(int dtype, const int64_t dims[3]) {
         if (dims[ax] <= 1) continue;
         std::vector<const KernelEntry*> ks = kernels_for(dtype, (int)dims[ax]);
         for (const KernelEntry* k : ks) {
-            if (k->nparts > 1) continue;   // the exhaustive tuner covers exchanges in parts
+            if (k->nparts > 1 && k != base.k[ax]) continue;   // the exhaustive tuner covers exchanges in parts
             const int l0 = default_logW(k, dtype, axis_strided(ax, dims));
             for (int dl = -1; dl <= 1; ++dl) {
                 const int lw = l0 + dl;

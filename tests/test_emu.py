@@ -102,10 +102,10 @@ def plan_passes(dims, dtype):
 
 
 def many_logW(p, es):
-    """Tile width inside the batch executors: fill THREADS threads within an
-    80 KiB LDS budget."""
+    """Tile width inside the batch executors: fill THREADS threads within a
+    52 KiB LDS budget."""
     lw = 0
-    while (2 << lw) * p["tpl"] <= THREADS and tile_lds_elems(2 << lw, p["L"]) * es <= min(80 * 1024, LDS_LIMIT):
+    while (2 << lw) * p["tpl"] <= THREADS and tile_lds_elems(2 << lw, p["L"]) * es <= min(52 * 1024, LDS_LIMIT):
         lw += 1
     return lw
 
