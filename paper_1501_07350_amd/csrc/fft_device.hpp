@@ -46,7 +46,7 @@ template <typename V, typename S> __device__ __forceinline__ V cscale(V a, S s) 
 
 // ---- small forward DFTs on registers (W_R = exp(-2 pi i / R)) -----------------
 // Each is derived from the definition y_k = sum_j x_j W_R^(jk) by pairing
-// x_j with x_{R-j} (radix 3, 5) or by one even/odd split (radix 4, 8, 16).
+// x_j with x_{R-j} (radix 3, 5) or by one even/odd split (radix 4, 8, 16, 32).
 
 template <typename V> __device__ __forceinline__ void dft2(V& a, V& b) {
     V t = a; a = cadd(t, b); b = csub(t, b);
@@ -135,6 +135,43 @@ template <typename V> __device__ __forceinline__ void dft16(V* v) {
     for (int k = 0; k < 8; ++k) { v[k] = cadd(e[k], w[k]); v[k + 8] = csub(e[k], w[k]); }
 }
 
+// y_k = E_k + W_32^k O_k, y_{k+16} = E_k - W_32^k O_k with E, O the 16-point
+// DFTs of the even and odd samples; W_32^k = cos(k pi/16) - i sin(k pi/16).
+template <typename V> __device__ __forceinline__ void dft32(V* v) {
+    using S = decltype(v[0].x);
+    // cos(k pi/16) and sin(k pi/16) for k = 0..8
+    const S C[9] = {S(1), S(0.980785280403230449126182236134239037), S(0.923879532511286756128183189396788287),
+                    S(0.831469612302545237078788377617905757), S(0.707106781186547524400844362104849039),
+                    S(0.555570233019602224742830813948532874), S(0.382683432365089771728459984030398867),
+                    S(0.195090322016128267848284868477022241), S(0)};
+    const S Sn[9] = {S(0), S(0.195090322016128267848284868477022241), S(0.382683432365089771728459984030398867),
+                     S(0.555570233019602224742830813948532874), S(0.707106781186547524400844362104849039),
+                     S(0.831469612302545237078788377617905757), S(0.923879532511286756128183189396788287),
+                     S(0.980785280403230449126182236134239037), S(1)};
+    V e[16], o[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) { e[k] = v[2 * k]; o[k] = v[2 * k + 1]; }
+    dft16(e);
+    dft16(o);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        V w;
+        if (k == 0) {
+            w = o[0];
+        } else if (k == 8) {
+            w = mul_mi(o[8]);
+        } else {
+            // cos(k pi/16) = -cos((16-k) pi/16), sin(k pi/16) = sin((16-k) pi/16) for k > 8
+            const S c = k < 8 ? C[k] : -C[16 - k];
+            const S sn = k < 8 ? Sn[k] : Sn[16 - k];
+            w.x = c * o[k].x + sn * o[k].y;
+            w.y = c * o[k].y - sn * o[k].x;
+        }
+        v[k] = cadd(e[k], w);
+        v[k + 16] = csub(e[k], w);
+    }
+}
+
 template <int R, typename V> __device__ __forceinline__ void dft(V* v) {
     if constexpr (R == 2) dft2(v[0], v[1]);
     else if constexpr (R == 3) dft3(v);
@@ -142,6 +179,7 @@ template <int R, typename V> __device__ __forceinline__ void dft(V* v) {
     else if constexpr (R == 5) dft5(v);
     else if constexpr (R == 8) dft8(v);
     else if constexpr (R == 16) dft16(v);
+    else if constexpr (R == 32) dft32(v);
     else static_assert(R == 2, "unsupported radix");
 }
 

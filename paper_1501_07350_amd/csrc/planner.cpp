@@ -32,9 +32,10 @@ const std::vector<const KernelEntry*>& registry() {
     return all;
 }
 
-// Kernels of one length, default first: fewest stages, then largest leading
-// radix, then the most threads per line (one butterfly of the largest radix
-// per thread), then whole-line exchanges before exchanges in parts.
+// Kernels of one length, default first: radix <= 16 before radix-32
+// sequences, then fewest stages, then largest leading radix, then the most
+// threads per line (one butterfly of the largest radix per thread), then
+// whole-line exchanges before exchanges in parts.
 std::vector<const KernelEntry*> kernels_for(int dtype, int L) {
     std::vector<const KernelEntry*> v;
     for (const KernelEntry* e : registry())
@@ -42,7 +43,7 @@ std::vector<const KernelEntry*> kernels_for(int dtype, int L) {
     auto key = [](const KernelEntry* e) {
         int maxr = 0;
         for (int i = 0; i < e->nstages; ++i) maxr = std::max(maxr, e->radices[i]);
-        return std::make_tuple(e->nstages, -maxr, -e->tpl, e->nparts);
+        return std::make_tuple(maxr > 16, e->nstages, -maxr, -e->tpl, e->nparts);
     };
     std::stable_sort(v.begin(), v.end(),
                      [&](const KernelEntry* x, const KernelEntry* y) { return key(x) < key(y); });
@@ -98,37 +99,51 @@ int fit_logW(const KernelEntry* k, int logW, int dtype) {
     return logW;
 }
 
+static int max_radix(const KernelEntry* k) {
+    int maxr = 0;
+    for (int i = 0; i < k->nstages; ++i) maxr = std::max(maxr, k->radices[i]);
+    return maxr;
+}
+
 // Heuristic tile width: strided lines get 256-byte row segments (16 columns
-// of complex128, 32 of complex64) when the tile fits, contiguous lines ~512
-// threads per workgroup for complex128 and ~128 for complex64.
+// of complex128, 32 of complex64), and radix-32 kernels 32 columns in both
+// precisions; contiguous lines ~512 threads per workgroup for complex128 and
+// ~128 for complex64.
+static int strided_logW(const KernelEntry* k, int dtype) {
+    return max_radix(k) >= 32 ? 5 : (dtype == OFFT_C2C_F64 ? 4 : 5);
+}
+
 static int default_logW(const KernelEntry* k, int dtype, bool strided) {
     if (!k) return 0;
     int logW;
     if (strided)
-        logW = dtype == OFFT_C2C_F64 ? 4 : 5;
+        logW = strided_logW(k, dtype);
     else
         logW = ilog2(std::max<int64_t>(1, (dtype == OFFT_C2C_F64 ? 512 : 128) / k->tpl));
     return fit_logW(k, logW, dtype);
 }
 
 // Default kernel of an axis: the first in kernels_for() order whose tile at the
-// heuristic width reaches 256-byte rows for strided lines; otherwise the first.
-// Strided axes of length >= 512 look at the kernels whose LDS exchanges run in
-// 2 parts first: their tiles need half the LDS (two workgroups per CU, or 32
-// columns of complex64 at L = 1024), which was faster in every measured case
-// (512^3 and 1024^3 on MI355X).  Contiguous axes use whole-line exchanges.
+// heuristic width fits; contiguous axes take the first kernel with whole-line
+// exchanges and radix <= 16.  Strided axes of length >= 512 look first at
+// radix-32 kernels whose LDS exchanges run in 2 parts (one exchange per line
+// instead of two, half the LDS per tile), then at the other 2-part kernels:
+// on MI355X these were the fastest, or within 0.5% of it, for every strided
+// pass measured at 512^3 (both precisions) and 1024^3 (complex64).
 static const KernelEntry* default_kernel(int dtype, int L, bool strided) {
     std::vector<const KernelEntry*> ks;
-    if (strided && L >= 512)
+    if (strided && L >= 512) {
         for (const KernelEntry* k : kernels_for(dtype, L))
-            if (k->nparts == 2) ks.push_back(k);
+            if (k->nparts == 2 && max_radix(k) >= 32) ks.push_back(k);
+        for (const KernelEntry* k : kernels_for(dtype, L))
+            if (k->nparts == 2 && max_radix(k) <= 16) ks.push_back(k);
+    }
     for (const KernelEntry* k : kernels_for(dtype, L))
-        if (k->nparts == 1) ks.push_back(k);
+        if (k->nparts == 1 && max_radix(k) <= 16) ks.push_back(k);
     if (ks.empty()) return nullptr;
     if (!strided) return ks[0];
-    const int want = dtype == OFFT_C2C_F64 ? 4 : 5;
     for (const KernelEntry* k : ks)
-        if (default_logW(k, dtype, true) >= want) return k;
+        if (default_logW(k, dtype, true) >= strided_logW(k, dtype)) return k;
     for (const KernelEntry* k : ks)
         if (k->nparts == 1) return k;
     return ks[0];
@@ -163,14 +178,16 @@ std::vector<PlanChoice> candidate_choices(int dtype, const int64_t dims[3]) {
     std::vector<PlanChoice> out;
     const PlanChoice base = default_choice(dtype, dims);
     out.push_back(base);
-    // per-axis variants with the default order: other radix sequences and
-    // tile widths one step either side of the heuristic
+    // per-axis variants with the default order: other kernels (radix
+    // sequence, threads per line, exchange parts on strided axes) and tile
+    // widths one step either side of the heuristic
     for (int ax = 0; ax < 3; ++ax) {
         if (dims[ax] <= 1) continue;
+        const bool strided = axis_strided(ax, dims);
         std::vector<const KernelEntry*> ks = kernels_for(dtype, (int)dims[ax]);
         for (const KernelEntry* k : ks) {
-            if (k->nparts > 1 && k != base.k[ax]) continue;   // the exhaustive tuner covers exchanges in parts
-            const int l0 = default_logW(k, dtype, axis_strided(ax, dims));
+            if (k->nparts > 1 && !strided) continue;
+            const int l0 = default_logW(k, dtype, strided);
             for (int dl = -1; dl <= 1; ++dl) {
                 const int lw = l0 + dl;
                 if (lw < 0 || fit_logW(k, lw, dtype) != lw) continue;

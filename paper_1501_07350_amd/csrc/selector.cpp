@@ -42,7 +42,7 @@ void plan_features(int dtype, const int64_t dims[3], int64_t batch, const PlanCh
     int pos[3] = {0, 0, 0};
     for (int i = 0; i < 3; ++i) pos[c.order[i]] = i;
     for (int ax = 0; ax < 3; ++ax) {
-        float* g = f + 12 + 11 * ax;
+        float* g = f + 12 + kAxisFeatures * ax;
         const KernelEntry* k = c.k[ax];
         if (dims[ax] <= 1 || !k) continue;
         int64_t m2 = 1;
@@ -51,6 +51,7 @@ void plan_features(int dtype, const int64_t dims[3], int64_t batch, const PlanCh
         g[1] = (float)k->nstages;
         for (int s = 0; s < k->nstages; ++s) {
             switch (k->radices[s]) {
+                case 32: g[11] += 1.f; break;
                 case 16: g[2] += 1.f; break;
                 case 8: g[3] += 1.f; break;
                 case 4: g[4] += 1.f; break;
@@ -63,6 +64,7 @@ void plan_features(int dtype, const int64_t dims[3], int64_t batch, const PlanCh
         g[8] = (float)c.logW[ax];
         g[9] = (float)std::log2((double)k->tpl);
         g[10] = (float)pos[ax] * 0.5f;
+        g[12] = (float)std::log2((double)k->nparts);
     }
 }
 

@@ -36,6 +36,15 @@ def gen_kernels():
     return mod
 
 
+# cases the emulated stand-alone passes add to the executor's: the radix-32
+# butterfly, as a single stage and before a radix-2 stage
+EXTRA_PASS_CASES = [(32, [32], 1), (64, [32, 2], 2)]
+
+
+def plain_cases(gk, prec):
+    return gk.many_cases(prec, "all") + EXTRA_PASS_CASES
+
+
 @pytest.fixture(scope="module")
 def emu_binary():
     gk = gen_kernels()
@@ -53,7 +62,7 @@ def emu_binary():
         lines.append(f"template <> struct EmuDispatchPlain<{vt}> {{")
         lines.append(f"  void operator()(int kid, int P, const PassArgs& a, {vt}* lds, int64_t l0) const {{")
         lines.append("    switch (kid) {")
-        for i, (L, seq, tpl) in enumerate(gk.many_cases(prec, "all")):
+        for i, (L, seq, tpl) in enumerate(plain_cases(gk, prec)):
             rad = ", ".join(map(str, seq))
             body = " else ".join(f"if (P == {P}) pass_tile_parts<{vt}, {L}, {tpl}, {P}, {rad}>(a, lds, l0);"
                                  for P in (1, 2, 4) if gk.splits(L, seq, P))
@@ -207,7 +216,7 @@ def run_pass(exe, dtype, L, seq, tpl, M1, M2, logW, logP):
     by line against the oracle's naive DFT."""
     gk = gen_kernels()
     prec = "f64" if dtype == torch.complex128 else "f32"
-    kid = gk.many_cases(prec, "all").index((L, seq, tpl))
+    kid = plain_cases(gk, prec).index((L, seq, tpl))
     code = "0" if dtype == torch.complex128 else "1"
     args = [exe, "pass", code] + [str(v) for v in (kid, L, M1, M2, logW, logP, tpl)]
     r = subprocess.run(args, capture_output=True, text=True, timeout=600)
@@ -246,6 +255,25 @@ PART_CASES = [
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
 @pytest.mark.parametrize("case", PART_CASES, ids=lambda c: f"L{c[0]}-{'x'.join(map(str, c[1]))}-M2_{c[4]}-W{1 << c[5]}-P{1 << c[6]}")
 def test_emulated_strided_pass_exchange_parts(emu_binary, dtype, case):
+    L, seq, tpl, M1, M2, logW, logP = case
+    assert gen_kernels().splits(L, seq, 1 << logP)
+    run_pass(emu_binary, dtype, L, seq, tpl, M1, M2, logW, logP)
+
+
+# the radix-32 butterfly: contiguous lines (M2 = 1) and strided lines with a
+# ragged last tile, single stage and followed by a radix-2 stage
+RADIX32_CASES = [
+    (32, [32], 1, 7, 1, 2, 0),
+    (32, [32], 1, 2, 12, 3, 0),
+    (64, [32, 2], 2, 5, 1, 3, 0),
+    (64, [32, 2], 2, 1, 40, 5, 0),
+    (64, [32, 2], 2, 1, 40, 5, 1),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
+@pytest.mark.parametrize("case", RADIX32_CASES, ids=lambda c: f"L{c[0]}-{'x'.join(map(str, c[1]))}-M1_{c[3]}-M2_{c[4]}-P{1 << c[6]}")
+def test_emulated_radix32_pass(emu_binary, dtype, case):
     L, seq, tpl, M1, M2, logW, logP = case
     assert gen_kernels().splits(L, seq, 1 << logP)
     run_pass(emu_binary, dtype, L, seq, tpl, M1, M2, logW, logP)

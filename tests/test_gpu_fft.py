@@ -172,7 +172,8 @@ def _all_forced_plans(shape, dtype):
 
 
 @pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
-@pytest.mark.parametrize("shape", [(32, 32, 32), (48, 60, 80), (128, 16, 256), (1024, 2, 12)],
+@pytest.mark.parametrize("shape", [(32, 32, 32), (48, 60, 80), (128, 16, 256), (1024, 2, 12), (6, 512, 10),
+                                   (4, 6, 512)],
                          ids=lambda s: "x".join(map(str, s)))
 def test_every_radix_sequence_and_order(shape, dtype):
     x = gen(shape, dtype, synth.SEED + 77)

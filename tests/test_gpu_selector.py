@@ -14,7 +14,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-D, H = 45, 64
+D, H = selector.feature_dim(), 64
 
 
 def problem(B=200, seed=0):

@@ -12,7 +12,7 @@ import paper_1501_07350_amd as offt
 from paper_1501_07350_amd import _lib, selector
 import synth
 
-D = 45
+D = selector.feature_dim()
 
 
 def test_candidates_and_features():
