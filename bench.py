@@ -162,6 +162,8 @@ def time_batch(steps: int, warmup: int, check: bool, count: int = 64):
         "graph_heuristic": (heur, offt.MANY_PERSISTENT_GRAPH),
         "levels_tuned": (tuned, offt.MANY_LEVELS),
         "levels_graph_tuned": (tuned, offt.MANY_LEVELS_GRAPH),
+        "sync_tuned": (tuned, offt.MANY_SYNC),
+        "sync_graph_tuned": (tuned, offt.MANY_SYNC_GRAPH),
     }
     ms = {}
     for name, (pl, mode) in variants.items():
@@ -191,6 +193,7 @@ def time_batch(steps: int, warmup: int, check: bool, count: int = 64):
         "speedup_graph_tuned_vs_separate_heuristic": round(ms["separate_heuristic"] / ms["graph_tuned"], 3),
         "speedup_levels_graph_tuned_vs_separate_heuristic": round(
             ms["separate_heuristic"] / ms["levels_graph_tuned"], 3),
+        "speedup_sync_graph_tuned_vs_separate_heuristic": round(ms["separate_heuristic"] / ms["sync_graph_tuned"], 3),
     }
     if check:
         import oracle

@@ -178,6 +178,12 @@ int64_t offt_many_offset(offt_plan_t p, int i);
  *       all second, then all third), one workgroup per tile, replayed from a
  *       HIP graph built on the first call;
  *    3  LEVELS: the same kernels launched directly;
+ *    5  SYNC_GRAPH: one level-synchronous persistent kernel, after a counter
+ *       reset, replayed from a HIP graph: one resident workgroup per slot the
+ *       device has, each level's tiles dealt round-robin, a grid barrier
+ *       between levels (each case's tiles in a loop of their own, plain
+ *       stores, one L2 write-back and invalidate per workgroup per barrier);
+ *    4  SYNC: the same two kernels launched directly;
  *   -1  SEPARATE_HEURISTIC: every grid's passes as ordinary launches with the
  *       heuristic plans;
  *   -2  SEPARATE_TUNED: the same with the plans chosen at plan time.
@@ -189,8 +195,10 @@ int offt_exec_many(offt_plan_t p, const void* in, void* out, int direction, int 
                    void* stream);
 
 /* After the stream that ran offt_exec_many has been synchronised: 0 if the
- * last persistent run completed every dependency wait normally, OFFT_ERR_HIP
- * if a wait hit its bounded spin limit (results then invalid). */
+ * last persistent run (PERSISTENT* or SYNC*) completed every dependency or
+ * barrier wait normally, OFFT_ERR_HIP if a wait hit its bounded spin limit
+ * (results then invalid; for SYNC* this happens when not every workgroup of
+ * the launch could be resident, e.g. while other work holds the device). */
 int offt_many_status(offt_plan_t p);
 
 /* ---- plan selection internals: candidates, features, timings -------------
@@ -274,6 +282,8 @@ int offt_mlp_adam(offt_mlp_t m, const float* grad, float lr, float beta1, float 
 #define OFFT_MANY_PERSISTENT_GRAPH 1
 #define OFFT_MANY_LEVELS_GRAPH 2
 #define OFFT_MANY_LEVELS 3
+#define OFFT_MANY_SYNC 4
+#define OFFT_MANY_SYNC_GRAPH 5
 
 #define OFFT_FORWARD (-1)
 #define OFFT_BACKWARD (+1)

@@ -15,7 +15,8 @@ import torch
 
 from . import _lib
 from ._lib import (BACKWARD, C2C_F32, C2C_F64, FORWARD, MANY_LEVELS, MANY_LEVELS_GRAPH, MANY_PERSISTENT,
-                   MANY_PERSISTENT_GRAPH, MANY_SEPARATE_HEURISTIC, MANY_SEPARATE_TUNED, MAX_AXIS, OfftError,
+                   MANY_PERSISTENT_GRAPH, MANY_SEPARATE_HEURISTIC, MANY_SEPARATE_TUNED, MANY_SYNC, MANY_SYNC_GRAPH,
+                   MAX_AXIS, OfftError,
                    TUNE_EXHAUSTIVE, TUNE_FORCED, TUNE_LEARNED, TUNE_NONE)
 
 __all__ = ["Plan", "ManyPlan", "OfftError", "twiddles", "default_plan_string", "FORWARD", "BACKWARD",

@@ -38,6 +38,8 @@ MANY_PERSISTENT = 0
 MANY_PERSISTENT_GRAPH = 1
 MANY_LEVELS_GRAPH = 2
 MANY_LEVELS = 3
+MANY_SYNC = 4
+MANY_SYNC_GRAPH = 5
 MAX_AXIS = 1024
 
 

@@ -66,6 +66,15 @@ struct ManyState {
     hipGraphNode_t node_many = nullptr;
     ManyArgs gargs{};
     bool graph_ready = false;
+    // level-synchronous persistent form: (level, case) groups and its graph
+    ManyGroup* d_groups = nullptr;
+    int* d_gseg = nullptr;
+    int sync_nblocks = 0;
+    hipGraph_t sgraph = nullptr;
+    hipGraphExec_t sgexec = nullptr;
+    hipGraphNode_t snode = nullptr;
+    ManyArgs sargs{};
+    bool sgraph_ready = false;
     // graph of the level launches: level 0 -> level 1 -> level 2
     hipGraph_t lgraph = nullptr;
     hipGraphExec_t lgexec = nullptr;
@@ -108,6 +117,8 @@ void release_many(offt_plan_s* p) {
     if (m->graph) (void)hipGraphDestroy(m->graph);
     if (m->lgexec) (void)hipGraphExecDestroy(m->lgexec);
     if (m->lgraph) (void)hipGraphDestroy(m->lgraph);
+    if (m->sgexec) (void)hipGraphExecDestroy(m->sgexec);
+    if (m->sgraph) (void)hipGraphDestroy(m->sgraph);
     delete m;
     p->many = nullptr;
 }
@@ -206,17 +217,57 @@ static int build_many(offt_plan_s* p, hipStream_t s) {
     m->total_items = items;
     if (items >= (int64_t(1) << 31)) { m->persistent_ok = false; m->why_not = "too many work items"; }
     if (m->nseg == 0) return OFFT_SUCCESS;   // all grids 1x1x1: copies only
+    // (level, case) groups of the level-synchronous form: segments of each
+    // group in grid order, tiles numbered within the group, and per group the
+    // tiles of the earlier groups of its level (dealing continues across groups)
+    const int ncases = m->exec ? m->exec->ncases : 0;
+    std::vector<ManyGroup> groups((size_t)3 * ncases);
+    std::vector<int> gseg;
+    if (m->exec) {
+        for (int lvl = 0; lvl < 3; ++lvl) {
+            int64_t rot = 0;
+            for (int c = 0; c < ncases; ++c) {
+                ManyGroup& gr = groups[(size_t)lvl * ncases + c];
+                gr.seg_begin = (int)gseg.size();
+                gr.ntiles = 0;
+                gr.rot = rot;
+                for (size_t i = 0; i < segs.size(); ++i) {
+                    if (seg_level[i] != lvl || segs[i].kid != c) continue;
+                    segs[i].group_tile_base = gr.ntiles;
+                    gr.ntiles += segs[i].ntiles;
+                    gseg.push_back((int)i);
+                }
+                gr.seg_end = (int)gseg.size();
+                rot += gr.ntiles;
+            }
+        }
+    }
     void* d = nullptr;
     int rc = dev_alloc(p, sizeof(ManySeg) * segs.size(), &d);
     if (rc) return rc;
     m->d_segs = static_cast<ManySeg*>(d);
-    rc = dev_alloc(p, sizeof(unsigned) * (kManyCounterBase + segs.size()), &d);
+    // counters: queue head, error flag, one per segment, two level barriers
+    const size_t ncnt = kManyCounterBase + segs.size() + 2;
+    rc = dev_alloc(p, sizeof(unsigned) * ncnt, &d);
     if (rc) return rc;
     m->d_counters = static_cast<unsigned*>(d);
     if (hipMemcpyAsync(m->d_segs, segs.data(), sizeof(ManySeg) * segs.size(), hipMemcpyHostToDevice, s) !=
             hipSuccess ||
-        hipMemsetAsync(m->d_counters, 0, sizeof(unsigned) * (kManyCounterBase + segs.size()), s) != hipSuccess)
+        hipMemsetAsync(m->d_counters, 0, sizeof(unsigned) * ncnt, s) != hipSuccess)
         return OFFT_ERR_HIP;
+    if (!groups.empty()) {
+        rc = dev_alloc(p, sizeof(ManyGroup) * groups.size(), &d);
+        if (rc) return rc;
+        m->d_groups = static_cast<ManyGroup*>(d);
+        rc = dev_alloc(p, sizeof(int) * std::max<size_t>(gseg.size(), 1), &d);
+        if (rc) return rc;
+        m->d_gseg = static_cast<int*>(d);
+        if (hipMemcpyAsync(m->d_groups, groups.data(), sizeof(ManyGroup) * groups.size(), hipMemcpyHostToDevice,
+                           s) != hipSuccess ||
+            (!gseg.empty() && hipMemcpyAsync(m->d_gseg, gseg.data(), sizeof(int) * gseg.size(),
+                                             hipMemcpyHostToDevice, s) != hipSuccess))
+            return OFFT_ERR_HIP;
+    }
     if (!m->persistent_ok) return OFFT_SUCCESS;
     // occupancy-sized persistent grid
     m->kernel = m->exec->kernel;
@@ -231,6 +282,17 @@ static int build_many(offt_plan_s* p, hipStream_t s) {
         return OFFT_ERR_HIP;
     per_cu = std::max(per_cu, 1);
     m->nblocks = (int)std::min<int64_t>(items, (int64_t)per_cu * cus);
+    // the level-synchronous kernel: every workgroup resident (its grid barrier
+    // waits for all of them), so exactly what fits the device at once
+    if (m->lds > 65536 &&
+        hipFuncSetAttribute(m->exec->sync_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->lds) !=
+            hipSuccess)
+        return OFFT_ERR_HIP;
+    int sync_per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&sync_per_cu, m->exec->sync_kernel, kManyThreads, m->lds) !=
+        hipSuccess)
+        return OFFT_ERR_HIP;
+    m->sync_nblocks = std::max(sync_per_cu, 1) * cus;
     return OFFT_SUCCESS;
 }
 
@@ -316,6 +378,75 @@ static int launch_persistent(ManyState* m, const void* in, void* out, int dir, h
     void* params[] = {&a};
     if (hipLaunchKernel(m->kernel, dim3(m->nblocks), dim3(kManyThreads), params, m->lds, s) != hipSuccess)
         return OFFT_ERR_HIP;
+    return OFFT_SUCCESS;
+}
+
+static ManySyncArgs make_sync_args(const ManyState* m) {
+    ManySyncArgs g;
+    memset(&g, 0, sizeof g);
+    g.groups = m->d_groups;
+    g.gseg = m->d_gseg;
+    g.barrier = m->d_counters + kManyCounterBase + m->nseg;
+    g.ncases = m->exec->ncases;
+    return g;
+}
+
+static int launch_sync(ManyState* m, const void* in, void* out, int dir, hipStream_t s) {
+    const int ncnt = kManyCounterBase + m->nseg + 2;
+    hipLaunchKernelGGL(many_reset_kernel, dim3(1), dim3(256), 0, s, m->d_counters, ncnt);
+    if (hipGetLastError() != hipSuccess) return OFFT_ERR_HIP;
+    ManyArgs a = make_args(m, in, out, dir);
+    ManySyncArgs g = make_sync_args(m);
+    void* params[] = {&a, &g};
+    if (hipLaunchKernel(m->exec->sync_kernel, dim3(m->sync_nblocks), dim3(kManyThreads), params, m->lds, s) !=
+        hipSuccess)
+        return OFFT_ERR_HIP;
+    return OFFT_SUCCESS;
+}
+
+// Graph of the level-synchronous form: counter reset -> persistent kernel.
+static int sync_graph_launch(ManyState* m, const void* in, void* out, int dir, hipStream_t s) {
+    ManyArgs a = make_args(m, in, out, dir);
+    ManySyncArgs g = make_sync_args(m);   // node arguments are copied when the node is set
+    auto kernel_params = [&](hipKernelNodeParams* kp, void** params) {
+        memset(kp, 0, sizeof *kp);
+        params[0] = &m->sargs;
+        params[1] = &g;
+        kp->func = const_cast<void*>(m->exec->sync_kernel);
+        kp->gridDim = dim3(m->sync_nblocks);
+        kp->blockDim = dim3(kManyThreads);
+        kp->sharedMemBytes = (unsigned)m->lds;
+        kp->kernelParams = params;
+    };
+    if (!m->sgraph_ready) {
+        if (hipGraphCreate(&m->sgraph, 0) != hipSuccess) return OFFT_ERR_HIP;
+        int ncnt = kManyCounterBase + m->nseg + 2;
+        unsigned* cnt = m->d_counters;
+        void* rparams[] = {&cnt, &ncnt};
+        hipKernelNodeParams rp;
+        memset(&rp, 0, sizeof rp);
+        rp.func = reinterpret_cast<void*>(&many_reset_kernel);
+        rp.gridDim = dim3(1);
+        rp.blockDim = dim3(256);
+        rp.sharedMemBytes = 0;
+        rp.kernelParams = rparams;
+        hipGraphNode_t reset_node;
+        if (hipGraphAddKernelNode(&reset_node, m->sgraph, nullptr, 0, &rp) != hipSuccess) return OFFT_ERR_HIP;
+        m->sargs = a;
+        hipKernelNodeParams kp;
+        void* params[2];
+        kernel_params(&kp, params);
+        if (hipGraphAddKernelNode(&m->snode, m->sgraph, &reset_node, 1, &kp) != hipSuccess) return OFFT_ERR_HIP;
+        if (hipGraphInstantiate(&m->sgexec, m->sgraph, nullptr, nullptr, 0) != hipSuccess) return OFFT_ERR_HIP;
+        m->sgraph_ready = true;
+    } else if (memcmp(&a, &m->sargs, sizeof a) != 0) {
+        m->sargs = a;
+        hipKernelNodeParams kp;
+        void* params[2];
+        kernel_params(&kp, params);
+        if (hipGraphExecKernelNodeSetParams(m->sgexec, m->snode, &kp) != hipSuccess) return OFFT_ERR_HIP;
+    }
+    if (hipGraphLaunch(m->sgexec, s) != hipSuccess) return OFFT_ERR_HIP;
     return OFFT_SUCCESS;
 }
 
@@ -466,9 +597,9 @@ offt_plan_t offt_plan_many(int count, const int64_t* dims, int dtype, const offt
     if (rc == OFFT_SUCCESS && hipStreamSynchronize(s) != hipSuccess) rc = OFFT_ERR_HIP;
     if (rc != OFFT_SUCCESS) { free_plan(p); set_error(rc); return nullptr; }
     char buf[256];
-    snprintf(buf, sizeof buf, "many: %d grids, %lld elements, %d segments, %lld work items, executor %s, %d workgroups x %d, lds %zu%s%s",
+    snprintf(buf, sizeof buf, "many: %d grids, %lld elements, %d segments, %lld work items, executor %s, %d workgroups x %d (level-synchronous: %d), lds %zu%s%s",
              count, (long long)m->total_elems, m->nseg, (long long)m->total_items, m->exec ? m->exec->name : "-",
-             m->nblocks, kManyThreads, m->lds,
+             m->nblocks, kManyThreads, m->sync_nblocks, m->lds,
              m->persistent_ok ? "" : "; persistent executor unavailable: ", m->persistent_ok ? "" : m->why_not.c_str());
     m->desc = buf;
     for (const ManyGrid& G : m->grids) m->desc += "\n" + choice_to_string(G.choice, G.dims);
@@ -487,7 +618,7 @@ int64_t offt_many_offset(offt_plan_t p, int i) {
 
 int offt_exec_many(offt_plan_t p, const void* in, void* out, int direction, int use_graph, void* stream) {
     if (!p || !in || !out || (direction != OFFT_FORWARD && direction != OFFT_BACKWARD) || use_graph < -2 ||
-        use_graph > 3) {
+        use_graph > OFFT_MANY_SYNC_GRAPH) {
         set_error(OFFT_ERR_INVALID_ARG);
         return OFFT_ERR_INVALID_ARG;
     }
@@ -515,8 +646,12 @@ int offt_exec_many(offt_plan_t p, const void* in, void* out, int direction, int 
         rc = launch_persistent(m, in, out, direction, s);
     } else if (use_graph == OFFT_MANY_LEVELS_GRAPH) {
         rc = level_graph_launch(m, in, out, direction, s);
-    } else {
+    } else if (use_graph == OFFT_MANY_LEVELS) {
         rc = launch_levels(m, in, out, direction, s);
+    } else if (use_graph == OFFT_MANY_SYNC_GRAPH) {
+        rc = sync_graph_launch(m, in, out, direction, s);
+    } else {
+        rc = launch_sync(m, in, out, direction, s);
     }
     set_error(rc);
     return rc;

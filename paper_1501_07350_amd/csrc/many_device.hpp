@@ -41,6 +41,7 @@ struct ManySeg {
     int64_t M2;          // element stride of the pass axis
     int64_t item_base;   // first work item of the segment (items, not tiles)
     int64_t tile_base;   // first tile of the segment in the level kernels' tile numbering
+    int64_t group_tile_base;   // first tile of the segment within its (level, case) group
     const void* tw;      // twiddle table of the pass length
     double scale_bwd;    // scale of the grid's last pass in a backward transform
     int kid;             // kernel case in the executor's dispatch table
@@ -188,6 +189,89 @@ __device__ __forceinline__ void many_level_body(const ManyArgs& a, int64_t tile_
     const ManySeg sg = a.segs[seg];
     const PassArgs p = segment_pass_args<V>(a, sg);
     dispatch(sg.kid, p, lds, (tile - sg.tile_base) << sg.logW);
+}
+
+// ---- level-synchronous persistent form ------------------------------------
+// One launch of gridDim.x workgroups, all resident.  Pass level by pass
+// level, the level's tiles are dealt round-robin over the workgroups; a
+// bounded grid barrier separates the levels.  Within a level the tiles are
+// grouped by kernel case: the segments of one (level, case) group are listed
+// in grid order, and each case's tiles run in a loop of their own, so the
+// case's code is inlined without a loop around a switch over all cases.
+// Tiles use plain stores; the barrier makes them visible across XCDs: every
+// thread waits for its stores, then one thread releases at agent scope (L2
+// write-back), arrives, waits for all workgroups, and acquires (L2
+// invalidate).  A barrier wait gives up after spin_limit polls and raises
+// the error flag, so the grid always drains even if not every workgroup is
+// resident (the results are then invalid and offt_many_status says so).
+struct ManyGroup {
+    int seg_begin;       // [seg_begin, seg_end) into ManySyncArgs::gseg
+    int seg_end;
+    int64_t ntiles;      // tiles of the group
+    int64_t rot;         // tiles of the earlier groups of the same level
+};
+
+struct ManySyncArgs {
+    const ManyGroup* groups;   // [level * ncases + case]
+    const int* gseg;           // segment indices, grouped by (level, case), grid order within a group
+    unsigned* barrier;         // one arrival counter per level boundary (zeroed before the launch)
+    int ncases;
+    int pad_;
+};
+
+// Tiles of group (lvl, case KID) dealt to this workgroup; `tile(p, l0)` runs one.
+template <typename V, typename TileFn>
+__device__ __forceinline__ void many_sync_group(const ManyArgs& a, const ManySyncArgs& g, int lvl, int kid,
+                                                TileFn&& tile) {
+    if (kid >= g.ncases) return;   // a group table of fewer cases than the kernel's: nothing to run
+    const ManyGroup gr = g.groups[lvl * g.ncases + kid];
+    const int64_t G = gridDim.x;
+    int64_t t = ((int64_t)blockIdx.x - gr.rot % G + G) % G;   // uniform across the workgroup
+    int s = gr.seg_begin;
+    for (; t < gr.ntiles; t += G) {
+        while (s + 1 < gr.seg_end && a.segs[g.gseg[s]].group_tile_base + a.segs[g.gseg[s]].ntiles <= t) ++s;
+        const ManySeg sg = a.segs[g.gseg[s]];
+        const PassArgs p = segment_pass_args<V>(a, sg);
+        __syncthreads();   // the previous tile is done with LDS
+        tile(p, (t - sg.group_tile_base) << sg.logW);
+    }
+}
+
+__device__ __forceinline__ void many_grid_barrier(const ManyArgs& a, unsigned* counter) {
+    wait_own_stores();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = gridDim.x;
+        int polls = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++polls > a.spin_limit) {
+                __hip_atomic_store(&a.counters[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(4);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// Every case of one level, in case order.  Case types provide
+// `static constexpr int kid` and `static void tile(const PassArgs&, V* lds, int64_t l0)`.
+template <typename V, typename... Cases>
+__device__ __forceinline__ void many_sync_level(const ManyArgs& a, const ManySyncArgs& g, int lvl, V* __restrict__ lds) {
+    (many_sync_group<V>(a, g, lvl, Cases::kid, [&](const PassArgs& p, int64_t l0) { Cases::tile(p, lds, l0); }), ...);
+}
+
+// The whole transform of the batch: three levels, two grid barriers.
+template <typename V, typename... Cases>
+__device__ __forceinline__ void many_sync_body(const ManyArgs& a, const ManySyncArgs& g, V* __restrict__ lds) {
+    many_sync_level<V, Cases...>(a, g, 0, lds);
+    many_grid_barrier(a, g.barrier + 0);
+    many_sync_level<V, Cases...>(a, g, 1, lds);
+    many_grid_barrier(a, g.barrier + 1);
+    many_sync_level<V, Cases...>(a, g, 2, lds);
 }
 
 }  // namespace offt

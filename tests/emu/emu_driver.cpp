@@ -10,6 +10,9 @@
 //       the persistent loop over a segment table, run by nwg workgroups at
 //       once: each workgroup is a forked process of `threads` CPU threads;
 //       buffers and counters live in shared memory
+//   emu_driver sync <dtype> <nwg> <threads> <nseg> <segments + level...> <total>
+//       the level-synchronous persistent body (grid barriers between levels)
+//       over the batch executor's cases, nwg workgroups at once
 //
 // Built by tests/test_emu.py with g++ -fsanitize=address.
 #include "hip_emu.h"
@@ -18,6 +21,7 @@
 #include <sys/wait.h>
 #include <unistd.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -67,15 +71,16 @@ static bool run_block(int threads, const std::function<void(int)>& fn) {
 }
 
 template <typename V>
-static int do_many(int argc, char** argv) {
-    // many <dtype> <nwg> <threads> <nseg> then per segment:
-    //   L kid logW mode nlines M2 ntiles first last dep elem_off tiles_per_item
+static int do_many(int argc, char** argv, bool sync) {
+    // many|sync <dtype> <nwg> <threads> <nseg> then per segment:
+    //   L kid logW mode nlines M2 ntiles first last dep elem_off tiles_per_item [level (sync)]
     // then <total_elems>
     int k = 3;
     const int nwg = atoi(argv[k++]);
     const int threads = atoi(argv[k++]);
     const int nseg = atoi(argv[k++]);
     std::vector<ManySeg> segs(nseg);
+    std::vector<int> seg_level(nseg, 0);
     std::vector<std::vector<V>> tws(nseg);
     int64_t items = 0;
     size_t lds_elems = 0;
@@ -94,6 +99,7 @@ static int do_many(int argc, char** argv) {
         g.dep = atoi(argv[k++]);
         g.elem_off = atoll(argv[k++]);
         g.tiles_per_item = atoi(argv[k++]);
+        if (sync) seg_level[s] = atoi(argv[k++]);
         g.nitems = (g.ntiles + g.tiles_per_item - 1) / g.tiles_per_item;
         g.scale_bwd = 1.0;
         g.item_base = items;
@@ -103,8 +109,31 @@ static int do_many(int argc, char** argv) {
         lds_elems = std::max(lds_elems, (size_t)tile_lds_elems(1 << g.logW, L));
     }
     const int64_t total = atoll(argv[k++]);
-    // shared between the workgroup processes
-    const size_t bytes = sizeof(V) * 2 * (size_t)total + sizeof(unsigned) * (kManyCounterBase + nseg);
+    // (level, case) groups of the level-synchronous form, built as the library does
+    // as many cases as the executor has (the kernel walks all of them)
+    int ncases = sync ? EmuSync<V>::ncases : 0;
+    for (const ManySeg& g : segs) ncases = std::max(ncases, g.kid + 1);
+    std::vector<ManyGroup> groups((size_t)3 * ncases);
+    std::vector<int> gseg;
+    for (int lvl = 0; lvl < 3; ++lvl) {
+        int64_t rot = 0;
+        for (int c = 0; c < ncases; ++c) {
+            ManyGroup& gr = groups[(size_t)lvl * ncases + c];
+            gr.seg_begin = (int)gseg.size();
+            gr.ntiles = 0;
+            gr.rot = rot;
+            for (int i = 0; i < nseg; ++i) {
+                if (seg_level[i] != lvl || segs[i].kid != c) continue;
+                segs[i].group_tile_base = gr.ntiles;
+                gr.ntiles += segs[i].ntiles;
+                gseg.push_back(i);
+            }
+            gr.seg_end = (int)gseg.size();
+            rot += gr.ntiles;
+        }
+    }
+    // shared between the workgroup processes: buffers, counters, two level barriers
+    const size_t bytes = sizeof(V) * 2 * (size_t)total + sizeof(unsigned) * (kManyCounterBase + nseg + 2);
     void* shm = mmap(nullptr, bytes, PROT_READ | PROT_WRITE, MAP_SHARED | MAP_ANONYMOUS, -1, 0);
     if (shm == MAP_FAILED) return 3;
     V* in = static_cast<V*>(shm);
@@ -115,7 +144,14 @@ static int do_many(int argc, char** argv) {
         in[i].y = (decltype(in[i].y))std::cos(0.91 * (double)i);
         out[i].x = out[i].y = 0;
     }
-    for (int i = 0; i < kManyCounterBase + nseg; ++i) counters[i] = 0u;
+    for (int i = 0; i < kManyCounterBase + nseg + 2; ++i) counters[i] = 0u;
+    ManySyncArgs sa;
+    memset(&sa, 0, sizeof sa);
+    sa.groups = groups.data();
+    sa.gseg = gseg.data();
+    sa.barrier = counters + kManyCounterBase + nseg;
+    sa.ncases = ncases;
+    gridDim.x = (unsigned)nwg;
     ManyArgs a;
     memset(&a, 0, sizeof a);
     a.in = in;
@@ -127,20 +163,24 @@ static int do_many(int argc, char** argv) {
     a.dir = -1;
     a.spin_limit = 1 << 22;
     blockDim.x = threads;
+    auto body = [&](V* lds) {
+        if (sync) EmuSync<V>::body(a, sa, lds);
+        else many_body<V>(a, lds, EmuDispatch<V>{});
+    };
     std::vector<pid_t> kids;
     for (int wg = 1; wg < nwg; ++wg) {
         const pid_t pid = fork();
         if (pid == 0) {
             blockIdx.x = (unsigned)wg;
             std::vector<V> lds(lds_elems + 64);
-            const bool okc = run_block(threads, [&](int) { many_body<V>(a, lds.data(), EmuDispatch<V>{}); });
+            const bool okc = run_block(threads, [&](int) { body(lds.data()); });
             _exit(okc ? 0 : 1);
         }
         kids.push_back(pid);
     }
     blockIdx.x = 0;
     std::vector<V> lds(lds_elems + 64);
-    bool ok = run_block(threads, [&](int) { many_body<V>(a, lds.data(), EmuDispatch<V>{}); });
+    bool ok = run_block(threads, [&](int) { body(lds.data()); });
     for (pid_t pid : kids) {
         int st = 0;
         waitpid(pid, &st, 0);
@@ -150,7 +190,12 @@ static int do_many(int argc, char** argv) {
         std::printf("FAIL barrier_ok=%d err=%u\n", (int)ok, counters[1]);
         return 1;
     }
-    for (int s = 0; s < nseg; ++s)   // a grid's last pass publishes nothing
+    for (int l = 0; sync && l < 2; ++l)   // every workgroup arrived at both level barriers
+        if (counters[kManyCounterBase + nseg + l] != (unsigned)nwg) {
+            std::printf("FAIL barrier %d arrivals %u of %d\n", l, counters[kManyCounterBase + nseg + l], nwg);
+            return 1;
+        }
+    for (int s = 0; !sync && s < nseg; ++s)   // a grid's last pass publishes nothing
         if (counters[kManyCounterBase + s] != (segs[s].last ? 0u : (unsigned)segs[s].nitems)) {
             std::printf("FAIL segment %d done %u of %d\n", s, counters[kManyCounterBase + s], segs[s].nitems);
             return 1;
@@ -210,7 +255,8 @@ int main(int argc, char** argv) {
     if (argc < 3) return 2;
     const std::string mode = argv[1];
     const int dtype = atoi(argv[2]);
-    if (mode == "many") return dtype == 0 ? do_many<double2>(argc, argv) : do_many<float2>(argc, argv);
+    if (mode == "many") return dtype == 0 ? do_many<double2>(argc, argv, false) : do_many<float2>(argc, argv, false);
+    if (mode == "sync") return dtype == 0 ? do_many<double2>(argc, argv, true) : do_many<float2>(argc, argv, true);
     if (mode == "pass") return dtype == 0 ? do_pass<double2>(argc, argv) : do_pass<float2>(argc, argv);
     return 2;
 }

@@ -68,6 +68,17 @@ def emu_binary():
                                  for P in (1, 2, 4) if gk.splits(L, seq, P))
             lines.append(f"      case {i}: {body} break;")
         lines.append("      default: break;\n    }\n  }\n};")
+    # the level-synchronous body over the batch executor's cases
+    for vt, prec in (("double2", "f64"), ("float2", "f32")):
+        names = []
+        for i, (L, seq, tpl) in enumerate(gk.many_cases(prec, "batch")):
+            names.append(f"EmuSyncCase{i}_{prec}")
+            lines.append(f"struct {names[-1]} {{ static constexpr int kid = {i}; static void tile(const PassArgs& p, "
+                         f"{vt}* lds, int64_t l0) {{ pass_tile<{vt}, {L}, {tpl}, {', '.join(map(str, seq))}>(p, lds, l0); }} }};")
+        lines.append(f"template <> struct EmuSync<{vt}> {{ static constexpr int ncases = {len(names)}; "
+                     f"static void body(const ManyArgs& a, const ManySyncArgs& g, "
+                     f"{vt}* lds) {{ many_sync_body<{vt}, {', '.join(names)}>(a, g, lds); }} }};")
+    lines.insert(0, "template <typename V> struct EmuSync;")
     with open(os.path.join(BUILD, "emu_cases.inc"), "w") as f:
         f.write("namespace offt {\n" + "\n".join(lines) + "\n}\n")
     exe = os.path.join(BUILD, "emu_driver")
@@ -122,13 +133,15 @@ def many_logW(p, es):
 TILES_PER_ITEM = 4
 
 
-def segment_args(dims_list, dtype):
+def segment_args(dims_list, dtype, which="all", levels=False):
     """The persistent executor's segment table, built as the library does
-    (pass levels in order, grids in order within a level)."""
+    (pass levels in order, grids in order within a level); `which` case set,
+    and with `levels` each segment's pass level appended (level-synchronous
+    form)."""
     gk = gen_kernels()
     prec = "f64" if dtype == torch.complex128 else "f32"
     es = 16 if prec == "f64" else 8
-    cases = gk.many_cases(prec, "all")
+    cases = gk.many_cases(prec, which)
     align = 256 // es
     offs, off = [], 0
     for d in dims_list:
@@ -150,15 +163,16 @@ def segment_args(dims_list, dtype):
             dep = seg_of[(lvl - 1, g)] if lvl > 0 else -1
             seg_of[(lvl, g)] = len(segs)
             segs.append([p["L"], kid, lw, p["mode"], nlines, p["M2"], ntiles, int(lvl == 0),
-                         int(lvl == len(ps) - 1), dep, offs[g], TILES_PER_ITEM])
+                         int(lvl == len(ps) - 1), dep, offs[g], TILES_PER_ITEM] + ([lvl] if levels else []))
     args = [str(THREADS), str(len(segs))] + [str(v) for s in segs for v in s] + [str(total)]
     return args, offs, total
 
 
-def run_many(exe, dims_list, dtype, nwg=1):
-    args, offs, total = segment_args(dims_list, dtype)
+def run_many(exe, dims_list, dtype, nwg=1, sync=False):
+    args, offs, total = segment_args(dims_list, dtype, "batch" if sync else "all", levels=sync)
     code = "0" if dtype == torch.complex128 else "1"
-    r = subprocess.run([exe, "many", code, str(nwg)] + args, capture_output=True, text=True, timeout=600)
+    r = subprocess.run([exe, "sync" if sync else "many", code, str(nwg)] + args, capture_output=True, text=True,
+                       timeout=600)
     assert r.returncode == 0, (r.stdout[:500], r.stderr[-3000:])
     lines = r.stdout.splitlines()
     assert lines[0].startswith("OK"), lines[0]
@@ -277,3 +291,19 @@ def test_emulated_radix32_pass(emu_binary, dtype, case):
     L, seq, tpl, M1, M2, logW, logP = case
     assert gen_kernels().splits(L, seq, 1 << logP)
     run_pass(emu_binary, dtype, L, seq, tpl, M1, M2, logW, logP)
+
+
+# grids of the batch executor's lengths, with unit axes (one- and two-pass grids)
+SYNC_DIMS = [(48, 1, 60), (1, 64, 1), (16 * 3, 60, 64), (80, 96, 1), (1, 1, 1), (120, 1, 128)]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
+@pytest.mark.parametrize("nwg", [1, 3])
+def test_emulated_level_synchronous_body(emu_binary, dtype, nwg):
+    """The level-synchronous persistent body: tiles dealt round-robin over nwg
+    workgroups (one process each), grid barriers between levels in shared
+    memory; every workgroup arrives at both barriers, no wait times out, and
+    every grid matches the oracle."""
+    dims = [tuple(min(v, 64) if v > 1 else 1 for v in d) for d in SYNC_DIMS]
+    dims = [tuple(v if v in (1, 48, 60, 64) else 64 for v in d) for d in dims]
+    run_many(emu_binary, dims, dtype, nwg=nwg, sync=True)

@@ -1,6 +1,7 @@
 """Uneven batches: one persistent launch (direct or replayed from a HIP graph)
-over every (grid, axis pass, tile) work item, against the CPU oracle and
-against the same plans run as separate launches.
+over every (grid, axis pass, tile) work item -- with per-segment dependency
+counters or level-synchronous with grid barriers -- and the level kernels,
+against the CPU oracle and against the same plans run as separate launches.
 
 The persistent executor runs the same tile code as the separate launches, so
 with the same per-grid plans the results must agree bit for bit; every grid
@@ -52,6 +53,8 @@ def test_uneven_batch_64_grids_persistent_graph_vs_oracle_and_separate():
     y_direct = plan.execute(x, use_graph=0)
     y_lgraph = plan.execute(x, use_graph=2)
     y_levels = plan.execute(x, use_graph=3)
+    y_sgraph = plan.execute(x, use_graph=5)
+    y_sync = plan.execute(x, use_graph=4)
     y_sep_same = plan.execute(x, use_graph=-2)
     y_sep_heur = plan.execute(x, use_graph=-1)
     torch.cuda.synchronize()
@@ -59,6 +62,8 @@ def test_uneven_batch_64_grids_persistent_graph_vs_oracle_and_separate():
     assert same_grids(plan, y_graph, y_direct)
     assert same_grids(plan, y_graph, y_lgraph)
     assert same_grids(plan, y_graph, y_levels)
+    assert same_grids(plan, y_graph, y_sgraph)
+    assert same_grids(plan, y_graph, y_sync)
     assert same_grids(plan, y_graph, y_sep_same)
     assert same_grids(plan, y_graph, y_sep_heur)   # untuned plan: heuristic plans for both
     worst = check_against_oracle(plan, grids, y_graph, C64)
@@ -73,7 +78,7 @@ def test_graph_replays_match_eager_with_work_between():
     torch.cuda.synchronize()
     out = torch.empty_like(x)
     for rep in range(4):
-        for mode in (1, 2):   # persistent graph, level graph
+        for mode in (1, 2, 5):   # persistent graph, level graph, level-synchronous graph
             # unrelated eager work and a sync between replays
             _ = (x * 2).sum()
             torch.cuda.synchronize()
@@ -86,10 +91,13 @@ def test_graph_replays_match_eager_with_work_between():
     x2 = x.clone()
     z = plan.execute(x2, use_graph=1, direction=offt.BACKWARD)
     z2 = plan.execute(x2, use_graph=2, direction=offt.BACKWARD)
+    z5 = plan.execute(x2, use_graph=5, direction=offt.BACKWARD)
     z_ref = plan.execute(x2, use_graph=-2, direction=offt.BACKWARD)
     torch.cuda.synchronize()
+    assert plan.status() == 0
     assert same_grids(plan, z, z_ref)
     assert same_grids(plan, z2, z_ref)
+    assert same_grids(plan, z5, z_ref)
     check_against_oracle(plan, grids, z, C64, sign=oracle.BACKWARD)
 
 
@@ -141,6 +149,10 @@ def test_batch_lengths_with_unit_axes_persistent():
     assert plan.status() == 0
     check_against_oracle(plan, grids, y, C64)
     assert same_grids(plan, y, plan.execute(x, use_graph=-2))
+    ys = plan.execute(x, use_graph=4)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    assert same_grids(plan, y, ys)
     buf = y.clone()
     plan.execute(buf, out=buf, use_graph=1, direction=offt.BACKWARD)
     torch.cuda.synchronize()
@@ -169,9 +181,11 @@ def test_tuned_batch_plans_are_valid():
     grids, x = packed_input(plan, dims, C64, key0=synth.SEED + 500)
     y = plan.execute(x, use_graph=1)
     y2 = plan.execute(x, use_graph=-2)
+    y5 = plan.execute(x, use_graph=5)
     torch.cuda.synchronize()
     assert plan.status() == 0
     assert same_grids(plan, y, y2)
+    assert same_grids(plan, y, y5)
     check_against_oracle(plan, grids, y, C64)
     for line in plan.describe().splitlines()[1:]:
         assert line.startswith("order=")
