@@ -201,6 +201,37 @@ int offt_exec_many(offt_plan_t p, const void* in, void* out, int direction, int 
  * the launch could be resident, e.g. while other work holds the device). */
 int offt_many_status(offt_plan_t p);
 
+/* ---- byte and volume accounting (host only, no device) --------------------
+ * Per plan: HBM bytes of one axis pass.  Per decomposition: the row-wise
+ * block distribution of Duy & Ozaki, Sec. 2 (Eq. 2 and the index ranges
+ * derived from it) and the elements each transpose of the order sequence
+ * abc -> cab -> cba (Sec. 2, Fig. 1b) moves between processes, the volume of
+ * communication of Sec. 4.1.  Results are element counts or bytes (>= 0), or
+ * a negative error code (also in offt_last_error()). */
+
+/* Bytes one axis pass of a plan moves to and from HBM: every element of the
+ * batch read once and written once, 2 * batch * Na * Nb * Nc * (16 | 8).
+ * Twiddle tables are not counted.  Errors: INVALID_ARG, UNSUPPORTED_SIZE. */
+int64_t offt_pass_bytes(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch);
+
+/* f(N1, N2, N3, Np, id) of Eq. 2: first row-major linear index of process
+ * id's block (0 <= id <= Np; id = Np gives N1 N2 N3).  Whole N2 x N3 planes
+ * when Np <= N1, whole N3-lines when N1 < Np <= N1 N2.  Errors: INVALID_ARG
+ * (a length < 1 or > 2^20, Np outside [1, N1 N2], id outside [0, Np]). */
+int64_t offt_decomp_start(int64_t n1, int64_t n2, int64_t n3, int64_t np, int64_t id);
+
+/* Elements process src holds before transpose `step` and process dst holds
+ * after it, for an n1 x n2 x n3 grid (a, b, c) over np processes; step 0:
+ * abc -> cab (each order split by Eq. 2 over its own leading lengths), step
+ * 1: cab -> cba.  src == dst counts what stays local.  Errors: INVALID_ARG
+ * (np above what Eq. 2 covers for either order, src or dst outside [0, np)). */
+int64_t offt_transpose_count(int64_t n1, int64_t n2, int64_t n3, int64_t np, int step, int64_t src,
+                             int64_t dst);
+
+/* Elements that leave their process in transpose `step` (the sum of
+ * offt_transpose_count over src != dst).  Errors as offt_transpose_count. */
+int64_t offt_transpose_volume(int64_t n1, int64_t n2, int64_t n3, int64_t np, int step);
+
 /* ---- plan selection internals: candidates, features, timings -------------
  * The tuners choose among a deterministic list of candidate plans per grid
  * shape (the heuristic plan first; then other radix sequences and tile widths

@@ -19,8 +19,8 @@ from ._lib import (BACKWARD, C2C_F32, C2C_F64, FORWARD, MANY_LEVELS, MANY_LEVELS
                    MAX_AXIS, OfftError,
                    TUNE_EXHAUSTIVE, TUNE_FORCED, TUNE_LEARNED, TUNE_NONE)
 
-__all__ = ["Plan", "ManyPlan", "OfftError", "twiddles", "default_plan_string", "FORWARD", "BACKWARD",
-           "MAX_AXIS"]
+__all__ = ["Plan", "ManyPlan", "OfftError", "twiddles", "default_plan_string", "pass_bytes", "decomp_start",
+           "transpose_count", "transpose_volume", "FORWARD", "BACKWARD", "MAX_AXIS"]
 
 _TUNE = {"none": TUNE_NONE, "exhaustive": TUNE_EXHAUSTIVE, "learned": TUNE_LEARNED,
          "forced": TUNE_FORCED}
@@ -248,3 +248,26 @@ def twiddles(n: int, dtype=torch.complex128):
     out = np.empty(n, dtype=np.complex128 if code == C2C_F64 else np.complex64)
     _lib.check(_lib.load().offt_twiddles(n, code, out.ctypes.data_as(ctypes.c_void_p)), "twiddles")
     return out
+
+
+# ---- byte and volume accounting (host only) ---------------------------------
+def pass_bytes(shape, dtype=torch.complex128, batch: int = 1) -> int:
+    """HBM bytes one axis pass moves (every element read and written once)."""
+    a, b, c = shape
+    return _lib.check(_lib.load().offt_pass_bytes(a, b, c, _dtype_code(dtype), batch), "pass_bytes")
+
+
+def decomp_start(n1: int, n2: int, n3: int, np_: int, myid: int) -> int:
+    """First linear index of process myid's block (Sec. 2, Eq. 2)."""
+    return _lib.check(_lib.load().offt_decomp_start(n1, n2, n3, np_, myid), "decomp_start")
+
+
+def transpose_count(n1: int, n2: int, n3: int, np_: int, step: int, src: int, dst: int) -> int:
+    """Elements src holds before transpose `step` (0: abc -> cab, 1: cab -> cba)
+    and dst holds after it."""
+    return _lib.check(_lib.load().offt_transpose_count(n1, n2, n3, np_, step, src, dst), "transpose_count")
+
+
+def transpose_volume(n1: int, n2: int, n3: int, np_: int, step: int) -> int:
+    """Elements that leave their process in transpose `step`."""
+    return _lib.check(_lib.load().offt_transpose_volume(n1, n2, n3, np_, step), "transpose_volume")

@@ -98,6 +98,10 @@ SIGNATURES = {
     "offt_many_offset": (_i64, [_vp, _ci]),
     "offt_exec_many": (_ci, [_vp, _vp, _vp, _ci, _ci, _vp]),
     "offt_many_status": (_ci, [_vp]),
+    "offt_pass_bytes": (_i64, [_i64, _i64, _i64, _ci, _i64]),
+    "offt_decomp_start": (_i64, [_i64, _i64, _i64, _i64, _i64]),
+    "offt_transpose_count": (_i64, [_i64, _i64, _i64, _i64, _ci, _i64, _i64]),
+    "offt_transpose_volume": (_i64, [_i64, _i64, _i64, _i64, _ci]),
 }
 
 _lib = None
