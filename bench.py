@@ -211,6 +211,49 @@ def time_batch(steps: int, warmup: int, check: bool, count: int = 64):
     return out
 
 
+def time_small(steps: int, warmup: int, check: bool, n: int = 32):
+    """Config 1: one n^3 complex128 grid, forward then inverse with 1/N,
+    latency per round trip with the pass kernels launched directly and
+    replayed from a HIP graph (use_graph)."""
+    import numpy as np
+    import torch
+
+    import paper_1501_07350_amd as offt
+    import synth
+
+    shape = (n, n, n)
+    x = synth.complex_grid(shape, torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    h = int(torch.cuda.current_stream().cuda_stream)
+    res = {"workload": f"{n}x{n}x{n} complex128, forward then inverse with 1/N", "us_per_round_trip": {}}
+    for name, use_graph in (("direct", False), ("graph", True)):
+        plan = offt.Plan(shape, dtype=torch.complex128, normalize_inverse=True, use_graph=use_graph)
+        for _ in range(warmup):
+            plan.exec_ptr(offt.FORWARD, x.data_ptr(), y.data_ptr(), h)
+            plan.exec_ptr(offt.BACKWARD, y.data_ptr(), z.data_ptr(), h)
+        reps = max(steps, 100)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            plan.exec_ptr(offt.FORWARD, x.data_ptr(), y.data_ptr(), h)
+            plan.exec_ptr(offt.BACKWARD, y.data_ptr(), z.data_ptr(), h)
+        e1.record()
+        torch.cuda.synchronize()
+        res["us_per_round_trip"][name] = round(1e3 * e0.elapsed_time(e1) / reps, 2)
+        res["plan"] = plan.describe()
+        plan.close()
+    if check:
+        import oracle
+        xh = x.cpu().numpy()
+        res["rel_l2_forward_vs_per_axis_dft"] = oracle.rel_l2(y.cpu().numpy(), oracle.dft3_axes(xh))
+        res["rel_l2_round_trip"] = oracle.rel_l2(z.cpu().numpy(), xh)
+        res["tolerance"] = oracle.tolerance(x.numel(), False)
+    return res
+
+
 def roofline(res, tag):
     i = max(range(len(res["pass_ms"])), key=lambda j: res["pass_ms"][j])
     dur_ms = res["pass_ms"][i]
@@ -475,6 +518,7 @@ def main():
             out[key] = {"rel_l2_sampled_lines": r["check_rel_l2_sampled_lines"],
                         "tolerance": r["check_tolerance"]}
     if not args.no_batch:
+        out["small"] = time_small(args.steps, args.warmup, not args.no_check)
         out["batch"] = time_batch(args.steps, args.warmup, not args.no_check)
     if args.calibrate:
         calibrate_copy()

@@ -82,6 +82,12 @@ typedef struct offt_opts {
     void* stream;             /* hipStream_t for tuning runs (NULL = null stream) */
     int tune_inplace;         /* 1: time whole transforms in place (in == out) when tuning;
                                  0 (default): out of place, with a second temporary buffer */
+    int use_graph;            /* 1: offt_exec_fwd/bwd replay a HIP graph of the plan's pass
+                                 kernels, one per direction, captured (on a private stream
+                                 made at plan time) by that direction's first exec and
+                                 captured again, updating the instantiated graph in place,
+                                 when an exec brings other buffers; 0 (default): the kernels
+                                 are launched directly */
 } offt_opts;
 
 /* Fill *o with the defaults listed above. */

@@ -40,7 +40,7 @@ def _stream_handle(stream=None) -> int:
 
 
 def _make_opts(tune="none", reps=2, normalize_inverse=False, forced_plan=None, cache_path=None,
-               weights_path=None, stream=None, tune_inplace=False):
+               weights_path=None, stream=None, tune_inplace=False, use_graph=False):
     o = _lib.default_opts()
     if tune not in _TUNE:
         raise ValueError(f"tune must be one of {sorted(_TUNE)}")
@@ -56,16 +56,19 @@ def _make_opts(tune="none", reps=2, normalize_inverse=False, forced_plan=None, c
             setattr(o, field, b)
     o.stream = ctypes.c_void_p(stream) if stream else None
     o.tune_inplace = 1 if tune_inplace else 0
+    o.use_graph = 1 if use_graph else 0
     return o, keep
 
 
 class Plan:
-    """Plan for `batch` grids of `shape` = (Na, Nb, Nc)."""
+    """Plan for `batch` grids of `shape` = (Na, Nb, Nc).  use_graph: forward
+    and backward replay a HIP graph of the pass kernels (captured by the first
+    call, updated when buffers or direction change)."""
 
     def __init__(self, shape, dtype=torch.complex128, batch: int = 1, tune: str = "none",
                  normalize_inverse: bool = False, forced_plan: str | None = None,
                  cache_path: str | None = None, weights_path: str | None = None, reps: int = 2,
-                 tune_inplace: bool = False):
+                 tune_inplace: bool = False, use_graph: bool = False):
         lib = _lib.load()
         if len(shape) != 3:
             raise ValueError("shape must be (Na, Nb, Nc)")
@@ -76,7 +79,7 @@ class Plan:
         code = _dtype_code(dtype)
         stream = _stream_handle() if torch.cuda.is_available() else None
         opts, keep = _make_opts(tune, reps, normalize_inverse, forced_plan, cache_path, weights_path,
-                                stream, tune_inplace)
+                                stream, tune_inplace, use_graph)
         h = lib.offt_plan_ex(self.shape[0], self.shape[1], self.shape[2], code, self.batch,
                              ctypes.byref(opts))
         del keep

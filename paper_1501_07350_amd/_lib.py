@@ -53,6 +53,7 @@ class Opts(ctypes.Structure):
         ("weights_path", ctypes.c_char_p),
         ("stream", ctypes.c_void_p),
         ("tune_inplace", ctypes.c_int),
+        ("use_graph", ctypes.c_int),
     ]
 
 

@@ -108,6 +108,11 @@ namespace offt {
 void free_plan(offt_plan_s* p) {
     if (!p) return;
     release_many(p);
+    for (int d = 0; d < 2; ++d) {
+        if (p->gexec[d]) (void)hipGraphExecDestroy(p->gexec[d]);
+        if (p->graph[d]) (void)hipGraphDestroy(p->graph[d]);
+    }
+    if (p->cap) (void)hipStreamDestroy(p->cap);
     for (void* d : p->allocs) (void)hipFree(d);
     delete p;
 }
@@ -128,6 +133,7 @@ void offt_opts_default(offt_opts* o) {
     o->weights_path = nullptr;
     o->stream = nullptr;
     o->tune_inplace = 0;
+    o->use_graph = 0;
 }
 
 int offt_last_error(void) { return g_last_error; }
@@ -160,7 +166,8 @@ offt_plan_t offt_plan_ex(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t 
         rc = OFFT_ERR_INVALID_ARG;
     if (rc == OFFT_SUCCESS && opts.tune == OFFT_TUNE_FORCED && !opts.forced_plan)
         rc = OFFT_ERR_INVALID_ARG;
-    if (rc == OFFT_SUCCESS && opts.reps < 1) rc = OFFT_ERR_INVALID_ARG;
+    if (rc == OFFT_SUCCESS && (opts.reps < 1 || (opts.use_graph != 0 && opts.use_graph != 1)))
+        rc = OFFT_ERR_INVALID_ARG;
     if (rc != OFFT_SUCCESS) { set_error(rc); return nullptr; }
     const int64_t dims[3] = {Na, Nb, Nc};
     PlanChoice forced;
@@ -188,15 +195,76 @@ offt_plan_t offt_plan_ex(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t 
     }
     rc = set_choice(p, choice, s);
     if (rc == OFFT_SUCCESS && hipStreamSynchronize(s) != hipSuccess) rc = OFFT_ERR_HIP;
+    // the capture stream of use_graph (default priority, non-blocking)
+    p->use_graph = opts.use_graph;
+    if (rc == OFFT_SUCCESS && p->use_graph && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        p->cap = nullptr;
+        rc = OFFT_ERR_HIP;
+    }
     if (rc != OFFT_SUCCESS) { free_plan(p); set_error(rc); return nullptr; }
     set_error(OFFT_SUCCESS);
     return p;
 }
 
+// use_graph: capture the passes for (in, out, dir) on the plan's private
+// stream.  Each direction has its own instantiated graph: the first capture
+// is instantiated, later ones (other buffers) update it in place
+// (re-instantiated only if the update is refused).  The graphs hold only the
+// pass kernels.
+static int capture_passes(offt_plan_s* p, const void* in, void* out, int dir) {
+    const int d = dir > 0 ? 1 : 0;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipGetLastError();
+        return OFFT_ERR_HIP;
+    }
+    const int rc = exec_passes(p, p->passes, p->npass, in, out, dir, p->cap);
+    const hipError_t e = hipStreamEndCapture(p->cap, &g);
+    if (rc != OFFT_SUCCESS || e != hipSuccess || !g) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        return OFFT_ERR_HIP;
+    }
+    bool updated = false;
+    if (p->gexec[d]) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res;
+        updated = hipGraphExecUpdate(p->gexec[d], g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+        if (!updated) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(p->gexec[d]);
+            p->gexec[d] = nullptr;
+        }
+    }
+    if (!updated && hipGraphInstantiate(&p->gexec[d], g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        p->gexec[d] = nullptr;
+        (void)hipGraphDestroy(g);
+        return OFFT_ERR_HIP;
+    }
+    if (p->graph[d]) (void)hipGraphDestroy(p->graph[d]);
+    p->graph[d] = g;
+    p->g_in[d] = in;
+    p->g_out[d] = out;
+    return OFFT_SUCCESS;
+}
+
 static int exec_checked(offt_plan_t p, const void* in, void* out, void* stream, int dir) {
     if (!p || !in || !out) { set_error(OFFT_ERR_INVALID_ARG); return OFFT_ERR_INVALID_ARG; }
     if (p->kind != 1) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
-    const int rc = exec_passes(p, p->passes, p->npass, in, out, dir, static_cast<hipStream_t>(stream));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = OFFT_SUCCESS;
+    if (p->use_graph && p->npass > 0) {
+        const int d = dir > 0 ? 1 : 0;
+        if (!p->gexec[d] || in != p->g_in[d] || out != p->g_out[d]) rc = capture_passes(p, in, out, dir);
+        if (rc == OFFT_SUCCESS && hipGraphLaunch(p->gexec[d], s) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = OFFT_ERR_HIP;
+        }
+    } else {
+        rc = exec_passes(p, p->passes, p->npass, in, out, dir, s);
+    }
     set_error(rc);
     return rc;
 }

@@ -28,6 +28,14 @@ struct offt_plan_s {
     std::vector<size_t> alloc_bytes;
     std::string tune_log;         // how the plan was chosen (for describe)
     offt::ManyState* many = nullptr;
+    // use_graph: the passes replayed from HIP graphs captured on `cap`, one
+    // per direction ([0] forward, [1] backward)
+    int use_graph = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    const void* g_in[2] = {nullptr, nullptr};   // buffers each instantiated graph holds
+    void* g_out[2] = {nullptr, nullptr};
 
     int64_t workspace_bytes() const;
 };

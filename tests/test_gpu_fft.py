@@ -330,6 +330,43 @@ def test_bitwise_deterministic_and_stream_ordered():
     assert torch.equal(y1, y3)
 
 
+@pytest.mark.parametrize("shape,dtype", [((32, 32, 32), C128), ((48, 60, 80), C64), ((6, 512, 10), C64),
+                                         ((1, 1, 1), C128)], ids=["32cubed-c128", "48x60x80-c64", "6x512x10-c64",
+                                                                  "1x1x1"])
+def test_graph_replay_matches_direct_launches(shape, dtype):
+    """use_graph: the captured pass kernels give the direct launches' results
+    bit for bit on every replay (eager work and a synchronisation between
+    replays), after a change of buffers and direction, and in place."""
+    x = gen(shape, dtype, synth.SEED + 41)
+    direct = offt.Plan(shape, dtype=dtype, normalize_inverse=True)
+    graph = offt.Plan(shape, dtype=dtype, normalize_inverse=True, use_graph=True)
+    assert graph.describe() == direct.describe()
+    ref_f = direct.forward(x)
+    ref_b = direct.backward(ref_f)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(host(ref_f), oracle.fft3(host(x))) <= tol(x.numel(), dtype)
+    out = torch.empty_like(x)
+    for rep in range(3):
+        _ = (x * 2).sum()
+        torch.cuda.synchronize()
+        out.zero_()
+        graph.forward(x, out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref_f), f"replay {rep}"
+    y = graph.backward(ref_f.clone())          # other buffers, other direction: graph updated
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref_b)
+    z = x.clone()
+    graph.forward(z, out=z)                    # in place
+    torch.cuda.synchronize()
+    assert torch.equal(z, ref_f)
+    graph.forward(x, out=out)                  # back to the first buffers
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref_f)
+    direct.close()
+    graph.close()
+
+
 def test_normalized_inverse_and_linearity():
     shape = (20, 24, 30)
     for dtype in (C128, C64):
