@@ -290,6 +290,84 @@ def cpu_baseline(n: int):
                       f"binary64, mean {dt:.2f} s each"}
 
 
+def configs_report(steps: int, warmup: int):
+    """Every workload of the measurement plan besides the 512^3 headline:
+    config 1 (32^3 round trip), config 2 (256^3 complex128, forward error vs
+    the full oracle and round-trip error), config 3's 1024^3 complex64, and
+    the CPU oracle timed on this host (O1 brute force, O2 per-axis DFT, O3
+    recursive FFT; all cores and one thread)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1501_07350_amd as offt
+    import synth
+
+    cpu = "unknown"
+    try:
+        cpu = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    rep = {"cpu_model": cpu, "cores": oracle.max_threads()}
+    rep["config1"] = time_small(steps, warmup, True)
+
+    def round_trip(n, dtype, check_full):
+        shape = (n, n, n)
+        x = synth.complex_grid(shape, dtype, device="cuda")
+        plan = offt.Plan(shape, dtype=dtype, normalize_inverse=True, tune="exhaustive")
+        y = plan.forward(x)
+        z = plan.backward(y)
+        torch.cuda.synchronize()
+        d = {"plan": plan.describe(),
+             "rel_l2_round_trip": float(((z - x).abs().double().pow(2).sum() / x.abs().double().pow(2).sum()).sqrt()),
+             "tolerance": oracle.tolerance(x.numel(), dtype == torch.complex64)}
+        if check_full:
+            d["rel_l2_forward_vs_O3"] = oracle.rel_l2(y.cpu().numpy(), oracle.fft3(x.cpu().numpy()))
+        plan.close()
+        del x, y, z
+        torch.cuda.empty_cache()
+        return d
+
+    r2 = time_transform(256, torch.complex128, steps, warmup, False, "exhaustive")
+    rep["config2"] = {"workload": "256x256x256 complex128", "ms": round(r2["ms"], 4),
+                      "gflops": round(r2["gflops"], 1), "eff_gbs": round(r2["eff_gbs"], 1),
+                      "pass_ms": [round(v, 4) for v in r2["pass_ms"]], **round_trip(256, torch.complex128, True)}
+    r3 = time_transform(1024, torch.complex64, steps, warmup, True, "exhaustive")
+    rep["config3_1024"] = {"workload": "1024x1024x1024 complex64", "ms": round(r3["ms"], 4),
+                           "gflops": round(r3["gflops"], 1), "eff_gbs": round(r3["eff_gbs"], 1),
+                           "frac_of_peak_effective": round(r3["eff_gbs"] / PEAK_HBM_GBS, 4),
+                           "pass_ms": [round(v, 4) for v in r3["pass_ms"]], "plan": r3["plan"],
+                           "rel_l2_sampled_lines_vs_definition": r3["check_rel_l2_sampled_lines"],
+                           **{k: v for k, v in round_trip(1024, torch.complex64, False).items() if k != "plan"}}
+
+    def cpu_time(fn, n, threads, reps):
+        x = synth.complex_grid((n, n, n), torch.complex128).numpy()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn(x, nthreads=threads)
+            ts.append(time.perf_counter() - t0)
+        N = x.size
+        dt = sum(ts) / len(ts)
+        return {"seconds": round(dt, 4), "gflops": round(5.0 * N * math.log2(N) / (dt * 1e9), 3),
+                "threads": threads or oracle.max_threads(), "runs": reps}
+
+    table = {}
+    for name, fn, n, threads, reps in (("O1_brute_32", oracle.dft3_brute, 32, 0, 1),
+                                       ("O2_axes_32", oracle.dft3_axes, 32, 0, 3),
+                                       ("O2_axes_256", oracle.dft3_axes, 256, 0, 1),
+                                       ("O3_fft_32", oracle.fft3, 32, 0, 10),
+                                       ("O3_fft_256", oracle.fft3, 256, 0, 3),
+                                       ("O3_fft_512", oracle.fft3, 512, 0, 3),
+                                       ("O2_axes_32_1thread", oracle.dft3_axes, 32, 1, 3),
+                                       ("O3_fft_32_1thread", oracle.fft3, 32, 1, 10),
+                                       ("O3_fft_256_1thread", oracle.fft3, 256, 1, 1)):
+        table[name] = cpu_time(fn, n, threads, reps)
+        print(f"cpu {name}: {table[name]}", file=sys.stderr, flush=True)
+    rep["cpu_oracle"] = table
+    return rep
+
+
 # ---------------------------------------------------------------- profiling ----
 # rocprofv3 runs of this script (their commands head each summary under profiles/) are reduced to
 # short text summaries and to profiles/pmc_traffic.json with the modes below.
@@ -448,6 +526,8 @@ def main():
                     help="reduce a rocprofv3 --stats output dir (LOG: the profiled run's stdout)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "LOG"),
                     help="reduce two rocprofv3 --pmc output dirs to profiles/pmc_traffic.json")
+    ap.add_argument("--configs", action="store_true",
+                    help="report configs 1, 2 and 1024^3 of config 3, and the CPU oracle table, instead")
     ap.add_argument("--command", default="", help="profiling command recorded in the summary")
     ap.add_argument("--out", help="summary text file")
     args = ap.parse_args()
@@ -471,6 +551,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.configs:
+        print(json.dumps(configs_report(args.steps, args.warmup)), flush=True)
+        return
     n = args.n
     # plans tuned at init (excluded from the timing, as the paper excludes its
     # initialization phase with auto-tuning); the heuristic plan beside them
