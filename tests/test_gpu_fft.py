@@ -272,6 +272,52 @@ def test_exchange_parts_rejected_for_contiguous_axes():
         offt.Plan(shape, dtype=C128, tune="forced", forced_plan="order=cba;a=4/16;b=4/16;c=16x16x2/1/p2")
 
 
+@pytest.mark.parametrize("shape,dtype", [((32, 32, 32), C128), ((48, 60, 80), C64)],
+                         ids=["32cubed-c128", "48x60x80-c64"])
+def test_tuner_candidates_choice_and_cache(shape, dtype, tmp_path):
+    """Every candidate plan the tuners choose among meets the oracle; the
+    exhaustive choice meets it; the plan cache replays the stored choice (the
+    latest valid entry of the grid's key wins); offt_tune_table times every
+    candidate."""
+    from paper_1501_07350_amd import selector
+    code = 0 if dtype == C128 else 1
+    x = gen(shape, dtype, synth.SEED + 57)
+    ref = oracle.fft3(host(x))
+    plans, _ = selector.candidates(shape, 1, code)
+    assert len(plans) == len(set(plans)) >= 6
+    for ps in plans:
+        p = offt.Plan(shape, dtype=dtype, tune="forced", forced_plan=ps)
+        assert p.describe() == ps
+        y = p.forward(x)
+        torch.cuda.synchronize()
+        assert oracle.rel_l2(host(y), ref) <= tol(x.numel(), dtype), ps
+        p.close()
+    cache = str(tmp_path / "plans.txt")
+    tuned = offt.Plan(shape, dtype=dtype, tune="exhaustive", cache_path=cache)
+    y = tuned.forward(x)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(host(y), ref) <= tol(x.numel(), dtype)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].split("\t")[1] == tuned.describe() and float(lines[0].split("\t")[2]) > 0
+    again = offt.Plan(shape, dtype=dtype, tune="exhaustive", cache_path=cache)
+    assert again.describe() == tuned.describe()
+    # a later entry for the same key (another candidate) is the one replayed
+    other = next(ps for ps in plans if ps != tuned.describe())
+    with open(cache, "a") as f:
+        f.write(lines[0].split("\t")[0] + "\t" + other + "\t1.0\n")
+    assert offt.Plan(shape, dtype=dtype, tune="exhaustive", cache_path=cache).describe() == other
+    # timings of the candidate list, as the selector's data collection takes them
+    import ctypes
+    from paper_1501_07350_amd import _lib
+    buf = torch.zeros(x.numel() * 2, dtype=torch.float64 if dtype == C128 else torch.float32, device="cuda")
+    times = np.zeros(len(plans), dtype=np.float32)
+    n = _lib.check(_lib.load().offt_tune_table(shape[0], shape[1], shape[2], code, 1, 2,
+                                               ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                                               ctypes.c_void_p(int(torch.cuda.current_stream().cuda_stream)),
+                                               times.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), len(plans)))
+    assert n == len(plans) and np.all(np.isfinite(times)) and np.all(times > 0)
+
+
 # ------------------------------------------------------------- twiddles ----
 def roots_extended(n):
     """exp(-2 pi i m / n) in x87 extended precision (independent of both the
