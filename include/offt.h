@@ -257,7 +257,8 @@ int offt_candidates(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch
 /* Times every candidate plan of a grid as the exhaustive tuner does
  * (1 warm-up + reps timed forward transforms, minimum, HIP events on
  * `stream`), in place on the caller's device buffer `buf` of at least
- * batch*Na*Nb*Nc elements (its contents are destroyed).  times_ms[i] is
+ * batch*Na*Nb*Nc elements, which is filled with uniform random values before
+ * each candidate (its contents are destroyed).  times_ms[i] is
  * candidate i's time for i < min(n, max).  Returns n.  Synchronises the
  * stream.  Errors: INVALID_ARG, UNSUPPORTED_SIZE, NO_DEVICE, HIP. */
 int offt_tune_table(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch, int reps, void* buf,

@@ -93,6 +93,9 @@ bool tile_fits(const KernelEntry* k, int logW, int dtype);
 int fit_logW(const KernelEntry* k, int logW, int dtype);
 
 hipError_t launch_twiddles(void* out, int64_t n, int dtype, hipStream_t s);
+// Fills nelem complex elements of `dtype` with values uniform in [-1, 1)
+// (tuning data; `key` selects the stream).
+hipError_t launch_fill_uniform(void* out, int64_t nelem, int dtype, uint64_t key, hipStream_t s);
 hipError_t launch_pass(const PassPlan& p, const void* in, void* out, int conj_in, int conj_out,
                        double scale, hipStream_t s);
 

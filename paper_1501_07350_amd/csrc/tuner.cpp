@@ -8,7 +8,9 @@
 //
 // Protocol: 1 warm-up + `reps` timed executions per candidate (hipEvents on the
 // tuning stream), score = minimum; ties go to the earlier candidate (the
-// heuristic's choices come first).
+// heuristic's choices come first).  The data is refilled with uniform random
+// values before each candidate (timings on all-zero buffers are not
+// representative of real data on this device).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -83,6 +85,10 @@ int time_choice(offt_plan_s* p, const PlanChoice& c, void* src, void* dst, hipSt
         if (!passes[i].k) return OFFT_ERR_UNSUPPORTED_SIZE;
     int rc = attach_twiddles(p, passes, n, s);
     if (rc != OFFT_SUCCESS) return rc;
+    // fresh random data per candidate: unnormalised transforms repeated in
+    // place would otherwise grow the values towards overflow
+    if (launch_fill_uniform(src, p->dims[0] * p->dims[1] * p->dims[2] * p->batch, p->dtype, 1501, s) != hipSuccess)
+        return OFFT_ERR_HIP;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return OFFT_ERR_HIP;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OFFT_ERR_HIP; }
@@ -112,6 +118,8 @@ static int time_pass(offt_plan_s* p, const PlanChoice& c, int axis, void* buf, h
     if (i == n || !passes[i].k) return OFFT_ERR_UNSUPPORTED_SIZE;
     int rc = attach_twiddles(p, &passes[i], 1, s);
     if (rc != OFFT_SUCCESS) return rc;
+    if (launch_fill_uniform(buf, p->dims[0] * p->dims[1] * p->dims[2] * p->batch, p->dtype, 1502, s) != hipSuccess)
+        return OFFT_ERR_HIP;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return OFFT_ERR_HIP;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OFFT_ERR_HIP; }
@@ -153,8 +161,8 @@ static int exhaustive(offt_plan_s* p, const offt_opts& o, PlanChoice* choice) {
         (void)hipFree(buf);
         return OFFT_ERR_OUT_OF_MEMORY;
     }
-    int rc = hipMemsetAsync(buf, 0, bytes, s) == hipSuccess ? OFFT_SUCCESS : OFFT_ERR_HIP;
-    if (rc == OFFT_SUCCESS && src != buf && hipMemsetAsync(src, 0, bytes, s) != hipSuccess) rc = OFFT_ERR_HIP;
+    // the timed buffers are filled with random values before every candidate
+    int rc = OFFT_SUCCESS;
     PlanChoice best = default_choice(p->dtype, p->dims);
     int timed = 0;
     for (int ax = 0; ax < 3 && rc == OFFT_SUCCESS; ++ax) {

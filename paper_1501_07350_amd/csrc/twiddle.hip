@@ -7,6 +7,8 @@
 // the complementary angle otherwise, so the argument of sinpi/cospi never
 // exceeds 1/4; then (cos, sin) is rotated by q quarter turns.  Values at the
 // quarter points (r = 0) are exactly 1, -i, -1, +i.
+#include <algorithm>
+
 #include "offt_internal.h"
 
 namespace offt {
@@ -54,6 +56,35 @@ hipError_t launch_twiddles(void* out, int64_t n, int dtype, hipStream_t s) {
     else
         hipLaunchKernelGGL(twiddle_kernel<float2>, dim3(blocks), dim3(threads), 0, s,
                            static_cast<float2*>(out), n);
+    return hipGetLastError();
+}
+
+// Tuning data: n reals (two per complex element) uniform in [-1, 1) from a
+// SplitMix64-style hash of (index, key).  Timings on all-zero buffers are not
+// representative: on this device's HBM a copy of zeros moves far more bytes
+// per second than a copy of random values.
+template <typename S>
+__global__ void fill_uniform_kernel(S* __restrict__ out, int64_t n, uint64_t key) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t z = key + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        out[i] = (S)((double)(z >> 11) * 0x1.0p-52 - 1.0);
+    }
+}
+
+hipError_t launch_fill_uniform(void* out, int64_t nelem, int dtype, uint64_t key, hipStream_t s) {
+    const int threads = 256;
+    const int64_t n = 2 * nelem;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + threads - 1) / threads, 8192);
+    if (n <= 0) return hipSuccess;
+    if (dtype == 0)
+        hipLaunchKernelGGL(fill_uniform_kernel<double>, dim3(blocks), dim3(threads), 0, s,
+                           static_cast<double*>(out), n, key);
+    else
+        hipLaunchKernelGGL(fill_uniform_kernel<float>, dim3(blocks), dim3(threads), 0, s,
+                           static_cast<float*>(out), n, key);
     return hipGetLastError();
 }
 

@@ -11,7 +11,9 @@ on the tile code, the barrier structure and the bookkeeping.
 """
 import importlib.util
 import os
+import shutil
 import subprocess
+import tempfile
 
 import numpy as np
 import pytest
@@ -47,8 +49,11 @@ def plain_cases(gk, prec):
 
 @pytest.fixture(scope="module")
 def emu_binary():
+    # one build folder per test process, so that parallel workers never run a
+    # driver another worker is still writing
     gk = gen_kernels()
     os.makedirs(BUILD, exist_ok=True)
+    build = tempfile.mkdtemp(prefix=f"pid{os.getpid()}_", dir=BUILD)
     lines = ["template <typename V> struct EmuDispatch;"]
     for vt, prec in (("double2", "f64"), ("float2", "f32")):
         lines.append(f"template <> struct EmuDispatch<{vt}> {{")
@@ -79,14 +84,15 @@ def emu_binary():
                      f"static void body(const ManyArgs& a, const ManySyncArgs& g, "
                      f"{vt}* lds) {{ many_sync_body<{vt}, {', '.join(names)}>(a, g, lds); }} }};")
     lines.insert(0, "template <typename V> struct EmuSync;")
-    with open(os.path.join(BUILD, "emu_cases.inc"), "w") as f:
+    with open(os.path.join(build, "emu_cases.inc"), "w") as f:
         f.write("namespace offt {\n" + "\n".join(lines) + "\n}\n")
-    exe = os.path.join(BUILD, "emu_driver")
+    exe = os.path.join(build, "emu_driver")
     cmd = ["g++", "-std=c++17", "-O1", "-g", "-pthread", "-fsanitize=address,undefined",
-           "-fno-sanitize-recover=undefined", "-I", EMU, "-I", BUILD, "-I", CSRC,
+           "-fno-sanitize-recover=undefined", "-I", EMU, "-I", build, "-I", CSRC,
            os.path.join(EMU, "emu_driver.cpp"), "-o", exe]
     subprocess.run(cmd, check=True)
-    return exe
+    yield exe
+    shutil.rmtree(build, ignore_errors=True)
 
 
 def lds_idx(j):
