@@ -88,7 +88,30 @@ typedef struct offt_opts {
                                  captured again, updating the instantiated graph in place,
                                  when an exec brings other buffers; 0 (default): the kernels
                                  are launched directly */
+    int layout;               /* OFFT_LAYOUT_* (default NATURAL), see below */
 } offt_opts;
+
+/* Order of the transformed grids (offt_opts.layout).
+ *   NATURAL   forward output and backward input in the input's order,
+ *             Na x Nb x Nc with c fastest.
+ *   REVERSED  forward output and backward input in cba order: each grid is
+ *             Nc x Nb x Na with a fastest, Y[c][b][a] = X[a][b][c] -- the
+ *             distribution the paper's transform finishes in (Sec. 2, the
+ *             transpose order abc -> cab -> cba; Sec. 3.1.1, the output
+ *             index set differs from the input's).  Forward input and
+ *             backward output stay natural.  One pass of each direction
+ *             transposes on the fly (it reads the lines of its axis in one
+ *             order and writes them in the other), so the reversal costs no
+ *             pass of its own.  The plan owns a workspace of one batch of
+ *             grids (offt_workspace_bytes) that the passes route through;
+ *             in == out stays allowed.  Plan strings of such plans read
+ *             "<forward>|<backward>", the backward plan naming the axes of
+ *             its cba input (its a is the grid's c), each with ";rev=a" or
+ *             ";rev=c" for the axis whose pass transposes.  With at most one
+ *             axis longer than 1 both orders are the same memory and the
+ *             plan is the natural one. */
+#define OFFT_LAYOUT_NATURAL 0
+#define OFFT_LAYOUT_REVERSED 1
 
 /* Fill *o with the defaults listed above. */
 void offt_opts_default(offt_opts* o);
@@ -125,7 +148,9 @@ int offt_plan_passes(offt_plan_t p);
  * (direction = OFFT_FORWARD) or backward (OFFT_BACKWARD) transform.  Launching
  * passes 0..n-1 in order on one stream with the same in/out is exactly
  * offt_exec_fwd / offt_exec_bwd (pass 0 reads `in`, later passes work in place
- * on `out`); it exists so that each pass can be timed on its own.
+ * on `out`; in REVERSED layouts the passes route through the plan's
+ * workspace exactly as exec does); it exists so that each pass can be timed
+ * on its own.
  * Errors: INVALID_ARG (NULL plan/pointer, i out of range, bad direction),
  * BAD_PLAN, HIP. */
 int offt_exec_pass(offt_plan_t p, int i, int direction, const void* in, void* out, void* stream);
@@ -152,6 +177,17 @@ const char* offt_error_string(int code);
  * Returns the full string length or INVALID_ARG / UNSUPPORTED_SIZE. */
 int offt_default_plan_string(int64_t Na, int64_t Nb, int64_t Nc, int dtype, char* buf, size_t n);
 
+/* Plan strings of either layout without a device: with plan == NULL the
+ * heuristic plan of `layout` (OFFT_LAYOUT_*) for one grid shape; otherwise
+ * `plan` parsed and written back in canonical form, after checking that it
+ * names compiled kernels, that exchanges in parts sit on strided lines only,
+ * that the transposing axis (";rev=") has a transposing kernel and that the
+ * output order matches `layout` (tile sizes are checked against the device
+ * at plan time, not here).  Returns the full string length, or
+ * INVALID_ARG / UNSUPPORTED_SIZE / BAD_PLAN. */
+int offt_plan_string(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int layout, const char* plan, char* buf,
+                     size_t n);
+
 /* Write the device-generated forward twiddle table W_n^m, m < n, of precision
  * `dtype` to host memory `host_out` (n interleaved complex values).  The table
  * is computed in binary64 on the GPU and rounded to nearest for OFFT_C2C_F32.
@@ -165,7 +201,8 @@ int offt_twiddles(int64_t n, int dtype, void* host_out);
  * o->tune = OFFT_TUNE_EXHAUSTIVE each distinct grid shape gets its own tuned
  * plan.  The execution is one persistent kernel launch over all (grid, axis
  * pass, tile) work items, captured once into a HIP graph and replayed.
- * Errors as offt_plan_ex. */
+ * Grids stay in natural order (o->layout other than NATURAL is
+ * OFFT_ERR_INVALID_ARG).  Errors as offt_plan_ex. */
 offt_plan_t offt_plan_many(int count, const int64_t* dims, int dtype, const offt_opts* o);
 
 /* Element offset of grid i in the packed buffer, total elements of the

@@ -6,6 +6,9 @@ and streams only; the transform runs in the library's HIP kernels.
     plan = Plan((Na, Nb, Nc), dtype=torch.complex128, batch=1)
     y = plan.forward(x)            # x: contiguous cuda tensor (batch?, Na, Nb, Nc)
     z = plan.backward(y)           # unnormalised unless normalize_inverse=True
+
+With layout="cba" the forward output and the backward input are in reversed
+axis order, (batch?, Nc, Nb, Na), as the paper's transform finishes.
 """
 from __future__ import annotations
 
@@ -16,11 +19,20 @@ import torch
 from . import _lib
 from ._lib import (BACKWARD, C2C_F32, C2C_F64, FORWARD, MANY_LEVELS, MANY_LEVELS_GRAPH, MANY_PERSISTENT,
                    MANY_PERSISTENT_GRAPH, MANY_SEPARATE_HEURISTIC, MANY_SEPARATE_TUNED, MANY_SYNC, MANY_SYNC_GRAPH,
-                   MAX_AXIS, OfftError,
+                   LAYOUT_NATURAL, LAYOUT_REVERSED, MAX_AXIS, OfftError,
                    TUNE_EXHAUSTIVE, TUNE_FORCED, TUNE_LEARNED, TUNE_NONE)
 
-__all__ = ["Plan", "ManyPlan", "OfftError", "twiddles", "default_plan_string", "pass_bytes", "decomp_start",
-           "transpose_count", "transpose_volume", "FORWARD", "BACKWARD", "MAX_AXIS"]
+__all__ = ["Plan", "ManyPlan", "OfftError", "twiddles", "default_plan_string", "plan_string", "pass_bytes",
+           "decomp_start", "transpose_count", "transpose_volume", "FORWARD", "BACKWARD", "MAX_AXIS"]
+
+_LAYOUT = {"natural": LAYOUT_NATURAL, "abc": LAYOUT_NATURAL, "cba": LAYOUT_REVERSED,
+           "reversed": LAYOUT_REVERSED}
+
+
+def _layout_code(layout) -> int:
+    if layout not in _LAYOUT:
+        raise ValueError(f"layout must be one of {sorted(_LAYOUT)}")
+    return _LAYOUT[layout]
 
 _TUNE = {"none": TUNE_NONE, "exhaustive": TUNE_EXHAUSTIVE, "learned": TUNE_LEARNED,
          "forced": TUNE_FORCED}
@@ -40,7 +52,7 @@ def _stream_handle(stream=None) -> int:
 
 
 def _make_opts(tune="none", reps=2, normalize_inverse=False, forced_plan=None, cache_path=None,
-               weights_path=None, stream=None, tune_inplace=False, use_graph=False):
+               weights_path=None, stream=None, tune_inplace=False, use_graph=False, layout="natural"):
     o = _lib.default_opts()
     if tune not in _TUNE:
         raise ValueError(f"tune must be one of {sorted(_TUNE)}")
@@ -57,18 +69,20 @@ def _make_opts(tune="none", reps=2, normalize_inverse=False, forced_plan=None, c
     o.stream = ctypes.c_void_p(stream) if stream else None
     o.tune_inplace = 1 if tune_inplace else 0
     o.use_graph = 1 if use_graph else 0
+    o.layout = _layout_code(layout)
     return o, keep
 
 
 class Plan:
     """Plan for `batch` grids of `shape` = (Na, Nb, Nc).  use_graph: forward
     and backward replay a HIP graph of the pass kernels (captured by the first
-    call, updated when buffers or direction change)."""
+    call, updated when buffers or direction change).  layout="cba": forward
+    output and backward input are (batch?, Nc, Nb, Na), Y[c, b, a] = X[a, b, c]."""
 
     def __init__(self, shape, dtype=torch.complex128, batch: int = 1, tune: str = "none",
                  normalize_inverse: bool = False, forced_plan: str | None = None,
                  cache_path: str | None = None, weights_path: str | None = None, reps: int = 2,
-                 tune_inplace: bool = False, use_graph: bool = False):
+                 tune_inplace: bool = False, use_graph: bool = False, layout: str = "natural"):
         lib = _lib.load()
         if len(shape) != 3:
             raise ValueError("shape must be (Na, Nb, Nc)")
@@ -76,10 +90,11 @@ class Plan:
         self.dtype = dtype
         self.batch = int(batch)
         self.normalize_inverse = bool(normalize_inverse)
+        self.reversed = _layout_code(layout) == LAYOUT_REVERSED
         code = _dtype_code(dtype)
         stream = _stream_handle() if torch.cuda.is_available() else None
         opts, keep = _make_opts(tune, reps, normalize_inverse, forced_plan, cache_path, weights_path,
-                                stream, tune_inplace, use_graph)
+                                stream, tune_inplace, use_graph, layout)
         h = lib.offt_plan_ex(self.shape[0], self.shape[1], self.shape[2], code, self.batch,
                              ctypes.byref(opts))
         del keep
@@ -87,33 +102,38 @@ class Plan:
             raise OfftError(_lib.last_error(), f"offt_plan_ex{self.shape}")
         self._h = h
 
-    def _check_tensor(self, x: torch.Tensor, name: str):
+    @property
+    def spectral_shape(self):
+        """Grid shape of the forward output and backward input."""
+        return self.shape[::-1] if self.reversed else self.shape
+
+    def _check_tensor(self, x: torch.Tensor, name: str, shape):
         if not isinstance(x, torch.Tensor) or not x.is_cuda:
             raise ValueError(f"{name} must be a CUDA (HIP) tensor")
         if x.dtype != self.dtype:
             raise ValueError(f"{name} has dtype {x.dtype}, plan expects {self.dtype}")
         if not x.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
-        n = self.batch * self.shape[0] * self.shape[1] * self.shape[2]
-        if x.numel() != n or tuple(x.shape[-3:]) != self.shape:
+        n = self.batch * shape[0] * shape[1] * shape[2]
+        if x.numel() != n or tuple(x.shape[-3:]) != tuple(shape):
             raise ValueError(f"{name} has shape {tuple(x.shape)}, plan expects "
-                             f"{(self.batch,) + self.shape if self.batch > 1 else self.shape}")
+                             f"{(self.batch,) + tuple(shape) if self.batch > 1 else tuple(shape)}")
 
-    def _run(self, fn, x, out):
-        self._check_tensor(x, "x")
+    def _run(self, fn, x, out, in_shape, out_shape):
+        self._check_tensor(x, "x", in_shape)
         if out is None:
-            out = torch.empty_like(x)
+            out = torch.empty(x.shape[:-3] + tuple(out_shape), dtype=x.dtype, device=x.device)
         else:
-            self._check_tensor(out, "out")
+            self._check_tensor(out, "out", out_shape)
         _lib.check(fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                       ctypes.c_void_p(_stream_handle())), "exec")
         return out
 
     def forward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        return self._run(_lib.load().offt_exec_fwd, x, out)
+        return self._run(_lib.load().offt_exec_fwd, x, out, self.shape, self.spectral_shape)
 
     def backward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        return self._run(_lib.load().offt_exec_bwd, x, out)
+        return self._run(_lib.load().offt_exec_bwd, x, out, self.spectral_shape, self.shape)
 
     def exec_ptr(self, direction: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
         """Raw-pointer execution (no tensor checks) for benchmarking loops."""
@@ -232,6 +252,19 @@ class ManyPlan:
             self.close()
         except Exception:
             pass
+
+
+def plan_string(shape, dtype=torch.complex128, layout: str = "natural", plan: str | None = None) -> str:
+    """Heuristic plan string of `layout` for a grid shape, or `plan` checked
+    and in canonical form (no device needed)."""
+    lib = _lib.load()
+    code = _dtype_code(dtype)
+    lay = _layout_code(layout)
+    p = plan.encode() if plan is not None else None
+    n = _lib.check(lib.offt_plan_string(shape[0], shape[1], shape[2], code, lay, p, None, 0), "plan string")
+    buf = ctypes.create_string_buffer(n + 1)
+    lib.offt_plan_string(shape[0], shape[1], shape[2], code, lay, p, buf, n + 1)
+    return buf.value.decode()
 
 
 def default_plan_string(shape, dtype=torch.complex128) -> str:

@@ -42,6 +42,10 @@ MANY_SYNC = 4
 MANY_SYNC_GRAPH = 5
 MAX_AXIS = 1024
 
+# order of transformed grids (offt_opts.layout)
+LAYOUT_NATURAL = 0
+LAYOUT_REVERSED = 1
+
 
 class Opts(ctypes.Structure):
     _fields_ = [
@@ -54,6 +58,7 @@ class Opts(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("tune_inplace", ctypes.c_int),
         ("use_graph", ctypes.c_int),
+        ("layout", ctypes.c_int),
     ]
 
 
@@ -76,6 +81,7 @@ SIGNATURES = {
     "offt_error_string": (ctypes.c_char_p, [_ci]),
     "offt_twiddles": (_ci, [_i64, _ci, _vp]),
     "offt_default_plan_string": (_ci, [_i64, _i64, _i64, _ci, ctypes.c_char_p, ctypes.c_size_t]),
+    "offt_plan_string": (_ci, [_i64, _i64, _i64, _ci, _ci, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t]),
     "offt_feature_dim": (_ci, []),
     "offt_candidates": (_ci, [_i64, _i64, _i64, _ci, _i64, ctypes.c_char_p, ctypes.c_size_t,
                               ctypes.POINTER(ctypes.c_float), _ci]),

@@ -73,8 +73,29 @@ int set_choice(offt_plan_s* p, const PlanChoice& c, hipStream_t s) {
     return attach_twiddles(p, p->passes, p->npass, s);
 }
 
+void reversed_dims(const int64_t dims[3], int64_t out[3]) {
+    out[0] = dims[2];
+    out[1] = dims[1];
+    out[2] = dims[0];
+}
+
+int set_choice_b(offt_plan_s* p, const PlanChoice& c, hipStream_t s) {
+    int64_t rd[3];
+    reversed_dims(p->dims, rd);
+    p->choice_b = c;
+    const int n = build_passes(c, rd, p->batch, p->passes_b);
+    if (n != p->npass) return OFFT_ERR_BAD_PLAN;
+    for (int i = 0; i < n; ++i)
+        if (!p->passes_b[i].k) return OFFT_ERR_UNSUPPORTED_SIZE;
+    return attach_twiddles(p, p->passes_b, n, s);
+}
+
+const PassPlan* dir_passes(const offt_plan_s* p, int dir) {
+    return (p->layout == OFFT_LAYOUT_REVERSED && dir > 0) ? p->passes_b : p->passes;
+}
+
 int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const void* in, void* out,
-                int dir, hipStream_t s) {
+                void* work, int dir, hipStream_t s) {
     const int64_t N = p->dims[0] * p->dims[1] * p->dims[2];
     if (npass == 0) {
         if (in != out) {
@@ -88,8 +109,10 @@ int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const v
     for (int i = 0; i < npass; ++i) {
         const bool last = i == npass - 1;
         const double scale = (bwd && last && p->normalize) ? 1.0 / (double)N : 1.0;
-        if (launch_pass(passes[i], i == 0 ? in : out, out, bwd && i == 0, bwd && last, scale, s) !=
-            hipSuccess)
+        const void* src = nullptr;
+        void* dst = nullptr;
+        if (!pass_io(passes, npass, i, in, out, work, &src, &dst)) return OFFT_ERR_BAD_PLAN;
+        if (launch_pass(passes[i], src, dst, bwd && i == 0, bwd && last, scale, s) != hipSuccess)
             return OFFT_ERR_HIP;
     }
     return OFFT_SUCCESS;
@@ -134,6 +157,7 @@ void offt_opts_default(offt_opts* o) {
     o->stream = nullptr;
     o->tune_inplace = 0;
     o->use_graph = 0;
+    o->layout = OFFT_LAYOUT_NATURAL;
 }
 
 int offt_last_error(void) { return g_last_error; }
@@ -168,12 +192,35 @@ offt_plan_t offt_plan_ex(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t 
         rc = OFFT_ERR_INVALID_ARG;
     if (rc == OFFT_SUCCESS && (opts.reps < 1 || (opts.use_graph != 0 && opts.use_graph != 1)))
         rc = OFFT_ERR_INVALID_ARG;
+    if (rc == OFFT_SUCCESS && opts.layout != OFFT_LAYOUT_NATURAL && opts.layout != OFFT_LAYOUT_REVERSED)
+        rc = OFFT_ERR_INVALID_ARG;
     if (rc != OFFT_SUCCESS) { set_error(rc); return nullptr; }
     const int64_t dims[3] = {Na, Nb, Nc};
-    PlanChoice forced;
-    if (opts.tune == OFFT_TUNE_FORCED && !choice_from_string(opts.forced_plan, dtype, dims, &forced)) {
-        set_error(OFFT_ERR_BAD_PLAN);
-        return nullptr;
+    int64_t rdims[3];
+    reversed_dims(dims, rdims);
+    const bool reversed = opts.layout == OFFT_LAYOUT_REVERSED;
+    PlanChoice forced, forced_b;
+    if (opts.tune == OFFT_TUNE_FORCED) {
+        // reversed layouts: "<forward plan>|<backward plan>", the backward
+        // half naming the axes of the cba input; without '|' the backward
+        // plan is the heuristic's
+        const std::string fp(opts.forced_plan);
+        const size_t bar = fp.find('|');
+        bool ok = choice_from_string(fp.substr(0, bar).c_str(), dtype, dims, &forced);
+        if (ok && reversed) {
+            if (bar != std::string::npos)
+                ok = choice_from_string(fp.substr(bar + 1).c_str(), dtype, rdims, &forced_b);
+            else
+                forced_b = default_choice_reversed(dtype, rdims);
+        }
+        // a plan string must give the output order the layout asks for
+        if (ok && (forced.tax >= 0) != (reversed && reversal_moves_data(dims))) ok = false;
+        if (ok && reversed && (forced_b.tax >= 0) != reversal_moves_data(dims)) ok = false;
+        if (ok && !reversed && bar != std::string::npos) ok = false;
+        if (!ok) {
+            set_error(OFFT_ERR_BAD_PLAN);
+            return nullptr;
+        }
     }
     rc = check_device();
     if (rc != OFFT_SUCCESS) { set_error(rc); return nullptr; }
@@ -184,16 +231,32 @@ offt_plan_t offt_plan_ex(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t 
     p->dims[0] = Na; p->dims[1] = Nb; p->dims[2] = Nc;
     p->batch = batch;
     p->normalize = opts.normalize_inverse ? 1 : 0;
+    p->layout = opts.layout;
     hipStream_t s = static_cast<hipStream_t>(opts.stream);
 
-    PlanChoice choice = default_choice(dtype, dims);
+    PlanChoice choice = reversed ? default_choice_reversed(dtype, dims) : default_choice(dtype, dims);
+    PlanChoice choice_b = reversed ? default_choice_reversed(dtype, rdims) : choice;
     if (opts.tune == OFFT_TUNE_FORCED) {
         choice = forced;
+        choice_b = forced_b;
     } else if (opts.tune == OFFT_TUNE_EXHAUSTIVE || opts.tune == OFFT_TUNE_LEARNED) {
-        rc = select_plan(p, opts, &choice);
+        rc = select_plan(p, opts, &choice, &choice_b);
         if (rc != OFFT_SUCCESS) { free_plan(p); set_error(rc); return nullptr; }
     }
     rc = set_choice(p, choice, s);
+    if (rc == OFFT_SUCCESS && reversed) rc = set_choice_b(p, choice_b, s);
+    if (rc == OFFT_SUCCESS && reversed && reversal_moves_data(dims)) {
+        // the workspace of the transposing passes: one batch of grids
+        const size_t bytes = (size_t)(Na * Nb * Nc * batch) * elem_size(dtype);
+        if (hipMalloc(&p->work, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p->work = nullptr;
+            rc = OFFT_ERR_OUT_OF_MEMORY;
+        } else {
+            p->allocs.push_back(p->work);
+            p->alloc_bytes.push_back(bytes);
+        }
+    }
     if (rc == OFFT_SUCCESS && hipStreamSynchronize(s) != hipSuccess) rc = OFFT_ERR_HIP;
     // the capture stream of use_graph (default priority, non-blocking)
     p->use_graph = opts.use_graph;
@@ -219,7 +282,7 @@ static int capture_passes(offt_plan_s* p, const void* in, void* out, int dir) {
         (void)hipGetLastError();
         return OFFT_ERR_HIP;
     }
-    const int rc = exec_passes(p, p->passes, p->npass, in, out, dir, p->cap);
+    const int rc = exec_passes(p, dir_passes(p, dir), p->npass, in, out, p->work, dir, p->cap);
     const hipError_t e = hipStreamEndCapture(p->cap, &g);
     if (rc != OFFT_SUCCESS || e != hipSuccess || !g) {
         (void)hipGetLastError();
@@ -263,7 +326,7 @@ static int exec_checked(offt_plan_t p, const void* in, void* out, void* stream, 
             rc = OFFT_ERR_HIP;
         }
     } else {
-        rc = exec_passes(p, p->passes, p->npass, in, out, dir, s);
+        rc = exec_passes(p, dir_passes(p, dir), p->npass, in, out, p->work, dir, s);
     }
     set_error(rc);
     return rc;
@@ -295,8 +358,15 @@ int offt_exec_pass(offt_plan_t p, int i, int direction, const void* in, void* ou
     const bool bwd = direction == OFFT_BACKWARD;
     const bool last = i == p->npass - 1;
     const double scale = (bwd && last && p->normalize) ? 1.0 / (double)N : 1.0;
-    const int rc = launch_pass(p->passes[i], i == 0 ? in : out, out, bwd && i == 0, bwd && last, scale,
-                               static_cast<hipStream_t>(stream)) == hipSuccess ? OFFT_SUCCESS : OFFT_ERR_HIP;
+    const PassPlan* ps = dir_passes(p, direction);
+    const void* src = nullptr;
+    void* dst = nullptr;
+    int rc = OFFT_SUCCESS;
+    if (!pass_io(ps, p->npass, i, in, out, p->work, &src, &dst))
+        rc = OFFT_ERR_BAD_PLAN;
+    else if (launch_pass(ps[i], src, dst, bwd && i == 0, bwd && last, scale, static_cast<hipStream_t>(stream)) !=
+             hipSuccess)
+        rc = OFFT_ERR_HIP;
     set_error(rc);
     return rc;
 }
@@ -334,6 +404,39 @@ int offt_default_plan_string(int64_t Na, int64_t Nb, int64_t Nc, int dtype, char
     }
     const int64_t dims[3] = {Na, Nb, Nc};
     const std::string s = choice_to_string(default_choice(dtype, dims), dims);
+    if (n) {
+        const size_t m = std::min(n - 1, s.size());
+        memcpy(buf, s.data(), m);
+        buf[m] = 0;
+    }
+    set_error(OFFT_SUCCESS);
+    return (int)s.size();
+}
+
+int offt_plan_string(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int layout, const char* plan, char* buf,
+                     size_t n) {
+    int rc = validate_dims(Na, Nb, Nc, dtype, 1);
+    if (rc == OFFT_SUCCESS && ((!buf && n) || (layout != OFFT_LAYOUT_NATURAL && layout != OFFT_LAYOUT_REVERSED)))
+        rc = OFFT_ERR_INVALID_ARG;
+    if (rc != OFFT_SUCCESS) { set_error(rc); return rc; }
+    const int64_t dims[3] = {Na, Nb, Nc};
+    int64_t rdims[3];
+    reversed_dims(dims, rdims);
+    const bool reversed = layout == OFFT_LAYOUT_REVERSED;
+    const bool moves = reversed && reversal_moves_data(dims);
+    PlanChoice c = reversed ? default_choice_reversed(dtype, dims) : default_choice(dtype, dims);
+    PlanChoice cb = reversed ? default_choice_reversed(dtype, rdims) : c;
+    if (plan) {
+        const std::string fp(plan);
+        const size_t bar = fp.find('|');
+        bool ok = (bar != std::string::npos) == reversed &&
+                  choice_from_string(fp.substr(0, bar).c_str(), dtype, dims, &c, false);
+        if (ok && reversed) ok = choice_from_string(fp.substr(bar + 1).c_str(), dtype, rdims, &cb, false);
+        if (ok) ok = (c.tax >= 0) == moves && (!reversed || (cb.tax >= 0) == moves);
+        if (!ok) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
+    }
+    std::string s = choice_to_string(c, dims);
+    if (reversed) s += "|" + choice_to_string(cb, rdims);
     if (n) {
         const size_t m = std::min(n - 1, s.size());
         memcpy(buf, s.data(), m);

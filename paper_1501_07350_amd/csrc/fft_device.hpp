@@ -197,6 +197,11 @@ __host__ __device__ constexpr int line_pitch(int L, int P) { return Pitch_value(
 __host__ __device__ constexpr int64_t tile_lds_elems(int W, int L, int P = 1) {
     return (int64_t)W * line_pitch(L, P) + L;
 }
+// A transposing pass adds a table of one 64-bit row offset per line (W
+// elements of at least 8 bytes).
+__host__ __device__ constexpr int64_t tile_lds_elems_transpose(int W, int L) {
+    return tile_lds_elems(W, L, 1) + W;
+}
 
 // ---- Stockham stages ---------------------------------------------------------
 // A thread of rank t (0 <= t < TPL) within its line owns butterflies
@@ -390,8 +395,11 @@ struct PassArgs {
     const void* tw;     // W_L^m, m < L, in the pass precision
     int64_t nlines;     // M1 * M2
     int64_t M2;         // element stride of the axis (1: contiguous lines)
+    int64_t X, Y;       // transposing passes: line m1*M2 + m2 is the contiguous row
+                        // m1*M2 + (m2 mod X)*Y + m2 div X of the other buffer
     int logW;           // log2 of lines per workgroup
-    int mode;           // 0: contiguous lines (M2 == 1), 1: strided lines
+    int mode;           // 0: contiguous lines (M2 == 1), 1: strided lines,
+                        // 2: rows in, strided lines out, 3: strided lines in, rows out
     int conj_in;        // negate imaginary parts on load
     int conj_out;       // negate imaginary parts on store
     double scale;       // multiply on store
@@ -516,6 +524,81 @@ __device__ __forceinline__ void pass_tile_impl(const PassArgs& a, V* __restrict_
                     const int lw = f / L, j = f - lw * L;
                     store_elem<COHERENT>(go + f, fix_out(lds[lw * LP + lds_idx(j)], cout, scale));
                 }
+            }
+        }
+    }
+}
+
+// One tile of a transposing pass (modes 2 and 3): W lines whose strided side
+// follows the [M1][L][M2] view (line l = m1*M2 + m2 at m1*L*M2 + m2, stride
+// M2) while the other buffer holds each line as the contiguous row
+// m1*M2 + (m2 mod X)*Y + m2 div X.  Mode 2 reads the rows and writes the
+// strided lines, mode 3 the reverse.  The row side goes through LDS with a
+// flat copy (consecutive lanes on consecutive elements of a row); the
+// strided side goes straight between registers and HBM with lanes walking
+// the W columns, as in a strided pass.  Threads: W * TPL; lds:
+// tile_lds_elems_transpose(W, L) elements.  Never in place.
+template <typename V, int L, int TPL, int... Rs>
+__device__ __forceinline__ void pass_tile_transpose(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
+    using S = decltype(V{}.x);
+    static_assert(RadixProduct<Rs...>::value == L, "radix sequence must multiply to L");
+    constexpr int LP = line_pitch(L, 1);
+    const int W = 1 << a.logW;
+    const int NT = W * TPL;
+    const int tid = threadIdx.x;
+    const int64_t rem = a.nlines - l0;
+    const int nl = rem < W ? (int)rem : W;
+    const V* __restrict__ in = static_cast<const V*>(a.in);
+    V* __restrict__ out = static_cast<V*>(a.out);
+    const V* tw = static_cast<const V*>(a.tw);
+    const int cin = a.conj_in, cout = a.conj_out;
+    const S scale = (S)a.scale;
+    const bool active = tid < NT;
+    const int64_t M2 = a.M2;
+    if constexpr (sizeof...(Rs) > 1) {
+        V* twl = lds + W * LP;
+        for (int i = tid; i < L; i += (int)blockDim.x) twl[i] = tw[i];
+        tw = twl;
+    }
+    // element offset of each line's row in the row-side buffer
+    int64_t* rows = reinterpret_cast<int64_t*>(lds + W * LP + L);
+    if (tid < nl) {
+        const int64_t l = l0 + tid;
+        const int64_t m1 = l / M2, m2 = l - m1 * M2;
+        rows[tid] = (m1 * M2 + (m2 % a.X) * a.Y + m2 / a.X) * (int64_t)L;
+    }
+    __syncthreads();
+    const int w = tid & (W - 1);
+    const int t = tid >> a.logW;
+    const bool ok = active && w < nl;
+    const int64_t l = l0 + (ok ? w : 0);   // rows beyond the tail compute on line l0, store nothing
+    const int64_t m1 = l / M2, m2 = l - m1 * M2;
+    const int64_t base = m1 * (int64_t)L * M2 + m2;
+    V* line = lds + w * LP;
+    if (a.mode == 2) {
+        if (active) {
+            for (int f = tid; f < nl * L; f += NT) {
+                const int lw = f / L, j = f - lw * L;
+                lds[lw * LP + lds_idx(j)] = fix_in(in[rows[lw] + j], cin);
+            }
+        }
+        __syncthreads();
+        V* go = out + base;
+        auto src = [&](int j) { return line[lds_idx(j)]; };
+        auto sink = [&](int j, V x) {
+            if (ok) go[(int64_t)j * M2] = fix_out(x, cout, scale);
+        };
+        run_fft<V, L, TPL, 1, true, false, Rs...>(line, tw, t, active, src, sink);
+    } else {
+        const V* g = in + base;
+        auto src = [&](int j) { return fix_in(g[(int64_t)j * M2], cin); };
+        auto sink = [&](int j, V x) { line[lds_idx(j)] = fix_out(x, cout, scale); };
+        run_fft<V, L, TPL, 1, false, true, Rs...>(line, tw, t, active, src, sink);
+        __syncthreads();
+        if (active) {
+            for (int f = tid; f < nl * L; f += NT) {
+                const int lw = f / L, j = f - lw * L;
+                out[rows[lw] + j] = lds[lw * LP + lds_idx(j)];
             }
         }
     }

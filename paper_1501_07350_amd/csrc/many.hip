@@ -515,7 +515,7 @@ static int choose_many(offt_plan_s* p, const offt_opts& o) {
                 memcpy(tmp.dims, G.dims, sizeof G.dims);
                 tmp.batch = 1;
                 offt_opts o2 = o;
-                const int rc = select_plan(&tmp, o2, &c);
+                const int rc = select_plan(&tmp, o2, &c, nullptr);
                 for (void* d : tmp.allocs) (void)hipFree(d);
                 if (rc != OFFT_SUCCESS) return rc;
             }
@@ -545,8 +545,8 @@ static int exec_separate(const offt_plan_s* p, const void* in, void* out, int di
         view.normalize = p->normalize;
         const char* gi = static_cast<const char*>(in) + G.off * es;
         char* go = static_cast<char*>(out) + G.off * es;
-        const int rc = tuned ? exec_passes(&view, G.tuned, G.ntuned, gi, go, dir, s)
-                             : exec_passes(&view, G.heur, G.nheur, gi, go, dir, s);
+        const int rc = tuned ? exec_passes(&view, G.tuned, G.ntuned, gi, go, nullptr, dir, s)
+                             : exec_passes(&view, G.heur, G.nheur, gi, go, nullptr, dir, s);
         if (rc != OFFT_SUCCESS) return rc;
     }
     return OFFT_SUCCESS;
@@ -563,7 +563,8 @@ offt_plan_t offt_plan_many(int count, const int64_t* dims, int dtype, const offt
     offt_opts_default(&opts);
     if (o) opts = *o;
     if (count < 1 || !dims || (dtype != OFFT_C2C_F64 && dtype != OFFT_C2C_F32) ||
-        opts.tune < OFFT_TUNE_NONE || opts.tune > OFFT_TUNE_LEARNED || opts.reps < 1) {
+        opts.tune < OFFT_TUNE_NONE || opts.tune > OFFT_TUNE_LEARNED || opts.reps < 1 ||
+        opts.layout != OFFT_LAYOUT_NATURAL) {
         set_error(OFFT_ERR_INVALID_ARG);
         return nullptr;
     }

@@ -30,6 +30,7 @@ struct KernelEntry {
     int max_threads;           // launch bound the kernel is compiled for
     int nparts;                // parts each LDS exchange runs in (> 1: strided lines only)
     LaunchFn launch;
+    LaunchFn launch_t;         // the same tile code as a transposing pass (nparts == 1), else nullptr
 };
 
 // One kernel case compiled into the persistent batch executor.
@@ -62,9 +63,10 @@ struct PassPlan {
     int axis;                  // 0 = a, 1 = b, 2 = c
     int L;
     int64_t M1, M2;
+    int64_t X, Y;              // transposing passes: row map of the other buffer (PassArgs)
     const KernelEntry* k;
     int logW;                  // lines per workgroup = 2^logW
-    int mode;                  // 0 contiguous lines, 1 strided lines
+    int mode;                  // 0 contiguous lines, 1 strided lines, 2/3 transposing (PassArgs)
     const void* tw;            // device twiddle table for L
 };
 
@@ -73,7 +75,30 @@ struct PlanChoice {
     int order[3];              // axis order of the passes (axis ids)
     const KernelEntry* k[3];   // per axis id (a, b, c); nullptr for L == 1
     int logW[3];               // per axis id
+    // Output order.  -1: the input's (abc).  0 or 2: reversed (cba), the
+    // pass along this axis transposing: axis a reads strided lines of the
+    // abc grid and writes cba rows (mode 3), axis c reads abc rows and
+    // writes strided lines of the cba grid (mode 2).  Passes before it see
+    // the abc grid, passes after it the cba grid.
+    int tax = -1;
 };
+
+// Where an axis pass of a choice runs: on the input's (abc) grid, on the
+// reversed (cba) grid, or as the transposing pass between them.
+enum AxisGeom { kGeomNatural = 0, kGeomReversed = 1, kGeomTranspose = 2 };
+int axis_geom(const PlanChoice& c, int ax);
+// The pass of axis ax in geometry g (k and logW filled in, tw left null).
+PassPlan make_pass(const int64_t dims[3], int64_t batch, int ax, int g, const KernelEntry* k, int logW);
+// Whether the output of a grid has a different memory order in cba than in
+// abc (at least two axes longer than 1).
+bool reversal_moves_data(const int64_t dims[3]);
+// Index of the transposing pass in a pass list, or -1.
+int transpose_index(const PassPlan* ps, int n);
+// Buffers of pass i: `in` to `out` through the plan's workspace where a
+// transposing pass needs one (it never runs in place).  Returns false when
+// the workspace is needed and `work` is null.
+bool pass_io(const PassPlan* ps, int n, int i, const void* in, void* out, void* work, const void** src,
+             void** dst);
 
 size_t elem_size(int dtype);
 bool smooth235(int64_t n);
@@ -82,6 +107,9 @@ std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]);
 // dims/dtype (with check_fit, also when a tile exceeds this device's limits).
 bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanChoice* out, bool check_fit = true);
 PlanChoice default_choice(int dtype, const int64_t dims[3]);
+// Heuristic plan with the output in reversed (cba) order; equal to
+// default_choice when the reversal moves no data.
+PlanChoice default_choice_reversed(int dtype, const int64_t dims[3]);
 // Candidate plans for tuning (deterministic order, default first).
 std::vector<PlanChoice> candidate_choices(int dtype, const int64_t dims[3]);
 // Pass descriptors (M1, M2, mode, W) for a grid + batch under a choice.
@@ -89,8 +117,12 @@ int build_passes(const PlanChoice& c, const int64_t dims[3], int64_t batch, Pass
 // Whether a tile of 2^logW lines of kernel k can be launched: thread limit
 // and LDS limit.
 bool tile_fits(const KernelEntry* k, int logW, int dtype);
+// The same for the kernel's transposing form (false if it has none).
+bool tile_fits_transpose(const KernelEntry* k, int logW, int dtype);
+// tile_fits or tile_fits_transpose, by geometry.
+bool tile_fits_geom(const KernelEntry* k, int logW, int dtype, int g);
 // Clamp logW so the tile fits LDS and the thread limit; returns the adjusted value.
-int fit_logW(const KernelEntry* k, int logW, int dtype);
+int fit_logW(const KernelEntry* k, int logW, int dtype, int g = kGeomNatural);
 
 hipError_t launch_twiddles(void* out, int64_t n, int dtype, hipStream_t s);
 // Fills nelem complex elements of `dtype` with values uniform in [-1, 1)

@@ -23,6 +23,14 @@ struct offt_plan_s {
     offt::PlanChoice choice{};
     offt::PassPlan passes[3]{};
     int npass = 0;
+    // OFFT_LAYOUT_REVERSED: the backward transform reads cba grids, so it is
+    // planned as a transform of the reversed shape (Nc, Nb, Na) whose output
+    // is reversed back to abc; both directions route through `work` (one
+    // batch of grids) where a transposing pass needs it
+    int layout = OFFT_LAYOUT_NATURAL;
+    offt::PlanChoice choice_b{};
+    offt::PassPlan passes_b[3]{};
+    void* work = nullptr;
     std::map<int, void*> tw;      // twiddle table per pass length
     std::vector<void*> allocs;    // every device allocation owned by the plan
     std::vector<size_t> alloc_bytes;
@@ -46,12 +54,17 @@ int check_device();
 int validate_dims(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch);
 int attach_twiddles(offt_plan_s* p, PassPlan* passes, int npass, hipStream_t s);
 int set_choice(offt_plan_s* p, const PlanChoice& c, hipStream_t s);
+int set_choice_b(offt_plan_s* p, const PlanChoice& c, hipStream_t s);
+// The passes a direction runs (the backward list differs for reversed layouts).
+const PassPlan* dir_passes(const offt_plan_s* p, int dir);
+void reversed_dims(const int64_t dims[3], int64_t out[3]);
 int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const void* in, void* out,
-                int dir, hipStream_t s);
+                void* work, int dir, hipStream_t s);
 void free_plan(offt_plan_s* p);
 
 // Tuning (tuner.cpp): fills *choice for EXHAUSTIVE / LEARNED modes.
-int select_plan(offt_plan_s* p, const offt_opts& o, PlanChoice* choice);
+// For reversed layouts also *choice_b (the backward plan on the reversed shape).
+int select_plan(offt_plan_s* p, const offt_opts& o, PlanChoice* choice, PlanChoice* choice_b);
 std::string describe_plan(const offt_plan_s* p);
 
 // Uneven batches (many.hip).

@@ -93,10 +93,112 @@ bool tile_fits(const KernelEntry* k, int logW, int dtype) {
     return lds <= lds_limit();
 }
 
-int fit_logW(const KernelEntry* k, int logW, int dtype) {
+bool tile_fits_transpose(const KernelEntry* k, int logW, int dtype) {
+    if (!k || !k->launch_t || k->nparts != 1 || logW < 0) return false;
+    const int64_t W = int64_t(1) << logW;
+    if (W * k->tpl > k->max_threads) return false;
+    return tile_lds_elems_transpose((int)W, k->L) * (int64_t)elem_size(dtype) <= lds_limit();
+}
+
+bool tile_fits_geom(const KernelEntry* k, int logW, int dtype, int g) {
+    return g == kGeomTranspose ? tile_fits_transpose(k, logW, dtype) : tile_fits(k, logW, dtype);
+}
+
+int fit_logW(const KernelEntry* k, int logW, int dtype, int g) {
     if (!k) return 0;
-    while (logW > 0 && !tile_fits(k, logW, dtype)) --logW;
+    while (logW > 0 && !tile_fits_geom(k, logW, dtype, g)) --logW;
     return logW;
+}
+
+// ---- geometry of the passes ---------------------------------------------------
+
+int axis_geom(const PlanChoice& c, int ax) {
+    if (c.tax < 0) return kGeomNatural;
+    if (ax == c.tax) return kGeomTranspose;
+    int pa = 0, pt = 0;
+    for (int i = 0; i < 3; ++i) {
+        if (c.order[i] == ax) pa = i;
+        if (c.order[i] == c.tax) pt = i;
+    }
+    return pa < pt ? kGeomNatural : kGeomReversed;
+}
+
+// On the abc grid the lines of axis ax form the [M1][L][M2] view with M1 the
+// product of the axes before it (times the batch) and M2 of those after it;
+// on the cba grid the two swap.  The transposing pass keeps the strided view
+// of its strided side: the abc grid for axis a (rows written to the cba
+// grid), the cba grid for axis c (rows read from the abc grid).  In both the
+// row of line m1*M2 + m2 is m1*M2 + (m2 mod X)*Y + m2 div X with X the
+// length of the opposite end axis and Y = Nb.
+PassPlan make_pass(const int64_t dims[3], int64_t batch, int ax, int g, const KernelEntry* k, int logW) {
+    PassPlan p;
+    p.axis = ax;
+    p.L = (int)dims[ax];
+    p.k = k;
+    p.logW = logW;
+    p.tw = nullptr;
+    p.X = 1;
+    p.Y = 1;
+    int64_t before = 1, after = 1;
+    for (int j = 0; j < ax; ++j) before *= dims[j];
+    for (int j = ax + 1; j < 3; ++j) after *= dims[j];
+    if (g == kGeomTranspose) {
+        p.M1 = batch;
+        p.M2 = before * after;
+        p.X = dims[2 - ax];
+        p.Y = dims[1];
+        p.mode = ax == 0 ? 3 : 2;
+    } else if (g == kGeomReversed) {
+        p.M1 = batch * after;
+        p.M2 = before;
+        p.mode = before > 1 ? 1 : 0;
+    } else {
+        p.M1 = batch * before;
+        p.M2 = after;
+        p.mode = after > 1 ? 1 : 0;
+    }
+    return p;
+}
+
+bool reversal_moves_data(const int64_t dims[3]) {
+    int n = 0;
+    for (int ax = 0; ax < 3; ++ax) n += dims[ax] > 1;
+    return n >= 2;
+}
+
+int transpose_index(const PassPlan* ps, int n) {
+    for (int i = 0; i < n; ++i)
+        if (ps[i].mode >= 2) return i;
+    return -1;
+}
+
+// Without a transposing pass (or with one first and distinct buffers) pass 0
+// reads `in` and every pass writes `out`.  Passes before a later transposing
+// pass run in the workspace, which it then reads; a transposing first pass
+// with in == out writes the workspace and the second pass brings the data
+// back to `out`.
+bool pass_io(const PassPlan* ps, int n, int i, const void* in, void* out, void* work, const void** src,
+             void** dst) {
+    const int tp = transpose_index(ps, n);
+    if (tp < 0 || (tp == 0 && in != out)) {
+        *src = i == 0 ? in : out;
+        *dst = out;
+        return true;
+    }
+    if (!work) return false;
+    if (tp == 0) {
+        *src = i == 0 ? in : (i == 1 ? (const void*)work : (const void*)out);
+        *dst = i == 0 ? work : out;
+        return true;
+    }
+    if (i < tp) {
+        *src = i == 0 ? in : (const void*)work;
+        *dst = work;
+    } else {
+        *src = i == tp ? (const void*)work : (const void*)out;
+        *dst = out;
+    }
+    return true;
 }
 
 static int max_radix(const KernelEntry* k) {
@@ -156,21 +258,61 @@ static bool axis_strided(int axis, const int64_t dims[3]) {
     return m2 > 1;
 }
 
-PlanChoice default_choice(int dtype, const int64_t dims[3]) {
-    PlanChoice c;
-    c.order[0] = 2; c.order[1] = 1; c.order[2] = 0;   // c, then b, then a
+// Default kernel of a transposing pass: the first whole-line kernel with
+// radix <= 16 (every whole-line kernel has a transposing form), at the
+// strided width (256-byte row segments on the strided side) or the widest
+// that fits below it.
+static const KernelEntry* default_kernel_transpose(int dtype, int L) {
+    for (const KernelEntry* k : kernels_for(dtype, L))
+        if (k->nparts == 1 && k->launch_t && max_radix(k) <= 16) return k;
+    for (const KernelEntry* k : kernels_for(dtype, L))
+        if (k->nparts == 1 && k->launch_t) return k;
+    return nullptr;
+}
+
+// The heuristic kernel and width of every axis, for the geometry the
+// choice's order and output order give it.
+static void assign_default_kernels(PlanChoice& c, int dtype, const int64_t dims[3]) {
     for (int ax = 0; ax < 3; ++ax) {
         c.k[ax] = nullptr;
         c.logW[ax] = 0;
-        if (dims[ax] > 1) {
-            const bool strided = axis_strided(ax, dims);
-            const KernelEntry* k = default_kernel(dtype, (int)dims[ax], strided);
-            if (k) {
-                c.k[ax] = k;
-                c.logW[ax] = default_logW(k, dtype, strided);
-            }
+        if (dims[ax] <= 1) continue;
+        const int g = axis_geom(c, ax);
+        const KernelEntry* k;
+        int logW;
+        if (g == kGeomTranspose) {
+            k = default_kernel_transpose(dtype, (int)dims[ax]);
+            logW = k ? fit_logW(k, strided_logW(k, dtype), dtype, g) : 0;
+        } else {
+            const bool strided = make_pass(dims, 1, ax, g, nullptr, 0).M2 > 1;
+            k = default_kernel(dtype, (int)dims[ax], strided);
+            logW = default_logW(k, dtype, strided);
+        }
+        if (k) {
+            c.k[ax] = k;
+            c.logW[ax] = logW;
         }
     }
+}
+
+PlanChoice default_choice(int dtype, const int64_t dims[3]) {
+    PlanChoice c;
+    c.order[0] = 2; c.order[1] = 1; c.order[2] = 0;   // c, then b, then a
+    c.tax = -1;
+    assign_default_kernels(c, dtype, dims);
+    return c;
+}
+
+// Reversed output: passes c, b, a with the pass along a transposing (strided
+// abc lines in, cba rows out), so the first pass reads contiguous lines and
+// only pass b runs on strided lines of one buffer; without an axis a, the
+// pass along c transposes (abc rows in, strided cba lines out).
+PlanChoice default_choice_reversed(int dtype, const int64_t dims[3]) {
+    if (!reversal_moves_data(dims)) return default_choice(dtype, dims);
+    PlanChoice c;
+    c.order[0] = 2; c.order[1] = 1; c.order[2] = 0;
+    c.tax = dims[0] > 1 ? 0 : 2;
+    assign_default_kernels(c, dtype, dims);
     return c;
 }
 
@@ -214,6 +356,7 @@ static const char kAxisName[] = "abc";
 std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]) {
     std::ostringstream os;
     os << "order=" << kAxisName[c.order[0]] << kAxisName[c.order[1]] << kAxisName[c.order[2]];
+    if (c.tax >= 0) os << ";rev=" << kAxisName[c.tax];
     for (int ax = 0; ax < 3; ++ax) {
         os << ";" << kAxisName[ax] << "=";
         if (!c.k[ax] || dims[ax] <= 1) {
@@ -230,7 +373,13 @@ std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]) {
 
 bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanChoice* out, bool check_fit) {
     if (!s) return false;
-    PlanChoice c = default_choice(dtype, dims);
+    struct AxisSpec {
+        bool given = false;
+        std::vector<int> rad;
+        long W = 0, tpl = 0, P = 1;
+    } spec[3];
+    PlanChoice c;
+    c.tax = -1;
     std::string str(s);
     std::stringstream ss(str);
     std::string item;
@@ -251,59 +400,74 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
                 c.order[i] = ax;
             }
             have_order = true;
+        } else if (key == "rev") {
+            if (val == "a") c.tax = 0;
+            else if (val == "c") c.tax = 2;
+            else return false;
         } else if (key.size() == 1 && strchr(kAxisName, key[0]) && key[0]) {
             const int ax = int(strchr(kAxisName, key[0]) - kAxisName);
             if (dims[ax] <= 1) {
                 if (val != "1") return false;
                 continue;
             }
+            AxisSpec& sp = spec[ax];
+            sp.given = true;
             const size_t slash = val.find('/');
             if (slash == std::string::npos) return false;
-            std::vector<int> rad;
             std::stringstream rs(val.substr(0, slash));
             std::string tok;
             while (std::getline(rs, tok, 'x')) {
                 char* end = nullptr;
                 const long r = strtol(tok.c_str(), &end, 10);
                 if (!end || *end || r < 2) return false;
-                rad.push_back((int)r);
+                sp.rad.push_back((int)r);
             }
             char* end = nullptr;
-            const long W = strtol(val.c_str() + slash + 1, &end, 10);
-            if (!end || W < 1 || (W & (W - 1))) return false;
-            long tpl = 0;   // 0: the sequence's default thread count
-            long P = 1;     // parts of each LDS exchange ("/p<P>", strided axes)
-            if (*end == '/' && end[1] != 'p') {
+            sp.W = strtol(val.c_str() + slash + 1, &end, 10);
+            if (!end || sp.W < 1 || (sp.W & (sp.W - 1))) return false;
+            if (*end == '/' && end[1] != 'p') {   // threads per line (default: the sequence's)
                 char* end2 = nullptr;
-                tpl = strtol(end + 1, &end2, 10);
-                if (!end2 || tpl < 1) return false;
+                sp.tpl = strtol(end + 1, &end2, 10);
+                if (!end2 || sp.tpl < 1) return false;
                 end = end2;
             }
-            if (*end == '/' && end[1] == 'p') {
+            if (*end == '/' && end[1] == 'p') {   // parts of each LDS exchange (strided axes)
                 char* end2 = nullptr;
-                P = strtol(end + 2, &end2, 10);
-                if (!end2 || (P != 1 && P != 2 && P != 4)) return false;
+                sp.P = strtol(end + 2, &end2, 10);
+                if (!end2 || (sp.P != 1 && sp.P != 2 && sp.P != 4)) return false;
                 end = end2;
             }
             if (*end) return false;
-            if (P > 1 && !axis_strided(ax, dims)) return false;
-            const KernelEntry* found = nullptr;
-            for (const KernelEntry* k : kernels_for(dtype, (int)dims[ax])) {
-                if (k->nstages != (int)rad.size()) continue;
-                bool eq2 = true;
-                for (int i = 0; i < k->nstages; ++i) eq2 = eq2 && k->radices[i] == rad[i];
-                if (eq2 && k->tpl == (tpl ? (int)tpl : default_tpl(k)) && k->nparts == (int)P) { found = k; break; }
-            }
-            if (!found) return false;
-            const int lw = ilog2(W);
-            if (check_fit && !tile_fits(found, lw, dtype)) return false;
-            c.k[ax] = found;
-            c.logW[ax] = lw;
         } else {
             return false;
         }
     }
     if (!have_order) return false;
+    if (c.tax >= 0 && (!reversal_moves_data(dims) || dims[c.tax] <= 1)) return false;
+    // axes the string leaves out take the heuristic's kernel for their geometry
+    assign_default_kernels(c, dtype, dims);
+    for (int ax = 0; ax < 3; ++ax) {
+        if (!spec[ax].given) continue;
+        const AxisSpec& sp = spec[ax];
+        const int g = axis_geom(c, ax);
+        const bool strided = g == kGeomTranspose || make_pass(dims, 1, ax, g, nullptr, 0).M2 > 1;
+        if (sp.P > 1 && (g == kGeomTranspose || !strided)) return false;
+        const KernelEntry* found = nullptr;
+        for (const KernelEntry* k : kernels_for(dtype, (int)dims[ax])) {
+            if (k->nstages != (int)sp.rad.size()) continue;
+            bool eq2 = true;
+            for (int i = 0; i < k->nstages; ++i) eq2 = eq2 && k->radices[i] == sp.rad[i];
+            if (eq2 && k->tpl == (sp.tpl ? (int)sp.tpl : default_tpl(k)) && k->nparts == (int)sp.P) {
+                found = k;
+                break;
+            }
+        }
+        if (!found || (g == kGeomTranspose && !found->launch_t)) return false;
+        const int lw = ilog2(sp.W);
+        if (check_fit && !tile_fits_geom(found, lw, dtype, g)) return false;
+        c.k[ax] = found;
+        c.logW[ax] = lw;
+    }
     *out = c;
     return true;
 }
@@ -313,19 +477,7 @@ int build_passes(const PlanChoice& c, const int64_t dims[3], int64_t batch, Pass
     for (int i = 0; i < 3; ++i) {
         const int ax = c.order[i];
         if (dims[ax] <= 1) continue;
-        PassPlan p;
-        p.axis = ax;
-        p.L = (int)dims[ax];
-        int64_t m1 = batch, m2 = 1;
-        for (int j = 0; j < ax; ++j) m1 *= dims[j];
-        for (int j = ax + 1; j < 3; ++j) m2 *= dims[j];
-        p.M1 = m1;
-        p.M2 = m2;
-        p.k = c.k[ax];
-        p.logW = c.logW[ax];
-        p.mode = m2 > 1 ? 1 : 0;
-        p.tw = nullptr;
-        out[n++] = p;
+        out[n++] = make_pass(dims, batch, ax, axis_geom(c, ax), c.k[ax], c.logW[ax]);
     }
     return n;
 }
@@ -338,6 +490,8 @@ hipError_t launch_pass(const PassPlan& p, const void* in, void* out, int conj_in
     a.tw = p.tw;
     a.nlines = p.M1 * p.M2;
     a.M2 = p.M2;
+    a.X = p.X;
+    a.Y = p.Y;
     a.logW = p.logW;
     a.mode = p.mode;
     a.conj_in = conj_in;
@@ -349,6 +503,13 @@ hipError_t launch_pass(const PassPlan& p, const void* in, void* out, int conj_in
     const int64_t W = int64_t(1) << p.logW;
     const int64_t nblocks = (a.nlines + W - 1) / W;
     const int threads = (int)(W * p.k->tpl);
+    if (p.mode >= 2) {
+        // transposing pass: never in place (its row side and strided side
+        // cover the same elements in different orders)
+        if (!p.k->launch_t || in == out || p.X < 1 || p.Y < 1 || p.X * p.Y != p.M2) return hipErrorInvalidValue;
+        const size_t lds_t = (size_t)tile_lds_elems_transpose((int)W, p.L) * elem_size(p.k->dtype);
+        return p.k->launch_t(a, nblocks, threads, lds_t, s);
+    }
     const size_t lds = (size_t)tile_lds_elems((int)W, p.L, p.k->nparts) * (p.k->dtype == OFFT_C2C_F64 ? 16 : 8);
     return p.k->launch(a, nblocks, threads, lds, s);
 }

@@ -41,18 +41,42 @@ static std::string device_name() {
     return n;
 }
 
-std::string cache_key(int dtype, const int64_t dims[3], int64_t batch) {
+std::string cache_key(int dtype, const int64_t dims[3], int64_t batch, int layout) {
     char buf[256];
-    snprintf(buf, sizeof buf, "dtype=%d dims=%lldx%lldx%lld batch=%lld dev=%s", dtype, (long long)dims[0],
-             (long long)dims[1], (long long)dims[2], (long long)batch, device_name().c_str());
+    snprintf(buf, sizeof buf, "dtype=%d dims=%lldx%lldx%lld batch=%lld dev=%s%s", dtype, (long long)dims[0],
+             (long long)dims[1], (long long)dims[2], (long long)batch, device_name().c_str(),
+             layout == OFFT_LAYOUT_REVERSED ? " layout=cba" : "");
     return buf;
 }
 
-// Returns OFFT_SUCCESS and fills *c when the cache holds a usable entry.
-static int cache_lookup(const char* path, int dtype, const int64_t dims[3], int64_t batch, PlanChoice* c) {
+// Parses a plan string of plan p's layout ("<forward>|<backward>" for
+// reversed layouts).
+static bool plan_from_string(const offt_plan_s* p, const std::string& plan, PlanChoice* c, PlanChoice* cb) {
+    const bool reversed = p->layout == OFFT_LAYOUT_REVERSED;
+    const size_t bar = plan.find('|');
+    if (reversed != (bar != std::string::npos)) return false;
+    if (!choice_from_string(plan.substr(0, bar).c_str(), p->dtype, p->dims, c)) return false;
+    if (!reversed) return true;
+    int64_t rd[3];
+    reversed_dims(p->dims, rd);
+    return choice_from_string(plan.substr(bar + 1).c_str(), p->dtype, rd, cb);
+}
+
+static std::string plan_to_string(const offt_plan_s* p, const PlanChoice& c, const PlanChoice& cb) {
+    std::string s = choice_to_string(c, p->dims);
+    if (p->layout == OFFT_LAYOUT_REVERSED) {
+        int64_t rd[3];
+        reversed_dims(p->dims, rd);
+        s += "|" + choice_to_string(cb, rd);
+    }
+    return s;
+}
+
+// Returns OFFT_SUCCESS and fills *c (and *cb) when the cache holds a usable entry.
+static int cache_lookup(const char* path, const offt_plan_s* p, PlanChoice* c, PlanChoice* cb) {
     std::ifstream f(path);
     if (!f) return OFFT_ERR_IO;
-    const std::string key = cache_key(dtype, dims, batch);
+    const std::string key = cache_key(p->dtype, p->dims, p->batch, p->layout);
     std::string line;
     int rc = OFFT_ERR_IO;
     while (std::getline(f, line)) {
@@ -60,43 +84,47 @@ static int cache_lookup(const char* path, int dtype, const int64_t dims[3], int6
         if (t1 == std::string::npos || line.compare(0, t1, key) != 0 || t1 != key.size()) continue;
         const size_t t2 = line.find('\t', t1 + 1);
         const std::string plan = line.substr(t1 + 1, t2 == std::string::npos ? std::string::npos : t2 - t1 - 1);
-        PlanChoice pc;
-        if (choice_from_string(plan.c_str(), dtype, dims, &pc)) {
+        PlanChoice pc, pcb;
+        if (plan_from_string(p, plan, &pc, &pcb)) {
             *c = pc;   // the latest valid entry wins
+            if (cb) *cb = pcb;
             rc = OFFT_SUCCESS;
         }
     }
     return rc;
 }
 
-static void cache_store(const char* path, int dtype, const int64_t dims[3], int64_t batch,
-                        const PlanChoice& c, float ms) {
+static void cache_store(const char* path, const offt_plan_s* p, const PlanChoice& c, const PlanChoice& cb,
+                        float ms) {
     std::ofstream f(path, std::ios::app);
     if (!f) return;
-    f << cache_key(dtype, dims, batch) << '\t' << choice_to_string(c, dims) << '\t' << ms << '\n';
+    f << cache_key(p->dtype, p->dims, p->batch, p->layout) << '\t' << plan_to_string(p, c, cb) << '\t' << ms
+      << '\n';
 }
 
-// Times one candidate from `src` to `dst` (equal: in place).  Returns
+// Times one candidate for a grid of shape `dims` from `src` to `dst` (equal:
+// in place), through `work` where a transposing pass needs it.  Returns
 // OFFT_SUCCESS and the minimum time in *ms.
-int time_choice(offt_plan_s* p, const PlanChoice& c, void* src, void* dst, hipStream_t s, int reps, float* ms) {
+int time_choice(offt_plan_s* p, const PlanChoice& c, const int64_t dims[3], void* src, void* dst, void* work,
+                hipStream_t s, int reps, float* ms) {
     PassPlan passes[3];
-    const int n = build_passes(c, p->dims, p->batch, passes);
+    const int n = build_passes(c, dims, p->batch, passes);
     for (int i = 0; i < n; ++i)
         if (!passes[i].k) return OFFT_ERR_UNSUPPORTED_SIZE;
     int rc = attach_twiddles(p, passes, n, s);
     if (rc != OFFT_SUCCESS) return rc;
     // fresh random data per candidate: unnormalised transforms repeated in
     // place would otherwise grow the values towards overflow
-    if (launch_fill_uniform(src, p->dims[0] * p->dims[1] * p->dims[2] * p->batch, p->dtype, 1501, s) != hipSuccess)
+    if (launch_fill_uniform(src, dims[0] * dims[1] * dims[2] * p->batch, p->dtype, 1501, s) != hipSuccess)
         return OFFT_ERR_HIP;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return OFFT_ERR_HIP;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OFFT_ERR_HIP; }
-    rc = exec_passes(p, passes, n, src, dst, OFFT_FORWARD, s);   // warm-up
+    rc = exec_passes(p, passes, n, src, dst, work, OFFT_FORWARD, s);   // warm-up
     float best = 1e30f;
     for (int r = 0; r < reps && rc == OFFT_SUCCESS; ++r) {
         if (hipEventRecord(e0, s) != hipSuccess) { rc = OFFT_ERR_HIP; break; }
-        rc = exec_passes(p, passes, n, src, dst, OFFT_FORWARD, s);
+        rc = exec_passes(p, passes, n, src, dst, work, OFFT_FORWARD, s);
         if (rc != OFFT_SUCCESS) break;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = OFFT_ERR_HIP; break; }
         float t = 0.f;
@@ -109,25 +137,24 @@ int time_choice(offt_plan_s* p, const PlanChoice& c, void* src, void* dst, hipSt
     return rc;
 }
 
-// Times one axis pass of a plan alone (in place on buf): 1 warm-up + reps runs, minimum.
-static int time_pass(offt_plan_s* p, const PlanChoice& c, int axis, void* buf, hipStream_t s, int reps, float* ms) {
-    PassPlan passes[3];
-    const int n = build_passes(c, p->dims, p->batch, passes);
-    int i = 0;
-    while (i < n && passes[i].axis != axis) ++i;
-    if (i == n || !passes[i].k) return OFFT_ERR_UNSUPPORTED_SIZE;
-    int rc = attach_twiddles(p, &passes[i], 1, s);
+// Times one axis pass alone: 1 warm-up + reps runs, minimum.  Ordinary
+// passes run in place on buf; a transposing pass reads `other` (it never
+// runs in place).
+static int time_pass(offt_plan_s* p, PassPlan pass, void* buf, void* other, hipStream_t s, int reps, float* ms) {
+    if (!pass.k) return OFFT_ERR_UNSUPPORTED_SIZE;
+    int rc = attach_twiddles(p, &pass, 1, s);
     if (rc != OFFT_SUCCESS) return rc;
-    if (launch_fill_uniform(buf, p->dims[0] * p->dims[1] * p->dims[2] * p->batch, p->dtype, 1502, s) != hipSuccess)
-        return OFFT_ERR_HIP;
+    void* src = pass.mode >= 2 ? other : buf;
+    if (!src) return OFFT_ERR_INVALID_ARG;
+    if (launch_fill_uniform(src, pass.M1 * pass.M2 * pass.L, p->dtype, 1502, s) != hipSuccess) return OFFT_ERR_HIP;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return OFFT_ERR_HIP;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OFFT_ERR_HIP; }
-    if (launch_pass(passes[i], buf, buf, 0, 0, 1.0, s) != hipSuccess) rc = OFFT_ERR_HIP;   // warm-up
+    if (launch_pass(pass, src, buf, 0, 0, 1.0, s) != hipSuccess) rc = OFFT_ERR_HIP;   // warm-up
     float best = 1e30f;
     for (int r = 0; r < reps && rc == OFFT_SUCCESS; ++r) {
         float t = 0.f;
-        if (hipEventRecord(e0, s) != hipSuccess || launch_pass(passes[i], buf, buf, 0, 0, 1.0, s) != hipSuccess ||
+        if (hipEventRecord(e0, s) != hipSuccess || launch_pass(pass, src, buf, 0, 0, 1.0, s) != hipSuccess ||
             hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
             hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
             rc = OFFT_ERR_HIP;
@@ -141,94 +168,172 @@ static int time_pass(offt_plan_s* p, const PlanChoice& c, int axis, void* buf, h
     return rc;
 }
 
-// Exhaustive search over a factorised space: the passes are independent
-// kernels, so every (radix sequence, threads per line, tile width) of each
-// axis is timed as a single pass and the fastest kept per axis; then the six
-// pass orders are timed as whole transforms with those kernels.  Ties keep
-// the earlier candidate (the heuristic's kernels and order come first).
-static int exhaustive(offt_plan_s* p, const offt_opts& o, PlanChoice* choice) {
+namespace {
+struct TuneBuffers {
+    void* buf = nullptr;    // destination of whole transforms, in-place target of single passes
+    void* src = nullptr;    // source of whole transforms (== buf when tuning in place)
+    void* work = nullptr;   // reversed layouts: the transposing passes' workspace
+};
+}  // namespace
+
+// Exhaustive search for one grid shape over a factorised space: the passes
+// are independent kernels, so every (radix sequence, threads per line, tile
+// width) of each axis is timed as a single pass in every geometry the axis
+// can have (on the abc grid; for reversed output also on the cba grid and as
+// the transposing pass), and the fastest kept per axis and geometry; then
+// the six pass orders (times the transposing axes) are timed as whole
+// transforms with those kernels.  Ties keep the earlier candidate (the
+// heuristic's kernels and order come first).
+static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dims[3], bool reversed,
+                           const TuneBuffers& B, PlanChoice* choice, float* win_ms_out, int* timed) {
     hipStream_t s = static_cast<hipStream_t>(o.stream);
-    const size_t bytes = (size_t)(p->dims[0] * p->dims[1] * p->dims[2] * p->batch) * elem_size(p->dtype);
-    // two buffers: whole transforms are timed out of place (src -> buf) unless
-    // the caller tunes for in-place use; single passes run in place on buf
-    void* buf = nullptr;
-    void* src = nullptr;
-    if (hipMalloc(&buf, bytes) != hipSuccess) { (void)hipGetLastError(); return OFFT_ERR_OUT_OF_MEMORY; }
-    if (o.tune_inplace) {
-        src = buf;
-    } else if (hipMalloc(&src, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipFree(buf);
-        return OFFT_ERR_OUT_OF_MEMORY;
+    const bool rev = reversed && reversal_moves_data(dims);
+    const PlanChoice heur = rev ? default_choice_reversed(p->dtype, dims) : default_choice(p->dtype, dims);
+    std::vector<int> taxes;   // transposing axes to try
+    if (rev) {
+        for (int t : {0, 2})
+            if (dims[t] > 1) taxes.push_back(t);
+    } else {
+        taxes.push_back(-1);
     }
-    // the timed buffers are filled with random values before every candidate
+    const KernelEntry* best_k[3][3] = {};
+    int best_lw[3][3] = {};
     int rc = OFFT_SUCCESS;
-    PlanChoice best = default_choice(p->dtype, p->dims);
-    int timed = 0;
     for (int ax = 0; ax < 3 && rc == OFFT_SUCCESS; ++ax) {
-        if (p->dims[ax] <= 1) continue;
-        float best_ms = 1e30f;
-        PlanChoice cur = best;
-        const int lw0 = best.logW[ax];
-        // the heuristic's kernel first, so ties keep it
-        std::vector<const KernelEntry*> ks = kernels_for(p->dtype, (int)p->dims[ax]);
-        std::stable_partition(ks.begin(), ks.end(), [&](const KernelEntry* k) { return k == best.k[ax]; });
-        const KernelEntry* best_k = best.k[ax];
-        int best_lw = lw0;
-        int64_t m2 = 1;
-        for (int j = ax + 1; j < 3; ++j) m2 *= p->dims[j];
-        for (const KernelEntry* k : ks) {
-            // kernels whose LDS exchanges run in parts serve strided axes only
-            if (k->nparts > 1 && m2 == 1) continue;
-            const int top = fit_logW(k, 10, p->dtype);
-            // widths below 1/16 of the widest that fits are never competitive;
-            // of a kernel with exchanges in parts only the two widest are tried
-            const int span = k->nparts == 1 ? 4 : 1;
-            for (int lw = top; lw >= 0 && top - lw <= span && rc == OFFT_SUCCESS; --lw) {
-                if (!tile_fits(k, lw, p->dtype)) continue;
-                cur.k[ax] = k;
-                cur.logW[ax] = lw;
-                float ms = 0.f;
-                rc = time_pass(p, cur, ax, buf, s, o.reps, &ms);
-                ++timed;
-                if (rc == OFFT_SUCCESS && ms < best_ms) {
-                    best_ms = ms;
-                    best_k = k;
-                    best_lw = lw;
+        if (dims[ax] <= 1) continue;
+        for (int g = 0; g < 3 && rc == OFFT_SUCCESS; ++g) {
+            // geometries the axis can take under some candidate
+            bool reachable = false;
+            for (int t : taxes)
+                reachable = reachable || (g == kGeomTranspose ? t == ax
+                                                              : (t < 0 ? g == kGeomNatural : t != ax));
+            if (!reachable) continue;
+            const PassPlan shape = make_pass(dims, p->batch, ax, g, nullptr, 0);
+            // the heuristic's kernel for this geometry first, so ties keep it
+            const KernelEntry* hk = nullptr;
+            int hlw = 0;
+            {
+                PlanChoice h = heur;
+                if (g == kGeomTranspose) h.tax = ax;
+                if (axis_geom(h, ax) == g) { hk = h.k[ax]; hlw = h.logW[ax]; }
+            }
+            std::vector<const KernelEntry*> ks = kernels_for(p->dtype, (int)dims[ax]);
+            std::stable_partition(ks.begin(), ks.end(), [&](const KernelEntry* k) { return k == hk; });
+            float best_ms = 1e30f;
+            best_k[ax][g] = hk;
+            best_lw[ax][g] = hlw;
+            for (const KernelEntry* k : ks) {
+                // kernels whose LDS exchanges run in parts serve strided lines
+                // of ordinary passes only
+                if (k->nparts > 1 && (g == kGeomTranspose || shape.M2 == 1)) continue;
+                if (g == kGeomTranspose && !k->launch_t) continue;
+                const int top = fit_logW(k, 10, p->dtype, g);
+                // widths below 1/16 of the widest that fits are never competitive;
+                // of a kernel with exchanges in parts only the two widest are tried
+                const int span = k->nparts == 1 ? 4 : 1;
+                for (int lw = top; lw >= 0 && top - lw <= span && rc == OFFT_SUCCESS; --lw) {
+                    if (!tile_fits_geom(k, lw, p->dtype, g)) continue;
+                    float ms = 0.f;
+                    rc = time_pass(p, make_pass(dims, p->batch, ax, g, k, lw), B.buf, B.work, s, o.reps, &ms);
+                    ++*timed;
+                    if (rc == OFFT_SUCCESS && ms < best_ms) {
+                        best_ms = ms;
+                        best_k[ax][g] = k;
+                        best_lw[ax][g] = lw;
+                    }
                 }
             }
         }
-        best.k[ax] = best_k;
-        best.logW[ax] = best_lw;
     }
     static const int orders[6][3] = {{2, 1, 0}, {2, 0, 1}, {1, 2, 0}, {1, 0, 2}, {0, 2, 1}, {0, 1, 2}};
-    PlanChoice winner = best;
+    PlanChoice winner = heur;
     float win_ms = 1e30f;
-    for (int i = 0; i < 6 && rc == OFFT_SUCCESS; ++i) {
-        PlanChoice c = best;
-        for (int j = 0; j < 3; ++j) c.order[j] = orders[i][j];
-        float ms = 0.f;
-        rc = time_choice(p, c, src, buf, s, o.reps, &ms);
-        ++timed;
-        if (rc == OFFT_SUCCESS && ms < win_ms) { win_ms = ms; winner = c; }
+    for (int t : taxes) {
+        for (int i = 0; i < 6 && rc == OFFT_SUCCESS; ++i) {
+            PlanChoice c = heur;
+            c.tax = t;
+            for (int j = 0; j < 3; ++j) c.order[j] = orders[i][j];
+            for (int ax = 0; ax < 3; ++ax) {
+                if (dims[ax] <= 1) continue;
+                const int g = axis_geom(c, ax);
+                c.k[ax] = best_k[ax][g];
+                c.logW[ax] = best_lw[ax][g];
+            }
+            float ms = 0.f;
+            rc = time_choice(p, c, dims, B.src, B.buf, B.work, s, o.reps, &ms);
+            ++*timed;
+            if (rc == OFFT_SUCCESS && ms < win_ms) { win_ms = ms; winner = c; }
+        }
     }
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(buf);
-    if (src != buf) (void)hipFree(src);
     if (rc != OFFT_SUCCESS) return rc;
     *choice = winner;
-    char buf2[160];
-    snprintf(buf2, sizeof buf2, "exhaustive: %d timings (per-axis kernels and widths, then 6 orders %s), best %.4f ms",
-             timed, o.tune_inplace ? "in place" : "out of place", win_ms);
-    p->tune_log = buf2;
-    if (o.cache_path) cache_store(o.cache_path, p->dtype, p->dims, p->batch, *choice, win_ms);
+    *win_ms_out = win_ms;
     return OFFT_SUCCESS;
 }
 
-int select_plan(offt_plan_s* p, const offt_opts& o, PlanChoice* choice) {
-    if (o.cache_path && cache_lookup(o.cache_path, p->dtype, p->dims, p->batch, choice) == OFFT_SUCCESS) {
+static int exhaustive(offt_plan_s* p, const offt_opts& o, PlanChoice* choice, PlanChoice* choice_b) {
+    hipStream_t s = static_cast<hipStream_t>(o.stream);
+    const bool reversed = p->layout == OFFT_LAYOUT_REVERSED;
+    const size_t bytes = (size_t)(p->dims[0] * p->dims[1] * p->dims[2] * p->batch) * elem_size(p->dtype);
+    // whole transforms are timed out of place (src -> buf) unless the caller
+    // tunes for in-place use; single passes run in place on buf (transposing
+    // ones from work to buf)
+    TuneBuffers B;
+    int rc = OFFT_SUCCESS;
+    auto alloc = [&](void** d) {
+        if (rc == OFFT_SUCCESS && hipMalloc(d, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            *d = nullptr;
+            rc = OFFT_ERR_OUT_OF_MEMORY;
+        }
+    };
+    alloc(&B.buf);
+    if (o.tune_inplace) B.src = B.buf;
+    else alloc(&B.src);
+    if (reversed && reversal_moves_data(p->dims)) alloc(&B.work);
+    int timed = 0;
+    float ms = 0.f, ms_b = 0.f;
+    if (rc == OFFT_SUCCESS) rc = exhaustive_dims(p, o, p->dims, reversed, B, choice, &ms, &timed);
+    if (rc == OFFT_SUCCESS && reversed) {
+        int64_t rd[3];
+        reversed_dims(p->dims, rd);
+        if (rd[0] == p->dims[0]) {
+            *choice_b = *choice;   // Na == Nc: the backward shape is the same
+            ms_b = ms;
+        } else {
+            rc = exhaustive_dims(p, o, rd, true, B, choice_b, &ms_b, &timed);
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    if (B.buf) (void)hipFree(B.buf);
+    if (B.src && B.src != B.buf) (void)hipFree(B.src);
+    if (B.work) (void)hipFree(B.work);
+    if (rc != OFFT_SUCCESS) return rc;
+    char buf2[200];
+    if (reversed)
+        snprintf(buf2, sizeof buf2,
+                 "exhaustive: %d timings (per-axis kernels and widths per geometry, then orders and transposing "
+                 "axes %s), best %.4f ms forward, %.4f ms backward",
+                 timed, o.tune_inplace ? "in place" : "out of place", ms, ms_b);
+    else
+        snprintf(buf2, sizeof buf2,
+                 "exhaustive: %d timings (per-axis kernels and widths, then 6 orders %s), best %.4f ms", timed,
+                 o.tune_inplace ? "in place" : "out of place", ms);
+    p->tune_log = buf2;
+    if (o.cache_path) cache_store(o.cache_path, p, *choice, reversed ? *choice_b : *choice, ms);
+    return OFFT_SUCCESS;
+}
+
+int select_plan(offt_plan_s* p, const offt_opts& o, PlanChoice* choice, PlanChoice* choice_b) {
+    if (o.cache_path && cache_lookup(o.cache_path, p, choice, choice_b) == OFFT_SUCCESS) {
         p->tune_log = "cache";
         return OFFT_SUCCESS;
+    }
+    if (o.tune == OFFT_TUNE_LEARNED && p->layout == OFFT_LAYOUT_REVERSED) {
+        // the learned selector ranks natural-layout candidates only
+        const int rc = exhaustive(p, o, choice, choice_b);
+        p->tune_log = "learned-fallback(reversed layout) " + p->tune_log;
+        return rc;
     }
     if (o.tune == OFFT_TUNE_LEARNED) {
         std::string why;
@@ -237,11 +342,11 @@ int select_plan(offt_plan_s* p, const offt_opts& o, PlanChoice* choice) {
             return OFFT_SUCCESS;
         }
         // weights missing / unreadable / no feasible prediction: fall back
-        const int rc = exhaustive(p, o, choice);
+        const int rc = exhaustive(p, o, choice, choice_b);
         p->tune_log = "learned-fallback(" + why + ") " + p->tune_log;
         return rc;
     }
-    return exhaustive(p, o, choice);
+    return exhaustive(p, o, choice, choice_b);
 }
 
 }  // namespace offt
@@ -263,7 +368,7 @@ extern "C" int offt_tune_table(int64_t Na, int64_t Nb, int64_t Nc, int dtype, in
     hipStream_t s = static_cast<hipStream_t>(stream);
     const std::vector<PlanChoice> cands = candidate_choices(dtype, tmp.dims);
     for (int i = 0; i < std::min((int)cands.size(), max) && rc == OFFT_SUCCESS; ++i)
-        rc = time_choice(&tmp, cands[i], buf, buf, s, reps, &times_ms[i]);
+        rc = time_choice(&tmp, cands[i], tmp.dims, buf, buf, nullptr, s, reps, &times_ms[i]);
     (void)hipStreamSynchronize(s);
     for (void* d : tmp.allocs) (void)hipFree(d);
     if (rc != OFFT_SUCCESS) { set_error(rc); return rc; }
@@ -275,7 +380,7 @@ namespace offt {
 
 std::string describe_plan(const offt_plan_s* p) {
     if (p->kind == 2) return describe_many(p);
-    return choice_to_string(p->choice, p->dims);
+    return plan_to_string(p, p->choice, p->choice_b);
 }
 
 }  // namespace offt

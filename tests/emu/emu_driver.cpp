@@ -213,6 +213,10 @@ static int do_pass(int argc, char** argv) {
     const int64_t M1 = atoll(argv[5]), M2 = atoll(argv[6]);
     const int logW = atoi(argv[7]), logP = atoi(argv[8]);
     const int tpl = atoi(argv[9]);
+    // optional: transposing mode (2 or 3) and its row map X, Y
+    const int tmode = argc > 10 ? atoi(argv[10]) : 0;
+    const int64_t X = argc > 12 ? atoll(argv[11]) : 1, Y = argc > 12 ? atoll(argv[12]) : 1;
+    if (tmode != 0 && (tmode < 2 || tmode > 3 || X * Y != M2)) return 2;
     const int64_t total = M1 * L * M2;
     std::vector<V> in(total), out(total);
     for (int64_t i = 0; i < total; ++i) {
@@ -230,13 +234,15 @@ static int do_pass(int argc, char** argv) {
     a.nlines = M1 * M2;
     a.M2 = M2;
     a.logW = logW;
-    a.mode = M2 > 1 ? 1 : 0;
+    a.mode = tmode ? tmode : (M2 > 1 ? 1 : 0);
+    a.X = X;
+    a.Y = Y;
     a.scale = 1.0;
     const int W = 1 << logW;
     const int threads = W * tpl;
     // exactly the LDS the host launches the tile with: ASan flags any access beyond it
-    const int P = M2 > 1 ? 1 << logP : 1;
-    std::vector<V> lds((size_t)tile_lds_elems(W, L, P));
+    const int P = (M2 > 1 && !tmode) ? 1 << logP : 1;
+    std::vector<V> lds((size_t)(tmode ? tile_lds_elems_transpose(W, L) : tile_lds_elems(W, L, P)));
     blockDim.x = threads;
     const int64_t nblocks = (a.nlines + W - 1) / W;
     for (int64_t blk = 0; blk < nblocks; ++blk) {

@@ -69,8 +69,9 @@ def emu_binary():
         lines.append("    switch (kid) {")
         for i, (L, seq, tpl) in enumerate(plain_cases(gk, prec)):
             rad = ", ".join(map(str, seq))
-            body = " else ".join(f"if (P == {P}) pass_tile_parts<{vt}, {L}, {tpl}, {P}, {rad}>(a, lds, l0);"
-                                 for P in (1, 2, 4) if gk.splits(L, seq, P))
+            body = " else ".join([f"if (a.mode >= 2) pass_tile_transpose<{vt}, {L}, {tpl}, {rad}>(a, lds, l0);"] +
+                                 [f"if (P == {P}) pass_tile_parts<{vt}, {L}, {tpl}, {P}, {rad}>(a, lds, l0);"
+                                  for P in (1, 2, 4) if gk.splits(L, seq, P)])
             lines.append(f"      case {i}: {body} break;")
         lines.append("      default: break;\n    }\n  }\n};")
     # the level-synchronous body over the batch executor's cases
@@ -255,6 +256,63 @@ def run_pass(exe, dtype, L, seq, tpl, M1, M2, logW, logP):
     got = out.transpose(0, 2, 1).reshape(M1 * M2, L)
     worst = max(oracle.rel_l2(got[i], want[i]) for i in range(M1 * M2))
     assert worst <= oracle.tolerance(L, dtype == torch.complex64), worst
+
+
+def run_tpass(exe, dtype, L, seq, tpl, M1, X, Y, logW, mode):
+    """One transposing pass through the emulated tile code: line l = m1*M2 + m2
+    (M2 = X*Y) is strided in the [M1][L][M2] view and the contiguous row
+    m1*M2 + (m2 mod X)*Y + m2 div X of the other buffer; mode 3 reads the
+    strided side, mode 2 the rows.  Checked line by line against the
+    oracle's naive DFT."""
+    gk = gen_kernels()
+    prec = "f64" if dtype == torch.complex128 else "f32"
+    kid = plain_cases(gk, prec).index((L, seq, tpl))
+    code = "0" if dtype == torch.complex128 else "1"
+    M2 = X * Y
+    args = [exe, "pass", code] + [str(v) for v in (kid, L, M1, M2, logW, 0, tpl, mode, X, Y)]
+    r = subprocess.run(args, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, (r.stdout[:500], r.stderr[-3000:])
+    lines = r.stdout.splitlines()
+    assert lines[0].startswith("OK"), lines[0]
+    vals = np.array([[float(a) for a in ln.split()] for ln in lines[1:]])
+    out = vals[:, 0] + 1j * vals[:, 1]
+    i = np.arange(M1 * L * M2)
+    x = np.sin(0.37 * i + 0.1) + 1j * np.cos(0.91 * i)
+    if dtype == torch.complex64:
+        x = x.astype(np.complex64).astype(np.complex128)
+    m1, m2 = np.divmod(np.arange(M1 * M2), M2)
+    row = m1 * M2 + (m2 % X) * Y + m2 // X
+    assert sorted(row) == list(range(M1 * M2))      # the row map is a permutation
+    strided_in = x.reshape(M1, L, M2).transpose(0, 2, 1).reshape(M1 * M2, L)
+    if mode == 3:
+        want = oracle.fft1_lines(strided_in, method=0)
+        got = out.reshape(M1 * M2, L)[row]
+    else:
+        want = oracle.fft1_lines(x.reshape(M1 * M2, L)[row], method=0)
+        got = out.reshape(M1, L, M2).transpose(0, 2, 1).reshape(M1 * M2, L)
+    worst = max(oracle.rel_l2(got[k], want[k]) for k in range(M1 * M2))
+    assert worst <= oracle.tolerance(L, dtype == torch.complex64), worst
+
+
+# (L, radix sequence, threads per line, M1, X, Y, logW): transposing passes
+# with a ragged last tile (M1*X*Y not a multiple of W), several batches (M1),
+# X or Y of 1, multi-stage and single-stage sequences
+TPASS_CASES = [
+    (64, [8, 8], 8, 2, 5, 4, 4),
+    (60, [5, 4, 3], 12, 3, 7, 2, 3),
+    (128, [16, 8], 8, 1, 12, 3, 5),
+    (48, [16, 3], 3, 2, 1, 9, 4),
+    (32, [32], 1, 3, 6, 1, 2),
+    (160, [16, 5, 2], 10, 1, 4, 5, 3),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
+@pytest.mark.parametrize("mode", [2, 3])
+@pytest.mark.parametrize("case", TPASS_CASES, ids=lambda c: f"L{c[0]}-{'x'.join(map(str, c[1]))}-M1_{c[3]}-X{c[4]}-Y{c[5]}-W{1 << c[6]}")
+def test_emulated_transposing_pass(emu_binary, dtype, mode, case):
+    L, seq, tpl, M1, X, Y, logW = case
+    run_tpass(emu_binary, dtype, L, seq, tpl, M1, X, Y, logW, mode)
 
 
 # (L, radix sequence, threads per line, M1, M2, logW, logP): strided passes

@@ -1,0 +1,82 @@
+"""Host logic of the reversed (cba) output order: plan strings, the heuristic's
+choice of transposing axis, and rejection of unusable plans (no GPU)."""
+import pytest
+import torch
+
+import paper_1501_07350_amd as offt
+
+C128, C64 = torch.complex128, torch.complex64
+
+
+def halves(s):
+    fwd, bwd = s.split("|")
+    return dict(f.split("=", 1) for f in fwd.split(";")), dict(f.split("=", 1) for f in bwd.split(";"))
+
+
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("shape,fwd_rev,bwd_rev", [
+    ((512, 512, 512), "a", "a"),
+    ((64, 48, 30), "a", "a"),
+    ((1, 32, 40), "c", "a"),      # no axis a: the pass along c transposes
+    ((30, 40, 1), "a", "c"),      # the backward plan's grid (1, 40, 30) has no axis a
+    ((6, 1, 10), "a", "a"),
+])
+def test_heuristic_reversed_plans(shape, dtype, fwd_rev, bwd_rev):
+    s = offt.plan_string(shape, dtype, "cba")
+    f, b = halves(s)
+    assert f["rev"] == fwd_rev and b["rev"] == bwd_rev
+    assert f["order"] == "cba" and b["order"] == "cba"
+    # the backward half names the axes of the cba input: its a is the grid's c
+    assert f["a"] == "1" if shape[0] == 1 else f["a"] != "1"
+    assert b["c"] == "1" if shape[0] == 1 else b["c"] != "1"
+    assert offt.plan_string(shape, dtype, "cba", s) == s
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 60), (8, 1, 1), (1, 9, 1), (1, 1, 1)])
+def test_one_axis_grids_need_no_transposing_pass(shape):
+    s = offt.plan_string(shape, C128, "cba")
+    assert "rev=" not in s and s.count("|") == 1
+
+
+BASE = "order=cba;rev=a;a=16x16x2/4;b=16x16x2/4;c=16x16x2/4"
+
+
+@pytest.mark.parametrize("plan", [
+    BASE,                                              # no backward half
+    BASE + "|order=cba;a=16x16x2/4;b=16x16x2/4;c=16x16x2/4",   # backward half without a transposing axis
+    BASE + "|order=cba;rev=b;a=16x16x2/4;b=16x16x2/4;c=16x16x2/4",   # b cannot transpose
+    "order=cba;rev=a;a=16x16x2/4/p2;b=16x16x2/4;c=16x16x2/4|" + BASE,   # parts on the transposing pass
+    "order=cba;rev=c;a=16x16x2/4/p2;b=16x16x2/4;c=16x16x2/4|" + BASE,   # parts on a contiguous cba axis
+])
+def test_unusable_reversed_plans_rejected(plan):
+    with pytest.raises(offt.OfftError) as e:
+        offt.plan_string((512, 512, 512), C128, "cba", plan)
+    assert e.value.code == -6
+
+
+def test_strided_reversed_axis_takes_parts():
+    # after the transposing pass along c, axis b is strided on the cba grid
+    # (stride Na) and accepts exchanges in parts; axis a is contiguous there
+    s = "order=cba;rev=c;a=16x16x2/4;b=16x16x2/4/p2;c=16x16x2/4|" + BASE
+    assert offt.plan_string((512, 512, 512), C128, "cba", s) == s
+
+
+def test_natural_layout_rejects_reversed_strings():
+    for plan in [BASE, BASE + "|" + BASE]:
+        with pytest.raises(offt.OfftError):
+            offt.plan_string((512, 512, 512), C128, "natural", plan)
+    nat = offt.plan_string((512, 512, 512), C128, "natural")
+    assert nat == offt.default_plan_string((512, 512, 512), C128)
+    assert offt.plan_string((512, 512, 512), C128, "natural", nat) == nat
+
+
+def test_one_axis_reversed_plan_rejects_a_transposing_axis():
+    with pytest.raises(offt.OfftError):
+        offt.plan_string((1, 1, 60), C128, "cba", "order=cba;rev=c;a=1;b=1;c=5x4x3/8|order=cba;a=5x4x3/8;b=1;c=1")
+
+
+def test_bad_layout_names_rejected_before_the_device():
+    with pytest.raises(ValueError):
+        offt.plan_string((8, 8, 8), C128, "bca")
+    with pytest.raises(ValueError):
+        offt.Plan((8, 8, 8), layout="zyx")
