@@ -133,6 +133,60 @@ def time_transform(n: int, dtype, steps: int, warmup: int, check: bool, tune: st
     return res
 
 
+def time_reversed(n: int, dtype, steps: int, warmup: int, check: bool, tune: str = "exhaustive"):
+    """Forward and backward transforms whose spectral side is in reversed
+    (cba) order, beside the natural plan of the same tuning, in ms per
+    transform (events around `steps` back-to-back executions)."""
+    import numpy as np
+    import torch
+
+    import paper_1501_07350_amd as offt
+    import synth
+
+    shape = (n, n, n)
+    x = synth.complex_grid(shape, dtype, device="cuda")
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    h = int(stream.cuda_stream)
+
+    def timed(plan, direction, src, dst):
+        for _ in range(warmup):
+            plan.exec_ptr(direction, src.data_ptr(), dst.data_ptr(), h)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            plan.exec_ptr(direction, src.data_ptr(), dst.data_ptr(), h)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    res = {}
+    for name, lay in (("natural", "natural"), ("reversed", "cba")):
+        plan = offt.Plan(shape, dtype=dtype, tune=tune, layout=lay)
+        fwd = timed(plan, offt.FORWARD, x, y)
+        bwd = timed(plan, offt.BACKWARD, y, x)
+        res[name] = {"fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4), "plan": plan.describe()}
+        if name == "reversed" and check:
+            import oracle
+            x.copy_(synth.complex_grid(shape, dtype, device="cuda"))
+            plan.forward(x, out=y.view(shape[::-1]))
+            torch.cuda.synchronize()
+            xh = x.cpu().numpy().astype(np.complex128)
+            yh = y.view(shape[::-1]).cpu().numpy()
+            got, ref = [], []
+            for ka, kb in ((0, 0), (3, 5), (n - 1, 7)):
+                got.append(yh[:, kb, ka].astype(np.complex128))     # Y[c, b, a] = X[a, b, c]
+                ref.append(oracle.dft3_line(xh, ka, kb))
+            res[name]["check_rel_l2_sampled_lines"] = oracle.rel_l2(np.concatenate(got), np.concatenate(ref))
+            res[name]["check_tolerance"] = oracle.tolerance(x.numel(), dtype == torch.complex64)
+        plan.close()
+    res["reversed_over_natural_fwd"] = round(res["reversed"]["fwd_ms"] / res["natural"]["fwd_ms"], 3)
+    del x, y
+    torch.cuda.empty_cache()
+    return res
+
+
 def time_batch(steps: int, warmup: int, check: bool, count: int = 64):
     """Uneven batch of `count` complex64 grids (axes drawn from
     {48,...,160}): persistent launch replayed from a HIP graph vs every grid's
@@ -617,6 +671,10 @@ def main():
     if not args.no_batch:
         out["small"] = time_small(args.steps, args.warmup, not args.no_check)
         out["batch"] = time_batch(args.steps, args.warmup, not args.no_check)
+        out["reversed_output"] = {
+            "workload": f"{n}^3 forward with the output in cba order, and backward from it",
+            "f64": time_reversed(n, torch.complex128, args.steps, args.warmup, not args.no_check),
+            "f32": time_reversed(n, torch.complex64, args.steps, args.warmup, not args.no_check)}
     if args.calibrate:
         calibrate_copy()
     if not args.no_cpu:
