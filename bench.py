@@ -187,6 +187,57 @@ def time_reversed(n: int, dtype, steps: int, warmup: int, check: bool, tune: str
     return res
 
 
+def time_nd(shape, dtype, steps: int, warmup: int, check: bool, tune: str = "exhaustive"):
+    """A grid of 4 or 5 axes: the tuned plan (kernels per axis, then every
+    pass order) and the heuristic plan, ms per forward transform."""
+    import numpy as np
+    import torch
+
+    import paper_1501_07350_amd as offt
+    import synth
+
+    x = synth.complex_grid(shape, dtype, device="cuda")
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    h = int(stream.cuda_stream)
+    N = x.numel()
+    s = x.element_size()
+    res = {"shape": list(shape), "dtype": "f64" if dtype == torch.complex128 else "f32"}
+    for name, t in (("tuned", tune), ("heuristic", "none")):
+        t0 = time.perf_counter()
+        plan = offt.Plan(shape, dtype=dtype, tune=t)
+        plan_s = time.perf_counter() - t0
+        for _ in range(warmup):
+            plan.exec_ptr(offt.FORWARD, x.data_ptr(), y.data_ptr(), h)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            plan.exec_ptr(offt.FORWARD, x.data_ptr(), y.data_ptr(), h)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        npass = plan.npasses()
+        res[name] = {"ms": round(ms, 4), "gflops": round(5.0 * N * math.log2(N) / (ms * 1e6), 1),
+                     "eff_gbs": round(2.0 * npass * N * s / (ms * 1e6), 1), "plan": plan.describe(),
+                     "plan_seconds": round(plan_s, 3)}
+        plan.close()
+    if check:
+        import oracle
+        from oracle import ndim
+        xh = x.cpu().numpy()
+        yh = y.cpu().numpy()
+        pts = [tuple(0 for _ in shape), tuple(min(i + 1, n - 1) for i, n in enumerate(shape)),
+               tuple(n - 1 for n in shape)]
+        got = np.array([yh[k] for k in pts], dtype=np.complex128)
+        ref = np.array([ndim.dftn_point(xh, k) for k in pts])
+        res["check_rel_l2_sampled_points"] = oracle.rel_l2(got, ref)
+        res["check_tolerance"] = oracle.tolerance(N, dtype == torch.complex64)
+    del x, y
+    torch.cuda.empty_cache()
+    return res
+
+
 def time_batch(steps: int, warmup: int, check: bool, count: int = 64):
     """Uneven batch of `count` complex64 grids (axes drawn from
     {48,...,160}): persistent launch replayed from a HIP graph vs every grid's
@@ -675,6 +726,9 @@ def main():
             "workload": f"{n}^3 forward with the output in cba order, and backward from it",
             "f64": time_reversed(n, torch.complex128, args.steps, args.warmup, not args.no_check),
             "f32": time_reversed(n, torch.complex64, args.steps, args.warmup, not args.no_check)}
+        out["nd"] = [time_nd((128, 128, 128, 128), torch.complex64, args.steps, args.warmup, not args.no_check),
+                     time_nd((128, 128, 128, 128), torch.complex128, args.steps, args.warmup, False),
+                     time_nd((48, 48, 48, 48, 48), torch.complex64, args.steps, args.warmup, not args.no_check)]
     if args.calibrate:
         calibrate_copy()
     if not args.no_cpu:

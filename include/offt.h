@@ -132,6 +132,35 @@ offt_plan_t offt_plan_ex(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t 
 
 #define OFFT_MAX_AXIS 1024
 
+/* ---- grids of 1 to 5 axes -------------------------------------------------
+ * The decomposition method is stated for multi-dimensional transforms, axes
+ * named a, b, c, ... for the first, second, third dimension (Sec. 1), and the
+ * package's future work goes beyond three dimensions (Sec. 5).  A plan for
+ * `batch` grids of dims[0] x ... x dims[ndim-1] points, row-major with the
+ * last axis fastest (a contiguous tensor of shape (batch?, *dims)),
+ * 1 <= ndim <= OFFT_MAX_DIMS, each axis as in offt_plan.
+ *   ndim <= 3: the three-dimensional plan of the shape padded with leading
+ *              unit axes (every option of offt_plan_ex applies).
+ *   ndim 4, 5: one axis pass per axis longer than 1 on the same kernels,
+ *              lines of axis i strided by the product of the later axes.
+ *              The heuristic runs the passes from the last axis to the
+ *              first; OFFT_TUNE_EXHAUSTIVE times every kernel and tile width
+ *              of each axis, then every order of the passes (up to 5! = 120,
+ *              the GPU counterpart of the paper's search over transpose
+ *              orders); OFFT_TUNE_LEARNED falls back to it.  Plan strings
+ *              name the axes a..e ("order=edcba;a=...;...;e=...").  The layout
+ *              must be OFFT_LAYOUT_NATURAL.
+ * Executed, described and destroyed with the same calls as offt_plan.
+ * Errors as offt_plan_ex. */
+#define OFFT_MAX_DIMS 5
+offt_plan_t offt_plan_nd(int ndim, const int64_t* dims, int dtype, int64_t batch, const offt_opts* o);
+
+/* Plan string of a 4- or 5-axis grid without a device: with plan == NULL the
+ * heuristic plan, else `plan` checked and in canonical form (as
+ * offt_plan_string).  Returns the full length or INVALID_ARG /
+ * UNSUPPORTED_SIZE / BAD_PLAN. */
+int offt_plan_string_nd(int ndim, const int64_t* dims, int dtype, const char* plan, char* buf, size_t n);
+
 /* Forward / backward transform of the plan's `batch` grids from `in` to `out`
  * (device pointers, layout above).  in == out is allowed (in place); any other
  * overlap is invalid.  Never allocates, never synchronises.

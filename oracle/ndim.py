@@ -58,15 +58,16 @@ def fftn_batch(x, ndim: int, sign: int = FORWARD, nthreads: int = 0) -> np.ndarr
 
 
 def dftn_point(x, k, sign: int = FORWARD) -> complex:
-    """One output X[k] straight from the D-fold sum of the definition (for
-    sampled checks of large grids: O(N) per point)."""
-    x = _as_c128(x)
+    """One output X[k] straight from the D-fold sum of the definition, summed
+    over one coordinate at a time, the first coordinate first: O(N) work per
+    point, for sampled checks of large grids."""
+    x = np.asarray(x)
     if len(k) != x.ndim:
         raise ValueError("index has the wrong number of coordinates")
-    w = np.ones((), dtype=np.complex128)
-    for i, (n, ki) in enumerate(zip(x.shape, k)):
+    y = x
+    for n, ki in zip(x.shape, k):
         j = np.arange(n)
         # exact exponent reduction: (j k) mod n before the division by n
         phase = np.exp(sign * 2j * np.pi * ((j * ki) % n) / n)
-        w = np.multiply.outer(w, phase)
-    return complex(np.sum(x * w))
+        y = np.tensordot(phase, y.astype(np.complex128, copy=False), axes=(0, 0))
+    return complex(y)

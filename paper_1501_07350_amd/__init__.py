@@ -22,7 +22,7 @@ from ._lib import (BACKWARD, C2C_F32, C2C_F64, FORWARD, MANY_LEVELS, MANY_LEVELS
                    LAYOUT_NATURAL, LAYOUT_REVERSED, MAX_AXIS, OfftError,
                    TUNE_EXHAUSTIVE, TUNE_FORCED, TUNE_LEARNED, TUNE_NONE)
 
-__all__ = ["Plan", "ManyPlan", "OfftError", "twiddles", "default_plan_string", "plan_string", "pass_bytes",
+__all__ = ["Plan", "ManyPlan", "OfftError", "twiddles", "default_plan_string", "plan_string", "plan_string_nd", "pass_bytes",
            "decomp_start", "transpose_count", "transpose_volume", "FORWARD", "BACKWARD", "MAX_AXIS"]
 
 _LAYOUT = {"natural": LAYOUT_NATURAL, "abc": LAYOUT_NATURAL, "cba": LAYOUT_REVERSED,
@@ -77,15 +77,17 @@ class Plan:
     """Plan for `batch` grids of `shape` = (Na, Nb, Nc).  use_graph: forward
     and backward replay a HIP graph of the pass kernels (captured by the first
     call, updated when buffers or direction change).  layout="cba": forward
-    output and backward input are (batch?, Nc, Nb, Na), Y[c, b, a] = X[a, b, c]."""
+    output and backward input are (batch?, Nc, Nb, Na), Y[c, b, a] = X[a, b, c].
+    `shape` may have 1 to 5 axes (row-major, last axis fastest); up to three
+    are the three-dimensional plan of the shape padded with unit axes."""
 
     def __init__(self, shape, dtype=torch.complex128, batch: int = 1, tune: str = "none",
                  normalize_inverse: bool = False, forced_plan: str | None = None,
                  cache_path: str | None = None, weights_path: str | None = None, reps: int = 2,
                  tune_inplace: bool = False, use_graph: bool = False, layout: str = "natural"):
         lib = _lib.load()
-        if len(shape) != 3:
-            raise ValueError("shape must be (Na, Nb, Nc)")
+        if not 1 <= len(shape) <= _lib.MAX_DIMS:
+            raise ValueError(f"shape must have 1 to {_lib.MAX_DIMS} axes")
         self.shape = tuple(int(s) for s in shape)
         self.dtype = dtype
         self.batch = int(batch)
@@ -95,11 +97,15 @@ class Plan:
         stream = _stream_handle() if torch.cuda.is_available() else None
         opts, keep = _make_opts(tune, reps, normalize_inverse, forced_plan, cache_path, weights_path,
                                 stream, tune_inplace, use_graph, layout)
-        h = lib.offt_plan_ex(self.shape[0], self.shape[1], self.shape[2], code, self.batch,
-                             ctypes.byref(opts))
+        if len(self.shape) == 3:
+            h = lib.offt_plan_ex(self.shape[0], self.shape[1], self.shape[2], code, self.batch,
+                                 ctypes.byref(opts))
+        else:
+            dims = (ctypes.c_int64 * len(self.shape))(*self.shape)
+            h = lib.offt_plan_nd(len(self.shape), dims, code, self.batch, ctypes.byref(opts))
         del keep
         if not h:
-            raise OfftError(_lib.last_error(), f"offt_plan_ex{self.shape}")
+            raise OfftError(_lib.last_error(), f"offt_plan{self.shape}")
         self._h = h
 
     @property
@@ -114,15 +120,17 @@ class Plan:
             raise ValueError(f"{name} has dtype {x.dtype}, plan expects {self.dtype}")
         if not x.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
-        n = self.batch * shape[0] * shape[1] * shape[2]
-        if x.numel() != n or tuple(x.shape[-3:]) != tuple(shape):
+        n = self.batch
+        for v in shape:
+            n *= v
+        if x.numel() != n or tuple(x.shape[-len(shape):]) != tuple(shape):
             raise ValueError(f"{name} has shape {tuple(x.shape)}, plan expects "
                              f"{(self.batch,) + tuple(shape) if self.batch > 1 else tuple(shape)}")
 
     def _run(self, fn, x, out, in_shape, out_shape):
         self._check_tensor(x, "x", in_shape)
         if out is None:
-            out = torch.empty(x.shape[:-3] + tuple(out_shape), dtype=x.dtype, device=x.device)
+            out = torch.empty(x.shape[:-len(out_shape)] + tuple(out_shape), dtype=x.dtype, device=x.device)
         else:
             self._check_tensor(out, "out", out_shape)
         _lib.check(fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
@@ -264,6 +272,19 @@ def plan_string(shape, dtype=torch.complex128, layout: str = "natural", plan: st
     n = _lib.check(lib.offt_plan_string(shape[0], shape[1], shape[2], code, lay, p, None, 0), "plan string")
     buf = ctypes.create_string_buffer(n + 1)
     lib.offt_plan_string(shape[0], shape[1], shape[2], code, lay, p, buf, n + 1)
+    return buf.value.decode()
+
+
+def plan_string_nd(shape, dtype=torch.complex128, plan: str | None = None) -> str:
+    """Heuristic plan string of a 4- or 5-axis grid, or `plan` checked and in
+    canonical form (no device needed)."""
+    lib = _lib.load()
+    code = _dtype_code(dtype)
+    dims = (ctypes.c_int64 * len(shape))(*[int(v) for v in shape])
+    p = plan.encode() if plan is not None else None
+    n = _lib.check(lib.offt_plan_string_nd(len(shape), dims, code, p, None, 0), "plan string")
+    buf = ctypes.create_string_buffer(n + 1)
+    lib.offt_plan_string_nd(len(shape), dims, code, p, buf, n + 1)
     return buf.value.decode()
 
 

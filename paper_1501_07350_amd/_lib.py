@@ -41,6 +41,7 @@ MANY_LEVELS = 3
 MANY_SYNC = 4
 MANY_SYNC_GRAPH = 5
 MAX_AXIS = 1024
+MAX_DIMS = 5
 
 # order of transformed grids (offt_opts.layout)
 LAYOUT_NATURAL = 0
@@ -82,6 +83,8 @@ SIGNATURES = {
     "offt_twiddles": (_ci, [_i64, _ci, _vp]),
     "offt_default_plan_string": (_ci, [_i64, _i64, _i64, _ci, ctypes.c_char_p, ctypes.c_size_t]),
     "offt_plan_string": (_ci, [_i64, _i64, _i64, _ci, _ci, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t]),
+    "offt_plan_nd": (_vp, [_ci, ctypes.POINTER(_i64), _ci, _i64, ctypes.POINTER(Opts)]),
+    "offt_plan_string_nd": (_ci, [_ci, ctypes.POINTER(_i64), _ci, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t]),
     "offt_feature_dim": (_ci, []),
     "offt_candidates": (_ci, [_i64, _i64, _i64, _ci, _i64, ctypes.c_char_p, ctypes.c_size_t,
                               ctypes.POINTER(ctypes.c_float), _ci]),

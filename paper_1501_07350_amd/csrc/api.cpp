@@ -96,7 +96,7 @@ const PassPlan* dir_passes(const offt_plan_s* p, int dir) {
 
 int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const void* in, void* out,
                 void* work, int dir, hipStream_t s) {
-    const int64_t N = p->dims[0] * p->dims[1] * p->dims[2];
+    const int64_t N = p->grid_elems();
     if (npass == 0) {
         if (in != out) {
             const size_t bytes = (size_t)(N * p->batch) * elem_size(p->dtype);
@@ -119,6 +119,15 @@ int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const v
 }
 
 }  // namespace offt
+
+int64_t offt_plan_s::grid_elems() const {
+    if (kind == 3) {
+        int64_t n = 1;
+        for (int i = 0; i < ndim; ++i) n *= nd_dims[i];
+        return n;
+    }
+    return dims[0] * dims[1] * dims[2];
+}
 
 int64_t offt_plan_s::workspace_bytes() const {
     int64_t b = 0;
@@ -270,6 +279,94 @@ offt_plan_t offt_plan_ex(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t 
     return p;
 }
 
+// Grids of 1 to 5 axes.  Up to three axes are the three-dimensional plan of
+// the shape padded with leading unit axes; 4 and 5 axes get a kind-3 plan
+// over the same pass kernels.
+static int validate_nd(int ndim, const int64_t* dims, int dtype, int64_t batch) {
+    if (ndim < 1 || ndim > OFFT_MAX_DIMS || !dims) return OFFT_ERR_INVALID_ARG;
+    if (dtype != OFFT_C2C_F64 && dtype != OFFT_C2C_F32) return OFFT_ERR_INVALID_ARG;
+    if (batch < 1) return OFFT_ERR_INVALID_ARG;
+    long double bytes = (long double)batch * elem_size(dtype);
+    for (int i = 0; i < ndim; ++i) {
+        if (dims[i] < 1) return OFFT_ERR_INVALID_ARG;
+        if (!smooth235(dims[i]) || dims[i] > OFFT_MAX_AXIS) return OFFT_ERR_UNSUPPORTED_SIZE;
+        bytes *= (long double)dims[i];
+    }
+    if (bytes > 9.0e18L) return OFFT_ERR_INVALID_ARG;
+    return OFFT_SUCCESS;
+}
+
+offt_plan_t offt_plan_nd(int ndim, const int64_t* dims, int dtype, int64_t batch, const offt_opts* o) {
+    int rc = validate_nd(ndim, dims, dtype, batch);
+    if (rc != OFFT_SUCCESS) { set_error(rc); return nullptr; }
+    if (ndim <= 3) {
+        int64_t d3[3] = {1, 1, 1};
+        for (int i = 0; i < ndim; ++i) d3[3 - ndim + i] = dims[i];
+        return offt_plan_ex(d3[0], d3[1], d3[2], dtype, batch, o);
+    }
+    offt_opts opts;
+    offt_opts_default(&opts);
+    if (o) opts = *o;
+    if (opts.tune < OFFT_TUNE_NONE || opts.tune > OFFT_TUNE_FORCED || (opts.tune == OFFT_TUNE_FORCED && !opts.forced_plan) ||
+        opts.reps < 1 || (opts.use_graph != 0 && opts.use_graph != 1) || opts.layout != OFFT_LAYOUT_NATURAL) {
+        set_error(OFFT_ERR_INVALID_ARG);
+        return nullptr;
+    }
+    NdChoice choice = default_choice_nd(dtype, ndim, dims);
+    if (opts.tune == OFFT_TUNE_FORCED && !nd_choice_from_string(opts.forced_plan, dtype, ndim, dims, &choice)) {
+        set_error(OFFT_ERR_BAD_PLAN);
+        return nullptr;
+    }
+    rc = check_device();
+    if (rc != OFFT_SUCCESS) { set_error(rc); return nullptr; }
+    offt_plan_s* p = new offt_plan_s();
+    p->kind = 3;
+    p->dtype = dtype;
+    p->ndim = ndim;
+    for (int i = 0; i < ndim; ++i) p->nd_dims[i] = dims[i];
+    p->batch = batch;
+    p->normalize = opts.normalize_inverse ? 1 : 0;
+    hipStream_t s = static_cast<hipStream_t>(opts.stream);
+    if (opts.tune == OFFT_TUNE_EXHAUSTIVE || opts.tune == OFFT_TUNE_LEARNED) {
+        rc = select_plan_nd(p, opts, &choice);
+        if (rc != OFFT_SUCCESS) { free_plan(p); set_error(rc); return nullptr; }
+    }
+    p->ndc = choice;
+    p->npass = build_passes_nd(choice, p->nd_dims, batch, p->passes);
+    for (int i = 0; i < p->npass && rc == OFFT_SUCCESS; ++i)
+        if (!p->passes[i].k) rc = OFFT_ERR_UNSUPPORTED_SIZE;
+    if (rc == OFFT_SUCCESS) rc = attach_twiddles(p, p->passes, p->npass, s);
+    if (rc == OFFT_SUCCESS && hipStreamSynchronize(s) != hipSuccess) rc = OFFT_ERR_HIP;
+    p->use_graph = opts.use_graph;
+    if (rc == OFFT_SUCCESS && p->use_graph && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        p->cap = nullptr;
+        rc = OFFT_ERR_HIP;
+    }
+    if (rc != OFFT_SUCCESS) { free_plan(p); set_error(rc); return nullptr; }
+    set_error(OFFT_SUCCESS);
+    return p;
+}
+
+int offt_plan_string_nd(int ndim, const int64_t* dims, int dtype, const char* plan, char* buf, size_t n) {
+    int rc = validate_nd(ndim, dims, dtype, 1);
+    if (rc == OFFT_SUCCESS && (ndim < 4 || (!buf && n))) rc = OFFT_ERR_INVALID_ARG;
+    if (rc != OFFT_SUCCESS) { set_error(rc); return rc; }
+    NdChoice c = default_choice_nd(dtype, ndim, dims);
+    if (plan && !nd_choice_from_string(plan, dtype, ndim, dims, &c, false)) {
+        set_error(OFFT_ERR_BAD_PLAN);
+        return OFFT_ERR_BAD_PLAN;
+    }
+    const std::string s = nd_choice_to_string(c, dims);
+    if (n) {
+        const size_t m = std::min(n - 1, s.size());
+        memcpy(buf, s.data(), m);
+        buf[m] = 0;
+    }
+    set_error(OFFT_SUCCESS);
+    return (int)s.size();
+}
+
 // use_graph: capture the passes for (in, out, dir) on the plan's private
 // stream.  Each direction has its own instantiated graph: the first capture
 // is instantiated, later ones (other buffers) update it in place
@@ -315,7 +412,7 @@ static int capture_passes(offt_plan_s* p, const void* in, void* out, int dir) {
 
 static int exec_checked(offt_plan_t p, const void* in, void* out, void* stream, int dir) {
     if (!p || !in || !out) { set_error(OFFT_ERR_INVALID_ARG); return OFFT_ERR_INVALID_ARG; }
-    if (p->kind != 1) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
+    if (p->kind != 1 && p->kind != 3) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
     const hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = OFFT_SUCCESS;
     if (p->use_graph && p->npass > 0) {
@@ -342,7 +439,7 @@ int offt_exec_bwd(offt_plan_t p, const void* in, void* out, void* stream) {
 
 int offt_plan_passes(offt_plan_t p) {
     if (!p) { set_error(OFFT_ERR_INVALID_ARG); return OFFT_ERR_INVALID_ARG; }
-    if (p->kind != 1) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
+    if (p->kind != 1 && p->kind != 3) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
     set_error(OFFT_SUCCESS);
     return p->npass;
 }
@@ -352,9 +449,9 @@ int offt_exec_pass(offt_plan_t p, int i, int direction, const void* in, void* ou
         set_error(OFFT_ERR_INVALID_ARG);
         return OFFT_ERR_INVALID_ARG;
     }
-    if (p->kind != 1) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
+    if (p->kind != 1 && p->kind != 3) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
     if (i < 0 || i >= p->npass) { set_error(OFFT_ERR_INVALID_ARG); return OFFT_ERR_INVALID_ARG; }
-    const int64_t N = p->dims[0] * p->dims[1] * p->dims[2];
+    const int64_t N = p->grid_elems();
     const bool bwd = direction == OFFT_BACKWARD;
     const bool last = i == p->npass - 1;
     const double scale = (bwd && last && p->normalize) ? 1.0 / (double)N : 1.0;

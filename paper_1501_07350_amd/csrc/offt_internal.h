@@ -12,6 +12,7 @@
 namespace offt {
 
 constexpr int kMaxStages = 8;
+constexpr int kMaxDims = 5;       // axes of the grids of a D-dimensional plan
 // Bytes of LDS a pass tile may use: the device's per-workgroup limit (160 KiB
 // on gfx950), 64 KiB when no device is visible.
 int64_t lds_limit();
@@ -99,6 +100,20 @@ int transpose_index(const PassPlan* ps, int n);
 // the workspace is needed and `work` is null.
 bool pass_io(const PassPlan* ps, int n, int i, const void* in, void* out, void* work, const void** src,
              void** dst);
+
+// Plan choice for a grid of 4 or 5 axes (every axis on the input's order).
+struct NdChoice {
+    int ndim = 0;
+    int order[kMaxDims];              // axis order of the passes
+    const KernelEntry* k[kMaxDims];   // per axis; nullptr for length 1
+    int logW[kMaxDims];
+};
+PassPlan make_pass_nd(int ndim, const int64_t* dims, int64_t batch, int ax, const KernelEntry* k, int logW);
+NdChoice default_choice_nd(int dtype, int ndim, const int64_t* dims);
+std::string nd_choice_to_string(const NdChoice& c, const int64_t* dims);
+bool nd_choice_from_string(const char* s, int dtype, int ndim, const int64_t* dims, NdChoice* out,
+                           bool check_fit = true);
+int build_passes_nd(const NdChoice& c, const int64_t* dims, int64_t batch, PassPlan* out);
 
 size_t elem_size(int dtype);
 bool smooth235(int64_t n);

@@ -15,14 +15,18 @@ struct ManyState;
 }
 
 struct offt_plan_s {
-    int kind = 0;                 // 1: one grid shape (+batch), 2: uneven batch
+    int kind = 0;                 // 1: one grid shape (+batch), 2: uneven batch, 3: 4-D / 5-D grids
     int dtype = 0;
     int64_t dims[3] = {1, 1, 1};
     int64_t batch = 1;
     int normalize = 0;
     offt::PlanChoice choice{};
-    offt::PassPlan passes[3]{};
+    offt::PassPlan passes[offt::kMaxDims]{};
     int npass = 0;
+    // kind 3: the grid's axes and the plan over them
+    int ndim = 3;
+    int64_t nd_dims[offt::kMaxDims] = {1, 1, 1, 1, 1};
+    offt::NdChoice ndc{};
     // OFFT_LAYOUT_REVERSED: the backward transform reads cba grids, so it is
     // planned as a transform of the reversed shape (Nc, Nb, Na) whose output
     // is reversed back to abc; both directions route through `work` (one
@@ -46,6 +50,7 @@ struct offt_plan_s {
     void* g_out[2] = {nullptr, nullptr};
 
     int64_t workspace_bytes() const;
+    int64_t grid_elems() const;   // points of one grid
 };
 
 namespace offt {
@@ -65,6 +70,8 @@ void free_plan(offt_plan_s* p);
 // Tuning (tuner.cpp): fills *choice for EXHAUSTIVE / LEARNED modes.
 // For reversed layouts also *choice_b (the backward plan on the reversed shape).
 int select_plan(offt_plan_s* p, const offt_opts& o, PlanChoice* choice, PlanChoice* choice_b);
+// The same for kind-3 plans (EXHAUSTIVE; LEARNED falls back to it).
+int select_plan_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice);
 std::string describe_plan(const offt_plan_s* p);
 
 // Uneven batches (many.hip).

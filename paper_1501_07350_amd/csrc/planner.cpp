@@ -351,7 +351,85 @@ std::vector<PlanChoice> candidate_choices(int dtype, const int64_t dims[3]) {
     return out;
 }
 
-static const char kAxisName[] = "abc";
+static const char kAxisName[] = "abcde";
+
+// ---- plan strings ---------------------------------------------------------------
+// One axis: "<radix sequence>/<tile width>[/<threads per line>][/p<parts>]",
+// or "1" for a length-1 axis.
+
+static void axis_to_string(std::ostringstream& os, const KernelEntry* k, int logW, int64_t len) {
+    if (!k || len <= 1) {
+        os << "1";
+        return;
+    }
+    for (int i = 0; i < k->nstages; ++i) os << (i ? "x" : "") << k->radices[i];
+    os << "/" << (1 << logW);
+    if (k->tpl != default_tpl(k)) os << "/" << k->tpl;
+    if (k->nparts > 1) os << "/p" << k->nparts;
+}
+
+namespace {
+struct AxisSpec {
+    bool given = false;
+    std::vector<int> rad;
+    long W = 0, tpl = 0, P = 1;
+};
+}  // namespace
+
+static bool parse_axis_spec(const std::string& val, AxisSpec* sp) {
+    sp->given = true;
+    const size_t slash = val.find('/');
+    if (slash == std::string::npos) return false;
+    std::stringstream rs(val.substr(0, slash));
+    std::string tok;
+    while (std::getline(rs, tok, 'x')) {
+        char* end = nullptr;
+        const long r = strtol(tok.c_str(), &end, 10);
+        if (!end || *end || r < 2) return false;
+        sp->rad.push_back((int)r);
+    }
+    char* end = nullptr;
+    sp->W = strtol(val.c_str() + slash + 1, &end, 10);
+    if (!end || sp->W < 1 || (sp->W & (sp->W - 1))) return false;
+    if (*end == '/' && end[1] != 'p') {   // threads per line (default: the sequence's)
+        char* end2 = nullptr;
+        sp->tpl = strtol(end + 1, &end2, 10);
+        if (!end2 || sp->tpl < 1) return false;
+        end = end2;
+    }
+    if (*end == '/' && end[1] == 'p') {   // parts of each LDS exchange (strided axes)
+        char* end2 = nullptr;
+        sp->P = strtol(end + 2, &end2, 10);
+        if (!end2 || (sp->P != 1 && sp->P != 2 && sp->P != 4)) return false;
+        end = end2;
+    }
+    return *end == 0;
+}
+
+static const KernelEntry* find_kernel(int dtype, int L, const AxisSpec& sp) {
+    for (const KernelEntry* k : kernels_for(dtype, L)) {
+        if (k->nstages != (int)sp.rad.size()) continue;
+        bool eq = true;
+        for (int i = 0; i < k->nstages; ++i) eq = eq && k->radices[i] == sp.rad[i];
+        if (eq && k->tpl == (sp.tpl ? (int)sp.tpl : default_tpl(k)) && k->nparts == (int)sp.P) return k;
+    }
+    return nullptr;
+}
+
+// "order=<axis letters>": a permutation of the first ndim letters
+static bool parse_order(const std::string& val, int ndim, int* order) {
+    if ((int)val.size() != ndim) return false;
+    bool seen[kMaxDims] = {false, false, false, false, false};
+    for (int i = 0; i < ndim; ++i) {
+        const char* p = val[i] ? strchr(kAxisName, val[i]) : nullptr;
+        if (!p || p - kAxisName >= ndim) return false;
+        const int ax = int(p - kAxisName);
+        if (seen[ax]) return false;
+        seen[ax] = true;
+        order[i] = ax;
+    }
+    return true;
+}
 
 std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]) {
     std::ostringstream os;
@@ -359,25 +437,14 @@ std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]) {
     if (c.tax >= 0) os << ";rev=" << kAxisName[c.tax];
     for (int ax = 0; ax < 3; ++ax) {
         os << ";" << kAxisName[ax] << "=";
-        if (!c.k[ax] || dims[ax] <= 1) {
-            os << "1";
-            continue;
-        }
-        for (int i = 0; i < c.k[ax]->nstages; ++i) os << (i ? "x" : "") << c.k[ax]->radices[i];
-        os << "/" << (1 << c.logW[ax]);
-        if (c.k[ax]->tpl != default_tpl(c.k[ax])) os << "/" << c.k[ax]->tpl;
-        if (c.k[ax]->nparts > 1) os << "/p" << c.k[ax]->nparts;
+        axis_to_string(os, c.k[ax], c.logW[ax], dims[ax]);
     }
     return os.str();
 }
 
 bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanChoice* out, bool check_fit) {
     if (!s) return false;
-    struct AxisSpec {
-        bool given = false;
-        std::vector<int> rad;
-        long W = 0, tpl = 0, P = 1;
-    } spec[3];
+    AxisSpec spec[3];
     PlanChoice c;
     c.tax = -1;
     std::string str(s);
@@ -389,55 +456,19 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
         if (eq == std::string::npos) return false;
         const std::string key = item.substr(0, eq), val = item.substr(eq + 1);
         if (key == "order") {
-            if (val.size() != 3) return false;
-            bool seen[3] = {false, false, false};
-            for (int i = 0; i < 3; ++i) {
-                const char* p = strchr(kAxisName, val[i]);
-                if (!p || val[i] == 0) return false;
-                const int ax = int(p - kAxisName);
-                if (seen[ax]) return false;
-                seen[ax] = true;
-                c.order[i] = ax;
-            }
+            if (!parse_order(val, 3, c.order)) return false;
             have_order = true;
         } else if (key == "rev") {
             if (val == "a") c.tax = 0;
             else if (val == "c") c.tax = 2;
             else return false;
-        } else if (key.size() == 1 && strchr(kAxisName, key[0]) && key[0]) {
-            const int ax = int(strchr(kAxisName, key[0]) - kAxisName);
+        } else if (key.size() == 1 && key[0] >= 'a' && key[0] <= 'c') {
+            const int ax = key[0] - 'a';
             if (dims[ax] <= 1) {
                 if (val != "1") return false;
                 continue;
             }
-            AxisSpec& sp = spec[ax];
-            sp.given = true;
-            const size_t slash = val.find('/');
-            if (slash == std::string::npos) return false;
-            std::stringstream rs(val.substr(0, slash));
-            std::string tok;
-            while (std::getline(rs, tok, 'x')) {
-                char* end = nullptr;
-                const long r = strtol(tok.c_str(), &end, 10);
-                if (!end || *end || r < 2) return false;
-                sp.rad.push_back((int)r);
-            }
-            char* end = nullptr;
-            sp.W = strtol(val.c_str() + slash + 1, &end, 10);
-            if (!end || sp.W < 1 || (sp.W & (sp.W - 1))) return false;
-            if (*end == '/' && end[1] != 'p') {   // threads per line (default: the sequence's)
-                char* end2 = nullptr;
-                sp.tpl = strtol(end + 1, &end2, 10);
-                if (!end2 || sp.tpl < 1) return false;
-                end = end2;
-            }
-            if (*end == '/' && end[1] == 'p') {   // parts of each LDS exchange (strided axes)
-                char* end2 = nullptr;
-                sp.P = strtol(end + 2, &end2, 10);
-                if (!end2 || (sp.P != 1 && sp.P != 2 && sp.P != 4)) return false;
-                end = end2;
-            }
-            if (*end) return false;
+            if (!parse_axis_spec(val, &spec[ax])) return false;
         } else {
             return false;
         }
@@ -452,16 +483,7 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
         const int g = axis_geom(c, ax);
         const bool strided = g == kGeomTranspose || make_pass(dims, 1, ax, g, nullptr, 0).M2 > 1;
         if (sp.P > 1 && (g == kGeomTranspose || !strided)) return false;
-        const KernelEntry* found = nullptr;
-        for (const KernelEntry* k : kernels_for(dtype, (int)dims[ax])) {
-            if (k->nstages != (int)sp.rad.size()) continue;
-            bool eq2 = true;
-            for (int i = 0; i < k->nstages; ++i) eq2 = eq2 && k->radices[i] == sp.rad[i];
-            if (eq2 && k->tpl == (sp.tpl ? (int)sp.tpl : default_tpl(k)) && k->nparts == (int)sp.P) {
-                found = k;
-                break;
-            }
-        }
+        const KernelEntry* found = find_kernel(dtype, (int)dims[ax], sp);
         if (!found || (g == kGeomTranspose && !found->launch_t)) return false;
         const int lw = ilog2(sp.W);
         if (check_fit && !tile_fits_geom(found, lw, dtype, g)) return false;
@@ -470,6 +492,111 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
     }
     *out = c;
     return true;
+}
+
+// ---- grids of more than three dimensions -------------------------------------
+
+PassPlan make_pass_nd(int ndim, const int64_t* dims, int64_t batch, int ax, const KernelEntry* k, int logW) {
+    PassPlan p;
+    p.axis = ax;
+    p.L = (int)dims[ax];
+    p.k = k;
+    p.logW = logW;
+    p.tw = nullptr;
+    p.X = 1;
+    p.Y = 1;
+    int64_t before = 1, after = 1;
+    for (int j = 0; j < ax; ++j) before *= dims[j];
+    for (int j = ax + 1; j < ndim; ++j) after *= dims[j];
+    p.M1 = batch * before;
+    p.M2 = after;
+    p.mode = after > 1 ? 1 : 0;
+    return p;
+}
+
+// Heuristic: passes from the last (contiguous) axis to the first, each axis
+// with the kernel and width the three-dimensional heuristic gives a line of
+// its length and stride kind.
+NdChoice default_choice_nd(int dtype, int ndim, const int64_t* dims) {
+    NdChoice c;
+    c.ndim = ndim;
+    for (int i = 0; i < ndim; ++i) c.order[i] = ndim - 1 - i;
+    for (int ax = 0; ax < ndim; ++ax) {
+        c.k[ax] = nullptr;
+        c.logW[ax] = 0;
+        if (dims[ax] <= 1) continue;
+        const bool strided = make_pass_nd(ndim, dims, 1, ax, nullptr, 0).M2 > 1;
+        const KernelEntry* k = default_kernel(dtype, (int)dims[ax], strided);
+        if (k) {
+            c.k[ax] = k;
+            c.logW[ax] = default_logW(k, dtype, strided);
+        }
+    }
+    return c;
+}
+
+std::string nd_choice_to_string(const NdChoice& c, const int64_t* dims) {
+    std::ostringstream os;
+    os << "order=";
+    for (int i = 0; i < c.ndim; ++i) os << kAxisName[c.order[i]];
+    for (int ax = 0; ax < c.ndim; ++ax) {
+        os << ";" << kAxisName[ax] << "=";
+        axis_to_string(os, c.k[ax], c.logW[ax], dims[ax]);
+    }
+    return os.str();
+}
+
+bool nd_choice_from_string(const char* s, int dtype, int ndim, const int64_t* dims, NdChoice* out,
+                           bool check_fit) {
+    if (!s || ndim < 1 || ndim > kMaxDims) return false;
+    AxisSpec spec[kMaxDims];
+    NdChoice c = default_choice_nd(dtype, ndim, dims);
+    std::string str(s);
+    std::stringstream ss(str);
+    std::string item;
+    bool have_order = false;
+    while (std::getline(ss, item, ';')) {
+        const size_t eq = item.find('=');
+        if (eq == std::string::npos) return false;
+        const std::string key = item.substr(0, eq), val = item.substr(eq + 1);
+        if (key == "order") {
+            if (!parse_order(val, ndim, c.order)) return false;
+            have_order = true;
+        } else if (key.size() == 1 && key[0] >= 'a' && key[0] < 'a' + ndim) {
+            const int ax = key[0] - 'a';
+            if (dims[ax] <= 1) {
+                if (val != "1") return false;
+                continue;
+            }
+            if (!parse_axis_spec(val, &spec[ax])) return false;
+        } else {
+            return false;
+        }
+    }
+    if (!have_order) return false;
+    for (int ax = 0; ax < ndim; ++ax) {
+        if (!spec[ax].given) continue;
+        const bool strided = make_pass_nd(ndim, dims, 1, ax, nullptr, 0).M2 > 1;
+        if (spec[ax].P > 1 && !strided) return false;
+        const KernelEntry* found = find_kernel(dtype, (int)dims[ax], spec[ax]);
+        if (!found) return false;
+        const int lw = ilog2(spec[ax].W);
+        if (check_fit && !tile_fits(found, lw, dtype)) return false;
+        c.k[ax] = found;
+        c.logW[ax] = lw;
+    }
+    *out = c;
+    return true;
+}
+
+int build_passes_nd(const NdChoice& c, const int64_t* dims, int64_t batch, PassPlan* out) {
+    int n = 0;
+    for (int i = 0; i < c.ndim; ++i) {
+        const int ax = c.order[i];
+        if (dims[ax] <= 1) continue;
+        out[n++] = make_pass_nd(c.ndim, dims, batch, ax, c.k[ax], c.logW[ax]);
+    }
+    return n;
 }
 
 int build_passes(const PlanChoice& c, const int64_t dims[3], int64_t batch, PassPlan out[3]) {

@@ -105,18 +105,16 @@ static void cache_store(const char* path, const offt_plan_s* p, const PlanChoice
 // Times one candidate for a grid of shape `dims` from `src` to `dst` (equal:
 // in place), through `work` where a transposing pass needs it.  Returns
 // OFFT_SUCCESS and the minimum time in *ms.
-int time_choice(offt_plan_s* p, const PlanChoice& c, const int64_t dims[3], void* src, void* dst, void* work,
-                hipStream_t s, int reps, float* ms) {
-    PassPlan passes[3];
-    const int n = build_passes(c, dims, p->batch, passes);
+// Times a pass list over `nelem` elements (see time_choice).
+static int time_passes(offt_plan_s* p, PassPlan* passes, int n, int64_t nelem, void* src, void* dst, void* work,
+                       hipStream_t s, int reps, float* ms) {
     for (int i = 0; i < n; ++i)
         if (!passes[i].k) return OFFT_ERR_UNSUPPORTED_SIZE;
     int rc = attach_twiddles(p, passes, n, s);
     if (rc != OFFT_SUCCESS) return rc;
     // fresh random data per candidate: unnormalised transforms repeated in
     // place would otherwise grow the values towards overflow
-    if (launch_fill_uniform(src, dims[0] * dims[1] * dims[2] * p->batch, p->dtype, 1501, s) != hipSuccess)
-        return OFFT_ERR_HIP;
+    if (launch_fill_uniform(src, nelem, p->dtype, 1501, s) != hipSuccess) return OFFT_ERR_HIP;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return OFFT_ERR_HIP;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OFFT_ERR_HIP; }
@@ -135,6 +133,13 @@ int time_choice(offt_plan_s* p, const PlanChoice& c, const int64_t dims[3], void
     (void)hipEventDestroy(e1);
     *ms = best;
     return rc;
+}
+
+int time_choice(offt_plan_s* p, const PlanChoice& c, const int64_t dims[3], void* src, void* dst, void* work,
+                hipStream_t s, int reps, float* ms) {
+    PassPlan passes[3];
+    const int n = build_passes(c, dims, p->batch, passes);
+    return time_passes(p, passes, n, dims[0] * dims[1] * dims[2] * p->batch, src, dst, work, s, reps, ms);
 }
 
 // Times one axis pass alone: 1 warm-up + reps runs, minimum.  Ordinary
@@ -349,6 +354,140 @@ int select_plan(offt_plan_s* p, const offt_opts& o, PlanChoice* choice, PlanChoi
     return exhaustive(p, o, choice, choice_b);
 }
 
+// ---- grids of 4 and 5 axes -----------------------------------------------------
+
+static std::string cache_key_nd(const offt_plan_s* p) {
+    std::ostringstream os;
+    os << "dtype=" << p->dtype << " dims=";
+    for (int i = 0; i < p->ndim; ++i) os << (i ? "x" : "") << p->nd_dims[i];
+    os << " batch=" << p->batch << " dev=" << device_name();
+    return os.str();
+}
+
+// Exhaustive search for a D-dimensional grid: every kernel and width of each
+// axis timed as a single pass (its geometry does not depend on the order),
+// the fastest kept per axis, then every order of the passes over the axes
+// longer than 1 timed as whole transforms -- up to 5! = 120 orders, the
+// counterpart of the paper's analysis of all transpose orders.  Ties keep the
+// earlier candidate (the heuristic's kernels, then its order, first).
+static int exhaustive_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice, float* win_ms, int* timed) {
+    hipStream_t s = static_cast<hipStream_t>(o.stream);
+    const int64_t nelem = p->grid_elems() * p->batch;
+    const size_t bytes = (size_t)nelem * elem_size(p->dtype);
+    void* buf = nullptr;
+    void* src = nullptr;
+    if (hipMalloc(&buf, bytes) != hipSuccess) { (void)hipGetLastError(); return OFFT_ERR_OUT_OF_MEMORY; }
+    if (o.tune_inplace) {
+        src = buf;
+    } else if (hipMalloc(&src, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(buf);
+        return OFFT_ERR_OUT_OF_MEMORY;
+    }
+    const int D = p->ndim;
+    const int64_t* dims = p->nd_dims;
+    NdChoice best = default_choice_nd(p->dtype, D, dims);
+    int rc = OFFT_SUCCESS;
+    for (int ax = 0; ax < D && rc == OFFT_SUCCESS; ++ax) {
+        if (dims[ax] <= 1) continue;
+        const bool strided = make_pass_nd(D, dims, 1, ax, nullptr, 0).M2 > 1;
+        std::vector<const KernelEntry*> ks = kernels_for(p->dtype, (int)dims[ax]);
+        std::stable_partition(ks.begin(), ks.end(), [&](const KernelEntry* k) { return k == best.k[ax]; });
+        float best_ms = 1e30f;
+        const KernelEntry* bk = best.k[ax];
+        int blw = best.logW[ax];
+        for (const KernelEntry* k : ks) {
+            if (k->nparts > 1 && !strided) continue;
+            const int top = fit_logW(k, 10, p->dtype);
+            const int span = k->nparts == 1 ? 4 : 1;
+            for (int lw = top; lw >= 0 && top - lw <= span && rc == OFFT_SUCCESS; --lw) {
+                if (!tile_fits(k, lw, p->dtype)) continue;
+                float ms = 0.f;
+                rc = time_pass(p, make_pass_nd(D, dims, p->batch, ax, k, lw), buf, nullptr, s, o.reps, &ms);
+                ++*timed;
+                if (rc == OFFT_SUCCESS && ms < best_ms) {
+                    best_ms = ms;
+                    bk = k;
+                    blw = lw;
+                }
+            }
+        }
+        best.k[ax] = bk;
+        best.logW[ax] = blw;
+    }
+    // orders: the heuristic's first, then every other permutation of the
+    // transformed axes (unit axes keep their slots at the end)
+    std::vector<int> axes;
+    for (int i = 0; i < D; ++i)
+        if (dims[best.order[i]] > 1) axes.push_back(best.order[i]);
+    std::vector<std::vector<int>> orders{axes};
+    std::vector<int> perm = axes;
+    std::sort(perm.begin(), perm.end());
+    do {
+        if (perm != axes) orders.push_back(perm);
+    } while (std::next_permutation(perm.begin(), perm.end()));
+    NdChoice winner = best;
+    float wms = 1e30f;
+    for (size_t oi = 0; oi < orders.size() && rc == OFFT_SUCCESS; ++oi) {
+        NdChoice c = best;
+        int pos = 0;
+        for (int ax : orders[oi]) c.order[pos++] = ax;
+        for (int i = 0; i < D; ++i)
+            if (dims[i] <= 1) c.order[pos++] = i;
+        PassPlan passes[kMaxDims];
+        const int n = build_passes_nd(c, dims, p->batch, passes);
+        float ms = 0.f;
+        rc = time_passes(p, passes, n, nelem, src, buf, nullptr, s, o.reps, &ms);
+        ++*timed;
+        if (rc == OFFT_SUCCESS && ms < wms) { wms = ms; winner = c; }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    if (src != buf) (void)hipFree(src);
+    if (rc != OFFT_SUCCESS) return rc;
+    *choice = winner;
+    *win_ms = wms;
+    return OFFT_SUCCESS;
+}
+
+int select_plan_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice) {
+    const std::string key = cache_key_nd(p);
+    if (o.cache_path) {
+        std::ifstream f(o.cache_path);
+        std::string line;
+        bool hit = false;
+        while (f && std::getline(f, line)) {
+            const size_t t1 = line.find('\t');
+            if (t1 == std::string::npos || t1 != key.size() || line.compare(0, t1, key) != 0) continue;
+            const size_t t2 = line.find('\t', t1 + 1);
+            const std::string plan = line.substr(t1 + 1, t2 == std::string::npos ? std::string::npos : t2 - t1 - 1);
+            NdChoice c;
+            if (nd_choice_from_string(plan.c_str(), p->dtype, p->ndim, p->nd_dims, &c)) {
+                *choice = c;   // the latest valid entry wins
+                hit = true;
+            }
+        }
+        if (hit) {
+            p->tune_log = "cache";
+            return OFFT_SUCCESS;
+        }
+    }
+    int timed = 0;
+    float ms = 0.f;
+    const int rc = exhaustive_nd(p, o, choice, &ms, &timed);
+    if (rc != OFFT_SUCCESS) return rc;
+    char buf[200];
+    snprintf(buf, sizeof buf, "%sexhaustive: %d timings (per-axis kernels and widths, then every pass order %s), "
+             "best %.4f ms", o.tune == OFFT_TUNE_LEARNED ? "learned-fallback(4-D/5-D grid) " : "", timed,
+             o.tune_inplace ? "in place" : "out of place", ms);
+    p->tune_log = buf;
+    if (o.cache_path) {
+        std::ofstream f(o.cache_path, std::ios::app);
+        if (f) f << key << '\t' << nd_choice_to_string(*choice, p->nd_dims) << '\t' << ms << '\n';
+    }
+    return OFFT_SUCCESS;
+}
+
 }  // namespace offt
 
 extern "C" int offt_tune_table(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch, int reps, void* buf,
@@ -380,6 +519,7 @@ namespace offt {
 
 std::string describe_plan(const offt_plan_s* p) {
     if (p->kind == 2) return describe_many(p);
+    if (p->kind == 3) return nd_choice_to_string(p->ndc, p->nd_dims);
     return plan_to_string(p, p->choice, p->choice_b);
 }
 

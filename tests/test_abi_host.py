@@ -112,4 +112,7 @@ def test_python_plan_raises_with_code():
         offt.Plan((7, 8, 8))
     assert ei.value.code == _lib.ERR_UNSUPPORTED_SIZE
     with pytest.raises(ValueError):
-        offt.Plan((8, 8), )
+        offt.Plan((8,) * 6)                 # more axes than OFFT_MAX_DIMS
+    with pytest.raises(offt.OfftError) as ei:
+        offt.Plan((8, 8, 8, 7))             # 4-axis plans check the lengths too
+    assert ei.value.code == _lib.ERR_UNSUPPORTED_SIZE
