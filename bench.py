@@ -34,8 +34,17 @@ sys.path.insert(0, ROOT)
 METRIC = "3-D C2C FFT GFLOP/s (5N·log2N/t) + HBM GB/s at 512³, FP32 vs FP64"
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+# Plan cache of the exhaustive tuner ("user-select after tuning once"): the
+# timed plans are the ones the tuner chose on MI355X when the profiles were
+# taken; a shape or device without an entry is tuned and appended.
+PLAN_CACHE = os.path.join(ROOT, "paper_1501_07350_amd", "data", "plan_cache_mi355x.txt")
+
 KERNEL_SOURCES = ["paper_1501_07350_amd/csrc/fft_device.hpp", "paper_1501_07350_amd/csrc/planner.cpp",
                   "paper_1501_07350_amd/csrc/gen_kernels.py"]
+
+
+def _cache(tune: str):
+    return PLAN_CACHE if (PLAN_CACHE and tune in ("exhaustive", "learned")) else None
 
 
 def kernel_source_hash() -> str:
@@ -79,7 +88,7 @@ def time_transform(n: int, dtype, steps: int, warmup: int, check: bool, tune: st
     x = synth.complex_grid(shape, dtype, device="cuda")
     y = torch.empty_like(x)
     t0 = time.perf_counter()
-    plan = offt.Plan(shape, dtype=dtype, tune=tune, forced_plan=forced)
+    plan = offt.Plan(shape, dtype=dtype, tune=tune, forced_plan=forced, cache_path=_cache(tune))
     plan_s = time.perf_counter() - t0
     npass = plan.npasses()
     stream = torch.cuda.current_stream()
@@ -163,7 +172,7 @@ def time_reversed(n: int, dtype, steps: int, warmup: int, check: bool, tune: str
 
     res = {}
     for name, lay in (("natural", "natural"), ("reversed", "cba")):
-        plan = offt.Plan(shape, dtype=dtype, tune=tune, layout=lay)
+        plan = offt.Plan(shape, dtype=dtype, tune=tune, layout=lay, cache_path=_cache(tune))
         fwd = timed(plan, offt.FORWARD, x, y)
         bwd = timed(plan, offt.BACKWARD, y, x)
         res[name] = {"fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4), "plan": plan.describe()}
@@ -205,7 +214,7 @@ def time_nd(shape, dtype, steps: int, warmup: int, check: bool, tune: str = "exh
     res = {"shape": list(shape), "dtype": "f64" if dtype == torch.complex128 else "f32"}
     for name, t in (("tuned", tune), ("heuristic", "none")):
         t0 = time.perf_counter()
-        plan = offt.Plan(shape, dtype=dtype, tune=t)
+        plan = offt.Plan(shape, dtype=dtype, tune=t, cache_path=_cache(t))
         plan_s = time.perf_counter() - t0
         for _ in range(warmup):
             plan.exec_ptr(offt.FORWARD, x.data_ptr(), y.data_ptr(), h)
@@ -627,6 +636,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, log: str, n: int, steps: int, 
 
 
 def main():
+    global PLAN_CACHE
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -647,9 +657,12 @@ def main():
                     help="reduce two rocprofv3 --pmc output dirs to profiles/pmc_traffic.json")
     ap.add_argument("--configs", action="store_true",
                     help="report configs 1, 2 and 1024^3 of config 3, and the CPU oracle table, instead")
+    ap.add_argument("--plan-cache", default=PLAN_CACHE,
+                    help="plan cache of the tuned plans ('none': tune afresh without a cache)")
     ap.add_argument("--command", default="", help="profiling command recorded in the summary")
     ap.add_argument("--out", help="summary text file")
     args = ap.parse_args()
+    PLAN_CACHE = None if args.plan_cache == "none" else os.path.abspath(args.plan_cache)
     if args.summarize_stats:
         txt = summarize_stats(args.summarize_stats[0], args.summarize_stats[1], args.command, args.n,
                               args.steps, args.warmup)
@@ -701,6 +714,7 @@ def main():
         "hbm_gbs_effective": round(r64["eff_gbs"], 1),
         "frac_of_peak_effective": round(r64["eff_gbs"] / PEAK_HBM_GBS, 4),
         "plan": r64["plan"],
+        "plan_cache": os.path.relpath(PLAN_CACHE, ROOT) if PLAN_CACHE else None,
         "plan_tuning_seconds": round(r64["plan_seconds"], 3),
         "pass_ms": [round(v, 4) for v in r64["pass_ms"]],
         "heuristic_plan": {"f64": {"ms_per_step": round(h64["ms"], 4), "gflops": round(h64["gflops"], 1),
