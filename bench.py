@@ -583,6 +583,63 @@ def _pmc_per_dispatch(d: str, counter: str):
     return [per[k] for k in sorted(per)]
 
 
+SQ_COUNTERS = ["SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+               "SQ_LDS_BANK_CONFLICT", "SQ_WAVES", "SQ_WAVE_CYCLES", "GRBM_GUI_ACTIVE"]
+CU_NUM = 256
+MAX_WAVES_PER_CU = 32
+XCD_NUM = 8   # GRBM_GUI_ACTIVE arrives summed over the XCDs; rocprofv3's expressions take its max
+
+
+def summarize_sq(d: str, log: str, command: str, n: int, steps: int, warmup: int) -> str:
+    """Per-pass VALU / LDS figures from one rocprofv3 --pmc run of the SQ and
+    GRBM counters above (with --kernel-trace for the durations), averaged
+    over the timed steps.  Busy and conflict percentages use rocprofv3's own
+    derived-metric expressions for this device (VALUBusy, LDSBankConflict,
+    OccupancyPercent), with the LDS analogue of VALUBusy."""
+    runs = _profiled_runs(log, n)
+    vals = {c: _pmc_per_dispatch(d, c) for c in SQ_COUNTERS}
+    names = [nm for nm, _ in vals["SQ_WAVES"]]
+    idx = [i for i, nm in enumerate(names) if "fft_pass_kernel" in nm]
+    trace = _read_csv(_find(d, "kernel_trace.csv"))
+    trace.sort(key=lambda r: int(r["Dispatch_Id"]))
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace
+            if "fft_pass_kernel" in r["Kernel_Name"]]
+    if len(durs) != len(idx):
+        raise RuntimeError(f"{len(idx)} counter dispatches but {len(durs)} traced pass dispatches")
+    acc = {}
+    for r, i, st, k in _pass_dispatches(idx, runs, steps, warmup):
+        if st < warmup:
+            continue
+        a = acc.setdefault((r, i), {c: 0.0 for c in SQ_COUNTERS + ["us"]})
+        for c in SQ_COUNTERS:
+            a[c] += vals[c][idx[k]][1]
+        a["us"] += durs[k]
+        a["n"] = a.get("n", 0) + 1
+    lines = ["# rocprofv3 SQ / GRBM counters per axis pass (mean per dispatch over the timed steps)",
+             f"# command: {command}",
+             "# valu% = 100*SQ_ACTIVE_INST_VALU/CU_NUM/GRBM_GUI_ACTIVE (rocprofv3 VALUBusy); lds% the same with",
+             "# SQ_ACTIVE_INST_LDS; conflict% = 100*SQ_LDS_BANK_CONFLICT/GRBM_GUI_ACTIVE/CU_NUM (LDSBankConflict);",
+             "# occ% = 400*SQ_WAVE_CYCLES/GRBM_GUI_ACTIVE/CU_NUM/32 (OccupancyPercent); per-element counts are",
+             "# wave instructions x 64 lanes / grid points; GRBM_GUI_ACTIVE (summed over the 8 XCDs in the CSV)",
+             "# is divided by 8 for the max the expressions take; clock = that / dispatch duration",
+             f"{'grid':<12} {'pass':<18} {'us':>8} {'GHz':>5} {'valu%':>6} {'lds%':>6} {'confl%':>7} {'occ%':>6} "
+             f"{'valu/pt':>8} {'lds/pt':>7} {'vmem/pt':>8} {'waves':>8}"]
+    for r, (tag, label, plan) in enumerate(runs):
+        N = n ** 3
+        for i, key in enumerate(pass_keys(plan)):
+            a = acc[(r, i)]
+            m = {c: a[c] / a["n"] for c in SQ_COUNTERS + ["us"]}
+            g = m["GRBM_GUI_ACTIVE"] / XCD_NUM
+            lines.append(
+                f"{n}^3 c{label[7:]:<5} {key:<18} {m['us']:8.1f} {g / m['us'] / 1e3:5.2f} "
+                f"{100 * m['SQ_ACTIVE_INST_VALU'] / CU_NUM / g:6.1f} {100 * m['SQ_ACTIVE_INST_LDS'] / CU_NUM / g:6.1f} "
+                f"{100 * m['SQ_LDS_BANK_CONFLICT'] / CU_NUM / g:7.2f} "
+                f"{400 * m['SQ_WAVE_CYCLES'] / g / CU_NUM / MAX_WAVES_PER_CU:6.1f} "
+                f"{m['SQ_INSTS_VALU'] * 64 / N:8.1f} {m['SQ_INSTS_LDS'] * 64 / N:7.2f} "
+                f"{m['SQ_INSTS_VMEM'] * 64 / N:8.2f} {m['SQ_WAVES']:8.0f}")
+    return "\n".join(lines) + "\n"
+
+
 def summarize_pmc(fetch_dir: str, write_dir: str, log: str, n: int, steps: int, warmup: int, command: str):
     """Per-pass HBM bytes of the transforms, scaled by the copy calibration:
     factor = CALIB_BYTES / (counter bytes of one calibration copy).  Passes are
@@ -653,6 +710,8 @@ def main():
     ap.add_argument("--no-heuristic", action="store_true", help="skip the heuristic-plan comparison runs")
     ap.add_argument("--summarize-stats", nargs=2, metavar=("DIR", "LOG"),
                     help="reduce a rocprofv3 --stats output dir (LOG: the profiled run's stdout)")
+    ap.add_argument("--summarize-sq", nargs=2, metavar=("DIR", "LOG"),
+                    help="reduce a rocprofv3 --pmc run of the SQ/GRBM counters (VALU, LDS) to a per-pass table")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "LOG"),
                     help="reduce two rocprofv3 --pmc output dirs to profiles/pmc_traffic.json")
     ap.add_argument("--configs", action="store_true",
@@ -666,6 +725,11 @@ def main():
     if args.summarize_stats:
         txt = summarize_stats(args.summarize_stats[0], args.summarize_stats[1], args.command, args.n,
                               args.steps, args.warmup)
+        open(args.out, "w").write(txt) if args.out else print(txt)
+        return
+    if args.summarize_sq:
+        txt = summarize_sq(args.summarize_sq[0], args.summarize_sq[1], args.command, args.n, args.steps,
+                           args.warmup)
         open(args.out, "w").write(txt) if args.out else print(txt)
         return
     if args.summarize_pmc:
