@@ -199,8 +199,8 @@ __host__ __device__ constexpr int64_t tile_lds_elems(int W, int L, int P = 1) {
 }
 // A transposing pass adds a table of one 64-bit row offset per line (W
 // elements of at least 8 bytes).
-__host__ __device__ constexpr int64_t tile_lds_elems_transpose(int W, int L) {
-    return tile_lds_elems(W, L, 1) + W;
+__host__ __device__ constexpr int64_t tile_lds_elems_transpose(int W, int L, int P = 1) {
+    return tile_lds_elems(W, L, P) + W;
 }
 
 // ---- Stockham stages ---------------------------------------------------------
@@ -286,6 +286,39 @@ __device__ __forceinline__ void exchange(V* __restrict__ line, int t, bool act, 
     exchange_parts<V, L, TPL, NS, R, R2, P>(line, t, act, v, u);
 }
 
+// Sinks that take the outputs in parts: a sink type with a static kParts > 1
+// receives the outputs of part p (indices [p*L/kParts, (p+1)*L/kParts)) and
+// then its flush(p), between barriers, part after part (a line's outputs
+// then need only L/kParts slots of LDS at a time).  Other sinks take every
+// output at once.
+template <typename S, typename = void> struct SinkParts { static constexpr int value = 1; };
+template <typename S> struct SinkParts<S, decltype((void)S::kParts)> { static constexpr int value = S::kParts; };
+
+// The last stage's outputs j = b + r*L/R to the sink.  Output j lies in part
+// r div (R/kParts) when kParts divides R.
+template <typename V, int L, int TPL, int R, typename Sink>
+__device__ __forceinline__ void emit_outputs(StageRegs<V, L, TPL, R>& v, int t, bool act, Sink& sink) {
+    using SH = StageShape<V, L, TPL, R>;
+    constexpr int OP = SinkParts<Sink>::value;
+    static_assert(R % OP == 0, "the last radix must split into the sink's parts");
+#pragma unroll
+    for (int p = 0; p < OP; ++p) {
+#pragma unroll
+        for (int i = 0; i < SH::NB; ++i) {
+            const int b = t + i * TPL;
+            if (act && (SH::EXACT || b < SH::B)) {
+#pragma unroll
+                for (int r = p * (R / OP); r < (p + 1) * (R / OP); ++r) sink(b + r * SH::B, v[i][r]);
+            }
+        }
+        if constexpr (OP > 1) {
+            __syncthreads();
+            sink.flush(p);
+            __syncthreads();
+        }
+    }
+}
+
 // Stage with span NS > 1 and radix R on the register inputs v: twiddles
 // W_{Ns R}^(r (b mod Ns)) from the table W_L^m, the R-point DFT, then either
 // the sink (last stage: natural-order index j = b + r*L/R) or the exchange
@@ -307,14 +340,7 @@ __device__ __forceinline__ void stage_regs(StageRegs<V, L, TPL, R>& v, V* __rest
     }
     if constexpr (sizeof...(Rest) == 0) {
         static_assert(NS * R == L, "last stage must complete the transform");
-#pragma unroll
-        for (int i = 0; i < SH::NB; ++i) {
-            const int b = t + i * TPL;
-            if (act && (SH::EXACT || b < SH::B)) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) sink(b + r * SH::B, v[i][r]);
-            }
-        }
+        emit_outputs<V, L, TPL, R>(v, t, act, sink);
     } else {
         constexpr int R2 = FirstRadix<Rest...>::value;
         StageRegs<V, L, TPL, R2> u;
@@ -354,14 +380,7 @@ __device__ __forceinline__ void fft_from_regs(StageRegs<V, L, TPL, R>& v, V* __r
     if constexpr (sizeof...(Rest) == 0) {
         // a single stage: output j = r (one butterfly, b = 0)
         if constexpr (OUT_LDS || IN_LDS) __syncthreads();
-#pragma unroll
-        for (int i = 0; i < SH::NB; ++i) {
-            const int b = t + i * TPL;
-            if (act && (SH::EXACT || b < SH::B)) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) sink(b + r * SH::B, v[i][r]);
-            }
-        }
+        emit_outputs<V, L, TPL, R>(v, t, act, sink);
     } else {
         if constexpr (IN_LDS) __syncthreads();
         constexpr int R2 = FirstRadix<Rest...>::value;
@@ -529,20 +548,51 @@ __device__ __forceinline__ void pass_tile_impl(const PassArgs& a, V* __restrict_
     }
 }
 
+// Row-side stores of a transposing pass whose last stage emits in P parts:
+// part p of every line goes to its line's LDS slots, then the W half (or
+// quarter) rows leave with a flat coalesced copy.
+template <typename V, int L, int P>
+struct RowPartSink {
+    static constexpr int kParts = P;
+    static constexpr int PART = L / P;
+    static constexpr int LP = line_pitch(L, P);
+    V* line;                         // this thread's line slots
+    V* lds;                          // the tile (line w at lds + w*LP)
+    V* out;
+    const int64_t* rows;             // element offset of each line's row
+    int nl, tid, nt, cout;
+    decltype(V{}.x) scale;
+    bool active;
+    __device__ __forceinline__ void operator()(int j, V x) {
+        line[lds_idx(j % PART)] = fix_out(x, cout, scale);
+    }
+    __device__ __forceinline__ void flush(int p) {
+        if (!active) return;
+        for (int f = tid; f < nl * PART; f += nt) {
+            const int lw = f / PART, jj = f - lw * PART;
+            out[rows[lw] + p * PART + jj] = lds[lw * LP + lds_idx(jj)];
+        }
+    }
+};
+
 // One tile of a transposing pass (modes 2 and 3): W lines whose strided side
 // follows the [M1][L][M2] view (line l = m1*M2 + m2 at m1*L*M2 + m2, stride
 // M2) while the other buffer holds each line as the contiguous row
 // m1*M2 + (m2 mod X)*Y + m2 div X.  Mode 2 reads the rows and writes the
 // strided lines, mode 3 the reverse.  The row side goes through LDS with a
-// flat copy (consecutive lanes on consecutive elements of a row); the
-// strided side goes straight between registers and HBM with lanes walking
-// the W columns, as in a strided pass.  Threads: W * TPL; lds:
-// tile_lds_elems_transpose(W, L) elements.  Never in place.
-template <typename V, int L, int TPL, int... Rs>
+// flat coalesced copy (consecutive lanes on consecutive elements of a row);
+// the strided side goes straight between registers and HBM with lanes walking
+// the W columns, as in a strided pass.  With P > 1 the exchanges run in P
+// parts and the row side moves part by part (the first radix and the last
+// radix must split into P), so the tile needs LDS for only L/P elements of
+// each line.  Threads: W * TPL; lds: tile_lds_elems_transpose(W, L, P)
+// elements.  Never in place.
+template <typename V, int L, int TPL, int P, int... Rs>
 __device__ __forceinline__ void pass_tile_transpose(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
     using S = decltype(V{}.x);
     static_assert(RadixProduct<Rs...>::value == L, "radix sequence must multiply to L");
-    constexpr int LP = line_pitch(L, 1);
+    constexpr int LP = line_pitch(L, P);
+    constexpr int PART = L / P;
     const int W = 1 << a.logW;
     const int NT = W * TPL;
     const int tid = threadIdx.x;
@@ -576,30 +626,65 @@ __device__ __forceinline__ void pass_tile_transpose(const PassArgs& a, V* __rest
     const int64_t base = m1 * (int64_t)L * M2 + m2;
     V* line = lds + w * LP;
     if (a.mode == 2) {
-        if (active) {
-            for (int f = tid; f < nl * L; f += NT) {
-                const int lw = f / L, j = f - lw * L;
-                lds[lw * LP + lds_idx(j)] = fix_in(in[rows[lw] + j], cin);
-            }
-        }
-        __syncthreads();
         V* go = out + base;
-        auto src = [&](int j) { return line[lds_idx(j)]; };
         auto sink = [&](int j, V x) {
             if (ok) go[(int64_t)j * M2] = fix_out(x, cout, scale);
         };
-        run_fft<V, L, TPL, 1, true, false, Rs...>(line, tw, t, active, src, sink);
+        if constexpr (P == 1) {
+            if (active) {
+                for (int f = tid; f < nl * L; f += NT) {
+                    const int lw = f / L, j = f - lw * L;
+                    lds[lw * LP + lds_idx(j)] = fix_in(in[rows[lw] + j], cin);
+                }
+            }
+            __syncthreads();
+            auto src = [&](int j) { return line[lds_idx(j)]; };
+            run_fft<V, L, TPL, 1, true, false, Rs...>(line, tw, t, active, src, sink);
+        } else {
+            // the first stage's inputs part by part: input j = b + r*L/R0
+            // lies in part r div (R0/P)
+            constexpr int R0 = FirstRadix<Rs...>::value;
+            static_assert(R0 % P == 0, "the first radix must split into the parts");
+            using SH = StageShape<V, L, TPL, R0>;
+            StageRegs<V, L, TPL, R0> v;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (active) {
+                    for (int f = tid; f < nl * PART; f += NT) {
+                        const int lw = f / PART, jj = f - lw * PART;
+                        lds[lw * LP + lds_idx(jj)] = fix_in(in[rows[lw] + p * PART + jj], cin);
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < SH::NB; ++i) {
+                    const int b = t + i * TPL;
+                    if (active && (SH::EXACT || b < SH::B)) {
+#pragma unroll
+                        for (int r = p * (R0 / P); r < (p + 1) * (R0 / P); ++r)
+                            v[i][r] = line[lds_idx(b + r * SH::B - p * PART)];
+                    }
+                }
+                __syncthreads();
+            }
+            fft_from_regs<V, L, TPL, P, false, false, Rs...>(v, line, tw, t, active, sink);
+        }
     } else {
         const V* g = in + base;
         auto src = [&](int j) { return fix_in(g[(int64_t)j * M2], cin); };
-        auto sink = [&](int j, V x) { line[lds_idx(j)] = fix_out(x, cout, scale); };
-        run_fft<V, L, TPL, 1, false, true, Rs...>(line, tw, t, active, src, sink);
-        __syncthreads();
-        if (active) {
-            for (int f = tid; f < nl * L; f += NT) {
-                const int lw = f / L, j = f - lw * L;
-                out[rows[lw] + j] = lds[lw * LP + lds_idx(j)];
+        if constexpr (P == 1) {
+            auto sink = [&](int j, V x) { line[lds_idx(j)] = fix_out(x, cout, scale); };
+            run_fft<V, L, TPL, 1, false, true, Rs...>(line, tw, t, active, src, sink);
+            __syncthreads();
+            if (active) {
+                for (int f = tid; f < nl * L; f += NT) {
+                    const int lw = f / L, j = f - lw * L;
+                    out[rows[lw] + j] = lds[lw * LP + lds_idx(j)];
+                }
             }
+        } else {
+            RowPartSink<V, L, P> sink{line, lds, out, rows, nl, tid, NT, cout, scale, active};
+            run_fft<V, L, TPL, P, false, true, Rs...>(line, tw, t, active, src, sink);
         }
     }
 }

@@ -17,12 +17,12 @@ __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassArgs a) {
 }
 
 // Transposing pass (modes 2 and 3): one workgroup per tile of W lines.
-template <typename V, int MAXT, int L, int TPL, int... Rs>
+template <typename V, int MAXT, int L, int TPL, int P, int... Rs>
 __global__ void __launch_bounds__(MAXT) fft_tpass_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* lds = reinterpret_cast<V*>(smem_raw);
     const int64_t l0 = (int64_t)blockIdx.x << a.logW;
-    pass_tile_transpose<V, L, TPL, Rs...>(a, lds, l0);
+    pass_tile_transpose<V, L, TPL, P, Rs...>(a, lds, l0);
 }
 
 }  // namespace offt

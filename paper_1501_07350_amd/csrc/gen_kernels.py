@@ -70,11 +70,19 @@ def radix_seqs(L):
     return seqs
 
 
-def max_threads(prec):
-    """Launch bound of the stand-alone pass kernels: 1024 threads for binary32
-    (every binary32 kernel fits the 128 registers that allows), 512 for
-    binary64."""
-    return 1024 if prec == "f32" else 512
+def max_threads(prec, L=None, seq=None, tpl=None):
+    """Launch bound of a stand-alone pass kernel: 512 threads for binary64;
+    1024 for binary32, except the variants with half the threads per line
+    (two largest-radix butterflies per thread), which get 512 so that their
+    registers fit without spilling (a strided tile of 32 columns still fits:
+    that is what they are for).  A few binary32 kernels of L = 1024 at the
+    1024 bound, and binary64 ones of radix 32 x 32, still spill 8-76 bytes
+    per lane; the tuner weighs them like any other candidate."""
+    if prec != "f32":
+        return 512
+    if seq is not None and tpl < L // max(seq):
+        return 512
+    return 1024
 
 
 def lengths():
@@ -95,6 +103,19 @@ def splits(L, seq, P):
             return False
         ns *= r
     return True
+
+
+# Launch bound of the transposing kernels in both precisions: their row table
+# and row-side copy add registers, and at 1024 threads (128 registers) the
+# binary32 ones would spill.
+TRANSPOSE_MAX_THREADS = 512
+
+
+def transposes(seq, P):
+    """Whether a kernel also comes as a transposing pass: with P parts its row
+    side moves part by part, which needs P to divide the first radix (rows
+    in) and the last radix (rows out)."""
+    return P == 1 or (seq[0] % P == 0 and seq[-1] % P == 0)
 
 
 # Lengths whose strided tiles also get kernels with LDS exchanges in 2 and 4
@@ -139,9 +160,9 @@ def emit(outdir):
                 '#include "fft_kernel.hpp"',
                 "namespace offt {",
                 "namespace {",
-                "template <int L, int TPL, int P, int... Rs>",
+                "template <int MAXT, int L, int TPL, int P, int... Rs>",
                 "hipError_t launch_one(const PassArgs& a, int64_t nblocks, int threads, size_t lds, hipStream_t s) {",
-                f"    auto* k = &fft_pass_kernel<{vt}, {max_threads(prec)}, L, TPL, P, Rs...>;",
+                f"    auto* k = &fft_pass_kernel<{vt}, MAXT, L, TPL, P, Rs...>;",
                 "    static size_t lds_set = 65536;",
                 "    if (lds > lds_set) {",
                 "        hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);",
@@ -151,9 +172,9 @@ def emit(outdir):
                 "    hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(threads), lds, s, a);",
                 "    return hipGetLastError();",
                 "}",
-                "template <int L, int TPL, int... Rs>",
+                "template <int L, int TPL, int P, int... Rs>",
                 "hipError_t launch_t_one(const PassArgs& a, int64_t nblocks, int threads, size_t lds, hipStream_t s) {",
-                f"    auto* k = &fft_tpass_kernel<{vt}, {max_threads(prec)}, L, TPL, Rs...>;",
+                f"    auto* k = &fft_tpass_kernel<{vt}, {TRANSPOSE_MAX_THREADS}, L, TPL, P, Rs...>;",
                 "    static size_t lds_set = 65536;",
                 "    if (lds > lds_set) {",
                 "        hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);",
@@ -171,10 +192,12 @@ def emit(outdir):
             for L, seq, tpl, P in mine:
                 rad = ", ".join(str(x) for x in seq)
                 padded = ", ".join(str(x) for x in (seq + [0] * (8 - len(seq))))
-                # whole-line kernels also come as transposing passes
-                lt = f"&launch_t_one<{L}, {tpl}, {rad}>" if P == 1 else "nullptr"
-                lines.append(f"    {{{dcode}, {L}, {len(seq)}, {{{padded}}}, {tpl}, {max_threads(prec)}, {P}, "
-                             f"&launch_one<{L}, {tpl}, {P}, {rad}>, {lt}}},")
+                # whole-line kernels, and kernels in parts whose first and last
+                # radix split into the parts, also come as transposing passes
+                lt = f"&launch_t_one<{L}, {tpl}, {P}, {rad}>" if transposes(seq, P) else "nullptr"
+                mt = max_threads(prec, L, seq, tpl)
+                lines.append(f"    {{{dcode}, {L}, {len(seq)}, {{{padded}}}, {tpl}, {mt}, {P}, "
+                             f"&launch_one<{mt}, {L}, {tpl}, {P}, {rad}>, {lt}}},")
             lines.append("};")
             lines.append(f"const int g_{name}_n = {len(mine)};")
             lines.append("}  // namespace offt")

@@ -13,6 +13,7 @@ namespace offt {
 
 constexpr int kMaxStages = 8;
 constexpr int kMaxDims = 5;       // axes of the grids of a D-dimensional plan
+constexpr int kTransposeMaxThreads = 512;   // launch bound of every transposing kernel
 // Bytes of LDS a pass tile may use: the device's per-workgroup limit (160 KiB
 // on gfx950), 64 KiB when no device is visible.
 int64_t lds_limit();
@@ -31,7 +32,7 @@ struct KernelEntry {
     int max_threads;           // launch bound the kernel is compiled for
     int nparts;                // parts each LDS exchange runs in (> 1: strided lines only)
     LaunchFn launch;
-    LaunchFn launch_t;         // the same tile code as a transposing pass (nparts == 1), else nullptr
+    LaunchFn launch_t;         // the same tile code as a transposing pass, else nullptr
 };
 
 // One kernel case compiled into the persistent batch executor.

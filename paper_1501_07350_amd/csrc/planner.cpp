@@ -94,10 +94,10 @@ bool tile_fits(const KernelEntry* k, int logW, int dtype) {
 }
 
 bool tile_fits_transpose(const KernelEntry* k, int logW, int dtype) {
-    if (!k || !k->launch_t || k->nparts != 1 || logW < 0) return false;
+    if (!k || !k->launch_t || logW < 0) return false;
     const int64_t W = int64_t(1) << logW;
-    if (W * k->tpl > k->max_threads) return false;
-    return tile_lds_elems_transpose((int)W, k->L) * (int64_t)elem_size(dtype) <= lds_limit();
+    if (W * k->tpl > kTransposeMaxThreads) return false;
+    return tile_lds_elems_transpose((int)W, k->L, k->nparts) * (int64_t)elem_size(dtype) <= lds_limit();
 }
 
 bool tile_fits_geom(const KernelEntry* k, int logW, int dtype, int g) {
@@ -258,11 +258,15 @@ static bool axis_strided(int axis, const int64_t dims[3]) {
     return m2 > 1;
 }
 
-// Default kernel of a transposing pass: the first whole-line kernel with
-// radix <= 16 (every whole-line kernel has a transposing form), at the
-// strided width (256-byte row segments on the strided side) or the widest
-// that fits below it.
+// Default kernel of a transposing pass: for L >= 512 the first radix <= 16
+// kernel whose exchanges and row side run in 2 parts (half the LDS of a
+// whole-line tile, so two workgroups share a CU: on MI355X at 512^3 these
+// ran the transposing pass 13-17% faster than whole-line tiles), else the
+// first whole-line kernel with radix <= 16.  Tiles of 16 lines.
 static const KernelEntry* default_kernel_transpose(int dtype, int L) {
+    if (L >= 512)
+        for (const KernelEntry* k : kernels_for(dtype, L))
+            if (k->nparts == 2 && k->launch_t && max_radix(k) <= 16 && tile_fits_transpose(k, 4, dtype)) return k;
     for (const KernelEntry* k : kernels_for(dtype, L))
         if (k->nparts == 1 && k->launch_t && max_radix(k) <= 16) return k;
     for (const KernelEntry* k : kernels_for(dtype, L))
@@ -282,7 +286,7 @@ static void assign_default_kernels(PlanChoice& c, int dtype, const int64_t dims[
         int logW;
         if (g == kGeomTranspose) {
             k = default_kernel_transpose(dtype, (int)dims[ax]);
-            logW = k ? fit_logW(k, strided_logW(k, dtype), dtype, g) : 0;
+            logW = k ? fit_logW(k, 4, dtype, g) : 0;
         } else {
             const bool strided = make_pass(dims, 1, ax, g, nullptr, 0).M2 > 1;
             k = default_kernel(dtype, (int)dims[ax], strided);
@@ -482,7 +486,7 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
         const AxisSpec& sp = spec[ax];
         const int g = axis_geom(c, ax);
         const bool strided = g == kGeomTranspose || make_pass(dims, 1, ax, g, nullptr, 0).M2 > 1;
-        if (sp.P > 1 && (g == kGeomTranspose || !strided)) return false;
+        if (sp.P > 1 && !strided) return false;
         const KernelEntry* found = find_kernel(dtype, (int)dims[ax], sp);
         if (!found || (g == kGeomTranspose && !found->launch_t)) return false;
         const int lw = ilog2(sp.W);
@@ -625,8 +629,8 @@ hipError_t launch_pass(const PassPlan& p, const void* in, void* out, int conj_in
     a.conj_out = conj_out;
     a.scale = scale;
     // a kernel with exchanges in parts keeps only part of each line in LDS:
-    // strided lines only
-    if (p.k->nparts > 1 && p.mode != 1) return hipErrorInvalidValue;
+    // strided lines (or the strided side of a transposing pass) only
+    if (p.k->nparts > 1 && p.mode == 0) return hipErrorInvalidValue;
     const int64_t W = int64_t(1) << p.logW;
     const int64_t nblocks = (a.nlines + W - 1) / W;
     const int threads = (int)(W * p.k->tpl);
@@ -634,7 +638,7 @@ hipError_t launch_pass(const PassPlan& p, const void* in, void* out, int conj_in
         // transposing pass: never in place (its row side and strided side
         // cover the same elements in different orders)
         if (!p.k->launch_t || in == out || p.X < 1 || p.Y < 1 || p.X * p.Y != p.M2) return hipErrorInvalidValue;
-        const size_t lds_t = (size_t)tile_lds_elems_transpose((int)W, p.L) * elem_size(p.k->dtype);
+        const size_t lds_t = (size_t)tile_lds_elems_transpose((int)W, p.L, p.k->nparts) * elem_size(p.k->dtype);
         return p.k->launch_t(a, nblocks, threads, lds_t, s);
     }
     const size_t lds = (size_t)tile_lds_elems((int)W, p.L, p.k->nparts) * (p.k->dtype == OFFT_C2C_F64 ? 16 : 8);

@@ -229,8 +229,8 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
             best_lw[ax][g] = hlw;
             for (const KernelEntry* k : ks) {
                 // kernels whose LDS exchanges run in parts serve strided lines
-                // of ordinary passes only
-                if (k->nparts > 1 && (g == kGeomTranspose || shape.M2 == 1)) continue;
+                // (and transposing passes, whose one side is strided)
+                if (k->nparts > 1 && shape.M2 == 1) continue;
                 if (g == kGeomTranspose && !k->launch_t) continue;
                 const int top = fit_logW(k, 10, p->dtype, g);
                 // widths below 1/16 of the widest that fits are never competitive;

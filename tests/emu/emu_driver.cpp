@@ -241,8 +241,8 @@ static int do_pass(int argc, char** argv) {
     const int W = 1 << logW;
     const int threads = W * tpl;
     // exactly the LDS the host launches the tile with: ASan flags any access beyond it
-    const int P = (M2 > 1 && !tmode) ? 1 << logP : 1;
-    std::vector<V> lds((size_t)(tmode ? tile_lds_elems_transpose(W, L) : tile_lds_elems(W, L, P)));
+    const int P = M2 > 1 ? 1 << logP : 1;
+    std::vector<V> lds((size_t)(tmode ? tile_lds_elems_transpose(W, L, P) : tile_lds_elems(W, L, P)));
     blockDim.x = threads;
     const int64_t nblocks = (a.nlines + W - 1) / W;
     for (int64_t blk = 0; blk < nblocks; ++blk) {

@@ -69,8 +69,9 @@ def emu_binary():
         lines.append("    switch (kid) {")
         for i, (L, seq, tpl) in enumerate(plain_cases(gk, prec)):
             rad = ", ".join(map(str, seq))
-            body = " else ".join([f"if (a.mode >= 2) pass_tile_transpose<{vt}, {L}, {tpl}, {rad}>(a, lds, l0);"] +
-                                 [f"if (P == {P}) pass_tile_parts<{vt}, {L}, {tpl}, {P}, {rad}>(a, lds, l0);"
+            body = " else ".join([f"if (a.mode >= 2 && P == {P}) pass_tile_transpose<{vt}, {L}, {tpl}, {P}, {rad}>(a, lds, l0);"
+                                  for P in (1, 2, 4) if gk.splits(L, seq, P) and gk.transposes(seq, P)] +
+                                 [f"if (a.mode < 2 && P == {P}) pass_tile_parts<{vt}, {L}, {tpl}, {P}, {rad}>(a, lds, l0);"
                                   for P in (1, 2, 4) if gk.splits(L, seq, P)])
             lines.append(f"      case {i}: {body} break;")
         lines.append("      default: break;\n    }\n  }\n};")
@@ -258,7 +259,7 @@ def run_pass(exe, dtype, L, seq, tpl, M1, M2, logW, logP):
     assert worst <= oracle.tolerance(L, dtype == torch.complex64), worst
 
 
-def run_tpass(exe, dtype, L, seq, tpl, M1, X, Y, logW, mode):
+def run_tpass(exe, dtype, L, seq, tpl, M1, X, Y, logW, mode, logP=0):
     """One transposing pass through the emulated tile code: line l = m1*M2 + m2
     (M2 = X*Y) is strided in the [M1][L][M2] view and the contiguous row
     m1*M2 + (m2 mod X)*Y + m2 div X of the other buffer; mode 3 reads the
@@ -269,7 +270,7 @@ def run_tpass(exe, dtype, L, seq, tpl, M1, X, Y, logW, mode):
     kid = plain_cases(gk, prec).index((L, seq, tpl))
     code = "0" if dtype == torch.complex128 else "1"
     M2 = X * Y
-    args = [exe, "pass", code] + [str(v) for v in (kid, L, M1, M2, logW, 0, tpl, mode, X, Y)]
+    args = [exe, "pass", code] + [str(v) for v in (kid, L, M1, M2, logW, logP, tpl, mode, X, Y)]
     r = subprocess.run(args, capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, (r.stdout[:500], r.stderr[-3000:])
     lines = r.stdout.splitlines()
@@ -313,6 +314,29 @@ TPASS_CASES = [
 def test_emulated_transposing_pass(emu_binary, dtype, mode, case):
     L, seq, tpl, M1, X, Y, logW = case
     run_tpass(emu_binary, dtype, L, seq, tpl, M1, X, Y, logW, mode)
+
+
+# transposing tiles whose exchanges and row side run in 2 and 4 parts:
+# (L, radix sequence, threads per line, M1, X, Y, logW, logP), ragged tails,
+# butterflies per thread of one and of several
+TPASS_PART_CASES = [
+    (64, [8, 8], 8, 2, 5, 4, 4, 1),
+    (64, [8, 8], 8, 1, 6, 3, 3, 2),
+    (128, [16, 8], 8, 1, 12, 3, 5, 1),
+    (128, [8, 4, 4], 16, 3, 4, 5, 3, 1),
+    (128, [8, 4, 4], 16, 1, 7, 3, 4, 2),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
+@pytest.mark.parametrize("mode", [2, 3])
+@pytest.mark.parametrize("case", TPASS_PART_CASES,
+                         ids=lambda c: f"L{c[0]}-{'x'.join(map(str, c[1]))}-X{c[4]}-Y{c[5]}-W{1 << c[6]}-P{1 << c[7]}")
+def test_emulated_transposing_pass_in_parts(emu_binary, dtype, mode, case):
+    L, seq, tpl, M1, X, Y, logW, logP = case
+    gk = gen_kernels()
+    assert gk.splits(L, seq, 1 << logP) and gk.transposes(seq, 1 << logP)
+    run_tpass(emu_binary, dtype, L, seq, tpl, M1, X, Y, logW, mode, logP)
 
 
 # (L, radix sequence, threads per line, M1, M2, logW, logP): strided passes

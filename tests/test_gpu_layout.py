@@ -208,3 +208,37 @@ def test_full_size_sampled_lines(n, dtype):
     print(f"{shape} {dtype} cba: lines {e_lines:.2e} parseval {e_pars:.2e} roundtrip {e_rt:.2e} "
           f"plan {plan.describe()}", flush=True)
     assert e_lines <= t and e_pars <= t and e_rt <= t
+
+
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("inplace", [False, True], ids=["oop", "inplace"])
+@pytest.mark.parametrize("shape,fwd", [
+    ((256, 6, 10), "order=cba;rev=a;a=16x16/16/p2"),     # rows out in 2 parts, transposing pass last
+    ((256, 6, 10), "order=acb;rev=a;a=16x16/8/p4"),      # 4 parts, transposing pass first
+    ((6, 10, 256), "order=cba;rev=c;c=16x16/16/p2"),     # rows in in 2 parts, first
+    ((5, 12, 512), "order=abc;rev=c;c=16x16x2/16/p2"),   # rows in, last; 512-point lines
+    ((512, 3, 5), "order=bca;rev=a;a=32x16/16/p2"),      # radix-32 first stage, 15 lines: one ragged tile
+])
+def test_transposing_pass_in_parts(shape, fwd, inplace, dtype):
+    """Transposing passes whose exchanges and row side run in 2 and 4 parts,
+    forward and backward, ragged tiles, against the oracle."""
+    print(f"case {shape} {dtype} {fwd} inplace={inplace}", flush=True)
+    rs = shape[::-1]
+    bwd = offt.plan_string(rs, dtype, "cba").split("|")[0]
+    plan = offt.Plan(shape, dtype=dtype, layout="cba", tune="forced", forced_plan=fwd + "|" + bwd,
+                     normalize_inverse=True)
+    assert fwd.split(";")[2] in plan.describe()
+    x = gen(shape, dtype)
+    xh = host(x)
+    t = tol(x.numel(), dtype)
+    if inplace:
+        buf = x.clone()
+        plan.forward(buf, out=buf.view(rs))
+        y = buf.view(rs)
+    else:
+        y = plan.forward(x)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(host(y), layout.fft3_reversed(xh)) <= t
+    z = plan.backward(y)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(host(z), xh) <= t

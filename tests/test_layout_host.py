@@ -45,13 +45,20 @@ BASE = "order=cba;rev=a;a=16x16x2/4;b=16x16x2/4;c=16x16x2/4"
     BASE,                                              # no backward half
     BASE + "|order=cba;a=16x16x2/4;b=16x16x2/4;c=16x16x2/4",   # backward half without a transposing axis
     BASE + "|order=cba;rev=b;a=16x16x2/4;b=16x16x2/4;c=16x16x2/4",   # b cannot transpose
-    "order=cba;rev=a;a=16x16x2/4/p2;b=16x16x2/4;c=16x16x2/4|" + BASE,   # parts on the transposing pass
     "order=cba;rev=c;a=16x16x2/4/p2;b=16x16x2/4;c=16x16x2/4|" + BASE,   # parts on a contiguous cba axis
+    "order=cba;rev=a;a=16x16x2/4/p4;b=16x16x2/4;c=16x16x2/4|" + BASE,   # no such kernel in 4 parts
 ])
 def test_unusable_reversed_plans_rejected(plan):
     with pytest.raises(offt.OfftError) as e:
         offt.plan_string((512, 512, 512), C128, "cba", plan)
     assert e.value.code == -6
+
+
+def test_transposing_pass_in_parts():
+    # 2-part exchanges on the transposing axis: its strided side is strided,
+    # and the first and last radix of 16x16x2 split into 2
+    s = "order=cba;rev=a;a=16x16x2/4/p2;b=16x16x2/4;c=16x16x2/4|" + BASE
+    assert offt.plan_string((512, 512, 512), C128, "cba", s) == s
 
 
 def test_strided_reversed_axis_takes_parts():
