@@ -47,6 +47,12 @@ def _cache(tune: str):
     return PLAN_CACHE if (PLAN_CACHE and tune in ("exhaustive", "learned")) else None
 
 
+# timed runs per candidate when a plan is tuned here (a cache miss): the
+# minimum of 5 after a warm-up separates near-equal kernels more reliably than
+# the library's default of 2
+TUNE_REPS = 5
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
@@ -88,7 +94,7 @@ def time_transform(n: int, dtype, steps: int, warmup: int, check: bool, tune: st
     x = synth.complex_grid(shape, dtype, device="cuda")
     y = torch.empty_like(x)
     t0 = time.perf_counter()
-    plan = offt.Plan(shape, dtype=dtype, tune=tune, forced_plan=forced, cache_path=_cache(tune))
+    plan = offt.Plan(shape, dtype=dtype, tune=tune, forced_plan=forced, cache_path=_cache(tune), reps=TUNE_REPS)
     plan_s = time.perf_counter() - t0
     npass = plan.npasses()
     stream = torch.cuda.current_stream()
@@ -172,7 +178,7 @@ def time_reversed(n: int, dtype, steps: int, warmup: int, check: bool, tune: str
 
     res = {}
     for name, lay in (("natural", "natural"), ("reversed", "cba")):
-        plan = offt.Plan(shape, dtype=dtype, tune=tune, layout=lay, cache_path=_cache(tune))
+        plan = offt.Plan(shape, dtype=dtype, tune=tune, layout=lay, cache_path=_cache(tune), reps=TUNE_REPS)
         fwd = timed(plan, offt.FORWARD, x, y)
         bwd = timed(plan, offt.BACKWARD, y, x)
         res[name] = {"fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4), "plan": plan.describe()}
@@ -214,7 +220,7 @@ def time_nd(shape, dtype, steps: int, warmup: int, check: bool, tune: str = "exh
     res = {"shape": list(shape), "dtype": "f64" if dtype == torch.complex128 else "f32"}
     for name, t in (("tuned", tune), ("heuristic", "none")):
         t0 = time.perf_counter()
-        plan = offt.Plan(shape, dtype=dtype, tune=t, cache_path=_cache(t))
+        plan = offt.Plan(shape, dtype=dtype, tune=t, cache_path=_cache(t), reps=TUNE_REPS)
         plan_s = time.perf_counter() - t0
         for _ in range(warmup):
             plan.exec_ptr(offt.FORWARD, x.data_ptr(), y.data_ptr(), h)
