@@ -185,10 +185,10 @@ struct TuneBuffers {
 // are independent kernels, so every (radix sequence, threads per line, tile
 // width) of each axis is timed as a single pass in every geometry the axis
 // can have (on the abc grid; for reversed output also on the cba grid and as
-// the transposing pass), and the fastest kept per axis and geometry; then
-// the six pass orders (times the transposing axes) are timed as whole
-// transforms with those kernels.  Ties keep the earlier candidate (the
-// heuristic's kernels and order come first).
+// the transposing pass), and the two fastest kept per axis and geometry;
+// then the six pass orders (times the transposing axes) are timed as whole
+// transforms with every combination of those kernels.  Ties keep the earlier
+// candidate (the heuristic's kernels and order come first).
 static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dims[3], bool reversed,
                            const TuneBuffers& B, PlanChoice* choice, float* win_ms_out, int* timed) {
     hipStream_t s = static_cast<hipStream_t>(o.stream);
@@ -201,8 +201,12 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
     } else {
         taxes.push_back(-1);
     }
-    const KernelEntry* best_k[3][3] = {};
-    int best_lw[3][3] = {};
+    // the two fastest (kernel, width) of each axis and geometry: a pass timed
+    // alone can rank near-equal kernels differently than inside the whole
+    // transform (what the previous pass leaves in the caches differs), so
+    // both go on to the whole-transform stage
+    const KernelEntry* best_k[3][3][2] = {};
+    int best_lw[3][3][2] = {};
     int rc = OFFT_SUCCESS;
     for (int ax = 0; ax < 3 && rc == OFFT_SUCCESS; ++ax) {
         if (dims[ax] <= 1) continue;
@@ -224,9 +228,9 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
             }
             std::vector<const KernelEntry*> ks = kernels_for(p->dtype, (int)dims[ax]);
             std::stable_partition(ks.begin(), ks.end(), [&](const KernelEntry* k) { return k == hk; });
-            float best_ms = 1e30f;
-            best_k[ax][g] = hk;
-            best_lw[ax][g] = hlw;
+            float best_ms[2] = {1e30f, 1e30f};
+            best_k[ax][g][0] = hk;
+            best_lw[ax][g][0] = hlw;
             for (const KernelEntry* k : ks) {
                 // kernels whose LDS exchanges run in parts serve strided lines
                 // (and transposing passes, whose one side is strided)
@@ -241,33 +245,56 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
                     float ms = 0.f;
                     rc = time_pass(p, make_pass(dims, p->batch, ax, g, k, lw), B.buf, B.work, s, o.reps, &ms);
                     ++*timed;
-                    if (rc == OFFT_SUCCESS && ms < best_ms) {
-                        best_ms = ms;
-                        best_k[ax][g] = k;
-                        best_lw[ax][g] = lw;
+                    if (rc != OFFT_SUCCESS) break;
+                    if (ms < best_ms[0]) {
+                        best_ms[1] = best_ms[0];
+                        best_k[ax][g][1] = best_k[ax][g][0];
+                        best_lw[ax][g][1] = best_lw[ax][g][0];
+                        best_ms[0] = ms;
+                        best_k[ax][g][0] = k;
+                        best_lw[ax][g][0] = lw;
+                    } else if (ms < best_ms[1]) {
+                        best_ms[1] = ms;
+                        best_k[ax][g][1] = k;
+                        best_lw[ax][g][1] = lw;
                     }
                 }
             }
+            // the heuristic's kernel seeded slot 0 before any timing: if it was
+            // displaced without being timed faster, slot 1 may still hold it
+            if (best_k[ax][g][1] == best_k[ax][g][0] && best_lw[ax][g][1] == best_lw[ax][g][0])
+                best_k[ax][g][1] = nullptr;
         }
     }
+    // whole transforms: every order (and transposing axis) with every
+    // combination of each axis's two fastest kernels
     static const int orders[6][3] = {{2, 1, 0}, {2, 0, 1}, {1, 2, 0}, {1, 0, 2}, {0, 2, 1}, {0, 1, 2}};
     PlanChoice winner = heur;
     float win_ms = 1e30f;
     for (int t : taxes) {
         for (int i = 0; i < 6 && rc == OFFT_SUCCESS; ++i) {
-            PlanChoice c = heur;
-            c.tax = t;
-            for (int j = 0; j < 3; ++j) c.order[j] = orders[i][j];
-            for (int ax = 0; ax < 3; ++ax) {
-                if (dims[ax] <= 1) continue;
-                const int g = axis_geom(c, ax);
-                c.k[ax] = best_k[ax][g];
-                c.logW[ax] = best_lw[ax][g];
+            for (int combo = 0; combo < 8 && rc == OFFT_SUCCESS; ++combo) {
+                PlanChoice c = heur;
+                c.tax = t;
+                for (int j = 0; j < 3; ++j) c.order[j] = orders[i][j];
+                bool valid = true;
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int pick = (combo >> ax) & 1;
+                    if (dims[ax] <= 1) {
+                        valid = valid && pick == 0;
+                        continue;
+                    }
+                    const int g = axis_geom(c, ax);
+                    valid = valid && best_k[ax][g][pick] != nullptr;
+                    c.k[ax] = best_k[ax][g][pick];
+                    c.logW[ax] = best_lw[ax][g][pick];
+                }
+                if (!valid) continue;
+                float ms = 0.f;
+                rc = time_choice(p, c, dims, B.src, B.buf, B.work, s, o.reps, &ms);
+                ++*timed;
+                if (rc == OFFT_SUCCESS && ms < win_ms) { win_ms = ms; winner = c; }
             }
-            float ms = 0.f;
-            rc = time_choice(p, c, dims, B.src, B.buf, B.work, s, o.reps, &ms);
-            ++*timed;
-            if (rc == OFFT_SUCCESS && ms < win_ms) { win_ms = ms; winner = c; }
         }
     }
     if (rc != OFFT_SUCCESS) return rc;
@@ -366,10 +393,12 @@ static std::string cache_key_nd(const offt_plan_s* p) {
 
 // Exhaustive search for a D-dimensional grid: every kernel and width of each
 // axis timed as a single pass (its geometry does not depend on the order),
-// the fastest kept per axis, then every order of the passes over the axes
-// longer than 1 timed as whole transforms -- up to 5! = 120 orders, the
-// counterpart of the paper's analysis of all transpose orders.  Ties keep the
-// earlier candidate (the heuristic's kernels, then its order, first).
+// the two fastest kept per axis, then every order of the passes over the
+// axes longer than 1 timed as whole transforms with the fastest kernels --
+// up to 5! = 120 orders, the counterpart of the paper's analysis of all
+// transpose orders -- and the winning order with every mix of the two.
+// Ties keep the earlier candidate (the heuristic's kernels, then its order,
+// first).
 static int exhaustive_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice, float* win_ms, int* timed) {
     hipStream_t s = static_cast<hipStream_t>(o.stream);
     const int64_t nelem = p->grid_elems() * p->batch;
@@ -387,13 +416,16 @@ static int exhaustive_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice, f
     const int D = p->ndim;
     const int64_t* dims = p->nd_dims;
     NdChoice best = default_choice_nd(p->dtype, D, dims);
+    // runner-up (kernel, width) per axis, tried with the winning order at the end
+    const KernelEntry* second_k[kMaxDims] = {};
+    int second_lw[kMaxDims] = {};
     int rc = OFFT_SUCCESS;
     for (int ax = 0; ax < D && rc == OFFT_SUCCESS; ++ax) {
         if (dims[ax] <= 1) continue;
         const bool strided = make_pass_nd(D, dims, 1, ax, nullptr, 0).M2 > 1;
         std::vector<const KernelEntry*> ks = kernels_for(p->dtype, (int)dims[ax]);
         std::stable_partition(ks.begin(), ks.end(), [&](const KernelEntry* k) { return k == best.k[ax]; });
-        float best_ms = 1e30f;
+        float best_ms = 1e30f, second_ms = 1e30f;
         const KernelEntry* bk = best.k[ax];
         int blw = best.logW[ax];
         for (const KernelEntry* k : ks) {
@@ -405,10 +437,20 @@ static int exhaustive_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice, f
                 float ms = 0.f;
                 rc = time_pass(p, make_pass_nd(D, dims, p->batch, ax, k, lw), buf, nullptr, s, o.reps, &ms);
                 ++*timed;
-                if (rc == OFFT_SUCCESS && ms < best_ms) {
+                if (rc != OFFT_SUCCESS) break;
+                if (ms < best_ms) {
+                    if (best_ms < 1e30f) {
+                        second_ms = best_ms;
+                        second_k[ax] = bk;
+                        second_lw[ax] = blw;
+                    }
                     best_ms = ms;
                     bk = k;
                     blw = lw;
+                } else if (ms < second_ms) {
+                    second_ms = ms;
+                    second_k[ax] = k;
+                    second_lw[ax] = lw;
                 }
             }
         }
@@ -434,6 +476,27 @@ static int exhaustive_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice, f
         for (int ax : orders[oi]) c.order[pos++] = ax;
         for (int i = 0; i < D; ++i)
             if (dims[i] <= 1) c.order[pos++] = i;
+        PassPlan passes[kMaxDims];
+        const int n = build_passes_nd(c, dims, p->batch, passes);
+        float ms = 0.f;
+        rc = time_passes(p, passes, n, nelem, src, buf, nullptr, s, o.reps, &ms);
+        ++*timed;
+        if (rc == OFFT_SUCCESS && ms < wms) { wms = ms; winner = c; }
+    }
+    // with the winning order, every combination of each axis's two fastest
+    // kernels (a pass timed alone can rank near-equal kernels differently
+    // than inside the whole transform)
+    const NdChoice base = winner;
+    for (int combo = 1; combo < (1 << D) && rc == OFFT_SUCCESS; ++combo) {
+        NdChoice c = base;
+        bool valid = true;
+        for (int ax = 0; ax < D; ++ax) {
+            if (!((combo >> ax) & 1)) continue;
+            valid = valid && dims[ax] > 1 && second_k[ax] != nullptr;
+            c.k[ax] = second_k[ax];
+            c.logW[ax] = second_lw[ax];
+        }
+        if (!valid) continue;
         PassPlan passes[kMaxDims];
         const int n = build_passes_nd(c, dims, p->batch, passes);
         float ms = 0.f;
