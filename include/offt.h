@@ -266,6 +266,12 @@ int64_t offt_many_offset(offt_plan_t p, int i);
 int offt_exec_many(offt_plan_t p, const void* in, void* out, int direction, int use_graph,
                    void* stream);
 
+/* offt_exec_many in the default launch form: LEVELS_GRAPH when the batch
+ * executor covers every pass of the batch, else SEPARATE_TUNED.  Same
+ * errors. */
+int offt_exec_many_fwd(offt_plan_t p, const void* in, void* out, void* stream);
+int offt_exec_many_bwd(offt_plan_t p, const void* in, void* out, void* stream);
+
 /* After the stream that ran offt_exec_many has been synchronised: 0 if the
  * last persistent run (PERSISTENT* or SYNC*) completed every dependency or
  * barrier wait normally, OFFT_ERR_HIP if a wait hit its bounded spin limit

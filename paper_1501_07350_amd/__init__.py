@@ -231,6 +231,23 @@ class ManyPlan:
                                       ctypes.c_void_p(_stream_handle())), "exec_many")
         return out
 
+    def _default(self, fn, x, out):
+        if not x.is_cuda or x.dtype != self.dtype or not x.is_contiguous() or x.numel() < self.total:
+            raise ValueError("x must be a contiguous CUDA tensor holding the packed grids")
+        if out is None:
+            out = torch.empty_like(x)
+        _lib.check(fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                      ctypes.c_void_p(_stream_handle())), "exec_many")
+        return out
+
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Forward transform of every grid in the default launch form (level
+        kernels from a graph where the batch executor covers the batch)."""
+        return self._default(_lib.load().offt_exec_many_fwd, x, out)
+
+    def backward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        return self._default(_lib.load().offt_exec_many_bwd, x, out)
+
     def exec_ptr(self, in_ptr: int, out_ptr: int, direction: int = FORWARD, use_graph: int = 1,
                  stream: int = 0) -> None:
         _lib.check(_lib.load().offt_exec_many(self._h, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),

@@ -107,6 +107,8 @@ SIGNATURES = {
     "offt_plan_many": (_vp, [_ci, ctypes.POINTER(_i64), _ci, ctypes.POINTER(Opts)]),
     "offt_many_offset": (_i64, [_vp, _ci]),
     "offt_exec_many": (_ci, [_vp, _vp, _vp, _ci, _ci, _vp]),
+    "offt_exec_many_fwd": (_ci, [_vp, _vp, _vp, _vp]),
+    "offt_exec_many_bwd": (_ci, [_vp, _vp, _vp, _vp]),
     "offt_many_status": (_ci, [_vp]),
     "offt_pass_bytes": (_i64, [_i64, _i64, _i64, _ci, _i64]),
     "offt_decomp_start": (_i64, [_i64, _i64, _i64, _i64, _i64]),

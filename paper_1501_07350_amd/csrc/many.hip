@@ -617,6 +617,22 @@ int64_t offt_many_offset(offt_plan_t p, int i) {
     return i == m->count ? m->total_elems : m->grids[i].off;
 }
 
+// The default launch of a many-plan: the level kernels replayed from a graph
+// (the fastest form measured on MI355X) when the batch executor covers every
+// pass, else the tuned plans as separate launches.
+static int many_default_form(offt_plan_t p) {
+    if (!p || p->kind != 2 || !p->many) return OFFT_MANY_LEVELS_GRAPH;   // rejected below
+    return p->many->persistent_ok ? OFFT_MANY_LEVELS_GRAPH : OFFT_MANY_SEPARATE_TUNED;
+}
+
+int offt_exec_many_fwd(offt_plan_t p, const void* in, void* out, void* stream) {
+    return offt_exec_many(p, in, out, OFFT_FORWARD, many_default_form(p), stream);
+}
+
+int offt_exec_many_bwd(offt_plan_t p, const void* in, void* out, void* stream) {
+    return offt_exec_many(p, in, out, OFFT_BACKWARD, many_default_form(p), stream);
+}
+
 int offt_exec_many(offt_plan_t p, const void* in, void* out, int direction, int use_graph, void* stream) {
     if (!p || !in || !out || (direction != OFFT_FORWARD && direction != OFFT_BACKWARD) || use_graph < -2 ||
         use_graph > OFFT_MANY_SYNC_GRAPH) {

@@ -189,3 +189,28 @@ def test_tuned_batch_plans_are_valid():
     check_against_oracle(plan, grids, y, C64)
     for line in plan.describe().splitlines()[1:]:
         assert line.startswith("order=")
+
+
+def test_default_launch_form():
+    """offt_exec_many_fwd / _bwd: the level kernels from a graph where the
+    batch executor covers the batch (bit-identical to use_graph=2), the tuned
+    separate launches where it does not; backward round trip with 1/N."""
+    dims = synth.uneven_batch_dims(8, key=synth.KEY_DIMS + 23)
+    plan = offt.ManyPlan(dims, dtype=C64, normalize_inverse=True)
+    grids, x = packed_input(plan, dims, C64, key0=synth.SEED + 700)
+    y = plan.forward(x)
+    y2 = plan.execute(x, use_graph=2)
+    z = plan.backward(y)
+    torch.cuda.synchronize()
+    assert same_grids(plan, y, y2)
+    check_against_oracle(plan, grids, y, C64)
+    for g, (a, b) in enumerate(zip(grids, plan.unpack(z))):
+        assert oracle.rel_l2(b.cpu().numpy(), a.cpu().numpy()) <= oracle.tolerance(a.numel(), True), g
+    dims = [(256, 4, 4), (8, 8, 8)]
+    lplan = offt.ManyPlan(dims, dtype=C64)
+    grids, x = packed_input(lplan, dims, C64)
+    y = lplan.forward(x)
+    y2 = lplan.execute(x, use_graph=-2)
+    torch.cuda.synchronize()
+    assert same_grids(lplan, y, y2)
+    check_against_oracle(lplan, grids, y, C64)
