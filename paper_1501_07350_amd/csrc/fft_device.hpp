@@ -419,10 +419,22 @@ struct PassArgs {
     int logW;           // log2 of lines per workgroup
     int mode;           // 0: contiguous lines (M2 == 1), 1: strided lines,
                         // 2: rows in, strided lines out, 3: strided lines in, rows out
+    int xcd_remap;      // 1: tiles in contiguous runs per XCD (xcd_tile)
     int conj_in;        // negate imaginary parts on load
     int conj_out;       // negate imaginary parts on store
     double scale;       // multiply on store
 };
+
+// Workgroups go to the 8 XCDs round-robin in launch order.  With remap, the
+// first 8*floor(n/8) of n workgroups take tiles so that each XCD works through
+// one contiguous run of tiles (workgroup i: tile (i mod 8)*floor(n/8) +
+// i div 8), the rest keep their own index; a bijection on [0, n).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t i, int64_t n, int remap) {
+    if (!remap) return i;
+    const int64_t q = n / kXcds;
+    return i < kXcds * q ? (i % kXcds) * q + i / kXcds : i;
+}
 
 template <typename V> __device__ __forceinline__ V fix_in(V x, int conj) {
     if (conj) x.y = -x.y;

@@ -12,7 +12,7 @@ template <typename V, int MAXT, int L, int TPL, int P, int... Rs>
 __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* lds = reinterpret_cast<V*>(smem_raw);
-    const int64_t l0 = (int64_t)blockIdx.x << a.logW;
+    const int64_t l0 = xcd_tile(blockIdx.x, gridDim.x, a.xcd_remap) << a.logW;
     pass_tile_parts<V, L, TPL, P, Rs...>(a, lds, l0);
 }
 
@@ -21,7 +21,7 @@ template <typename V, int MAXT, int L, int TPL, int P, int... Rs>
 __global__ void __launch_bounds__(MAXT) fft_tpass_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* lds = reinterpret_cast<V*>(smem_raw);
-    const int64_t l0 = (int64_t)blockIdx.x << a.logW;
+    const int64_t l0 = xcd_tile(blockIdx.x, gridDim.x, a.xcd_remap) << a.logW;
     pass_tile_transpose<V, L, TPL, P, Rs...>(a, lds, l0);
 }
 

@@ -112,6 +112,9 @@ __device__ __forceinline__ PassArgs segment_pass_args(const ManyArgs& a, const M
     p.M2 = sg.M2;
     p.logW = sg.logW;
     p.mode = sg.mode;
+    p.X = 1;
+    p.Y = 1;
+    p.xcd_remap = 0;   // the batch executors map tiles themselves
     p.conj_in = bwd && sg.first;
     p.conj_out = bwd && sg.last;
     p.scale = (bwd && sg.last) ? sg.scale_bwd : 1.0;

@@ -69,6 +69,7 @@ struct PassPlan {
     const KernelEntry* k;
     int logW;                  // lines per workgroup = 2^logW
     int mode;                  // 0 contiguous lines, 1 strided lines, 2/3 transposing (PassArgs)
+    int xcd = 0;               // tiles in contiguous runs per XCD (PassArgs::xcd_remap)
     const void* tw;            // device twiddle table for L
 };
 
@@ -77,6 +78,7 @@ struct PlanChoice {
     int order[3];              // axis order of the passes (axis ids)
     const KernelEntry* k[3];   // per axis id (a, b, c); nullptr for L == 1
     int logW[3];               // per axis id
+    int xcd[3] = {0, 0, 0};    // per axis id: XCD-contiguous tile order (plan string "/x")
     // Output order.  -1: the input's (abc).  0 or 2: reversed (cba), the
     // pass along this axis transposing: axis a reads strided lines of the
     // abc grid and writes cba rows (mode 3), axis c reads abc rows and
@@ -90,7 +92,8 @@ struct PlanChoice {
 enum AxisGeom { kGeomNatural = 0, kGeomReversed = 1, kGeomTranspose = 2 };
 int axis_geom(const PlanChoice& c, int ax);
 // The pass of axis ax in geometry g (k and logW filled in, tw left null).
-PassPlan make_pass(const int64_t dims[3], int64_t batch, int ax, int g, const KernelEntry* k, int logW);
+PassPlan make_pass(const int64_t dims[3], int64_t batch, int ax, int g, const KernelEntry* k, int logW,
+                   int xcd = 0);
 // Whether the output of a grid has a different memory order in cba than in
 // abc (at least two axes longer than 1).
 bool reversal_moves_data(const int64_t dims[3]);
@@ -108,8 +111,10 @@ struct NdChoice {
     int order[kMaxDims];              // axis order of the passes
     const KernelEntry* k[kMaxDims];   // per axis; nullptr for length 1
     int logW[kMaxDims];
+    int xcd[kMaxDims] = {0, 0, 0, 0, 0};
 };
-PassPlan make_pass_nd(int ndim, const int64_t* dims, int64_t batch, int ax, const KernelEntry* k, int logW);
+PassPlan make_pass_nd(int ndim, const int64_t* dims, int64_t batch, int ax, const KernelEntry* k, int logW,
+                      int xcd = 0);
 NdChoice default_choice_nd(int dtype, int ndim, const int64_t* dims);
 std::string nd_choice_to_string(const NdChoice& c, const int64_t* dims);
 bool nd_choice_from_string(const char* s, int dtype, int ndim, const int64_t* dims, NdChoice* out,

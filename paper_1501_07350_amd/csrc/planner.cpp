@@ -130,12 +130,13 @@ int axis_geom(const PlanChoice& c, int ax) {
 // grid), the cba grid for axis c (rows read from the abc grid).  In both the
 // row of line m1*M2 + m2 is m1*M2 + (m2 mod X)*Y + m2 div X with X the
 // length of the opposite end axis and Y = Nb.
-PassPlan make_pass(const int64_t dims[3], int64_t batch, int ax, int g, const KernelEntry* k, int logW) {
+PassPlan make_pass(const int64_t dims[3], int64_t batch, int ax, int g, const KernelEntry* k, int logW, int xcd) {
     PassPlan p;
     p.axis = ax;
     p.L = (int)dims[ax];
     p.k = k;
     p.logW = logW;
+    p.xcd = xcd;
     p.tw = nullptr;
     p.X = 1;
     p.Y = 1;
@@ -361,7 +362,7 @@ static const char kAxisName[] = "abcde";
 // One axis: "<radix sequence>/<tile width>[/<threads per line>][/p<parts>]",
 // or "1" for a length-1 axis.
 
-static void axis_to_string(std::ostringstream& os, const KernelEntry* k, int logW, int64_t len) {
+static void axis_to_string(std::ostringstream& os, const KernelEntry* k, int logW, int64_t len, int xcd) {
     if (!k || len <= 1) {
         os << "1";
         return;
@@ -370,6 +371,7 @@ static void axis_to_string(std::ostringstream& os, const KernelEntry* k, int log
     os << "/" << (1 << logW);
     if (k->tpl != default_tpl(k)) os << "/" << k->tpl;
     if (k->nparts > 1) os << "/p" << k->nparts;
+    if (xcd) os << "/x";
 }
 
 namespace {
@@ -377,6 +379,7 @@ struct AxisSpec {
     bool given = false;
     std::vector<int> rad;
     long W = 0, tpl = 0, P = 1;
+    int xcd = 0;
 };
 }  // namespace
 
@@ -395,7 +398,7 @@ static bool parse_axis_spec(const std::string& val, AxisSpec* sp) {
     char* end = nullptr;
     sp->W = strtol(val.c_str() + slash + 1, &end, 10);
     if (!end || sp->W < 1 || (sp->W & (sp->W - 1))) return false;
-    if (*end == '/' && end[1] != 'p') {   // threads per line (default: the sequence's)
+    if (*end == '/' && end[1] >= '0' && end[1] <= '9') {   // threads per line (default: the sequence's)
         char* end2 = nullptr;
         sp->tpl = strtol(end + 1, &end2, 10);
         if (!end2 || sp->tpl < 1) return false;
@@ -406,6 +409,10 @@ static bool parse_axis_spec(const std::string& val, AxisSpec* sp) {
         sp->P = strtol(end + 2, &end2, 10);
         if (!end2 || (sp->P != 1 && sp->P != 2 && sp->P != 4)) return false;
         end = end2;
+    }
+    if (end[0] == '/' && end[1] == 'x' && end[2] == 0) {   // XCD-contiguous tile order
+        sp->xcd = 1;
+        end += 2;
     }
     return *end == 0;
 }
@@ -441,7 +448,7 @@ std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]) {
     if (c.tax >= 0) os << ";rev=" << kAxisName[c.tax];
     for (int ax = 0; ax < 3; ++ax) {
         os << ";" << kAxisName[ax] << "=";
-        axis_to_string(os, c.k[ax], c.logW[ax], dims[ax]);
+        axis_to_string(os, c.k[ax], c.logW[ax], dims[ax], c.xcd[ax]);
     }
     return os.str();
 }
@@ -493,6 +500,7 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
         if (check_fit && !tile_fits_geom(found, lw, dtype, g)) return false;
         c.k[ax] = found;
         c.logW[ax] = lw;
+        c.xcd[ax] = sp.xcd;
     }
     *out = c;
     return true;
@@ -500,12 +508,14 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
 
 // ---- grids of more than three dimensions -------------------------------------
 
-PassPlan make_pass_nd(int ndim, const int64_t* dims, int64_t batch, int ax, const KernelEntry* k, int logW) {
+PassPlan make_pass_nd(int ndim, const int64_t* dims, int64_t batch, int ax, const KernelEntry* k, int logW,
+                      int xcd) {
     PassPlan p;
     p.axis = ax;
     p.L = (int)dims[ax];
     p.k = k;
     p.logW = logW;
+    p.xcd = xcd;
     p.tw = nullptr;
     p.X = 1;
     p.Y = 1;
@@ -545,7 +555,7 @@ std::string nd_choice_to_string(const NdChoice& c, const int64_t* dims) {
     for (int i = 0; i < c.ndim; ++i) os << kAxisName[c.order[i]];
     for (int ax = 0; ax < c.ndim; ++ax) {
         os << ";" << kAxisName[ax] << "=";
-        axis_to_string(os, c.k[ax], c.logW[ax], dims[ax]);
+        axis_to_string(os, c.k[ax], c.logW[ax], dims[ax], c.xcd[ax]);
     }
     return os.str();
 }
@@ -588,6 +598,7 @@ bool nd_choice_from_string(const char* s, int dtype, int ndim, const int64_t* di
         if (check_fit && !tile_fits(found, lw, dtype)) return false;
         c.k[ax] = found;
         c.logW[ax] = lw;
+        c.xcd[ax] = spec[ax].xcd;
     }
     *out = c;
     return true;
@@ -598,7 +609,7 @@ int build_passes_nd(const NdChoice& c, const int64_t* dims, int64_t batch, PassP
     for (int i = 0; i < c.ndim; ++i) {
         const int ax = c.order[i];
         if (dims[ax] <= 1) continue;
-        out[n++] = make_pass_nd(c.ndim, dims, batch, ax, c.k[ax], c.logW[ax]);
+        out[n++] = make_pass_nd(c.ndim, dims, batch, ax, c.k[ax], c.logW[ax], c.xcd[ax]);
     }
     return n;
 }
@@ -608,7 +619,7 @@ int build_passes(const PlanChoice& c, const int64_t dims[3], int64_t batch, Pass
     for (int i = 0; i < 3; ++i) {
         const int ax = c.order[i];
         if (dims[ax] <= 1) continue;
-        out[n++] = make_pass(dims, batch, ax, axis_geom(c, ax), c.k[ax], c.logW[ax]);
+        out[n++] = make_pass(dims, batch, ax, axis_geom(c, ax), c.k[ax], c.logW[ax], c.xcd[ax]);
     }
     return n;
 }
@@ -625,6 +636,7 @@ hipError_t launch_pass(const PassPlan& p, const void* in, void* out, int conj_in
     a.Y = p.Y;
     a.logW = p.logW;
     a.mode = p.mode;
+    a.xcd_remap = p.xcd;
     a.conj_in = conj_in;
     a.conj_out = conj_out;
     a.scale = scale;

@@ -207,6 +207,7 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
     // both go on to the whole-transform stage
     const KernelEntry* best_k[3][3][2] = {};
     int best_lw[3][3][2] = {};
+    int best_x[3][3][2] = {};   // XCD-contiguous tile order
     int rc = OFFT_SUCCESS;
     for (int ax = 0; ax < 3 && rc == OFFT_SUCCESS; ++ax) {
         if (dims[ax] <= 1) continue;
@@ -264,6 +265,24 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
             // displaced without being timed faster, slot 1 may still hold it
             if (best_k[ax][g][1] == best_k[ax][g][0] && best_lw[ax][g][1] == best_lw[ax][g][0])
                 best_k[ax][g][1] = nullptr;
+            // the fastest kernel with its tiles in XCD-contiguous order (at
+            // 1024^3 every pass gained 2-5% from it, at 512^3 some lost)
+            if (rc == OFFT_SUCCESS && best_k[ax][g][0] && best_ms[0] < 1e30f) {
+                float ms = 0.f;
+                rc = time_pass(p, make_pass(dims, p->batch, ax, g, best_k[ax][g][0], best_lw[ax][g][0], 1), B.buf,
+                               B.work, s, o.reps, &ms);
+                ++*timed;
+                if (rc == OFFT_SUCCESS && ms < best_ms[0]) {
+                    best_k[ax][g][1] = best_k[ax][g][0];
+                    best_lw[ax][g][1] = best_lw[ax][g][0];
+                    best_x[ax][g][1] = 0;
+                    best_x[ax][g][0] = 1;
+                } else if (rc == OFFT_SUCCESS && ms < best_ms[1]) {
+                    best_k[ax][g][1] = best_k[ax][g][0];
+                    best_lw[ax][g][1] = best_lw[ax][g][0];
+                    best_x[ax][g][1] = 1;
+                }
+            }
         }
     }
     // whole transforms: every order (and transposing axis) with every
@@ -288,6 +307,7 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
                     valid = valid && best_k[ax][g][pick] != nullptr;
                     c.k[ax] = best_k[ax][g][pick];
                     c.logW[ax] = best_lw[ax][g][pick];
+                    c.xcd[ax] = best_x[ax][g][pick];
                 }
                 if (!valid) continue;
                 float ms = 0.f;
@@ -419,6 +439,7 @@ static int exhaustive_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice, f
     // runner-up (kernel, width) per axis, tried with the winning order at the end
     const KernelEntry* second_k[kMaxDims] = {};
     int second_lw[kMaxDims] = {};
+    int second_x[kMaxDims] = {};
     int rc = OFFT_SUCCESS;
     for (int ax = 0; ax < D && rc == OFFT_SUCCESS; ++ax) {
         if (dims[ax] <= 1) continue;
@@ -456,6 +477,22 @@ static int exhaustive_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice, f
         }
         best.k[ax] = bk;
         best.logW[ax] = blw;
+        // the fastest kernel with its tiles in XCD-contiguous order
+        if (rc == OFFT_SUCCESS && bk && best_ms < 1e30f) {
+            float ms = 0.f;
+            rc = time_pass(p, make_pass_nd(D, dims, p->batch, ax, bk, blw, 1), buf, nullptr, s, o.reps, &ms);
+            ++*timed;
+            if (rc == OFFT_SUCCESS && ms < best_ms) {
+                second_k[ax] = bk;
+                second_lw[ax] = blw;
+                second_x[ax] = 0;
+                best.xcd[ax] = 1;
+            } else if (rc == OFFT_SUCCESS && ms < second_ms) {
+                second_k[ax] = bk;
+                second_lw[ax] = blw;
+                second_x[ax] = 1;
+            }
+        }
     }
     // orders: the heuristic's first, then every other permutation of the
     // transformed axes (unit axes keep their slots at the end)
@@ -495,6 +532,7 @@ static int exhaustive_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice, f
             valid = valid && dims[ax] > 1 && second_k[ax] != nullptr;
             c.k[ax] = second_k[ax];
             c.logW[ax] = second_lw[ax];
+            c.xcd[ax] = second_x[ax];
         }
         if (!valid) continue;
         PassPlan passes[kMaxDims];

@@ -435,3 +435,36 @@ def test_tensor_checks():
         plan.forward(torch.zeros((8, 8, 16), dtype=C64, device="cuda")[:, :, :8])
     with pytest.raises(ValueError):
         plan.forward(torch.zeros((8, 8, 8), dtype=C64))
+
+
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("shape,axes", [((64, 48, 80), "abc"), ((30, 9, 512), "c"), ((512, 6, 10), "a"),
+                                        ((5 * 9, 3, 64), "abc")])
+def test_xcd_tile_order_is_bit_identical(shape, axes, dtype):
+    """The XCD-contiguous tile order ("/x") only changes which workgroup runs
+    which tile: tile counts divisible by 8 and not, contiguous and strided
+    passes, exchanges in parts, and the transposing pass give the same bits."""
+    x = gen(shape, dtype)
+    base = offt.default_plan_string(shape, dtype)
+    fields = base.split(";")
+    marked = ";".join(f + "/x" if f[0] in axes and f[1] == "=" and f[2:] != "1" else f for f in fields)
+    assert marked != base
+    p0 = offt.Plan(shape, dtype=dtype, tune="forced", forced_plan=base)
+    p1 = offt.Plan(shape, dtype=dtype, tune="forced", forced_plan=marked)
+    assert p1.describe() == marked
+    y0, y1 = p0.forward(x), p1.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+    assert oracle.rel_l2(host(y1), ref3(host(x))) <= tol(x.numel(), dtype)
+    # the transposing pass of the reversed order
+    rs = shape[::-1]
+    fwd = offt.plan_string(shape, dtype, "cba").split("|")[0]
+    bwd = offt.plan_string(rs, dtype, "cba").split("|")[0]
+    if "rev=" in fwd:
+        tax = fwd.split("rev=")[1][0]
+        fx = ";".join(f + "/x" if f.startswith(tax + "=") else f for f in fwd.split(";"))
+        r0 = offt.Plan(shape, dtype=dtype, layout="cba", tune="forced", forced_plan=fwd + "|" + bwd)
+        r1 = offt.Plan(shape, dtype=dtype, layout="cba", tune="forced", forced_plan=fx + "|" + bwd)
+        z0, z1 = r0.forward(x), r1.forward(x)
+        torch.cuda.synchronize()
+        assert torch.equal(z0, z1)

@@ -87,3 +87,15 @@ def test_bad_layout_names_rejected_before_the_device():
         offt.plan_string((8, 8, 8), C128, "bca")
     with pytest.raises(ValueError):
         offt.Plan((8, 8, 8), layout="zyx")
+
+
+def test_xcd_tile_order_in_plan_strings():
+    """"/x" after an axis spec: the pass takes its tiles in XCD-contiguous order."""
+    s = "order=bac;a=16x16x2/16/p2/x;b=32x16/32/p2;c=16x16x2/2/x"
+    assert offt.plan_string((512, 512, 512), C128, "natural", s) == s
+    r = "order=cba;rev=a;a=16x16x2/4/p2/x;b=16x16x2/4;c=16x16x2/4|" + BASE
+    assert offt.plan_string((512, 512, 512), C128, "cba", r) == r
+    assert offt.plan_string_nd((64, 64, 64, 64), C64, "order=dcba;a=16x4/32/x").startswith("order=dcba;a=16x4/32/x;")
+    for bad in ["order=cba;c=16x16x2/2/y", "order=cba;c=16x16x2/2/x/p2", "order=cba;c=16x16x2/2/xx"]:
+        with pytest.raises(offt.OfftError):
+            offt.plan_string((512, 512, 512), C128, "natural", bad)
