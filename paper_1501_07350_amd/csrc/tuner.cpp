@@ -7,10 +7,10 @@
 // passes.
 //
 // Protocol: 1 warm-up + `reps` timed executions per candidate (hipEvents on the
-// tuning stream), score = minimum; ties go to the earlier candidate (the
-// heuristic's choices come first).  The data is refilled with uniform random
-// values before each candidate (timings on all-zero buffers are not
-// representative of real data on this device).
+// tuning stream), score = minimum of up to two runs, median of more; ties go
+// to the earlier candidate (the heuristic's choices come first).  The data is
+// refilled with uniform random values before each candidate (timings on
+// all-zero buffers are not representative of real data on this device).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -105,6 +105,18 @@ static void cache_store(const char* path, const offt_plan_s* p, const PlanChoice
 // Times one candidate for a grid of shape `dims` from `src` to `dst` (equal:
 // in place), through `work` where a transposing pass needs it.  Returns
 // OFFT_SUCCESS and the minimum time in *ms.
+// Score of a candidate's timed runs: the minimum of up to two runs (the
+// library's default), the median of three or more -- a minimum over many
+// runs favours kernels whose time varies from run to run, which then lose
+// in steady use.
+static float score(std::vector<float>& t) {
+    if (t.empty()) return 1e30f;
+    std::sort(t.begin(), t.end());
+    if (t.size() <= 2) return t[0];
+    const size_t m = t.size() / 2;
+    return t.size() % 2 ? t[m] : 0.5f * (t[m - 1] + t[m]);
+}
+
 // Times a pass list over `nelem` elements (see time_choice).
 static int time_passes(offt_plan_s* p, PassPlan* passes, int n, int64_t nelem, void* src, void* dst, void* work,
                        hipStream_t s, int reps, float* ms) {
@@ -119,7 +131,7 @@ static int time_passes(offt_plan_s* p, PassPlan* passes, int n, int64_t nelem, v
     if (hipEventCreate(&e0) != hipSuccess) return OFFT_ERR_HIP;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OFFT_ERR_HIP; }
     rc = exec_passes(p, passes, n, src, dst, work, OFFT_FORWARD, s);   // warm-up
-    float best = 1e30f;
+    std::vector<float> runs;
     for (int r = 0; r < reps && rc == OFFT_SUCCESS; ++r) {
         if (hipEventRecord(e0, s) != hipSuccess) { rc = OFFT_ERR_HIP; break; }
         rc = exec_passes(p, passes, n, src, dst, work, OFFT_FORWARD, s);
@@ -127,11 +139,11 @@ static int time_passes(offt_plan_s* p, PassPlan* passes, int n, int64_t nelem, v
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = OFFT_ERR_HIP; break; }
         float t = 0.f;
         if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) { rc = OFFT_ERR_HIP; break; }
-        if (t < best) best = t;
+        runs.push_back(t);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    *ms = best;
+    *ms = score(runs);
     return rc;
 }
 
@@ -156,7 +168,7 @@ static int time_pass(offt_plan_s* p, PassPlan pass, void* buf, void* other, hipS
     if (hipEventCreate(&e0) != hipSuccess) return OFFT_ERR_HIP;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OFFT_ERR_HIP; }
     if (launch_pass(pass, src, buf, 0, 0, 1.0, s) != hipSuccess) rc = OFFT_ERR_HIP;   // warm-up
-    float best = 1e30f;
+    std::vector<float> runs;
     for (int r = 0; r < reps && rc == OFFT_SUCCESS; ++r) {
         float t = 0.f;
         if (hipEventRecord(e0, s) != hipSuccess || launch_pass(pass, src, buf, 0, 0, 1.0, s) != hipSuccess ||
@@ -165,11 +177,11 @@ static int time_pass(offt_plan_s* p, PassPlan pass, void* buf, void* other, hipS
             rc = OFFT_ERR_HIP;
             break;
         }
-        best = std::min(best, t);
+        runs.push_back(t);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    *ms = best;
+    *ms = score(runs);
     return rc;
 }
 
