@@ -173,3 +173,19 @@ def test_128_4_complex64_sampled_points():
     t = tol(x.numel(), C64)
     print(f"128^4 c64: points {e_pts:.2e} roundtrip {e_rt:.2e} plan {plan.describe()}", flush=True)
     assert e_pts <= t and e_rt <= t
+
+
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+def test_longest_axes_in_4_and_5_axis_grids(dtype):
+    """Axes of 1024 points (exchanges in parts on the strided ones) inside 4-
+    and 5-axis grids, against the full oracle."""
+    for shape in [(1024, 3, 1024, 2), (2, 1024, 1, 3, 512)]:
+        x = gen(shape, dtype)
+        plan = offt.Plan(shape, dtype=dtype, normalize_inverse=True)
+        y = plan.forward(x)
+        z = plan.backward(y)
+        torch.cuda.synchronize()
+        xh = host(x)
+        t = tol(x.numel(), dtype)
+        assert oracle.rel_l2(host(y), ndim.fftn(xh)) <= t, (shape, plan.describe())
+        assert oracle.rel_l2(host(z), xh) <= t
