@@ -297,11 +297,17 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
             }
         }
     }
-    // whole transforms: every order (and transposing axis) with every
-    // combination of each axis's two fastest kernels
+    // whole transforms: the heuristic plan itself first (so the choice is
+    // never slower than it by this measure), then every order (and
+    // transposing axis) with every combination of each axis's two fastest
+    // kernels
     static const int orders[6][3] = {{2, 1, 0}, {2, 0, 1}, {1, 2, 0}, {1, 0, 2}, {0, 2, 1}, {0, 1, 2}};
     PlanChoice winner = heur;
     float win_ms = 1e30f;
+    if (rc == OFFT_SUCCESS) {
+        rc = time_choice(p, heur, dims, B.src, B.buf, B.work, s, o.reps, &win_ms);
+        ++*timed;
+    }
     for (int t : taxes) {
         for (int i = 0; i < 6 && rc == OFFT_SUCCESS; ++i) {
             for (int combo = 0; combo < 8 && rc == OFFT_SUCCESS; ++combo) {
@@ -517,8 +523,15 @@ static int exhaustive_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice, f
     do {
         if (perm != axes) orders.push_back(perm);
     } while (std::next_permutation(perm.begin(), perm.end()));
-    NdChoice winner = best;
+    // the heuristic plan itself first, then every order with the fastest kernels
+    NdChoice winner = default_choice_nd(p->dtype, D, dims);
     float wms = 1e30f;
+    if (rc == OFFT_SUCCESS) {
+        PassPlan passes[kMaxDims];
+        const int n = build_passes_nd(winner, dims, p->batch, passes);
+        rc = time_passes(p, passes, n, nelem, src, buf, nullptr, s, o.reps, &wms);
+        ++*timed;
+    }
     for (size_t oi = 0; oi < orders.size() && rc == OFFT_SUCCESS; ++oi) {
         NdChoice c = best;
         int pos = 0;
