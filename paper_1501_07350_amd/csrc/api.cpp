@@ -307,8 +307,9 @@ offt_plan_t offt_plan_nd(int ndim, const int64_t* dims, int dtype, int64_t batch
     offt_opts opts;
     offt_opts_default(&opts);
     if (o) opts = *o;
-    if (opts.tune < OFFT_TUNE_NONE || opts.tune > OFFT_TUNE_FORCED || (opts.tune == OFFT_TUNE_FORCED && !opts.forced_plan) ||
-        opts.reps < 1 || (opts.use_graph != 0 && opts.use_graph != 1) || opts.layout != OFFT_LAYOUT_NATURAL) {
+    if (opts.tune < OFFT_TUNE_NONE || opts.tune > OFFT_TUNE_FORCED ||
+        (opts.tune == OFFT_TUNE_FORCED && !opts.forced_plan) || opts.reps < 1 ||
+        (opts.use_graph != 0 && opts.use_graph != 1) || opts.layout != OFFT_LAYOUT_NATURAL) {
         set_error(OFFT_ERR_INVALID_ARG);
         return nullptr;
     }

@@ -197,10 +197,11 @@ struct TuneBuffers {
 // are independent kernels, so every (radix sequence, threads per line, tile
 // width) of each axis is timed as a single pass in every geometry the axis
 // can have (on the abc grid; for reversed output also on the cba grid and as
-// the transposing pass), and the two fastest kept per axis and geometry;
-// then the six pass orders (times the transposing axes) are timed as whole
-// transforms with every combination of those kernels.  Ties keep the earlier
-// candidate (the heuristic's kernels and order come first).
+// the transposing pass), and the two fastest kept per axis and geometry
+// (the fastest also tried with its tiles in XCD-contiguous order); then the
+// heuristic plan and the six pass orders (times the transposing axes) with
+// every combination of those kernels are timed as whole transforms.  Ties
+// keep the earlier candidate (the heuristic's kernels and order come first).
 static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dims[3], bool reversed,
                            const TuneBuffers& B, PlanChoice* choice, float* win_ms_out, int* timed) {
     hipStream_t s = static_cast<hipStream_t>(o.stream);
