@@ -311,10 +311,11 @@ int64_t offt_transpose_count(int64_t n1, int64_t n2, int64_t n3, int64_t np, int
 int64_t offt_transpose_volume(int64_t n1, int64_t n2, int64_t n3, int64_t np, int step);
 
 /* ---- plan selection internals: candidates, features, timings -------------
- * The tuners choose among a deterministic list of candidate plans per grid
- * shape (the heuristic plan first; then other radix sequences and tile widths
- * per axis; then the other five axis orders).  These calls expose that list
- * for building and using the learned selector. */
+ * The learned selector chooses among a deterministic list of candidate plans
+ * per grid shape (the heuristic plan first; then other radix sequences and
+ * tile widths per axis; then the heuristic with one axis's tiles in
+ * XCD-contiguous order; then the other five axis orders).  These calls expose
+ * that list for building and using the learned selector. */
 
 /* Length of one plan feature vector. */
 int offt_feature_dim(void);
@@ -327,7 +328,8 @@ int offt_candidates(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch
                     size_t plans_bytes, float* features, int max);
 
 /* Times every candidate plan of a grid as the exhaustive tuner does
- * (1 warm-up + reps timed forward transforms, minimum, HIP events on
+ * (1 warm-up + reps timed forward transforms, minimum of up to two runs,
+ * median of more, HIP events on
  * `stream`), in place on the caller's device buffer `buf` of at least
  * batch*Na*Nb*Nc elements, which is filled with uniform random values before
  * each candidate (its contents are destroyed).  times_ms[i] is

@@ -65,6 +65,7 @@ void plan_features(int dtype, const int64_t dims[3], int64_t batch, const PlanCh
         g[9] = (float)std::log2((double)k->tpl);
         g[10] = (float)pos[ax] * 0.5f;
         g[12] = (float)std::log2((double)k->nparts);
+        g[13] = (float)c.xcd[ax];
     }
 }
 

@@ -15,8 +15,9 @@ namespace offt {
 // points, precision, one-hot axis order, and per axis (a, b, c): strided
 // flag, stage count, counts of radix-16/8/4/2/3/5 stages, log2 tile width,
 // log2 threads per line, position in the pass order, count of radix-32
-// stages, log2 of the parts its LDS exchanges run in.
-constexpr int kAxisFeatures = 13;
+// stages, log2 of the parts its LDS exchanges run in, XCD-contiguous tile
+// order.
+constexpr int kAxisFeatures = 14;
 constexpr int kFeatureDim = 12 + 3 * kAxisFeatures;
 void plan_features(int dtype, const int64_t dims[3], int64_t batch, const PlanChoice& c, float* out);
 

@@ -120,6 +120,7 @@ def plan_passes(dims, dtype):
         if L <= 1:
             continue
         rad_s, *rest = fields[ch].split("/")
+        rest = [t for t in rest if t != "x" and not t.startswith("p")]   # tile order, parts
         seq = [int(r) for r in rad_s.split("x")]
         W = int(rest[0])
         tpl = int(rest[1]) if len(rest) > 1 else L // max(seq)

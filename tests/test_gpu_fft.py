@@ -445,7 +445,7 @@ def test_xcd_tile_order_is_bit_identical(shape, axes, dtype):
     which tile: tile counts divisible by 8 and not, contiguous and strided
     passes, exchanges in parts, and the transposing pass give the same bits."""
     x = gen(shape, dtype)
-    base = offt.default_plan_string(shape, dtype)
+    base = offt.default_plan_string(shape, dtype).replace("/x", "")     # launch order everywhere
     fields = base.split(";")
     marked = ";".join(f + "/x" if f[0] in axes and f[1] == "=" and f[2:] != "1" else f for f in fields)
     assert marked != base
@@ -458,7 +458,7 @@ def test_xcd_tile_order_is_bit_identical(shape, axes, dtype):
     assert oracle.rel_l2(host(y1), ref3(host(x))) <= tol(x.numel(), dtype)
     # the transposing pass of the reversed order
     rs = shape[::-1]
-    fwd = offt.plan_string(shape, dtype, "cba").split("|")[0]
+    fwd = offt.plan_string(shape, dtype, "cba").split("|")[0].replace("/x", "")
     bwd = offt.plan_string(rs, dtype, "cba").split("|")[0]
     if "rev=" in fwd:
         tax = fwd.split("rev=")[1][0]
