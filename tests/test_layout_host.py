@@ -99,3 +99,27 @@ def test_xcd_tile_order_in_plan_strings():
     for bad in ["order=cba;c=16x16x2/2/y", "order=cba;c=16x16x2/2/x/p2", "order=cba;c=16x16x2/2/xx"]:
         with pytest.raises(offt.OfftError):
             offt.plan_string((512, 512, 512), C128, "natural", bad)
+
+
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("shape", [(512, 512, 512), (64, 48, 30), (1, 32, 40), (30, 40, 1), (6, 1, 9)])
+def test_heuristic_tile_order_follows_the_stride(shape, dtype):
+    """The heuristic plan takes the XCD-contiguous tile order ("/x") exactly on
+    the axes whose lines are strided (a later axis longer than 1)."""
+    f = dict(t.split("=", 1) for t in offt.default_plan_string(shape, dtype).split(";"))
+    for i, ax in enumerate("abc"):
+        if shape[i] == 1:
+            assert f[ax] == "1"
+            continue
+        strided = any(n > 1 for n in shape[i + 1:])
+        assert f[ax].endswith("/x") == strided, (ax, f[ax])
+
+
+def test_heuristic_tile_order_on_reversed_and_nd_plans():
+    # the transposing pass keeps the launch order; on the cba grid after it,
+    # axis b is strided (stride Na) and axis c is contiguous
+    f, b = halves(offt.plan_string((512, 512, 512), C128, "cba"))
+    assert f["rev"] == "a" and not f["a"].endswith("/x")
+    assert f["b"].endswith("/x") and not f["c"].endswith("/x")
+    nd = dict(t.split("=", 1) for t in offt.plan_string_nd((64, 64, 64, 64), C64).split(";"))
+    assert [nd[ax].endswith("/x") for ax in "abcd"] == [True, True, True, False]
