@@ -575,6 +575,48 @@ def summarize_stats(d: str, log: str, command: str, n: int, steps: int, warmup: 
     return "\n".join(lines) + "\n"
 
 
+def summarize_batch(d: str, command: str, steps: int, warmup: int) -> str:
+    """Kernel-trace figures of the uneven-batch executors from one
+    `--batch-only` run: per executor family, dispatches and mean duration;
+    per execution, the summed kernel time, and for the level kernels replayed
+    from the graph (the last `steps` executions) the span from the first
+    level's start to the last one's end."""
+    trace = _read_csv(_find(d, "kernel_trace.csv"))
+    trace.sort(key=lambda r: int(r["Dispatch_Id"]))
+    fams = [("persistent work-queue kernel", "many_kernel_", 3),
+            ("level kernels", "many_level_kernel_", 2),
+            ("level-synchronous persistent kernel", "many_sync_kernel_", 2)]
+    runs_per_variant = steps + warmup
+    lines = ["# rocprofv3 kernel trace of the uneven-batch executors (64 complex64 grids, one forward each)",
+             f"# command: {command}",
+             f"# {steps} timed + {warmup} warm-up executions per variant; the persistent kernel runs in 3 variants",
+             "# (tuned, tuned in a graph, heuristic in a graph), the level and level-synchronous kernels in 2",
+             "# (direct, in a graph)",
+             f"{'executor':<38} {'dispatches':>10} {'mean_us':>9} {'per_exec':>8} {'busy_us_per_exec':>17}"]
+    for label, key, nvar in fams:
+        rows = [r for r in trace if key in r["Kernel_Name"]]
+        if not rows:
+            lines.append(f"{label:<38} {'none traced':>10}")
+            continue
+        durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows]
+        execs = nvar * runs_per_variant
+        per = len(rows) / execs
+        lines.append(f"{label:<38} {len(rows):>10} {sum(durs) / len(rows):>9.2f} {per:>8.2f} "
+                     f"{sum(durs) / execs:>17.2f}")
+        if key == "many_level_kernel_" and per == int(per):
+            k = int(per)
+            tail = rows[len(rows) - steps * k:]
+            spans = []
+            for e in range(steps):
+                grp = tail[e * k:(e + 1) * k]
+                spans.append((max(int(r["End_Timestamp"]) for r in grp)
+                              - min(int(r["Start_Timestamp"]) for r in grp)) / 1e3)
+            busy = sum((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tail) / steps
+            lines.append(f"  graph replays: {k} level kernels per execution, span first start to last end "
+                         f"{sum(spans) / len(spans):.2f} us (min {min(spans):.2f}), summed kernel time {busy:.2f} us")
+    return "\n".join(lines) + "\n"
+
+
 def _pmc_per_dispatch(d: str, counter: str):
     """[(kernel_name, value_KiB)] in dispatch order for one counter."""
     rows = _read_csv(_find(d, "counter_collection.csv"))
@@ -720,6 +762,10 @@ def main():
                     help="reduce a rocprofv3 --pmc run of the SQ/GRBM counters (VALU, LDS) to a per-pass table")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "LOG"),
                     help="reduce two rocprofv3 --pmc output dirs to profiles/pmc_traffic.json")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="time only the uneven batch of 64 grids (to profile its executors)")
+    ap.add_argument("--summarize-batch", metavar="DIR",
+                    help="reduce a rocprofv3 --kernel-trace run of --batch-only")
     ap.add_argument("--configs", action="store_true",
                     help="report configs 1, 2 and 1024^3 of config 3, and the CPU oracle table, instead")
     ap.add_argument("--plan-cache", default=PLAN_CACHE,
@@ -738,6 +784,10 @@ def main():
                            args.warmup)
         open(args.out, "w").write(txt) if args.out else print(txt)
         return
+    if args.summarize_batch:
+        txt = summarize_batch(args.summarize_batch, args.command, args.steps, args.warmup)
+        open(args.out, "w").write(txt) if args.out else print(txt)
+        return
     if args.summarize_pmc:
         d, txt = summarize_pmc(*args.summarize_pmc, args.n, args.steps, args.warmup, args.command)
         with open(TRAFFIC_FILE, "w") as f:
@@ -745,7 +795,7 @@ def main():
         open(args.out, "w").write(txt) if args.out else print(txt)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the 3-D FFT is measured on a single MI355X)", file=sys.stderr)
         sys.exit(2)
     import torch
@@ -755,6 +805,9 @@ def main():
         sys.exit(2)
     if args.configs:
         print(json.dumps(configs_report(args.steps, args.warmup)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"batch": time_batch(args.steps, args.warmup, not args.no_check)}), flush=True)
         return
     n = args.n
     # plans tuned at init (excluded from the timing, as the paper excludes its
