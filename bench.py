@@ -253,6 +253,15 @@ def time_nd(shape, dtype, steps: int, warmup: int, check: bool, tune: str = "exh
     return res
 
 
+def nd_runs(steps: int, warmup: int, check: bool):
+    """The grids of 4 and 5 axes: 128^4 complex64 and complex128, 48^5 complex64."""
+    import torch
+
+    return [time_nd((128, 128, 128, 128), torch.complex64, steps, warmup, check),
+            time_nd((128, 128, 128, 128), torch.complex128, steps, warmup, False),
+            time_nd((48, 48, 48, 48, 48), torch.complex64, steps, warmup, check)]
+
+
 def time_batch(steps: int, warmup: int, check: bool, count: int = 64):
     """Uneven batch of `count` complex64 grids (axes drawn from
     {48,...,160}): persistent launch replayed from a HIP graph vs every grid's
@@ -617,6 +626,54 @@ def summarize_batch(d: str, command: str, steps: int, warmup: int) -> str:
     return "\n".join(lines) + "\n"
 
 
+def summarize_nd(d: str, log: str, command: str, steps: int, warmup: int) -> str:
+    """Per-pass durations of the 4- and 5-axis transforms from one rocprofv3
+    --kernel-trace run of `--nd-only` (plans from the plan cache, so every
+    pass dispatch belongs to a timed or warm-up transform): for each grid,
+    the tuned plan and then the heuristic plan, `warmup + steps` transforms
+    of one dispatch per axis in the plan's pass order."""
+    res = None
+    for line in open(log):
+        if line.startswith("{"):
+            res = json.loads(line)["nd"]
+    if res is None:
+        raise RuntimeError(f"no result line in {log}")
+    trace = _read_csv(_find(d, "kernel_trace.csv"))
+    trace.sort(key=lambda r: int(r["Dispatch_Id"]))
+    disp = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace
+            if "fft_pass_kernel" in r["Kernel_Name"]]
+    lines = ["# rocprofv3 kernel trace of the 4- and 5-axis transforms: mean duration per pass dispatch over",
+             "# the timed transforms; GB/s = algorithmic 2*N*s bytes per pass / duration",
+             f"# command: {command}"]
+    k = 0
+    for r in res:
+        N = math.prod(r["shape"])
+        s = 16 if r["dtype"] == "f64" else 8
+        for name in ("tuned", "heuristic"):
+            plan = r[name]["plan"]
+            fields = dict(f.split("=", 1) for f in plan.split(";"))
+            order = fields["order"]
+            lines.append(f"{'x'.join(map(str, r['shape']))} {r['dtype']} {name} plan {plan}: "
+                         f"{r[name]['ms'] * 1e3:.1f} us per transform (HIP events)")
+            per = [[] for _ in order]
+            for st in range(warmup + steps):
+                for i in range(len(order)):
+                    if k >= len(disp):
+                        raise RuntimeError(f"the trace holds {len(disp)} pass dispatches, fewer than expected")
+                    if st >= warmup:
+                        per[i].append(disp[k])
+                    k += 1
+            total = 0.0
+            for i, ax in enumerate(order):
+                m = sum(per[i]) / len(per[i])
+                total += m
+                lines.append(f"  pass {i} {ax}={fields[ax]:<14} {m:9.2f} us  {2.0 * N * s / (m * 1e3):7.1f} GB/s")
+            lines.append(f"  summed pass time {total:.1f} us")
+    if k != len(disp):
+        raise RuntimeError(f"expected {k} pass dispatches, the trace holds {len(disp)}")
+    return "\n".join(lines) + "\n"
+
+
 def _pmc_per_dispatch(d: str, counter: str):
     """[(kernel_name, value_KiB)] in dispatch order for one counter."""
     rows = _read_csv(_find(d, "counter_collection.csv"))
@@ -764,6 +821,10 @@ def main():
                     help="reduce two rocprofv3 --pmc output dirs to profiles/pmc_traffic.json")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the uneven batch of 64 grids (to profile its executors)")
+    ap.add_argument("--nd-only", action="store_true",
+                    help="time only the 4- and 5-axis grids (to profile their passes)")
+    ap.add_argument("--summarize-nd", nargs=2, metavar=("DIR", "LOG"),
+                    help="reduce a rocprofv3 --kernel-trace run of --nd-only")
     ap.add_argument("--summarize-batch", metavar="DIR",
                     help="reduce a rocprofv3 --kernel-trace run of --batch-only")
     ap.add_argument("--configs", action="store_true",
@@ -782,6 +843,10 @@ def main():
     if args.summarize_sq:
         txt = summarize_sq(args.summarize_sq[0], args.summarize_sq[1], args.command, args.n, args.steps,
                            args.warmup)
+        open(args.out, "w").write(txt) if args.out else print(txt)
+        return
+    if args.summarize_nd:
+        txt = summarize_nd(args.summarize_nd[0], args.summarize_nd[1], args.command, args.steps, args.warmup)
         open(args.out, "w").write(txt) if args.out else print(txt)
         return
     if args.summarize_batch:
@@ -805,6 +870,9 @@ def main():
         sys.exit(2)
     if args.configs:
         print(json.dumps(configs_report(args.steps, args.warmup)), flush=True)
+        return
+    if args.nd_only:
+        print(json.dumps({"nd": nd_runs(args.steps, args.warmup, not args.no_check)}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({"batch": time_batch(args.steps, args.warmup, not args.no_check)}), flush=True)
@@ -863,9 +931,7 @@ def main():
             "workload": f"{n}^3 forward with the output in cba order, and backward from it",
             "f64": time_reversed(n, torch.complex128, args.steps, args.warmup, not args.no_check),
             "f32": time_reversed(n, torch.complex64, args.steps, args.warmup, not args.no_check)}
-        out["nd"] = [time_nd((128, 128, 128, 128), torch.complex64, args.steps, args.warmup, not args.no_check),
-                     time_nd((128, 128, 128, 128), torch.complex128, args.steps, args.warmup, False),
-                     time_nd((48, 48, 48, 48, 48), torch.complex64, args.steps, args.warmup, not args.no_check)]
+        out["nd"] = nd_runs(args.steps, args.warmup, not args.no_check)
     if args.calibrate:
         calibrate_copy()
     if not args.no_cpu:

@@ -47,3 +47,27 @@ def test_batch_trace_summary(tmp_path):
     replay = [l for l in txt.splitlines() if "graph replays" in l][0]
     assert "3 level kernels per execution" in replay
     assert "span first start to last end 604.00 us" in replay and "summed kernel time 600.00 us" in replay
+
+
+def test_nd_trace_summary(tmp_path):
+    steps, warmup = 2, 1
+    res = [{"shape": [8, 8, 8, 8], "dtype": "f32",
+            "tuned": {"ms": 0.01, "plan": "order=dacb;a=8/8;b=8/8;c=8/8/x;d=8/8"},
+            "heuristic": {"ms": 0.02, "plan": "order=dcba;a=8/8/x;b=8/8/x;c=8/8/x;d=8/8"}}]
+    log = tmp_path / "nd.log"
+    log.write_text("noise\n" + __import__("json").dumps({"nd": res}) + "\n")
+    d = []
+    for plan_scale in (1, 2):
+        for st in range(warmup + steps):
+            # warm-up transforms take 50 us per pass, so a wrong split shows in the means
+            d += [("twiddle_kernel", 5, 0)] if st == 0 else []
+            d += [("offt::fft_pass_kernel<...>", (50_000 if st < warmup else 1_000 * (i + 1) * plan_scale), 10)
+                  for i in range(4)]
+    write_trace(str(tmp_path / "run" / "run_kernel_trace.csv"), d)
+    txt = load_bench().summarize_nd(str(tmp_path), str(log), "cmd", steps, warmup)
+    passes = [l.split() for l in txt.splitlines() if l.startswith("  pass")]
+    assert [p[2] for p in passes[:4]] == ["d=8/8", "a=8/8", "c=8/8/x", "b=8/8"]
+    assert [float(p[3]) for p in passes] == [1.0, 2.0, 3.0, 4.0, 2.0, 4.0, 6.0, 8.0]
+    # 2 * 4096 points * 8 bytes in 1 us = 65.5 GB/s
+    assert float(passes[0][5]) == 65.5
+    assert "summed pass time 10.0 us" in txt and "summed pass time 20.0 us" in txt
