@@ -253,6 +253,15 @@ def time_nd(shape, dtype, steps: int, warmup: int, check: bool, tune: str = "exh
     return res
 
 
+def reversed_runs(n: int, steps: int, warmup: int, check: bool):
+    """The reversed (cba) output order at n^3, complex128 and complex64."""
+    import torch
+
+    return {"workload": f"{n}^3 forward with the output in cba order, and backward from it",
+            "f64": time_reversed(n, torch.complex128, steps, warmup, check),
+            "f32": time_reversed(n, torch.complex64, steps, warmup, check)}
+
+
 def nd_runs(steps: int, warmup: int, check: bool):
     """The grids of 4 and 5 axes: 128^4 complex64 and complex128, 48^5 complex64."""
     import torch
@@ -626,6 +635,58 @@ def summarize_batch(d: str, command: str, steps: int, warmup: int) -> str:
     return "\n".join(lines) + "\n"
 
 
+def summarize_reversed(d: str, log: str, command: str, n: int, steps: int, warmup: int) -> str:
+    """Per-pass durations of the reversed (cba) output order from one
+    rocprofv3 --kernel-trace run of `--reversed-only` (plans from the plan
+    cache): for complex128 then complex64, the natural plan forward and
+    backward, then the reversed plan forward and backward, `warmup + steps`
+    transforms each, one dispatch per axis in the pass order.  The
+    transposing pass is marked (T)."""
+    res = None
+    for line in open(log):
+        if line.startswith("{"):
+            res = json.loads(line)["reversed_output"]
+    if res is None:
+        raise RuntimeError(f"no result line in {log}")
+    trace = _read_csv(_find(d, "kernel_trace.csv"))
+    trace.sort(key=lambda r: int(r["Dispatch_Id"]))
+    disp = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace
+            if "fft_pass_kernel" in r["Kernel_Name"] or "fft_tpass_kernel" in r["Kernel_Name"]]
+    lines = ["# rocprofv3 kernel trace of the reversed (cba) output order beside the natural one: mean duration",
+             "# per pass dispatch over the timed transforms; GB/s = algorithmic 2*N*s bytes per pass / duration",
+             f"# command: {command}"]
+    N = n ** 3
+    k = 0
+    for dt in ("f64", "f32"):
+        s_b = 16 if dt == "f64" else 8
+        for name in ("natural", "reversed"):
+            halves = res[dt][name]["plan"].split("|")
+            for direction, half in (("fwd", halves[0]), ("bwd", halves[-1])):
+                fields = dict(f.split("=", 1) for f in half.split(";"))
+                order = fields["order"]
+                ev = res[dt][name][f"{direction}_ms"]
+                lines.append(f"{n}^3 {dt} {name} {direction} plan {half}: {ev * 1e3:.1f} us per transform (HIP events)")
+                per = [[] for _ in order]
+                for st in range(warmup + steps):
+                    for i in range(len(order)):
+                        if k >= len(disp):
+                            raise RuntimeError(f"the trace holds {len(disp)} pass dispatches, fewer than expected")
+                        if st >= warmup:
+                            per[i].append(disp[k])
+                        k += 1
+                total = 0.0
+                for i, ax in enumerate(order):
+                    m = sum(per[i]) / len(per[i])
+                    total += m
+                    tag = " (T)" if fields.get("rev") == ax else ""
+                    lines.append(f"  pass {i} {ax}={fields[ax] + tag:<20} {m:9.2f} us  "
+                                 f"{2.0 * N * s_b / (m * 1e3):7.1f} GB/s")
+                lines.append(f"  summed pass time {total:.1f} us")
+    if k != len(disp):
+        raise RuntimeError(f"expected {k} pass dispatches, the trace holds {len(disp)}")
+    return "\n".join(lines) + "\n"
+
+
 def summarize_nd(d: str, log: str, command: str, steps: int, warmup: int) -> str:
     """Per-pass durations of the 4- and 5-axis transforms from one rocprofv3
     --kernel-trace run of `--nd-only` (plans from the plan cache, so every
@@ -821,6 +882,10 @@ def main():
                     help="reduce two rocprofv3 --pmc output dirs to profiles/pmc_traffic.json")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the uneven batch of 64 grids (to profile its executors)")
+    ap.add_argument("--reversed-only", action="store_true",
+                    help="time only the reversed (cba) output order at --n (to profile its passes)")
+    ap.add_argument("--summarize-reversed", nargs=2, metavar=("DIR", "LOG"),
+                    help="reduce a rocprofv3 --kernel-trace run of --reversed-only")
     ap.add_argument("--nd-only", action="store_true",
                     help="time only the 4- and 5-axis grids (to profile their passes)")
     ap.add_argument("--summarize-nd", nargs=2, metavar=("DIR", "LOG"),
@@ -843,6 +908,11 @@ def main():
     if args.summarize_sq:
         txt = summarize_sq(args.summarize_sq[0], args.summarize_sq[1], args.command, args.n, args.steps,
                            args.warmup)
+        open(args.out, "w").write(txt) if args.out else print(txt)
+        return
+    if args.summarize_reversed:
+        txt = summarize_reversed(args.summarize_reversed[0], args.summarize_reversed[1], args.command, args.n,
+                                 args.steps, args.warmup)
         open(args.out, "w").write(txt) if args.out else print(txt)
         return
     if args.summarize_nd:
@@ -870,6 +940,10 @@ def main():
         sys.exit(2)
     if args.configs:
         print(json.dumps(configs_report(args.steps, args.warmup)), flush=True)
+        return
+    if args.reversed_only:
+        print(json.dumps({"reversed_output": reversed_runs(args.n, args.steps, args.warmup, not args.no_check)}),
+              flush=True)
         return
     if args.nd_only:
         print(json.dumps({"nd": nd_runs(args.steps, args.warmup, not args.no_check)}), flush=True)
@@ -927,10 +1001,7 @@ def main():
     if not args.no_batch:
         out["small"] = time_small(args.steps, args.warmup, not args.no_check)
         out["batch"] = time_batch(args.steps, args.warmup, not args.no_check)
-        out["reversed_output"] = {
-            "workload": f"{n}^3 forward with the output in cba order, and backward from it",
-            "f64": time_reversed(n, torch.complex128, args.steps, args.warmup, not args.no_check),
-            "f32": time_reversed(n, torch.complex64, args.steps, args.warmup, not args.no_check)}
+        out["reversed_output"] = reversed_runs(n, args.steps, args.warmup, not args.no_check)
         out["nd"] = nd_runs(args.steps, args.warmup, not args.no_check)
     if args.calibrate:
         calibrate_copy()

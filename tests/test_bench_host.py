@@ -71,3 +71,32 @@ def test_nd_trace_summary(tmp_path):
     # 2 * 4096 points * 8 bytes in 1 us = 65.5 GB/s
     assert float(passes[0][5]) == 65.5
     assert "summed pass time 10.0 us" in txt and "summed pass time 20.0 us" in txt
+
+
+def test_reversed_trace_summary(tmp_path):
+    steps, warmup, n = 2, 1, 8
+    nat = "order=bca;a=8/8;b=8/8/x;c=8/8"
+    rev = "order=cba;rev=a;a=8/8;b=8/8/x;c=8/8|order=bca;rev=a;a=8/8;b=8/8;c=8/8"
+    res = {"workload": "w"}
+    for dt in ("f64", "f32"):
+        res[dt] = {"natural": {"fwd_ms": 0.006, "bwd_ms": 0.006, "plan": nat},
+                   "reversed": {"fwd_ms": 0.007, "bwd_ms": 0.008, "plan": rev}}
+    log = tmp_path / "rev.log"
+    log.write_text(__import__("json").dumps({"reversed_output": res}) + "\n")
+    d = []
+    for run in range(8):                 # (f64, f32) x (natural, reversed) x (fwd, bwd)
+        for st in range(warmup + steps):
+            for i in range(3):
+                name = "offt::fft_tpass_kernel<...>" if run % 4 >= 2 and i == 2 - (run % 2) else \
+                    "offt::fft_pass_kernel<...>"
+                d.append((name, 99_000 if st < warmup else 1_000 * (run + 1) + 100 * i, 10))
+            d.append(("offt::fill_uniform_kernel", 7, 0))
+    write_trace(str(tmp_path / "run" / "run_kernel_trace.csv"), d)
+    txt = load_bench().summarize_reversed(str(tmp_path), str(log), "cmd", n, steps, warmup)
+    passes = [l.split() for l in txt.splitlines() if l.startswith("  pass")]
+    assert len(passes) == 24
+    assert [p[2] for p in passes[6:9]] == ["c=8/8", "b=8/8/x", "a=8/8"]
+    assert passes[8][3] == "(T)" and passes[9][2] == "b=8/8" and passes[10][2] == "c=8/8"
+    assert passes[11][2] == "a=8/8" and passes[11][3] == "(T)"
+    assert [float(p[-4]) for p in passes[:3]] == [1.0, 1.1, 1.2]
+    assert float(passes[23][-4]) == 8.2
