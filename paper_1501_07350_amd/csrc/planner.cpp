@@ -211,7 +211,7 @@ static int max_radix(const KernelEntry* k) {
 // Heuristic tile width: strided lines get 256-byte row segments (16 columns
 // of complex128, 32 of complex64), and radix-32 kernels 32 columns in both
 // precisions; contiguous lines ~512 threads per workgroup for complex128 and
-// ~128 for complex64.
+// ~256 for complex64.
 static int strided_logW(const KernelEntry* k, int dtype) {
     return max_radix(k) >= 32 ? 5 : (dtype == OFFT_C2C_F64 ? 4 : 5);
 }
@@ -222,13 +222,17 @@ static int default_logW(const KernelEntry* k, int dtype, bool strided) {
     if (strided)
         logW = strided_logW(k, dtype);
     else
-        logW = ilog2(std::max<int64_t>(1, (dtype == OFFT_C2C_F64 ? 512 : 128) / k->tpl));
+        logW = ilog2(std::max<int64_t>(1, (dtype == OFFT_C2C_F64 ? 512 : 256) / k->tpl));
     return fit_logW(k, logW, dtype);
 }
 
 // Default kernel of an axis: the first in kernels_for() order whose tile at the
 // heuristic width fits; contiguous axes take the first kernel with whole-line
-// exchanges and radix <= 16.  Strided axes of length >= 512 look first at
+// exchanges and radix <= 16, complex64 ones first looking for radix <= 8 at
+// the default threads per line (over the 2200 grids of the selector's data
+// set, such a kernel at the same width made the complex64 transform faster in
+// 84% of the grids where the radix-16 kernel was the default, geometric mean
+// 0.93 of the time, 0.92 for axes up to 128 points).  Strided axes of length >= 512 look first at
 // radix-32 kernels whose LDS exchanges run in 2 parts (one exchange per line
 // instead of two, half the LDS per tile), then at the other 2-part kernels:
 // on MI355X these were the fastest, or within 0.5% of it, for every strided
@@ -241,6 +245,9 @@ static const KernelEntry* default_kernel(int dtype, int L, bool strided) {
         for (const KernelEntry* k : kernels_for(dtype, L))
             if (k->nparts == 2 && max_radix(k) <= 16) ks.push_back(k);
     }
+    if (!strided && dtype == OFFT_C2C_F32)
+        for (const KernelEntry* k : kernels_for(dtype, L))
+            if (k->nparts == 1 && max_radix(k) <= 8 && k->tpl * max_radix(k) == L) ks.push_back(k);
     for (const KernelEntry* k : kernels_for(dtype, L))
         if (k->nparts == 1 && max_radix(k) <= 16) ks.push_back(k);
     if (ks.empty()) return nullptr;

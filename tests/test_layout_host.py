@@ -123,3 +123,15 @@ def test_heuristic_tile_order_on_reversed_and_nd_plans():
     assert f["b"].endswith("/x") and not f["c"].endswith("/x")
     nd = dict(t.split("=", 1) for t in offt.plan_string_nd((64, 64, 64, 64), C64).split(";"))
     assert [nd[ax].endswith("/x") for ax in "abcd"] == [True, True, True, False]
+
+
+@pytest.mark.parametrize("L", [32, 64, 128, 160, 192, 256, 512])
+def test_heuristic_contiguous_kernel_by_precision(L):
+    """complex64 contiguous axes take a whole-line kernel of radix <= 8 at the
+    default threads per line; complex128 ones keep the radix-16 kernels."""
+    def c_spec(dtype):
+        return dict(t.split("=", 1) for t in offt.default_plan_string((8, 8, L), dtype).split(";"))["c"]
+    spec64 = c_spec(C64).split("/")
+    seq = [int(r) for r in spec64[0].split("x")]
+    assert max(seq) <= 8 and len(spec64) == 2          # radix <= 8, default threads per line, whole-line
+    assert max(int(r) for r in c_spec(C128).split("/")[0].split("x")) == 16
