@@ -169,6 +169,15 @@ int offt_plan_string_nd(int ndim, const int64_t* dims, int dtype, const char* pl
 int offt_exec_fwd(offt_plan_t p, const void* in, void* out, void* stream);
 int offt_exec_bwd(offt_plan_t p, const void* in, void* out, void* stream);
 
+/* offt_exec_bwd with the scaling chosen for this call: normalize = 1 multiplies
+ * the result by 1/(Na Nb Nc), 0 leaves it unnormalised, -1 takes the plan's
+ * normalize_inverse (the paper states no normalisation; the scaled inverse is
+ * the backward transform divided by the grid's point count).  A use_graph plan
+ * replays its graph when the choice equals the plan's and launches the pass
+ * kernels directly otherwise.  Errors as offt_exec_bwd, plus INVALID_ARG for
+ * normalize outside {-1, 0, 1}. */
+int offt_exec_bwd_norm(offt_plan_t p, const void* in, void* out, int normalize, void* stream);
+
 /* Number of axis passes of a plan (0..3: axes of length 1 need none), or a
  * negative code. */
 int offt_plan_passes(offt_plan_t p);
@@ -228,10 +237,13 @@ int offt_twiddles(int64_t n, int dtype, void* host_out);
  * `dtype`, packed back to back in one buffer; grid i starts at element offset
  * offt_many_offset(p, i) (every grid starts on a 256-byte boundary).  With
  * o->tune = OFFT_TUNE_EXHAUSTIVE each distinct grid shape gets its own tuned
- * plan.  The execution is one persistent kernel launch over all (grid, axis
- * pass, tile) work items, captured once into a HIP graph and replayed.
- * Grids stay in natural order (o->layout other than NATURAL is
- * OFFT_ERR_INVALID_ARG).  Errors as offt_plan_ex. */
+ * plan.  Execution (offt_exec_many and its default forms below) runs every
+ * (grid, axis pass, tile) work item of the batch in one of several launch
+ * forms: one kernel per pass level replayed from a HIP graph (the default,
+ * fastest measured), one persistent kernel replayed from a graph, or each
+ * grid's passes as separate launches.  Grids stay in natural order
+ * (o->layout other than NATURAL is OFFT_ERR_INVALID_ARG).  Errors as
+ * offt_plan_ex. */
 offt_plan_t offt_plan_many(int count, const int64_t* dims, int dtype, const offt_opts* o);
 
 /* Element offset of grid i in the packed buffer, total elements of the

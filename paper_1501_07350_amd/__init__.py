@@ -127,21 +127,27 @@ class Plan:
             raise ValueError(f"{name} has shape {tuple(x.shape)}, plan expects "
                              f"{(self.batch,) + tuple(shape) if self.batch > 1 else tuple(shape)}")
 
-    def _run(self, fn, x, out, in_shape, out_shape):
+    def _run(self, fn, x, out, in_shape, out_shape, *extra):
         self._check_tensor(x, "x", in_shape)
         if out is None:
             out = torch.empty(x.shape[:-len(out_shape)] + tuple(out_shape), dtype=x.dtype, device=x.device)
         else:
             self._check_tensor(out, "out", out_shape)
-        _lib.check(fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+        _lib.check(fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), *extra,
                       ctypes.c_void_p(_stream_handle())), "exec")
         return out
 
     def forward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         return self._run(_lib.load().offt_exec_fwd, x, out, self.shape, self.spectral_shape)
 
-    def backward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        return self._run(_lib.load().offt_exec_bwd, x, out, self.spectral_shape, self.shape)
+    def backward(self, x: torch.Tensor, out: torch.Tensor | None = None,
+                 normalize: bool | None = None) -> torch.Tensor:
+        """Backward transform; normalize=True divides by the grid's point
+        count, False does not, None (default) follows the plan's
+        normalize_inverse."""
+        norm = -1 if normalize is None else (1 if normalize else 0)
+        return self._run(_lib.load().offt_exec_bwd_norm, x, out, self.spectral_shape, self.shape,
+                         ctypes.c_int(norm))
 
     def exec_ptr(self, direction: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
         """Raw-pointer execution (no tensor checks) for benchmarking loops."""

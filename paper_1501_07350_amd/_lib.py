@@ -73,6 +73,7 @@ SIGNATURES = {
     "offt_plan_ex": (_vp, [_i64, _i64, _i64, _ci, _i64, ctypes.POINTER(Opts)]),
     "offt_exec_fwd": (_ci, [_vp, _vp, _vp, _vp]),
     "offt_exec_bwd": (_ci, [_vp, _vp, _vp, _vp]),
+    "offt_exec_bwd_norm": (_ci, [_vp, _vp, _vp, _ci, _vp]),
     "offt_destroy": (_ci, [_vp]),
     "offt_plan_passes": (_ci, [_vp]),
     "offt_exec_pass": (_ci, [_vp, _ci, _ci, _vp, _vp, _vp]),

@@ -95,7 +95,7 @@ const PassPlan* dir_passes(const offt_plan_s* p, int dir) {
 }
 
 int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const void* in, void* out,
-                void* work, int dir, hipStream_t s) {
+                void* work, int dir, hipStream_t s, int normalize) {
     const int64_t N = p->grid_elems();
     if (npass == 0) {
         if (in != out) {
@@ -108,7 +108,8 @@ int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const v
     const bool bwd = dir > 0;
     for (int i = 0; i < npass; ++i) {
         const bool last = i == npass - 1;
-        const double scale = (bwd && last && p->normalize) ? 1.0 / (double)N : 1.0;
+        const int norm = normalize < 0 ? p->normalize : normalize;
+        const double scale = (bwd && last && norm) ? 1.0 / (double)N : 1.0;
         const void* src = nullptr;
         void* dst = nullptr;
         if (!pass_io(passes, npass, i, in, out, work, &src, &dst)) return OFFT_ERR_BAD_PLAN;
@@ -411,12 +412,18 @@ static int capture_passes(offt_plan_s* p, const void* in, void* out, int dir) {
     return OFFT_SUCCESS;
 }
 
-static int exec_checked(offt_plan_t p, const void* in, void* out, void* stream, int dir) {
-    if (!p || !in || !out) { set_error(OFFT_ERR_INVALID_ARG); return OFFT_ERR_INVALID_ARG; }
+// normalize: -1 the plan's normalize_inverse, 0 or 1 this call's choice (the
+// graphs hold the plan's scaling, so another choice launches directly)
+static int exec_checked(offt_plan_t p, const void* in, void* out, void* stream, int dir, int normalize = -1) {
+    if (!p || !in || !out || normalize < -1 || normalize > 1) {
+        set_error(OFFT_ERR_INVALID_ARG);
+        return OFFT_ERR_INVALID_ARG;
+    }
     if (p->kind != 1 && p->kind != 3) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
     const hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = OFFT_SUCCESS;
-    if (p->use_graph && p->npass > 0) {
+    if (normalize == p->normalize) normalize = -1;
+    if (p->use_graph && p->npass > 0 && normalize < 0) {
         const int d = dir > 0 ? 1 : 0;
         if (!p->gexec[d] || in != p->g_in[d] || out != p->g_out[d]) rc = capture_passes(p, in, out, dir);
         if (rc == OFFT_SUCCESS && hipGraphLaunch(p->gexec[d], s) != hipSuccess) {
@@ -424,7 +431,7 @@ static int exec_checked(offt_plan_t p, const void* in, void* out, void* stream, 
             rc = OFFT_ERR_HIP;
         }
     } else {
-        rc = exec_passes(p, dir_passes(p, dir), p->npass, in, out, p->work, dir, s);
+        rc = exec_passes(p, dir_passes(p, dir), p->npass, in, out, p->work, dir, s, normalize);
     }
     set_error(rc);
     return rc;
@@ -436,6 +443,10 @@ int offt_exec_fwd(offt_plan_t p, const void* in, void* out, void* stream) {
 
 int offt_exec_bwd(offt_plan_t p, const void* in, void* out, void* stream) {
     return exec_checked(p, in, out, stream, OFFT_BACKWARD);
+}
+
+int offt_exec_bwd_norm(offt_plan_t p, const void* in, void* out, int normalize, void* stream) {
+    return exec_checked(p, in, out, stream, OFFT_BACKWARD, normalize);
 }
 
 int offt_plan_passes(offt_plan_t p) {

@@ -13,8 +13,8 @@
 // on items of a lower level, i.e. smaller indices.  So the smallest unfinished
 // item never waits, by induction every wait ends, and the number of resident
 // workgroups does not matter.  Each wait is still bounded: after spin_limit
-// polls the error flag is raised and the workgroup goes on, so the grid
-// always drains.
+// polls the error flag is raised; from then on no wait spins and no item is
+// computed, so the grid drains within about one spin limit.
 //
 // A work item covers tiles_per_item consecutive tiles of one segment, so the
 // publish/wait cost is paid once per several tiles.
@@ -115,16 +115,42 @@ __device__ __forceinline__ PassArgs segment_pass_args(const ManyArgs& a, const M
     p.X = 1;
     p.Y = 1;
     p.xcd_remap = 0;   // the batch executors map tiles themselves
+    p.stream_io = 0;
     p.conj_in = bwd && sg.first;
     p.conj_out = bwd && sg.last;
     p.scale = (bwd && sg.last) ? sg.scale_bwd : 1.0;
     return p;
 }
 
+// Error flag of a persistent run (counters[1]): raised by the first wait that
+// reaches its spin limit.  Once it is up, no later wait spins: the run's
+// results are invalid anyway, so every workgroup drains the queue without
+// computing and the kernel ends within about one spin limit.
+__device__ __forceinline__ bool many_failed(const ManyArgs& a) {
+    return __hip_atomic_load(&a.counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+}
+
+// Polls *counter until it reaches target, the spin limit is hit (raises the
+// error flag) or the flag is up.  Returns whether the target was reached.
+constexpr int kFlagPollInterval = 64;   // polls between two looks at the error flag
+__device__ __forceinline__ bool many_wait(const ManyArgs& a, const unsigned* counter, unsigned target) {
+    int polls = 0;
+    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (polls % kFlagPollInterval == 0 && many_failed(a)) return false;
+        if (++polls > a.spin_limit) {
+            __hip_atomic_store(&a.counters[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(4);
+    }
+    return true;
+}
+
 template <typename V, typename Dispatch>
 __device__ __forceinline__ void many_body(const ManyArgs& a, V* __restrict__ lds, const Dispatch& dispatch) {
     __shared__ int64_t s_item;
     __shared__ int s_seg;
+    __shared__ int s_run;
     const int tid = threadIdx.x;
     for (;;) {
         __syncthreads();   // the previous tile is done with LDS and the broadcast slots
@@ -132,30 +158,25 @@ __device__ __forceinline__ void many_body(const ManyArgs& a, V* __restrict__ lds
             const int64_t item = (int64_t)__hip_atomic_fetch_add(&a.counters[0], 1u, __ATOMIC_RELAXED,
                                                                  __HIP_MEMORY_SCOPE_AGENT);
             int seg = -1;
+            bool run = false;
             if (item < a.total_items) {
                 seg = find_segment(a.segs, a.nseg, item);
                 const int dep = a.segs[seg].dep;
-                if (dep >= 0) {
-                    const unsigned target = (unsigned)a.segs[dep].nitems;
-                    int polls = 0;
-                    while (__hip_atomic_load(&a.counters[kManyCounterBase + dep], __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT) < target) {
-                        if (++polls > a.spin_limit) {
-                            __hip_atomic_store(&a.counters[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(4);
-                    }
+                run = !many_failed(a);
+                if (run && dep >= 0) {
+                    run = many_wait(a, &a.counters[kManyCounterBase + dep], (unsigned)a.segs[dep].nitems);
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
             }
             s_item = item;
             s_seg = seg;
+            s_run = run ? 1 : 0;
         }
         __syncthreads();
         const int64_t item = s_item;
         const int seg = s_seg;
         if (item >= a.total_items) break;
+        if (!s_run) continue;   // a wait failed: drain the queue without computing
         const ManySeg sg = a.segs[seg];
         const PassArgs p = segment_pass_args<V>(a, sg);
         run_item(sg, p, item, lds, dispatch);
@@ -246,15 +267,7 @@ __device__ __forceinline__ void many_grid_barrier(const ManyArgs& a, unsigned* c
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned target = gridDim.x;
-        int polls = 0;
-        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (++polls > a.spin_limit) {
-                __hip_atomic_store(&a.counters[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(4);
-        }
+        (void)many_wait(a, counter, gridDim.x);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();

@@ -63,8 +63,9 @@ int set_choice_b(offt_plan_s* p, const PlanChoice& c, hipStream_t s);
 // The passes a direction runs (the backward list differs for reversed layouts).
 const PassPlan* dir_passes(const offt_plan_s* p, int dir);
 void reversed_dims(const int64_t dims[3], int64_t out[3]);
+// normalize: -1 the plan's normalize_inverse, else 0 / 1 for this call
 int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const void* in, void* out,
-                void* work, int dir, hipStream_t s);
+                void* work, int dir, hipStream_t s, int normalize = -1);
 void free_plan(offt_plan_s* p);
 
 // Tuning (tuner.cpp): fills *choice for EXHAUSTIVE / LEARNED modes.

@@ -161,7 +161,9 @@ static int do_many(int argc, char** argv, bool sync) {
     a.total_items = items;
     a.nseg = nseg;
     a.dir = -1;
-    a.spin_limit = 1 << 22;
+    // polls before a wait gives up (EMU_SPIN_LIMIT overrides, for the test of
+    // an unmet dependency)
+    a.spin_limit = getenv("EMU_SPIN_LIMIT") ? atoi(getenv("EMU_SPIN_LIMIT")) : 1 << 22;
     blockDim.x = threads;
     auto body = [&](V* lds) {
         if (sync) EmuSync<V>::body(a, sa, lds);

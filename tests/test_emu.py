@@ -218,6 +218,38 @@ def test_emulated_concurrent_workgroups_mixed_batch(emu_binary, nwg):
     run_many(emu_binary, MIXED, torch.complex64, nwg=nwg)
 
 
+def test_emulated_unmet_dependency_ends_within_one_spin_limit(emu_binary):
+    """A dependency that is never met (a segment made to wait on a grid's last
+    pass, which publishes nothing): the first wait gives up after its spin
+    limit and raises the error flag, and every later item then skips its wait
+    and its tile, so the loop ends after about one spin limit instead of one
+    per waiting item."""
+    import time
+    args, _, _ = segment_args(MIXED, torch.complex64, "all")
+    nseg = int(args[1])
+    segs = [args[2 + 12 * s: 2 + 12 * (s + 1)] for s in range(nseg)]
+    last = next(s for s in range(nseg) if segs[s][8] == "1")
+    # the waiting segment with the most tiles, and its dependants
+    waiting = max((s for s in range(nseg) if segs[s][9] != "-1"), key=lambda s: int(segs[s][6]))
+    segs[waiting][9] = str(last)
+    nitems = sum(-(-int(segs[s][6]) // TILES_PER_ITEM) for s in range(nseg) if s >= waiting)
+    assert nitems >= 8
+    table = args[:2] + [v for sg in segs for v in sg] + args[2 + 12 * nseg:]
+    t0 = time.perf_counter()
+    r = subprocess.run([emu_binary, "many", "1", "1"] + args, capture_output=True, text=True, timeout=600)
+    t_normal = time.perf_counter() - t0
+    assert r.returncode == 0, r.stdout[:300]
+    spin = 20000   # polls of at least 20 us each in the emulation: >= 0.4 s per full wait
+    t0 = time.perf_counter()
+    r = subprocess.run([emu_binary, "many", "1", "1"] + table, capture_output=True, text=True, timeout=600,
+                       env={**os.environ, "EMU_SPIN_LIMIT": str(spin)})
+    t_unmet = time.perf_counter() - t0
+    assert r.returncode == 1 and "err=1" in r.stdout, (r.stdout[:300], r.stderr[-2000:])
+    # one full wait beyond the normal run; one wait per waiting item would add
+    # at least nitems * 0.4 s
+    assert t_unmet < t_normal + 0.5 * nitems * spin * 20e-6, (t_normal, t_unmet, nitems)
+
+
 def test_emulated_persistent_loop_batch_lengths(emu_binary):
     dims = synth.uneven_batch_dims(4, key=synth.KEY_DIMS + 99)
     dims = [tuple(min(v, 64) for v in d) for d in dims]   # small enough for CPU threads

@@ -31,10 +31,10 @@ def same_grids(plan, a, b):
     return all(torch.equal(u, v) for u, v in zip(plan.unpack(a), plan.unpack(b)))
 
 
-def check_against_oracle(plan, grids, buf, dtype, sign=oracle.FORWARD, scale_inv=False):
+def check_against_oracle(plan, grids, buf, dtype, sign=oracle.FORWARD, scale_inv=False, refs=None):
     worst = 0.0
     for g, (x, y) in enumerate(zip(grids, plan.unpack(buf))):
-        ref = oracle.fft3(x.cpu().numpy().astype(np.complex128), sign)
+        ref = refs[g] if refs is not None else oracle.fft3(x.cpu().numpy().astype(np.complex128), sign)
         if scale_inv:
             ref = ref / x.numel()
         e = oracle.rel_l2(y.cpu().numpy(), ref)
@@ -68,6 +68,30 @@ def test_uneven_batch_64_grids_persistent_graph_vs_oracle_and_separate():
     assert same_grids(plan, y_graph, y_sep_heur)   # untuned plan: heuristic plans for both
     worst = check_against_oracle(plan, grids, y_graph, C64)
     print(f"64 grids: worst error / tolerance = {worst:.3e}", flush=True)
+
+
+def test_uneven_batch_64_grids_tuned_every_launch_form_vs_oracle():
+    """The benchmark's timed forms: exhaustively tuned per-grid plans, run as
+    the level graph, the level-synchronous graph, the queue-based persistent
+    graph and separate launches; every one of the 64 grids against O3."""
+    dims = synth.uneven_batch_dims(64)
+    plan = offt.ManyPlan(dims, dtype=C64, tune="exhaustive")
+    print(plan.describe().splitlines()[0], flush=True)
+    grids, x = packed_input(plan, dims, C64)
+    refs = [oracle.fft3(g.cpu().numpy().astype(np.complex128)) for g in grids]
+    first = None
+    for form in (offt.MANY_LEVELS_GRAPH, offt.MANY_SYNC_GRAPH, offt.MANY_PERSISTENT_GRAPH, offt.MANY_LEVELS,
+                 offt.MANY_SYNC, offt.MANY_PERSISTENT, offt.MANY_SEPARATE_TUNED):
+        print(f"form {form}", flush=True)
+        y = plan.execute(x, use_graph=form)
+        torch.cuda.synchronize()
+        assert plan.status() == 0
+        worst = check_against_oracle(plan, grids, y, C64, refs=refs)
+        print(f"form {form}: worst error / tolerance over 64 grids = {worst:.3e}", flush=True)
+        if first is None:
+            first = y
+        else:
+            assert same_grids(plan, first, y), f"form {form} differs from the level graph"
 
 
 def test_graph_replays_match_eager_with_work_between():
