@@ -420,6 +420,7 @@ struct PassArgs {
     int mode;           // 0: contiguous lines (M2 == 1), 1: strided lines,
                         // 2: rows in, strided lines out, 3: strided lines in, rows out
     int xcd_remap;      // 1: tiles in contiguous runs per XCD (xcd_tile)
+    int stream_io;      // 1: grid data loaded and stored with streaming (non-temporal) accesses
     int conj_in;        // negate imaginary parts on load
     int conj_out;       // negate imaginary parts on store
     double scale;       // multiply on store
@@ -447,6 +448,39 @@ template <typename V, typename S> __device__ __forceinline__ V fix_out(V x, int 
     return x;
 }
 
+// Grid data is read once and written once per pass.  A pass can access it
+// with non-temporal (streaming) loads and stores (PassArgs::stream_io): the
+// lines are then not kept in the caches for reuse.  On MI355X that raises the
+// rate of the strided tile loads and stores of grids much larger than the
+// 256 MB Infinity Cache, and lowers it for grids that fit there, whose next
+// pass reads what the previous one left in the cache.
+template <typename S> struct StreamVec { typedef S type __attribute__((vector_size(2 * sizeof(S)))); };
+template <typename V> __device__ __forceinline__ V load_stream(const V* p) {
+    using S = decltype(V{}.x);
+    using E = typename StreamVec<S>::type;
+    const E e = __builtin_nontemporal_load(reinterpret_cast<const E*>(p));
+    V v;
+    v.x = e[0];
+    v.y = e[1];
+    return v;
+}
+template <typename V> __device__ __forceinline__ void store_stream(V* p, V v) {
+    using S = decltype(V{}.x);
+    using E = typename StreamVec<S>::type;
+    E e;
+    e[0] = v.x;
+    e[1] = v.y;
+    __builtin_nontemporal_store(e, reinterpret_cast<E*>(p));
+}
+// Load / store of grid data: streaming when nt (uniform across the workgroup).
+template <typename V> __device__ __forceinline__ V load_io(const V* p, bool nt) {
+    return nt ? load_stream(p) : *p;
+}
+template <typename V> __device__ __forceinline__ void store_io(V* p, V v, bool nt) {
+    if (nt) store_stream(p, v);
+    else *p = v;
+}
+
 // Store of one element to HBM.  COHERENT stores are agent-scope relaxed
 // atomics: they write through the XCD's L2, so data another workgroup will
 // read after a release/acquire handshake never sits dirty in one L2 and the
@@ -465,6 +499,17 @@ template <> __device__ __forceinline__ void store_elem<true, double2>(double2* p
     __builtin_memcpy(&by, &x.y, sizeof by);
     __hip_atomic_store(reinterpret_cast<uint64_t*>(p), bx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(reinterpret_cast<uint64_t*>(p) + 1, by, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Load and store of grid data in a pass tile: streaming when the pass asks
+// for it, never in the batch executors' coherent form (whose tiles read what
+// other workgroups of the same launch wrote, after the acquire that orders it).
+template <bool COHERENT, typename V> __device__ __forceinline__ V load_elem(const V* p, bool nt) {
+    if constexpr (COHERENT) return *p;
+    else return load_io(p, nt);
+}
+template <bool COHERENT, typename V> __device__ __forceinline__ void store_elem_io(V* p, V x, bool nt) {
+    if constexpr (COHERENT) store_elem<true>(p, x);
+    else store_io(p, x, nt);
 }
 
 // Contiguous lines with fewer than this many threads per line are staged
@@ -496,6 +541,7 @@ __device__ __forceinline__ void pass_tile_impl(const PassArgs& a, V* __restrict_
     const int cin = a.conj_in, cout = a.conj_out;
     const S scale = (S)a.scale;
     const bool active = tid < W * TPL;
+    const bool nt = !COHERENT && a.stream_io;
     if constexpr (sizeof...(Rs) > 1) {
         // stage the twiddle table; the first barrier inside run_fft (after the
         // first stage, which needs no twiddles) orders it before any use
@@ -514,9 +560,9 @@ __device__ __forceinline__ void pass_tile_impl(const PassArgs& a, V* __restrict_
         const int64_t M2 = a.M2;
         const V* g = in + base;
         V* go = out + base;
-        auto src = [&](int j) { return fix_in(g[(int64_t)j * M2], cin); };
+        auto src = [&](int j) { return fix_in(load_elem<COHERENT>(g + (int64_t)j * M2, nt), cin); };
         auto sink = [&](int j, V x) {
-            if (ok) store_elem<COHERENT>(go + (int64_t)j * M2, fix_out(x, cout, scale));
+            if (ok) store_elem_io<COHERENT>(go + (int64_t)j * M2, fix_out(x, cout, scale), nt);
         };
         run_fft<V, L, TPL, P, false, false, Rs...>(lds + w * LP, tw, t, active, src, sink);
         return;
@@ -529,9 +575,9 @@ __device__ __forceinline__ void pass_tile_impl(const PassArgs& a, V* __restrict_
             const bool ok = active && tid / TPL < nl;
             const V* g = in + (l0 + (ok ? w : 0)) * L;
             V* go = out + (l0 + w) * L;
-            auto src = [&](int j) { return fix_in(g[j], cin); };
+            auto src = [&](int j) { return fix_in(load_elem<COHERENT>(g + j, nt), cin); };
             auto sink = [&](int j, V x) {
-                if (ok) store_elem<COHERENT>(go + j, fix_out(x, cout, scale));
+                if (ok) store_elem_io<COHERENT>(go + j, fix_out(x, cout, scale), nt);
             };
             run_fft<V, L, TPL, 1, false, false, Rs...>(line, tw, t, active, src, sink);
         } else {
@@ -542,7 +588,7 @@ __device__ __forceinline__ void pass_tile_impl(const PassArgs& a, V* __restrict_
             if (active) {
                 for (int f = tid; f < nl * L; f += NT) {
                     const int lw = f / L, j = f - lw * L;
-                    lds[lw * LP + lds_idx(j)] = fix_in(g[f], cin);
+                    lds[lw * LP + lds_idx(j)] = fix_in(load_elem<COHERENT>(g + f, nt), cin);
                 }
             }
             __syncthreads();
@@ -553,7 +599,7 @@ __device__ __forceinline__ void pass_tile_impl(const PassArgs& a, V* __restrict_
             if (active) {
                 for (int f = tid; f < nl * L; f += NT) {
                     const int lw = f / L, j = f - lw * L;
-                    store_elem<COHERENT>(go + f, fix_out(lds[lw * LP + lds_idx(j)], cout, scale));
+                    store_elem_io<COHERENT>(go + f, fix_out(lds[lw * LP + lds_idx(j)], cout, scale), nt);
                 }
             }
         }
@@ -575,6 +621,7 @@ struct RowPartSink {
     int nl, tid, nt, cout;
     decltype(V{}.x) scale;
     bool active;
+    bool stream;                     // streaming stores
     __device__ __forceinline__ void operator()(int j, V x) {
         line[lds_idx(j % PART)] = fix_out(x, cout, scale);
     }
@@ -582,7 +629,7 @@ struct RowPartSink {
         if (!active) return;
         for (int f = tid; f < nl * PART; f += nt) {
             const int lw = f / PART, jj = f - lw * PART;
-            out[rows[lw] + p * PART + jj] = lds[lw * LP + lds_idx(jj)];
+            store_io(out + rows[lw] + p * PART + jj, lds[lw * LP + lds_idx(jj)], stream);
         }
     }
 };
@@ -616,6 +663,7 @@ __device__ __forceinline__ void pass_tile_transpose(const PassArgs& a, V* __rest
     const int cin = a.conj_in, cout = a.conj_out;
     const S scale = (S)a.scale;
     const bool active = tid < NT;
+    const bool nts = a.stream_io != 0;
     const int64_t M2 = a.M2;
     if constexpr (sizeof...(Rs) > 1) {
         V* twl = lds + W * LP;
@@ -640,13 +688,13 @@ __device__ __forceinline__ void pass_tile_transpose(const PassArgs& a, V* __rest
     if (a.mode == 2) {
         V* go = out + base;
         auto sink = [&](int j, V x) {
-            if (ok) go[(int64_t)j * M2] = fix_out(x, cout, scale);
+            if (ok) store_io(go + (int64_t)j * M2, fix_out(x, cout, scale), nts);
         };
         if constexpr (P == 1) {
             if (active) {
                 for (int f = tid; f < nl * L; f += NT) {
                     const int lw = f / L, j = f - lw * L;
-                    lds[lw * LP + lds_idx(j)] = fix_in(in[rows[lw] + j], cin);
+                    lds[lw * LP + lds_idx(j)] = fix_in(load_io(in + rows[lw] + j, nts), cin);
                 }
             }
             __syncthreads();
@@ -664,7 +712,7 @@ __device__ __forceinline__ void pass_tile_transpose(const PassArgs& a, V* __rest
                 if (active) {
                     for (int f = tid; f < nl * PART; f += NT) {
                         const int lw = f / PART, jj = f - lw * PART;
-                        lds[lw * LP + lds_idx(jj)] = fix_in(in[rows[lw] + p * PART + jj], cin);
+                        lds[lw * LP + lds_idx(jj)] = fix_in(load_io(in + rows[lw] + p * PART + jj, nts), cin);
                     }
                 }
                 __syncthreads();
@@ -683,7 +731,7 @@ __device__ __forceinline__ void pass_tile_transpose(const PassArgs& a, V* __rest
         }
     } else {
         const V* g = in + base;
-        auto src = [&](int j) { return fix_in(g[(int64_t)j * M2], cin); };
+        auto src = [&](int j) { return fix_in(load_io(g + (int64_t)j * M2, nts), cin); };
         if constexpr (P == 1) {
             auto sink = [&](int j, V x) { line[lds_idx(j)] = fix_out(x, cout, scale); };
             run_fft<V, L, TPL, 1, false, true, Rs...>(line, tw, t, active, src, sink);
@@ -691,11 +739,11 @@ __device__ __forceinline__ void pass_tile_transpose(const PassArgs& a, V* __rest
             if (active) {
                 for (int f = tid; f < nl * L; f += NT) {
                     const int lw = f / L, j = f - lw * L;
-                    out[rows[lw] + j] = lds[lw * LP + lds_idx(j)];
+                    store_io(out + rows[lw] + j, lds[lw * LP + lds_idx(j)], nts);
                 }
             }
         } else {
-            RowPartSink<V, L, P> sink{line, lds, out, rows, nl, tid, NT, cout, scale, active};
+            RowPartSink<V, L, P> sink{line, lds, out, rows, nl, tid, NT, cout, scale, active, nts};
             run_fft<V, L, TPL, P, false, true, Rs...>(line, tw, t, active, src, sink);
         }
     }

@@ -70,8 +70,20 @@ struct PassPlan {
     int logW;                  // lines per workgroup = 2^logW
     int mode;                  // 0 contiguous lines, 1 strided lines, 2/3 transposing (PassArgs)
     int xcd = 0;               // tiles in contiguous runs per XCD (PassArgs::xcd_remap)
+    int stream = 0;            // streaming loads and stores (PassArgs::stream_io)
     const void* tw;            // device twiddle table for L
 };
+
+// Grid-data access mode of a pass (plan choices, plan-string suffix):
+// kIoAuto streams when the batch of grids exceeds kStreamMinBytes (it then
+// cannot stay in the 256 MB Infinity Cache between passes), kIoStream and
+// kIoCached force one mode ("/s", "/c").
+enum { kIoAuto = 0, kIoStream = 1, kIoCached = 2 };
+constexpr int64_t kStreamMinBytes = int64_t(256) << 20;
+// Whether a pass over `bytes` of grid data streams under access mode io.
+inline int resolve_stream(int io, int64_t bytes) {
+    return io == kIoStream || (io == kIoAuto && bytes > kStreamMinBytes) ? 1 : 0;
+}
 
 // Plan choice for one grid shape, independent of device memory.
 struct PlanChoice {
@@ -79,6 +91,7 @@ struct PlanChoice {
     const KernelEntry* k[3];   // per axis id (a, b, c); nullptr for L == 1
     int logW[3];               // per axis id
     int xcd[3] = {0, 0, 0};    // per axis id: XCD-contiguous tile order (plan string "/x")
+    int io[3] = {0, 0, 0};     // per axis id: grid-data access mode (kIo*, plan string "/s" or "/c")
     // Output order.  -1: the input's (abc).  0 or 2: reversed (cba), the
     // pass along this axis transposing: axis a reads strided lines of the
     // abc grid and writes cba rows (mode 3), axis c reads abc rows and
@@ -93,7 +106,7 @@ enum AxisGeom { kGeomNatural = 0, kGeomReversed = 1, kGeomTranspose = 2 };
 int axis_geom(const PlanChoice& c, int ax);
 // The pass of axis ax in geometry g (k and logW filled in, tw left null).
 PassPlan make_pass(const int64_t dims[3], int64_t batch, int ax, int g, const KernelEntry* k, int logW,
-                   int xcd = 0);
+                   int xcd = 0, int io = kIoAuto);
 // Whether the output of a grid has a different memory order in cba than in
 // abc (at least two axes longer than 1).
 bool reversal_moves_data(const int64_t dims[3]);
@@ -112,9 +125,10 @@ struct NdChoice {
     const KernelEntry* k[kMaxDims];   // per axis; nullptr for length 1
     int logW[kMaxDims];
     int xcd[kMaxDims] = {0, 0, 0, 0, 0};
+    int io[kMaxDims] = {0, 0, 0, 0, 0};
 };
 PassPlan make_pass_nd(int ndim, const int64_t* dims, int64_t batch, int ax, const KernelEntry* k, int logW,
-                      int xcd = 0);
+                      int xcd = 0, int io = kIoAuto);
 NdChoice default_choice_nd(int dtype, int ndim, const int64_t* dims);
 std::string nd_choice_to_string(const NdChoice& c, const int64_t* dims);
 bool nd_choice_from_string(const char* s, int dtype, int ndim, const int64_t* dims, NdChoice* out,

@@ -130,13 +130,15 @@ int axis_geom(const PlanChoice& c, int ax) {
 // grid), the cba grid for axis c (rows read from the abc grid).  In both the
 // row of line m1*M2 + m2 is m1*M2 + (m2 mod X)*Y + m2 div X with X the
 // length of the opposite end axis and Y = Nb.
-PassPlan make_pass(const int64_t dims[3], int64_t batch, int ax, int g, const KernelEntry* k, int logW, int xcd) {
+PassPlan make_pass(const int64_t dims[3], int64_t batch, int ax, int g, const KernelEntry* k, int logW, int xcd,
+                   int io) {
     PassPlan p;
     p.axis = ax;
     p.L = (int)dims[ax];
     p.k = k;
     p.logW = logW;
     p.xcd = xcd;
+    p.stream = k ? resolve_stream(io, dims[0] * dims[1] * dims[2] * batch * (int64_t)elem_size(k->dtype)) : 0;
     p.tw = nullptr;
     p.X = 1;
     p.Y = 1;
@@ -270,8 +272,23 @@ static bool axis_strided(int axis, const int64_t dims[3]) {
 // of the selector's data set (axes 16..1024, MI355X) that order made strided
 // passes faster in 59-75% of the grids above 64 MiB (geometric mean 0.93 of
 // the time) and slightly faster below; on contiguous lines it was neutral to
-// slower, and transposing passes keep the launch order.
-static int default_xcd(int g, bool strided) { return g != kGeomTranspose && strided ? 1 : 0; }
+// slower, and transposing passes keep the launch order.  With streaming
+// accesses (grids above the Infinity Cache) the launch order was faster for
+// lines strided by 2 MiB or more: 6% for pass a at 1024^3 complex64, 3% at
+// 512^3 complex64.
+constexpr int64_t kLongStrideBytes = int64_t(2) << 20;
+static int default_xcd(int g, bool strided, bool streamed_long_stride = false) {
+    return g != kGeomTranspose && strided && !streamed_long_stride ? 1 : 0;
+}
+// Whether the heuristic's pass along `ax` (natural geometry, one grid) streams
+// over lines strided by kLongStrideBytes or more.
+static bool streamed_long_stride(int dtype, const int64_t* dims, int ndim, int ax) {
+    int64_t n = 1, after = 1;
+    for (int j = 0; j < ndim; ++j) n *= dims[j];
+    for (int j = ax + 1; j < ndim; ++j) after *= dims[j];
+    const int64_t es = (int64_t)elem_size(dtype);
+    return resolve_stream(kIoAuto, n * es) && after * es >= kLongStrideBytes;
+}
 
 // Default kernel of a transposing pass: for L >= 512 the first radix <= 16
 // kernel whose exchanges and row side run in 2 parts (half the LDS of a
@@ -310,7 +327,8 @@ static void assign_default_kernels(PlanChoice& c, int dtype, const int64_t dims[
         if (k) {
             c.k[ax] = k;
             c.logW[ax] = logW;
-            c.xcd[ax] = default_xcd(g, make_pass(dims, 1, ax, g, nullptr, 0).M2 > 1);
+            c.xcd[ax] = default_xcd(g, make_pass(dims, 1, ax, g, nullptr, 0).M2 > 1,
+                                    g == kGeomNatural && streamed_long_stride(dtype, dims, 3, ax));
         }
     }
 }
@@ -382,10 +400,12 @@ std::vector<PlanChoice> candidate_choices(int dtype, const int64_t dims[3]) {
 static const char kAxisName[] = "abcde";
 
 // ---- plan strings ---------------------------------------------------------------
-// One axis: "<radix sequence>/<tile width>[/<threads per line>][/p<parts>]",
-// or "1" for a length-1 axis.
+// One axis: "<radix sequence>/<tile width>[/<threads per line>][/p<parts>][/x][/s|/c]",
+// or "1" for a length-1 axis ("/x": XCD-contiguous tile order; "/s", "/c":
+// streaming or cached grid-data accesses, by default chosen from the grid's
+// size).
 
-static void axis_to_string(std::ostringstream& os, const KernelEntry* k, int logW, int64_t len, int xcd) {
+static void axis_to_string(std::ostringstream& os, const KernelEntry* k, int logW, int64_t len, int xcd, int io) {
     if (!k || len <= 1) {
         os << "1";
         return;
@@ -395,6 +415,8 @@ static void axis_to_string(std::ostringstream& os, const KernelEntry* k, int log
     if (k->tpl != default_tpl(k)) os << "/" << k->tpl;
     if (k->nparts > 1) os << "/p" << k->nparts;
     if (xcd) os << "/x";
+    if (io == kIoStream) os << "/s";
+    if (io == kIoCached) os << "/c";
 }
 
 namespace {
@@ -403,6 +425,7 @@ struct AxisSpec {
     std::vector<int> rad;
     long W = 0, tpl = 0, P = 1;
     int xcd = 0;
+    int io = kIoAuto;
 };
 }  // namespace
 
@@ -433,8 +456,12 @@ static bool parse_axis_spec(const std::string& val, AxisSpec* sp) {
         if (!end2 || (sp->P != 1 && sp->P != 2 && sp->P != 4)) return false;
         end = end2;
     }
-    if (end[0] == '/' && end[1] == 'x' && end[2] == 0) {   // XCD-contiguous tile order
+    if (end[0] == '/' && end[1] == 'x' && (end[2] == 0 || end[2] == '/')) {   // XCD-contiguous tile order
         sp->xcd = 1;
+        end += 2;
+    }
+    if (end[0] == '/' && (end[1] == 's' || end[1] == 'c') && end[2] == 0) {   // grid-data access mode
+        sp->io = end[1] == 's' ? kIoStream : kIoCached;
         end += 2;
     }
     return *end == 0;
@@ -471,7 +498,7 @@ std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]) {
     if (c.tax >= 0) os << ";rev=" << kAxisName[c.tax];
     for (int ax = 0; ax < 3; ++ax) {
         os << ";" << kAxisName[ax] << "=";
-        axis_to_string(os, c.k[ax], c.logW[ax], dims[ax], c.xcd[ax]);
+        axis_to_string(os, c.k[ax], c.logW[ax], dims[ax], c.xcd[ax], c.io[ax]);
     }
     return os.str();
 }
@@ -524,6 +551,7 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
         c.k[ax] = found;
         c.logW[ax] = lw;
         c.xcd[ax] = sp.xcd;
+        c.io[ax] = sp.io;
     }
     *out = c;
     return true;
@@ -532,13 +560,16 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
 // ---- grids of more than three dimensions -------------------------------------
 
 PassPlan make_pass_nd(int ndim, const int64_t* dims, int64_t batch, int ax, const KernelEntry* k, int logW,
-                      int xcd) {
+                      int xcd, int io) {
     PassPlan p;
     p.axis = ax;
     p.L = (int)dims[ax];
     p.k = k;
     p.logW = logW;
     p.xcd = xcd;
+    int64_t bytes = batch;
+    for (int j = 0; j < ndim; ++j) bytes *= dims[j];
+    p.stream = k ? resolve_stream(io, bytes * (int64_t)elem_size(k->dtype)) : 0;
     p.tw = nullptr;
     p.X = 1;
     p.Y = 1;
@@ -567,7 +598,7 @@ NdChoice default_choice_nd(int dtype, int ndim, const int64_t* dims) {
         if (k) {
             c.k[ax] = k;
             c.logW[ax] = default_logW(k, dtype, strided);
-            c.xcd[ax] = default_xcd(kGeomNatural, strided);
+            c.xcd[ax] = default_xcd(kGeomNatural, strided, streamed_long_stride(dtype, dims, ndim, ax));
         }
     }
     return c;
@@ -579,7 +610,7 @@ std::string nd_choice_to_string(const NdChoice& c, const int64_t* dims) {
     for (int i = 0; i < c.ndim; ++i) os << kAxisName[c.order[i]];
     for (int ax = 0; ax < c.ndim; ++ax) {
         os << ";" << kAxisName[ax] << "=";
-        axis_to_string(os, c.k[ax], c.logW[ax], dims[ax], c.xcd[ax]);
+        axis_to_string(os, c.k[ax], c.logW[ax], dims[ax], c.xcd[ax], c.io[ax]);
     }
     return os.str();
 }
@@ -623,6 +654,7 @@ bool nd_choice_from_string(const char* s, int dtype, int ndim, const int64_t* di
         c.k[ax] = found;
         c.logW[ax] = lw;
         c.xcd[ax] = spec[ax].xcd;
+        c.io[ax] = spec[ax].io;
     }
     *out = c;
     return true;
@@ -633,7 +665,7 @@ int build_passes_nd(const NdChoice& c, const int64_t* dims, int64_t batch, PassP
     for (int i = 0; i < c.ndim; ++i) {
         const int ax = c.order[i];
         if (dims[ax] <= 1) continue;
-        out[n++] = make_pass_nd(c.ndim, dims, batch, ax, c.k[ax], c.logW[ax], c.xcd[ax]);
+        out[n++] = make_pass_nd(c.ndim, dims, batch, ax, c.k[ax], c.logW[ax], c.xcd[ax], c.io[ax]);
     }
     return n;
 }
@@ -643,7 +675,7 @@ int build_passes(const PlanChoice& c, const int64_t dims[3], int64_t batch, Pass
     for (int i = 0; i < 3; ++i) {
         const int ax = c.order[i];
         if (dims[ax] <= 1) continue;
-        out[n++] = make_pass(dims, batch, ax, axis_geom(c, ax), c.k[ax], c.logW[ax], c.xcd[ax]);
+        out[n++] = make_pass(dims, batch, ax, axis_geom(c, ax), c.k[ax], c.logW[ax], c.xcd[ax], c.io[ax]);
     }
     return n;
 }
@@ -661,6 +693,7 @@ hipError_t launch_pass(const PassPlan& p, const void* in, void* out, int conj_in
     a.logW = p.logW;
     a.mode = p.mode;
     a.xcd_remap = p.xcd;
+    a.stream_io = p.stream;
     a.conj_in = conj_in;
     a.conj_out = conj_out;
     a.scale = scale;

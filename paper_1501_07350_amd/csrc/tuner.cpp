@@ -221,6 +221,7 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
     const KernelEntry* best_k[3][3][2] = {};
     int best_lw[3][3][2] = {};
     int best_x[3][3][2] = {};   // XCD-contiguous tile order
+    int best_io[3][3][2] = {};  // grid-data access mode (kIoAuto unless a forced mode was faster)
     int rc = OFFT_SUCCESS;
     for (int ax = 0; ax < 3 && rc == OFFT_SUCCESS; ++ax) {
         if (dims[ax] <= 1) continue;
@@ -278,23 +279,39 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
             // displaced without being timed faster, slot 1 may still hold it
             if (best_k[ax][g][1] == best_k[ax][g][0] && best_lw[ax][g][1] == best_lw[ax][g][0])
                 best_k[ax][g][1] = nullptr;
-            // the fastest kernel with its tiles in XCD-contiguous order (at
-            // 1024^3 every pass gained 2-5% from it, at 512^3 some lost)
-            if (rc == OFFT_SUCCESS && best_k[ax][g][0] && best_ms[0] < 1e30f) {
+            // the fastest kernel with its tiles in the other tile order (at
+            // 1024^3 the XCD-contiguous order gained 2-5% on every pass with
+            // cached accesses, at 512^3 some passes lost), and with the grid
+            // data accessed the other way (streaming or cached)
+            auto try_variant = [&](int x, int io) {
+                if (rc != OFFT_SUCCESS || !best_k[ax][g][0] || best_ms[0] >= 1e30f) return;
                 float ms = 0.f;
-                rc = time_pass(p, make_pass(dims, p->batch, ax, g, best_k[ax][g][0], best_lw[ax][g][0], 1), B.buf,
-                               B.work, s, o.reps, &ms);
+                rc = time_pass(p, make_pass(dims, p->batch, ax, g, best_k[ax][g][0], best_lw[ax][g][0], x, io),
+                               B.buf, B.work, s, o.reps, &ms);
                 ++*timed;
-                if (rc == OFFT_SUCCESS && ms < best_ms[0]) {
+                if (rc != OFFT_SUCCESS) return;
+                if (ms < best_ms[0]) {
+                    best_ms[1] = best_ms[0];
                     best_k[ax][g][1] = best_k[ax][g][0];
                     best_lw[ax][g][1] = best_lw[ax][g][0];
-                    best_x[ax][g][1] = 0;
-                    best_x[ax][g][0] = 1;
-                } else if (rc == OFFT_SUCCESS && ms < best_ms[1]) {
+                    best_x[ax][g][1] = best_x[ax][g][0];
+                    best_io[ax][g][1] = best_io[ax][g][0];
+                    best_ms[0] = ms;
+                    best_x[ax][g][0] = x;
+                    best_io[ax][g][0] = io;
+                } else if (ms < best_ms[1]) {
+                    best_ms[1] = ms;
                     best_k[ax][g][1] = best_k[ax][g][0];
                     best_lw[ax][g][1] = best_lw[ax][g][0];
-                    best_x[ax][g][1] = 1;
+                    best_x[ax][g][1] = x;
+                    best_io[ax][g][1] = io;
                 }
+            };
+            if (g != kGeomTranspose) try_variant(1, kIoAuto);
+            {
+                const int64_t bytes = dims[0] * dims[1] * dims[2] * p->batch * (int64_t)elem_size(p->dtype);
+                const int other_io = resolve_stream(kIoAuto, bytes) ? kIoCached : kIoStream;
+                try_variant(best_x[ax][g][0], other_io);
             }
         }
     }
@@ -327,6 +344,7 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
                     c.k[ax] = best_k[ax][g][pick];
                     c.logW[ax] = best_lw[ax][g][pick];
                     c.xcd[ax] = best_x[ax][g][pick];
+                    c.io[ax] = best_io[ax][g][pick];
                 }
                 if (!valid) continue;
                 float ms = 0.f;
@@ -459,6 +477,7 @@ static int exhaustive_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice, f
     const KernelEntry* second_k[kMaxDims] = {};
     int second_lw[kMaxDims] = {};
     int second_x[kMaxDims] = {};
+    int second_io[kMaxDims] = {};
     int rc = OFFT_SUCCESS;
     for (int ax = 0; ax < D && rc == OFFT_SUCCESS; ++ax) {
         if (dims[ax] <= 1) continue;
@@ -496,22 +515,35 @@ static int exhaustive_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice, f
         }
         best.k[ax] = bk;
         best.logW[ax] = blw;
-        // the fastest kernel with its tiles in XCD-contiguous order
-        if (rc == OFFT_SUCCESS && bk && best_ms < 1e30f) {
+        // the fastest kernel with its tiles in XCD-contiguous order, then
+        // with the grid data accessed the other way (streaming or cached)
+        auto try_variant = [&](int x, int io) {
+            if (rc != OFFT_SUCCESS || !bk || best_ms >= 1e30f) return;
             float ms = 0.f;
-            rc = time_pass(p, make_pass_nd(D, dims, p->batch, ax, bk, blw, 1), buf, nullptr, s, o.reps, &ms);
+            rc = time_pass(p, make_pass_nd(D, dims, p->batch, ax, bk, blw, x, io), buf, nullptr, s, o.reps, &ms);
             ++*timed;
-            if (rc == OFFT_SUCCESS && ms < best_ms) {
+            if (rc != OFFT_SUCCESS) return;
+            if (ms < best_ms) {
+                second_ms = best_ms;
                 second_k[ax] = bk;
                 second_lw[ax] = blw;
-                second_x[ax] = 0;
-                best.xcd[ax] = 1;
-            } else if (rc == OFFT_SUCCESS && ms < second_ms) {
+                second_x[ax] = best.xcd[ax];
+                second_io[ax] = best.io[ax];
+                best_ms = ms;
+                best.xcd[ax] = x;
+                best.io[ax] = io;
+            } else if (ms < second_ms) {
+                second_ms = ms;
                 second_k[ax] = bk;
                 second_lw[ax] = blw;
-                second_x[ax] = 1;
+                second_x[ax] = x;
+                second_io[ax] = io;
             }
-        }
+        };
+        best.xcd[ax] = 0;
+        best.io[ax] = kIoAuto;
+        try_variant(1, kIoAuto);
+        try_variant(best.xcd[ax], resolve_stream(kIoAuto, nelem * (int64_t)elem_size(p->dtype)) ? kIoCached : kIoStream);
     }
     // orders: the heuristic's first, then every other permutation of the
     // transformed axes (unit axes keep their slots at the end)
@@ -559,6 +591,7 @@ static int exhaustive_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice, f
             c.k[ax] = second_k[ax];
             c.logW[ax] = second_lw[ax];
             c.xcd[ax] = second_x[ax];
+            c.io[ax] = second_io[ax];
         }
         if (!valid) continue;
         PassPlan passes[kMaxDims];

@@ -73,3 +73,7 @@ inline void __syncthreads() {
 #define __builtin_amdgcn_s_waitcnt(n) ((void)0)
 // One emulated thread per wavefront: a wave-uniform value is the thread's own.
 #define __builtin_amdgcn_readfirstlane(x) (x)
+
+// Streaming (non-temporal) accesses are ordinary accesses on the host.
+#define __builtin_nontemporal_load(p) (*(p))
+#define __builtin_nontemporal_store(v, p) (*(p) = (v))

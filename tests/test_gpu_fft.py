@@ -427,6 +427,77 @@ def test_normalized_inverse_and_linearity():
         assert oracle.rel_l2(host(fab), host(fa) + host(fb)) <= tol(a.numel(), dtype)
 
 
+@pytest.mark.parametrize("use_graph", [False, True], ids=["direct", "graph"])
+def test_backward_normalize_per_call(use_graph):
+    """backward(normalize=...) chooses the 1/N scaling per call: it equals the
+    plan-level choice bit for bit, in either direction of the override, with
+    direct launches and with graph replay."""
+    shape = (12, 20, 30)
+    for dtype in (C128, C64):
+        x = gen(shape, dtype, synth.SEED + 3)
+        plain = offt.Plan(shape, dtype=dtype, use_graph=use_graph)
+        scaled = offt.Plan(shape, dtype=dtype, normalize_inverse=True, use_graph=use_graph)
+        y = plain.forward(x)
+        z_plain = plain.backward(y)
+        z_scaled = scaled.backward(y)
+        z1 = plain.backward(y, normalize=True)
+        z0 = scaled.backward(y, normalize=False)
+        zd = scaled.backward(y, normalize=None)
+        torch.cuda.synchronize()
+        assert torch.equal(z1, z_scaled) and torch.equal(zd, z_scaled) and torch.equal(z0, z_plain)
+        assert oracle.rel_l2(host(z1), host(x)) <= tol(x.numel(), dtype)
+        ref = oracle.fft3(host(y).astype(np.complex128), oracle.BACKWARD)
+        assert oracle.rel_l2(host(z0), ref) <= tol(x.numel(), dtype)
+        plain.close()
+        scaled.close()
+
+
+def _with_mode(plan, mode):
+    """The plan string with every axis forced to access mode "/s" or "/c"."""
+    def fix(spec):
+        return spec if spec == "1" else spec + mode
+    halves = []
+    for half in plan.split("|"):
+        parts = []
+        for t in half.split(";"):
+            k, v = t.split("=", 1)
+            parts.append(f"{k}={fix(v)}" if k in "abcde" and len(k) == 1 else t)
+        halves.append(";".join(parts))
+    return "|".join(halves)
+
+
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("shape,layout", [((64, 48, 80), "natural"), ((30, 512, 12), "natural"),
+                                          ((40, 24, 60), "cba"), ((6, 8, 10, 12), "natural")])
+def test_streaming_and_cached_accesses_are_bit_identical(shape, layout, dtype):
+    """Streaming ("/s") and cached ("/c") grid-data accesses only change how
+    the loads and stores use the caches: the same plan gives the same bits
+    either way, in every pass kind (contiguous, strided, transposing,
+    4-axis), and matches the oracle."""
+    x = gen(shape, dtype, synth.SEED + 11)
+    heur = offt.Plan(shape, dtype=dtype, layout=layout)
+    base = heur.describe()
+    heur.close()
+    outs = {}
+    for mode in ("/s", "/c"):
+        plan = offt.Plan(shape, dtype=dtype, layout=layout, tune="forced", forced_plan=_with_mode(base, mode))
+        assert plan.describe() == _with_mode(base, mode)
+        outs[mode] = plan.forward(x)
+        torch.cuda.synchronize()
+        plan.close()
+    assert torch.equal(outs["/s"], outs["/c"])
+    xh = host(x).astype(np.complex128)
+    if len(shape) == 4:
+        from oracle import ndim
+        ref = ndim.fftn(xh)
+    elif layout == "cba":
+        from oracle import layout as lay
+        ref = lay.fft3_reversed(xh)
+    else:
+        ref = oracle.fft3(xh)
+    assert oracle.rel_l2(host(outs["/s"]), ref) <= tol(x.numel(), dtype)
+
+
 def test_tensor_checks():
     plan = offt.Plan((8, 8, 8), dtype=C64)
     with pytest.raises(ValueError):

@@ -1,5 +1,6 @@
 """Host logic of the reversed (cba) output order: plan strings, the heuristic's
 choice of transposing axis, and rejection of unusable plans (no GPU)."""
+import numpy as np
 import pytest
 import torch
 
@@ -105,14 +106,32 @@ def test_xcd_tile_order_in_plan_strings():
 @pytest.mark.parametrize("shape", [(512, 512, 512), (64, 48, 30), (1, 32, 40), (30, 40, 1), (6, 1, 9)])
 def test_heuristic_tile_order_follows_the_stride(shape, dtype):
     """The heuristic plan takes the XCD-contiguous tile order ("/x") exactly on
-    the axes whose lines are strided (a later axis longer than 1)."""
+    the axes whose lines are strided (a later axis longer than 1), except the
+    lines strided by 2 MiB or more of a grid above 256 MiB, whose passes stream
+    their data and keep the launch order."""
     f = dict(t.split("=", 1) for t in offt.default_plan_string(shape, dtype).split(";"))
+    es = 16 if dtype == C128 else 8
+    streams = np.prod(shape) * es > (256 << 20)
     for i, ax in enumerate("abc"):
         if shape[i] == 1:
             assert f[ax] == "1"
             continue
         strided = any(n > 1 for n in shape[i + 1:])
-        assert f[ax].endswith("/x") == strided, (ax, f[ax])
+        long_stride = int(np.prod(shape[i + 1:])) * es >= (2 << 20)
+        assert f[ax].endswith("/x") == (strided and not (streams and long_stride)), (ax, f[ax])
+
+
+def test_access_mode_in_plan_strings():
+    """"/s" and "/c" after an axis spec force streaming or cached grid-data
+    accesses; without either the pass streams when the grids exceed 256 MiB."""
+    s = "order=bca;a=16x16x2/16/p2/x/s;b=32x16/32/p2/c;c=16x16x2/2/s"
+    assert offt.plan_string((512, 512, 512), C128, "natural", s) == s
+    nd = offt.plan_string_nd((64, 64, 64, 64), C64, "order=dcba;a=16x4/32/c;d=8x8/4/x/s")
+    assert ";a=16x4/32/c;" in nd and nd.endswith(";d=8x8/4/x/s")
+    for bad in ["order=cba;c=16x16x2/2/s/x", "order=cba;c=16x16x2/2/q", "order=cba;c=16x16x2/2/s/c",
+                "order=cba;c=16x16x2/2/ss"]:
+        with pytest.raises(offt.OfftError):
+            offt.plan_string((512, 512, 512), C128, "natural", bad)
 
 
 def test_heuristic_tile_order_on_reversed_and_nd_plans():
