@@ -122,6 +122,20 @@ def time_transform(n: int, dtype, steps: int, warmup: int, check: bool, tune: st
     ms = total_ms / steps
     N = x.numel()
     s = x.element_size()
+    # the copy of each pass's own memory accesses (offt_copy_pass): the same
+    # tiles, threads, tile order and access mode, no arithmetic
+    copy_ms = []
+    for i in range(npass):
+        for _ in range(warmup):
+            plan.copy_pass(i, xp, yp, h)
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(steps):
+            plan.copy_pass(i, xp, yp, h)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        copy_ms.append(c0.elapsed_time(c1) / steps)
     res = {
         "ms": ms,
         "gflops": 5.0 * N * math.log2(N) / (ms * 1e6),
@@ -131,6 +145,7 @@ def time_transform(n: int, dtype, steps: int, warmup: int, check: bool, tune: st
         "plan_seconds": plan_s,
         "pass_ms": pass_ms,
         "pass_bytes": 2 * N * s,
+        "copy_ms": copy_ms,
     }
     if check:
         import oracle
@@ -349,6 +364,69 @@ def time_batch(steps: int, warmup: int, check: bool, count: int = 64):
     return out
 
 
+def time_dist(n: int, dtype, steps: int, warmup: int, check: bool, nprocs=(2, 4, 8)):
+    """The paper's distributed flow over Np virtual processes on this GPU
+    (per-process line transforms, abc -> cab and cab -> cba transposes with
+    pack, communicate, unpack; output in cba order): time of one forward
+    transform with each communication method, the method the plan-time
+    auto-tuning picks, and the elements each transpose moves between
+    processes.  Block methods use groups of Np/2 processes."""
+    import numpy as np
+    import torch
+
+    import paper_1501_07350_amd as offt
+    import synth
+
+    shape = (n, n, n)
+    x = synth.complex_grid(shape, dtype, device="cuda")
+    y = torch.empty(shape[::-1], dtype=dtype, device="cuda")
+    h = int(torch.cuda.current_stream().cuda_stream)
+    N = x.numel()
+    out = {"workload": f"{n}x{n}x{n} {'complex128' if dtype == torch.complex128 else 'complex64'}, forward, "
+                       f"output in cba order", "nprocs": {}}
+    for np_ in nprocs:
+        plan = offt.DistPlan(shape, np_, dtype=dtype, method="auto", block_size=max(1, np_ // 2), reps=3)
+        ms = {}
+        for m in offt.COMM_METHODS:
+            def run():
+                plan.exec_ptr(offt.FORWARD, x.data_ptr(), y.data_ptr(), h, method=m)
+
+            for _ in range(warmup):
+                run()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(steps):
+                run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms[m] = round(e0.elapsed_time(e1) / steps, 4)
+        moved = [int(sum(c for p, row in enumerate(plan.counts(st)) for q, c in enumerate(row) if p != q))
+                 for st in (0, 1)]
+        rec = {"decomposition": plan.describe().split(",")[1].strip(), "ms": ms,
+               "auto_choice": plan.method, "auto_tuning_ms": {k: round(v, 4) for k, v in plan.method_times().items()},
+               "elements_moved": {"abc->cab": moved[0], "cab->cba": moved[1]},
+               "gflops_best": round(5.0 * N * math.log2(N) / (min(ms.values()) * 1e6), 1)}
+        if check:
+            import oracle
+            plan.forward(x, out=y)
+            torch.cuda.synchronize()
+            xh = x.cpu().numpy().astype(np.complex128)
+            yh = y.cpu().numpy()
+            got, ref = [], []
+            for ka, kb in ((0, 0), (3, 5), (n - 1, 7)):
+                got.append(yh[:, kb, ka].astype(np.complex128))
+                ref.append(oracle.dft3_line(xh, ka, kb))
+            rec["check_rel_l2_sampled_lines"] = oracle.rel_l2(np.concatenate(got), np.concatenate(ref))
+        out["nprocs"][str(np_)] = rec
+        print(f"dist Np={np_}: {rec}", file=sys.stderr, flush=True)
+        plan.close()
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_small(steps: int, warmup: int, check: bool, n: int = 32):
     """Config 1: one n^3 complex128 grid, forward then inverse with 1/N,
     latency per round trip with the pass kernels launched directly and
@@ -397,9 +475,22 @@ def roofline(res, tag):
     dur_ms = res["pass_ms"][i]
     achieved = res["pass_bytes"] / (dur_ms * 1e6)
     key = pass_keys(res["plan"])[i]
+    copy_gbs = res["pass_bytes"] / (res["copy_ms"][i] * 1e6)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": load_traffic(tag, key), "kernel_pass": i,
-            "kernel": key, "kernel_ms": round(dur_ms, 4), "algorithmic_bytes_per_launch": res["pass_bytes"]}
+            "kernel": key, "kernel_ms": round(dur_ms, 4), "algorithmic_bytes_per_launch": res["pass_bytes"],
+            "copy_ceiling_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
+
+
+def copy_ceilings(res):
+    """Per pass: the copy of the pass's own access pattern (GB/s of the
+    algorithmic bytes) and the pass's rate as a fraction of it."""
+    out = []
+    for key, pm, cm in zip(pass_keys(res["plan"]), res["pass_ms"], res["copy_ms"]):
+        g = res["pass_bytes"] / (cm * 1e6)
+        out.append({"pass": key, "copy_ms": round(cm, 4), "copy_gbs": round(g, 1),
+                    "pass_gbs": round(res["pass_bytes"] / (pm * 1e6), 1), "frac_of_copy": round(cm / pm, 4)})
+    return out
 
 
 def cpu_baseline(n: int):
@@ -886,6 +977,8 @@ def main():
                     help="time only the reversed (cba) output order at --n (to profile its passes)")
     ap.add_argument("--summarize-reversed", nargs=2, metavar=("DIR", "LOG"),
                     help="reduce a rocprofv3 --kernel-trace run of --reversed-only")
+    ap.add_argument("--dist-only", action="store_true",
+                    help="time only the distributed flow over virtual processes at --n")
     ap.add_argument("--nd-only", action="store_true",
                     help="time only the 4- and 5-axis grids (to profile their passes)")
     ap.add_argument("--summarize-nd", nargs=2, metavar=("DIR", "LOG"),
@@ -945,6 +1038,10 @@ def main():
         print(json.dumps({"reversed_output": reversed_runs(args.n, args.steps, args.warmup, not args.no_check)}),
               flush=True)
         return
+    if args.dist_only:
+        print(json.dumps({"dist": time_dist(args.n, torch.complex128, args.steps, args.warmup, not args.no_check)}),
+              flush=True)
+        return
     if args.nd_only:
         print(json.dumps({"nd": nd_runs(args.steps, args.warmup, not args.no_check)}), flush=True)
         return
@@ -982,6 +1079,7 @@ def main():
         "plan_cache": os.path.relpath(PLAN_CACHE, ROOT) if PLAN_CACHE else None,
         "plan_tuning_seconds": round(r64["plan_seconds"], 3),
         "pass_ms": [round(v, 4) for v in r64["pass_ms"]],
+        "copy_ceiling": copy_ceilings(r64),
         "heuristic_plan": {"f64": {"ms_per_step": round(h64["ms"], 4), "gflops": round(h64["gflops"], 1),
                                    "plan": h64["plan"]},
                            "f32": {"ms_per_step": round(h32["ms"], 4), "gflops": round(h32["gflops"], 1),
@@ -991,6 +1089,7 @@ def main():
                 "frac_of_peak_effective": round(r32["eff_gbs"] / PEAK_HBM_GBS, 4), "plan": r32["plan"],
                 "plan_tuning_seconds": round(r32["plan_seconds"], 3),
                 "pass_ms": [round(v, 4) for v in r32["pass_ms"]],
+                "copy_ceiling": copy_ceilings(r32),
                 "roofline": roofline(r32, f"{n}_f32")},
         "roofline": roofline(r64, f"{n}_f64"),
     }
@@ -1003,6 +1102,7 @@ def main():
         out["batch"] = time_batch(args.steps, args.warmup, not args.no_check)
         out["reversed_output"] = reversed_runs(n, args.steps, args.warmup, not args.no_check)
         out["nd"] = nd_runs(args.steps, args.warmup, not args.no_check)
+        out["dist"] = time_dist(n, torch.complex128, args.steps, args.warmup, not args.no_check)
     if args.calibrate:
         calibrate_copy()
     if not args.no_cpu:

@@ -193,6 +193,16 @@ int offt_plan_passes(offt_plan_t p);
  * BAD_PLAN, HIP. */
 int offt_exec_pass(offt_plan_t p, int i, int direction, const void* in, void* out, void* stream);
 
+/* Copy of axis pass i's memory accesses, the measured ceiling of that pass:
+ * the pass's tiles (lines per workgroup, threads, tile order, grid-data
+ * access mode), every thread loading the elements its first-stage
+ * butterflies read (positions b + r L/R0 of its line) in one burst and
+ * storing them to the same positions of `out`; no arithmetic, no LDS
+ * exchange.  Moves the same bytes as the pass (2 N s per grid).  in != out,
+ * each holding batch grids.  Errors: INVALID_ARG, BAD_PLAN (not a plan of
+ * kind offt_plan/offt_plan_nd, or a transposing pass), UNSUPPORTED_SIZE, HIP. */
+int offt_copy_pass(offt_plan_t p, int i, const void* in, void* out, void* stream);
+
 /* Free every plan-owned allocation.  NULL is a no-op.  The handle is invalid
  * afterwards. */
 int offt_destroy(offt_plan_t p);
@@ -290,6 +300,109 @@ int offt_exec_many_bwd(offt_plan_t p, const void* in, void* out, void* stream);
  * (results then invalid; for SYNC* this happens when not every workgroup of
  * the launch could be resident, e.g. while other work holds the device). */
 int offt_many_status(offt_plan_t p);
+
+/* ---- the distributed calculation flow on virtual processes ----------------
+ * The paper's method itself (Sec. 2, Sec. 3.1.1, Fig. 1b) run by `nprocs`
+ * virtual processes on one GPU.  Process p owns the block of Eq. 2 of the
+ * linear index of the order the data is currently held in: whole N2 x N3
+ * planes when nprocs <= N1, whole N3-lines when N1 < nprocs <= N1 N2 (the
+ * 1-D and 2-D decompositions, Eq. 2-9), over that order's leading dimensions
+ * (N1, N2, N3) = (Na, Nb, Nc) for abc, (Nc, Na, Nb) for cab, (Nc, Nb, Na) for
+ * cba.  Each block is a contiguous slice of the grid held in that order, so
+ * the processes' local arrays are consecutive slices of one array.
+ *
+ * Forward (offt_exec_fwd): `in` is the grid in abc order (process p's input
+ * is its abc block); per process, the 1-D transforms of its lines along c,
+ * the transpose abc -> cab, the transforms along b, the transpose
+ * cab -> cba, the transforms along a; `out` receives the transform in cba
+ * order, Y[c][b][a] = X[a][b][c] (process p's output is its cba block: the
+ * distribution the paper's transform finishes in).  Backward
+ * (offt_exec_bwd, offt_exec_bwd_norm): cba input, abc output, the steps in
+ * reverse with the conjugate roots of unity.  in == out is allowed.
+ *
+ * A transpose packs each process's elements into one chunk per destination
+ * (in the sender's local order), copies the chunks between the processes'
+ * send and receive slices, and unpacks them into the destination's local
+ * array.  The copies follow one of the six communication methods of
+ * Sec. 3.2.1 (OFFT_COMM_*):
+ *   ISEND_WAITALL        every chunk posted at once as its own copy on a
+ *                        communication stream, then one wait for all, then
+ *                        the unpacks;
+ *   ALLTOALLV            one collective copy launch over every chunk, then
+ *                        the unpacks;
+ *   ISEND_WAITALL_BLOCK  the processes taken in groups of block_size
+ *                        destinations (the paper's B_SIZE, 32 there): each
+ *                        group's chunks posted, then waited for, group after
+ *                        group; then the unpacks;
+ *   ISEND_WAITSOME       every chunk posted at once; each chunk is unpacked
+ *                        as soon as it has arrived (an event per chunk), while
+ *                        the others are still in flight;
+ *   ISEND_WAITSOME_BLOCK the same per group of block_size destinations, the
+ *                        next group posted once the current one is unpacked;
+ *   SENDRECV             nprocs steps: at step i every process sends to
+ *                        process myid + i and receives from myid - i (mod
+ *                        nprocs), the received chunk unpacked before the
+ *                        next step.
+ * OFFT_COMM_AUTO times every method at plan time on the plan's stream (one
+ * warm-up and o->reps timed forward transforms each, minimum of two, median
+ * of more) and keeps the fastest, ties to the lower id: the paper's
+ * auto-tuning of communication in the initialization phase (Sec. 3.2.3).
+ * Without it the given method is used (the paper's User-select; its default
+ * is ISEND_WAITSOME).
+ *
+ * Limits: 1 <= nprocs <= min(64, N1 N2 of every order); block_size >= 1.
+ * The plan owns three arrays of the grid's size (work, send, receive), a
+ * communication stream (default priority) and its events.  Exec never
+ * allocates; a plan must not run on two streams at once. */
+#define OFFT_COMM_AUTO (-1)
+#define OFFT_COMM_ISEND_WAITALL 0
+#define OFFT_COMM_ALLTOALLV 1
+#define OFFT_COMM_ISEND_WAITALL_BLOCK 2
+#define OFFT_COMM_ISEND_WAITSOME 3
+#define OFFT_COMM_ISEND_WAITSOME_BLOCK 4
+#define OFFT_COMM_SENDRECV 5
+
+/* Orders of offt_dist_block. */
+#define OFFT_ORDER_ABC 0
+#define OFFT_ORDER_CAB 1
+#define OFFT_ORDER_CBA 2
+
+/* Plan of the distributed flow for one grid over `nprocs` virtual processes
+ * with communication method `method` (OFFT_COMM_*) and group size
+ * block_size.  From o: normalize_inverse, reps and stream (tuning).  Errors:
+ * INVALID_ARG (sizes, nprocs, method, block_size), UNSUPPORTED_SIZE,
+ * NO_DEVICE, OUT_OF_MEMORY, HIP. */
+offt_plan_t offt_plan_dist(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int nprocs, int method, int block_size,
+                           const offt_opts* o);
+
+/* The method a distributed plan runs (OFFT_COMM_*), or a negative code. */
+int offt_dist_method(offt_plan_t p);
+
+/* ms[0..6): time of a forward transform with each method as measured at plan
+ * time by OFFT_COMM_AUTO (-1 each when the method was given).  Returns 6 or a
+ * negative code. */
+int offt_dist_method_times(offt_plan_t p, float* ms);
+
+/* Elements process src sends to process dst in transpose `step` of the
+ * forward (OFFT_FORWARD: 0 abc -> cab, 1 cab -> cba) or backward flow
+ * (OFFT_BACKWARD: 0 cba -> cab, 1 cab -> abc), as the plan moves them
+ * (src == dst: the elements that stay local).  Errors: INVALID_ARG,
+ * BAD_PLAN. */
+int64_t offt_dist_count(offt_plan_t p, int direction, int step, int src, int dst);
+
+/* Block of process proc in order OFFT_ORDER_*: returns its first linear index
+ * and writes one past its last to *end (if end != NULL).  Errors:
+ * INVALID_ARG, BAD_PLAN. */
+int64_t offt_dist_block(offt_plan_t p, int order, int proc, int64_t* end);
+
+/* The first `steps` (1..5) steps of the forward or backward flow from `in` to
+ * `out`, with `method` (OFFT_COMM_AUTO: the plan's): `out` then holds the
+ * processes' local arrays after that step, concatenated in process order --
+ * the grid in that step's order (forward: abc, cab, cab, cba, cba; backward:
+ * cba, cab, cab, abc, abc).  For tests of every step.  Never allocates.
+ * Errors: INVALID_ARG, BAD_PLAN, HIP. */
+int offt_dist_exec_steps(offt_plan_t p, int direction, int steps, int method, const void* in, void* out,
+                         void* stream);
 
 /* ---- byte and volume accounting (host only, no device) --------------------
  * Per plan: HBM bytes of one axis pass.  Per decomposition: the row-wise

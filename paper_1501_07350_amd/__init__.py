@@ -17,12 +17,12 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (BACKWARD, C2C_F32, C2C_F64, FORWARD, MANY_LEVELS, MANY_LEVELS_GRAPH, MANY_PERSISTENT,
+from ._lib import (BACKWARD, C2C_F32, C2C_F64, COMM_METHODS, FORWARD, MANY_LEVELS, MANY_LEVELS_GRAPH, MANY_PERSISTENT,
                    MANY_PERSISTENT_GRAPH, MANY_SEPARATE_HEURISTIC, MANY_SEPARATE_TUNED, MANY_SYNC, MANY_SYNC_GRAPH,
                    LAYOUT_NATURAL, LAYOUT_REVERSED, MAX_AXIS, OfftError,
                    TUNE_EXHAUSTIVE, TUNE_FORCED, TUNE_LEARNED, TUNE_NONE)
 
-__all__ = ["Plan", "ManyPlan", "OfftError", "twiddles", "default_plan_string", "plan_string", "plan_string_nd", "pass_bytes",
+__all__ = ["Plan", "ManyPlan", "DistPlan", "OfftError", "twiddles", "default_plan_string", "plan_string", "plan_string_nd", "pass_bytes",
            "decomp_start", "transpose_count", "transpose_volume", "FORWARD", "BACKWARD", "MAX_AXIS"]
 
 _LAYOUT = {"natural": LAYOUT_NATURAL, "abc": LAYOUT_NATURAL, "cba": LAYOUT_REVERSED,
@@ -165,6 +165,11 @@ class Plan:
                                               ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream)),
                    "exec_pass")
 
+    def copy_pass(self, i: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+        """The copy of pass i's memory accesses (its measured ceiling)."""
+        _lib.check(_lib.load().offt_copy_pass(self._h, int(i), ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
+                                              ctypes.c_void_p(stream)), "copy_pass")
+
     def describe(self) -> str:
         lib = _lib.load()
         n = _lib.check(lib.offt_plan_describe(self._h, None, 0), "describe")
@@ -271,6 +276,131 @@ class ManyPlan:
         buf = ctypes.create_string_buffer(n + 1)
         lib.offt_plan_describe(self._h, buf, n + 1)
         return buf.value.decode()
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.load().offt_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DistPlan:
+    """The paper's distributed flow over `nprocs` virtual processes on one GPU
+    (include/offt.h, offt_plan_dist).  forward(x) takes a (Na, Nb, Nc) grid
+    and returns the transform in cba order, shape (Nc, Nb, Na), as the
+    paper's transform finishes; backward(y) the reverse.  method: one of
+    COMM_METHODS (User-select) or "auto" (every method timed at plan time,
+    the fastest kept)."""
+
+    def __init__(self, shape, nprocs: int, dtype=torch.complex128, method="auto", block_size: int = 32,
+                 normalize_inverse: bool = False, reps: int = 2):
+        lib = _lib.load()
+        self.shape = tuple(int(v) for v in shape)
+        if len(self.shape) != 3:
+            raise ValueError("shape must be (Na, Nb, Nc)")
+        self.dtype = dtype
+        self.nprocs = int(nprocs)
+        if method == "auto":
+            code_m = _lib.COMM_AUTO
+        elif method in _lib.COMM_METHODS:
+            code_m = _lib.COMM_METHODS.index(method)
+        elif isinstance(method, int):
+            code_m = method
+        else:
+            raise ValueError(f"method must be 'auto' or one of {_lib.COMM_METHODS}")
+        stream = _stream_handle() if torch.cuda.is_available() else None
+        opts, keep = _make_opts("none", reps, normalize_inverse, None, None, None, stream)
+        h = lib.offt_plan_dist(*self.shape, _dtype_code(dtype), self.nprocs, int(code_m), int(block_size),
+                               ctypes.byref(opts))
+        del keep
+        if not h:
+            raise OfftError(_lib.last_error(), "offt_plan_dist")
+        self._h = h
+
+    @property
+    def method(self) -> str:
+        return _lib.COMM_METHODS[_lib.check(_lib.load().offt_dist_method(self._h), "dist_method")]
+
+    def method_times(self):
+        """{method: ms} measured at plan time (empty when the method was given)."""
+        ms = (ctypes.c_float * 6)()
+        _lib.check(_lib.load().offt_dist_method_times(self._h, ms), "dist_method_times")
+        return {m: float(v) for m, v in zip(_lib.COMM_METHODS, ms) if v >= 0}
+
+    def counts(self, step: int, direction: int = FORWARD):
+        """counts[p][q]: elements process p sends to q in transpose `step`."""
+        lib = _lib.load()
+        return [[_lib.check(lib.offt_dist_count(self._h, int(direction), int(step), p, q), "dist_count")
+                 for q in range(self.nprocs)] for p in range(self.nprocs)]
+
+    def block(self, order: str, proc: int):
+        """[start, end) of process proc's block in order 'abc', 'cab' or 'cba'."""
+        end = ctypes.c_int64()
+        o = {"abc": _lib.ORDER_ABC, "cab": _lib.ORDER_CAB, "cba": _lib.ORDER_CBA}[order]
+        start = _lib.check(_lib.load().offt_dist_block(self._h, o, int(proc), ctypes.byref(end)), "dist_block")
+        return start, end.value
+
+    def _check(self, x, shape):
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != self.dtype or not x.is_contiguous():
+            raise ValueError(f"expected a contiguous CUDA tensor of dtype {self.dtype}")
+        if x.numel() != self.shape[0] * self.shape[1] * self.shape[2]:
+            raise ValueError(f"expected {shape}")
+
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._check(x, self.shape)
+        out = torch.empty(self.shape[::-1], dtype=x.dtype, device=x.device) if out is None else out
+        self._check(out, self.shape[::-1])
+        _lib.check(_lib.load().offt_exec_fwd(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                             ctypes.c_void_p(_stream_handle())), "exec")
+        return out
+
+    def backward(self, y: torch.Tensor, out: torch.Tensor | None = None,
+                 normalize: bool | None = None) -> torch.Tensor:
+        self._check(y, self.shape[::-1])
+        out = torch.empty(self.shape, dtype=y.dtype, device=y.device) if out is None else out
+        self._check(out, self.shape)
+        norm = -1 if normalize is None else (1 if normalize else 0)
+        _lib.check(_lib.load().offt_exec_bwd_norm(self._h, ctypes.c_void_p(y.data_ptr()),
+                                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_int(norm),
+                                                  ctypes.c_void_p(_stream_handle())), "exec")
+        return out
+
+    def exec_steps(self, x: torch.Tensor, steps: int, direction: int = FORWARD, method=None) -> torch.Tensor:
+        """The first `steps` steps of the flow; returns the flat array of the
+        processes' local arrays after that step, in process order."""
+        self._check(x, self.shape)
+        out = torch.empty(x.numel(), dtype=x.dtype, device=x.device)
+        m = _lib.COMM_AUTO if method is None else (_lib.COMM_METHODS.index(method) if isinstance(method, str)
+                                                  else int(method))
+        _lib.check(_lib.load().offt_dist_exec_steps(self._h, int(direction), int(steps), m,
+                                                    ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                                    ctypes.c_void_p(_stream_handle())), "dist_exec_steps")
+        return out
+
+    def exec_ptr(self, direction: int, in_ptr: int, out_ptr: int, stream: int = 0, method=None,
+                 steps: int = 5) -> None:
+        """Raw-pointer execution of the first `steps` steps (no tensor checks),
+        with `method` (None: the plan's) -- for benchmarking loops."""
+        m = _lib.COMM_AUTO if method is None else (_lib.COMM_METHODS.index(method) if isinstance(method, str)
+                                                  else int(method))
+        _lib.check(_lib.load().offt_dist_exec_steps(self._h, int(direction), int(steps), m, ctypes.c_void_p(in_ptr),
+                                                    ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream)), "exec")
+
+    def describe(self) -> str:
+        lib = _lib.load()
+        n = _lib.check(lib.offt_plan_describe(self._h, None, 0), "describe")
+        buf = ctypes.create_string_buffer(n + 1)
+        lib.offt_plan_describe(self._h, buf, n + 1)
+        return buf.value.decode()
+
+    def workspace_bytes(self) -> int:
+        return _lib.check(_lib.load().offt_workspace_bytes(self._h), "workspace_bytes")
 
     def close(self):
         h = getattr(self, "_h", None)

@@ -43,6 +43,18 @@ MANY_SYNC_GRAPH = 5
 MAX_AXIS = 1024
 MAX_DIMS = 5
 
+# communication methods of the distributed flow (offt_plan_dist)
+COMM_AUTO = -1
+COMM_ISEND_WAITALL = 0
+COMM_ALLTOALLV = 1
+COMM_ISEND_WAITALL_BLOCK = 2
+COMM_ISEND_WAITSOME = 3
+COMM_ISEND_WAITSOME_BLOCK = 4
+COMM_SENDRECV = 5
+COMM_METHODS = ["Isend_Waitall", "Alltoallv", "Isend_Waitall_Block", "Isend_Waitsome", "Isend_Waitsome_Block",
+                "Sendrecv"]
+ORDER_ABC, ORDER_CAB, ORDER_CBA = 0, 1, 2
+
 # order of transformed grids (offt_opts.layout)
 LAYOUT_NATURAL = 0
 LAYOUT_REVERSED = 1
@@ -77,6 +89,7 @@ SIGNATURES = {
     "offt_destroy": (_ci, [_vp]),
     "offt_plan_passes": (_ci, [_vp]),
     "offt_exec_pass": (_ci, [_vp, _ci, _ci, _vp, _vp, _vp]),
+    "offt_copy_pass": (_ci, [_vp, _ci, _vp, _vp, _vp]),
     "offt_plan_describe": (_ci, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "offt_workspace_bytes": (_i64, [_vp]),
     "offt_last_error": (_ci, []),
@@ -111,6 +124,12 @@ SIGNATURES = {
     "offt_exec_many_fwd": (_ci, [_vp, _vp, _vp, _vp]),
     "offt_exec_many_bwd": (_ci, [_vp, _vp, _vp, _vp]),
     "offt_many_status": (_ci, [_vp]),
+    "offt_plan_dist": (_vp, [_i64, _i64, _i64, _ci, _ci, _ci, _ci, ctypes.POINTER(Opts)]),
+    "offt_dist_method": (_ci, [_vp]),
+    "offt_dist_method_times": (_ci, [_vp, ctypes.POINTER(ctypes.c_float)]),
+    "offt_dist_count": (_i64, [_vp, _ci, _ci, _ci, _ci]),
+    "offt_dist_block": (_i64, [_vp, _ci, _ci, ctypes.POINTER(_i64)]),
+    "offt_dist_exec_steps": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, _vp]),
     "offt_pass_bytes": (_i64, [_i64, _i64, _i64, _ci, _i64]),
     "offt_decomp_start": (_i64, [_i64, _i64, _i64, _i64, _i64]),
     "offt_transpose_count": (_i64, [_i64, _i64, _i64, _i64, _ci, _i64, _i64]),

@@ -141,6 +141,7 @@ namespace offt {
 void free_plan(offt_plan_s* p) {
     if (!p) return;
     release_many(p);
+    release_dist(p);
     for (int d = 0; d < 2; ++d) {
         if (p->gexec[d]) (void)hipGraphExecDestroy(p->gexec[d]);
         if (p->graph[d]) (void)hipGraphDestroy(p->graph[d]);
@@ -419,9 +420,14 @@ static int exec_checked(offt_plan_t p, const void* in, void* out, void* stream, 
         set_error(OFFT_ERR_INVALID_ARG);
         return OFFT_ERR_INVALID_ARG;
     }
-    if (p->kind != 1 && p->kind != 3) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
+    if (p->kind != 1 && p->kind != 3 && p->kind != 4) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
     const hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = OFFT_SUCCESS;
+    if (p->kind == 4) {
+        rc = exec_dist(p, dir, 5, in, out, -1, normalize, s);
+        set_error(rc);
+        return rc;
+    }
     if (normalize == p->normalize) normalize = -1;
     if (p->use_graph && p->npass > 0 && normalize < 0) {
         const int d = dir > 0 ? 1 : 0;

@@ -147,6 +147,9 @@ PlanChoice default_choice(int dtype, const int64_t dims[3]);
 PlanChoice default_choice_reversed(int dtype, const int64_t dims[3]);
 // Candidate plans for tuning (deterministic order, default first).
 std::vector<PlanChoice> candidate_choices(int dtype, const int64_t dims[3]);
+// The heuristic pass over `lines` contiguous lines of length L (kernel, tile
+// width, access mode for grid data of grid_bytes), twiddles not attached.
+PassPlan contiguous_pass(int dtype, int L, int64_t lines, int64_t grid_bytes);
 // Pass descriptors (M1, M2, mode, W) for a grid + batch under a choice.
 int build_passes(const PlanChoice& c, const int64_t dims[3], int64_t batch, PassPlan out[3]);
 // Whether a tile of 2^logW lines of kernel k can be launched: thread limit

@@ -12,10 +12,12 @@
 
 namespace offt {
 struct ManyState;
+struct DistState;
 }
 
 struct offt_plan_s {
-    int kind = 0;                 // 1: one grid shape (+batch), 2: uneven batch, 3: 4-D / 5-D grids
+    int kind = 0;                 // 1: one grid shape (+batch), 2: uneven batch, 3: 4-D / 5-D grids,
+                                  // 4: the distributed flow over virtual processes
     int dtype = 0;
     int64_t dims[3] = {1, 1, 1};
     int64_t batch = 1;
@@ -40,6 +42,7 @@ struct offt_plan_s {
     std::vector<size_t> alloc_bytes;
     std::string tune_log;         // how the plan was chosen (for describe)
     offt::ManyState* many = nullptr;
+    offt::DistState* dist = nullptr;   // kind 4: Np virtual processes
     // use_graph: the passes replayed from HIP graphs captured on `cap`, one
     // per direction ([0] forward, [1] backward)
     int use_graph = 0;
@@ -78,5 +81,12 @@ std::string describe_plan(const offt_plan_s* p);
 // Uneven batches (many.hip).
 void release_many(offt_plan_s* p);
 std::string describe_many(const offt_plan_s* p);
+
+// The distributed flow over virtual processes (dist.hip): the first `steps`
+// of the five steps, method < 0 the plan's, normalize < 0 the plan's.
+void release_dist(offt_plan_s* p);
+std::string describe_dist(const offt_plan_s* p);
+int exec_dist(const offt_plan_s* p, int dir, int steps, const void* in, void* out, int method, int normalize,
+              hipStream_t s);
 
 }  // namespace offt

@@ -333,6 +333,23 @@ static void assign_default_kernels(PlanChoice& c, int dtype, const int64_t dims[
     }
 }
 
+PassPlan contiguous_pass(int dtype, int L, int64_t lines, int64_t grid_bytes) {
+    PassPlan p;
+    p.axis = 2;
+    p.L = L;
+    p.M1 = lines;
+    p.M2 = 1;
+    p.X = 1;
+    p.Y = 1;
+    p.mode = 0;
+    p.xcd = 0;
+    p.tw = nullptr;
+    p.k = default_kernel(dtype, L, false);
+    p.logW = default_logW(p.k, dtype, false);
+    p.stream = resolve_stream(kIoAuto, grid_bytes);
+    return p;
+}
+
 PlanChoice default_choice(int dtype, const int64_t dims[3]) {
     PlanChoice c;
     c.order[0] = 2; c.order[1] = 1; c.order[2] = 0;   // c, then b, then a

@@ -679,6 +679,7 @@ namespace offt {
 
 std::string describe_plan(const offt_plan_s* p) {
     if (p->kind == 2) return describe_many(p);
+    if (p->kind == 4) return describe_dist(p);
     if (p->kind == 3) return nd_choice_to_string(p->ndc, p->nd_dims);
     return plan_to_string(p, p->choice, p->choice_b);
 }

@@ -13,6 +13,12 @@
 //   emu_driver sync <dtype> <nwg> <threads> <nseg> <segments + level...> <total>
 //       the level-synchronous persistent body (grid barriers between levels)
 //       over the batch executor's cases, nwg workgroups at once
+//   emu_driver route <Na> <Nb> <Nc> <np> <in_order> <out_order> <per_chunk>
+//       one exchange of the distributed flow with the library's own tables
+//       (dist_tables.hpp) and exchange code (dist_device.hpp): every
+//       element of the O_in array holds its own O_in index; pack, chunk
+//       copies, unpack (per_chunk: one unpack per (src, dst) chunk); prints
+//       the chunk counts and the O_out array
 //
 // Built by tests/test_emu.py with g++ -fsanitize=address.
 #include "hip_emu.h"
@@ -31,6 +37,8 @@
 
 #include "fft_device.hpp"
 #include "many_device.hpp"
+#include "dist_device.hpp"
+#include "dist_tables.hpp"
 #include "emu_cases.inc"
 
 thread_local EmuDim threadIdx;
@@ -259,9 +267,108 @@ static int do_pass(int argc, char** argv) {
     return 0;
 }
 
+// Runs a kernel body for every (block, thread) of a grid, one at a time (the
+// exchange code has no barriers).
+static void run_grid(unsigned blocks, unsigned threads, const std::function<void()>& body) {
+    gridDim.x = blocks;
+    blockDim.x = threads;
+    for (unsigned b = 0; b < blocks; ++b) {
+        blockIdx.x = b;
+        for (unsigned t = 0; t < threads; ++t) {
+            threadIdx.x = t;
+            body();
+        }
+    }
+}
+
+static int do_route(int argc, char** argv) {
+    if (argc < 9) return 2;
+    const int64_t dims[3] = {atoll(argv[2]), atoll(argv[3]), atoll(argv[4])};
+    const int np = atoi(argv[5]), in_order = atoi(argv[6]), out_order = atoi(argv[7]);
+    const bool per_chunk = atoi(argv[8]) != 0;
+    std::vector<int64_t> st[3];
+    for (int o = 0; o < 3; ++o) {
+        st[o].resize(np + 1);
+        dist_line_starts(dims, o, np, st[o].data());
+    }
+    ExchangeTables t;
+    if (!build_exchange_tables(dims, np, in_order, out_order, st[in_order].data(), st[out_order].data(), &t)) {
+        std::printf("FAIL tables\n");
+        return 1;
+    }
+    const int64_t N = dims[0] * dims[1] * dims[2];
+    // exactly N elements per array: AddressSanitizer flags any access beyond
+    std::vector<double2> in(N), send(N), recv(N), out(N);
+    for (int64_t i = 0; i < N; ++i) {
+        in[i].x = (double)i;
+        in[i].y = 0.0;
+        out[i].x = -1.0;
+        out[i].y = 0.0;
+    }
+    RouteArgs r;
+    memset(&r, 0, sizeof r);
+    for (int i = 0; i < 3; ++i) {
+        r.in_n[i] = t.in_n[i];
+        r.out_n[i] = t.out_n[i];
+        r.in_ax[i] = t.in_ax[i];
+        r.out_ax[i] = t.out_ax[i];
+    }
+    r.sdispl = t.sdispl.data();
+    r.rdispl = t.rdispl.data();
+    r.klo = t.klo.data();
+    r.cnt = t.cnt.data();
+    r.pre = t.pre.data();
+    r.out_start = st[out_order].data();
+    r.base_mul = t.base_mul;
+    r.step = t.step;
+    r.nq = t.nq;
+    r.q_slowest = t.q_slowest;
+    r.np = np;
+    const unsigned blocks = 3;   // fewer blocks than lines: the grid-stride loop is exercised
+    for (int sp = 0; sp < np; ++sp) {
+        RouteArgs a = r;
+        a.from = in.data();
+        a.to = send.data();
+        a.src = sp;
+        a.dst_only = -1;
+        a.unpack = 0;
+        a.line_begin = st[in_order][sp];
+        a.line_end = st[in_order][sp + 1];
+        run_grid(blocks, kRouteThreads, [&] { route_lines<double2>(a); });
+    }
+    for (int sp = 0; sp < np; ++sp)
+        for (int d = 0; d < np; ++d) {
+            CopyDesc c;
+            c.from = t.sdispl[(size_t)sp * np + d];
+            c.to = t.rdispl[(size_t)d * np + sp];
+            c.n = t.count[(size_t)sp * np + d];
+            if (c.n) run_grid(2, kCopyThreads, [&] { copy_chunk(send.data(), recv.data(), c); });
+        }
+    for (int sp = 0; sp < np; ++sp)
+        for (int d = per_chunk ? 0 : -1; d < (per_chunk ? np : 0); ++d) {
+            RouteArgs a = r;
+            a.from = recv.data();
+            a.to = out.data();
+            a.src = sp;
+            a.dst_only = d;
+            a.unpack = 1;
+            a.line_begin = st[in_order][sp];
+            a.line_end = st[in_order][sp + 1];
+            run_grid(blocks, kRouteThreads, [&] { route_lines<double2>(a); });
+        }
+    std::printf("OK\n");
+    for (int sp = 0; sp < np; ++sp) {
+        for (int d = 0; d < np; ++d) std::printf("%lld ", (long long)t.count[(size_t)sp * np + d]);
+        std::printf("\n");
+    }
+    for (int64_t i = 0; i < N; ++i) std::printf("%lld\n", (long long)out[i].x);
+    return 0;
+}
+
 int main(int argc, char** argv) {
     if (argc < 3) return 2;
     const std::string mode = argv[1];
+    if (mode == "route") return do_route(argc, argv);
     const int dtype = atoi(argv[2]);
     if (mode == "many") return dtype == 0 ? do_many<double2>(argc, argv, false) : do_many<float2>(argc, argv, false);
     if (mode == "sync") return dtype == 0 ? do_many<double2>(argc, argv, true) : do_many<float2>(argc, argv, true);

@@ -97,6 +97,40 @@ def emu_binary():
     shutil.rmtree(build, ignore_errors=True)
 
 
+ORDER_NAMES = ["abc", "cab", "cba"]
+# the flow's four transposes: forward abc -> cab -> cba, backward cba -> cab -> abc
+TRANSPOSES = [(0, 1), (1, 2), (2, 1), (1, 0)]
+# (shape, Np): 1-D and 2-D decompositions, unit axes, Np not dividing the lengths
+ROUTE_CASES = [((8, 8, 8), 3), ((4, 6, 8), 5), ((4, 6, 8), 8), ((2, 12, 3), 6), ((1, 4, 6), 3), ((5, 1, 12), 4),
+               ((6, 10, 9), 4), ((3, 5, 7), 1)]
+
+
+@pytest.mark.parametrize("per_chunk", [0, 1], ids=["unpack_all", "unpack_per_chunk"])
+@pytest.mark.parametrize("tr", TRANSPOSES, ids=lambda t: f"{ORDER_NAMES[t[0]]}-{ORDER_NAMES[t[1]]}")
+@pytest.mark.parametrize("case", ROUTE_CASES, ids=lambda c: f"{'x'.join(map(str, c[0]))}-np{c[1]}")
+def test_emulated_distributed_exchange(emu_binary, case, tr, per_chunk):
+    """One exchange of the distributed flow with the library's own tables and
+    pack / copy / unpack code, under AddressSanitizer on exactly sized
+    arrays: every element lands where the reference oracle/dist.py puts it,
+    and the chunk sizes equal the reference's counts."""
+    from oracle import dist
+    shape, np_ = case
+    src_o, dst_o = ORDER_NAMES[tr[0]], ORDER_NAMES[tr[1]]
+    r = subprocess.run([emu_binary, "route", *map(str, shape), str(np_), str(tr[0]), str(tr[1]), str(per_chunk)],
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, (r.stdout[:500], r.stderr[-3000:])
+    lines = r.stdout.splitlines()
+    assert lines[0] == "OK"
+    counts = np.array([[int(v) for v in ln.split()] for ln in lines[1:1 + np_]])
+    out = np.array([int(v) for v in lines[1 + np_:]])
+    n = int(np.prod(shape))
+    code = np.arange(n, dtype=np.float64).astype(np.complex128)    # O_in index of every element
+    local = [code[s:e] for s, e in dist.blocks(shape, src_o, np_)]
+    want, m = dist.exchange(local, shape, src_o, dst_o, np_)
+    assert np.array_equal(out, dist.gather(want).real.astype(np.int64))
+    assert np.array_equal(counts, m)
+
+
 def lds_idx(j):
     return j + (j >> 4)
 
