@@ -122,6 +122,18 @@ def time_transform(n: int, dtype, steps: int, warmup: int, check: bool, tune: st
     ms = total_ms / steps
     N = x.numel()
     s = x.element_size()
+    # the transform just timed, checked before the copies below overwrite y
+    checked = {}
+    if check:
+        import oracle
+        xh = x.cpu().numpy().astype(np.complex128)
+        yh = y.cpu().numpy()
+        got, ref = [], []
+        for ka, kb in ((0, 0), (3, 5), (n - 1, 7)):
+            got.append(yh[ka, kb].astype(np.complex128))
+            ref.append(oracle.dft3_line(xh, ka, kb))
+        checked["check_rel_l2_sampled_lines"] = oracle.rel_l2(np.concatenate(got), np.concatenate(ref))
+        checked["check_tolerance"] = oracle.tolerance(N, dtype == torch.complex64)
     # the copy of each pass's own memory accesses (offt_copy_pass): the same
     # tiles, threads, tile order and access mode, no arithmetic
     copy_ms = []
@@ -147,16 +159,7 @@ def time_transform(n: int, dtype, steps: int, warmup: int, check: bool, tune: st
         "pass_bytes": 2 * N * s,
         "copy_ms": copy_ms,
     }
-    if check:
-        import oracle
-        xh = x.cpu().numpy().astype(np.complex128)
-        yh = y.cpu().numpy()
-        got, ref = [], []
-        for ka, kb in ((0, 0), (3, 5), (n - 1, 7)):
-            got.append(yh[ka, kb].astype(np.complex128))
-            ref.append(oracle.dft3_line(xh, ka, kb))
-        res["check_rel_l2_sampled_lines"] = oracle.rel_l2(np.concatenate(got), np.concatenate(ref))
-        res["check_tolerance"] = oracle.tolerance(N, dtype == torch.complex64)
+    res.update(checked)
     plan.close()
     del x, y
     torch.cuda.empty_cache()
@@ -1096,7 +1099,8 @@ def main():
     for key, r in (("check", r64), ("check_f32", r32)):
         if "check_rel_l2_sampled_lines" in r:
             out[key] = {"rel_l2_sampled_lines": r["check_rel_l2_sampled_lines"],
-                        "tolerance": r["check_tolerance"]}
+                        "tolerance": r["check_tolerance"],
+                        "ok": bool(r["check_rel_l2_sampled_lines"] <= r["check_tolerance"])}
     if not args.no_batch:
         out["small"] = time_small(args.steps, args.warmup, not args.no_check)
         out["batch"] = time_batch(args.steps, args.warmup, not args.no_check)
@@ -1108,6 +1112,10 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out), flush=True)
+    bad = [k for k in ("check", "check_f32") if k in out and not out[k]["ok"]]
+    if bad:
+        print(f"bench: the timed transform failed its check against the definition: {bad}", file=sys.stderr)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

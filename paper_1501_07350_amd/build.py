@@ -26,6 +26,11 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed fp32 ops disabled on purpose (see DESIGN notes on code generation)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fused within one source expression only, so that the
+    # rounding of a tile's arithmetic does not depend on the kernel it is
+    # inlined into (stand-alone passes and the batch executors give the same
+    # bits)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]

@@ -17,20 +17,26 @@
 //
 // One exchange (O_in -> O_out): each element of process src moves to the
 // process dst that owns its linear index in O_out.
-//   pack         src's elements, in src's local order, grouped by dst into
-//                consecutive chunks of src's send slice;
-//   communicate  chunk (src, dst) copied from src's send slice into dst's
-//                receive slice, chunks ordered by src -- the six methods of
-//                Sec. 3.2.1 are six ways of issuing and waiting for these
-//                copies;
-//   unpack       every received element written to its place in dst's
-//                local array (O_out order).
-// Chunk positions need no index table: along a line of O_in (its fastest
-// axis, k) the O_out line index is base + k*step, increasing, so the elements
-// of one line that go to one dst form one run [klo, klo + cnt); base depends
-// on one coordinate q of the line (the slowest or the middle one), so the
-// number of elements dst receives from the lines before line l is a closed
-// form over per-q counts and their prefix sums.
+//   pack         src's elements grouped by dst into consecutive chunks of
+//                src's send slice, each chunk in dst's O_out order (a tiled
+//                transpose through LDS); src's own chunk goes straight to
+//                its place in the receive array -- or into the O_out array
+//                itself when src receives nothing from anyone else;
+//   communicate  chunk (src, dst), src != dst, copied from src's send slice
+//                into dst's receive slice, chunks ordered by src -- the six
+//                methods of Sec. 3.2.1 are six ways of issuing and waiting
+//                for these copies;
+//   unpack       dst's O_out lines filled from the received chunks: every
+//                line is a sequence of runs, one per sending process, each a
+//                contiguous piece of that process's chunk.
+// Positions need no index table: along an O_out line (its fastest axis, k')
+// the O_in line index is base + k'*step, increasing, so the elements of one
+// O_out line that come from one process form one run; base depends on one
+// coordinate q of the line, so the number of elements a process contributes
+// to the lines before line m is a closed form over per-q counts and their
+// prefix sums (the tables of the reverse exchange O_out -> O_in).  The
+// chunk sizes (the elements each process sends each other one) come from
+// the same construction in the forward direction.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -50,12 +56,18 @@ namespace offt {
 
 constexpr int kDistMaxProcs = 64;
 constexpr int kDistMethods = 6;
-constexpr int kRouteMaxBlocks = 16384;
+constexpr int kGatherMaxBlocks = 16384;
 
 // The kernels of one exchange (device code in dist_device.hpp).
 template <typename V>
-__global__ void __launch_bounds__(kRouteThreads) route_kernel(RouteArgs r) {
-    route_lines<V>(r);
+__global__ void __launch_bounds__(kPackThreads) pack_kernel(PackArgs a) {
+    __shared__ V tile[kPackTile][kPackTile + 1];
+    pack_tile<V>(a, tile);
+}
+
+template <typename V>
+__global__ void __launch_bounds__(kGatherThreads) gather_kernel(GatherArgs a) {
+    gather_lines<V>(a);
 }
 
 template <typename V>
@@ -84,7 +96,9 @@ struct Exchange {
     int in_order = 0, out_order = 0;
     std::vector<int64_t> count;        // [src * np + dst]
     std::vector<int64_t> sdispl, rdispl;
-    RouteArgs base{};                  // device table pointers and shape fields
+    std::vector<char> direct;          // [proc]: proc receives only from itself (its pack writes O_out)
+    PackArgs pack{};                   // device table pointers and shape fields
+    GatherArgs gather{};
     int64_t max_chunk = 0;
     // device descriptors of the chunk copies, per launch of each method
     CopyDesc* d_desc = nullptr;
@@ -140,39 +154,59 @@ static int build_exchange(offt_plan_s* p, DistState* ds, int in_order, int out_o
     const int np = ds->np;
     ex->in_order = in_order;
     ex->out_order = out_order;
-    ExchangeTables t;
-    if (!build_exchange_tables(p->dims, np, in_order, out_order, ds->line_start[in_order], ds->line_start[out_order],
-                               &t))
+    const int64_t* in_start = ds->line_start[in_order];
+    const int64_t* out_start = ds->line_start[out_order];
+    ExchangeTables t, rev;
+    if (!build_exchange_tables(p->dims, np, in_order, out_order, in_start, out_start, &t) ||
+        !build_exchange_tables(p->dims, np, out_order, in_order, out_start, in_start, &rev))
         return OFFT_ERR_BAD_PLAN;
+    // the pack's tiles run along the O_in axis that is O_out's fastest
+    const int u_axis = t.out_ax[2];
+    if (u_axis != t.in_ax[0] && u_axis != t.in_ax[1]) return OFFT_ERR_BAD_PLAN;
     ex->count = t.count;
     ex->sdispl = t.sdispl;
     ex->rdispl = t.rdispl;
     ex->max_chunk = t.max_chunk;
-    RouteArgs& r = ex->base;
-    memset(&r, 0, sizeof r);
+    ex->direct.assign(np, 0);
+    for (int d = 0; d < np; ++d)
+        ex->direct[d] = t.count[(size_t)d * np + d] == (out_start[d + 1] - out_start[d]) * t.out_n[2];
+    ReverseTables rt;
+    memset(&rt, 0, sizeof rt);
+    rt.nm = rev.in_n[1];
+    rt.base_mul = rev.base_mul;
+    rt.step = rev.step;
+    rt.nq = rev.nq;
+    rt.q_slowest = rev.q_slowest;
+    std::vector<int64_t> is(in_start, in_start + np + 1), os(out_start, out_start + np + 1);
+    int rc = upload(p, rev.klo, &rt.klo, s);
+    if (!rc) rc = upload(p, rev.cnt, &rt.cnt, s);
+    if (!rc) rc = upload(p, rev.pre, &rt.pre, s);
+    if (!rc) rc = upload(p, is, &rt.in_start, s);
+    PackArgs& pa = ex->pack;
+    memset(&pa, 0, sizeof pa);
+    pa.rev = rt;
     for (int i = 0; i < 3; ++i) {
-        r.in_n[i] = t.in_n[i];
-        r.out_n[i] = t.out_n[i];
-        r.in_ax[i] = t.in_ax[i];
-        r.out_ax[i] = t.out_ax[i];
+        pa.in_n[i] = t.in_n[i];
+        pa.out_n[i] = t.out_n[i];
+        pa.in_ax[i] = t.in_ax[i];
+        pa.out_ax[i] = t.out_ax[i];
     }
-    r.base_mul = t.base_mul;
-    r.step = t.step;
-    r.nq = t.nq;
-    r.q_slowest = t.q_slowest;
-    r.np = np;
-    const int64_t* out_start = ds->line_start[out_order];
-    int rc = upload(p, t.klo, &r.klo, s);
-    if (!rc) rc = upload(p, t.cnt, &r.cnt, s);
-    if (!rc) rc = upload(p, t.pre, &r.pre, s);
-    if (!rc) rc = upload(p, t.sdispl, &r.sdispl, s);
-    if (!rc) rc = upload(p, t.rdispl, &r.rdispl, s);
-    std::vector<int64_t> os(out_start, out_start + np + 1);
-    if (!rc) rc = upload(p, os, &r.out_start, s);
+    pa.u_slowest = u_axis == t.in_ax[0] ? 1 : 0;
+    pa.np = np;
+    GatherArgs& ga = ex->gather;
+    memset(&ga, 0, sizeof ga);
+    ga.rev = rt;
+    ga.nf = t.out_n[2];
+    ga.np = np;
+    if (!rc) rc = upload(p, t.sdispl, &pa.sdispl, s);
+    if (!rc) rc = upload(p, os, &pa.out_start, s);
+    if (!rc) rc = upload(p, t.rdispl, &ga.rdispl, s);
     if (rc) return rc;
     // copy descriptors, laid out per method so that each launch covers
-    // consecutive descriptors; empty chunks are not sent
+    // consecutive descriptors; empty chunks and a process's own chunk are
+    // not sent
     std::vector<CopyDesc> desc;
+    auto sent = [&](int sp, int d) { return sp != d && ex->count[(size_t)sp * np + d] != 0; };
     auto chunk = [&](int sp, int d) {
         CopyDesc c;
         c.from = ex->sdispl[(size_t)sp * np + d];
@@ -184,7 +218,7 @@ static int build_exchange(offt_plan_s* p, DistState* ds, int in_order, int out_o
     const int ngroups = (np + B - 1) / B;
     for (int m = 0; m < kDistMethods; ++m) {
         auto one = [&](int sp, int d) {
-            if (ex->count[(size_t)sp * np + d] == 0) return;
+            if (!sent(sp, d)) return;
             ex->launches[m].push_back({(int)desc.size(), 1, sp, d});
             desc.push_back(chunk(sp, d));
         };
@@ -197,7 +231,7 @@ static int build_exchange(offt_plan_s* p, DistState* ds, int in_order, int out_o
             const int first = (int)desc.size();
             for (int sp = 0; sp < np; ++sp)
                 for (int d = 0; d < np; ++d)
-                    if (ex->count[(size_t)sp * np + d]) desc.push_back(chunk(sp, d));
+                    if (sent(sp, d)) desc.push_back(chunk(sp, d));
             if ((int)desc.size() > first) ex->launches[m].push_back({first, (int)desc.size() - first, -1, -1});
         } else if (m == OFFT_COMM_ISEND_WAITALL_BLOCK || m == OFFT_COMM_ISEND_WAITSOME_BLOCK) {
             // group g: every process exchanges with the processes of group g
@@ -207,17 +241,19 @@ static int build_exchange(offt_plan_s* p, DistState* ds, int in_order, int out_o
                 ex->group_end[m].push_back((int)ex->launches[m].size());
             }
         } else {
-            // step i: process myid sends to myid + i and receives from myid - i
-            for (int i = 0; i < np; ++i) {
+            // step i >= 1: process myid sends to myid + i and receives from
+            // myid - i (step 0, the own chunk, needs no copy)
+            for (int i = 1; i < np; ++i) {
                 const int first = (int)desc.size();
                 for (int sp = 0; sp < np; ++sp) {
                     const int d = (sp + i) % np;
-                    if (ex->count[(size_t)sp * np + d]) desc.push_back(chunk(sp, d));
+                    if (sent(sp, d)) desc.push_back(chunk(sp, d));
                 }
                 if ((int)desc.size() > first) ex->launches[m].push_back({first, (int)desc.size() - first, -1, i});
             }
         }
     }
+    if (desc.empty()) return OFFT_SUCCESS;   // every process keeps its data
     const CopyDesc* dd = nullptr;
     rc = upload(p, desc, &dd, s);
     ex->d_desc = const_cast<CopyDesc*>(dd);
@@ -236,26 +272,58 @@ void release_dist(offt_plan_s* p) {
     p->dist = nullptr;
 }
 
-// Pack or unpack launch for the lines of process sp (dst_only: one
-// destination, -1 every one).
-static hipError_t launch_route(const offt_plan_s* p, const Exchange& ex, int sp, int dst_only, bool unpack,
-                               const void* from, void* to, hipStream_t s) {
+// Pack of process sp: its O_in lines of `from` into the send array (chunks to
+// the others) and its own chunk into `self`.
+static hipError_t launch_pack(const offt_plan_s* p, const Exchange& ex, int sp, const void* from, void* self,
+                              hipStream_t s) {
     const DistState* ds = p->dist;
-    RouteArgs r = ex.base;
-    r.from = from;
-    r.to = to;
-    r.src = sp;
-    r.dst_only = dst_only;
-    r.unpack = unpack ? 1 : 0;
-    r.line_begin = ds->line_start[ex.in_order][sp];
-    r.line_end = ds->line_start[ex.in_order][sp + 1];
-    const int64_t lines = r.line_end - r.line_begin;
-    if (lines <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)std::min<int64_t>(lines, kRouteMaxBlocks);
+    PackArgs a = ex.pack;
+    a.from = from;
+    a.send = ds->send;
+    a.self = self;
+    a.src = sp;
+    a.line_begin = ds->line_start[ex.in_order][sp];
+    a.line_end = ds->line_start[ex.in_order][sp + 1];
+    if (a.line_end <= a.line_begin) return hipSuccess;
+    const int64_t nm = a.in_n[1];
+    const int64_t lo = a.line_begin / nm, hi = (a.line_end - 1) / nm + 1;   // slowest coordinates of the lines
+    if (a.u_slowest) {
+        a.u_lo = lo; a.u_n = hi - lo;
+        a.v_lo = 0;  a.v_n = nm;
+    } else {
+        a.v_lo = lo; a.v_n = hi - lo;
+        a.u_lo = 0;  a.u_n = nm;
+    }
+    a.u_tiles = (a.u_n + kPackTile - 1) / kPackTile;
+    a.k_tiles = (a.in_n[2] + kPackTile - 1) / kPackTile;
+    const int64_t blocks = a.v_n * a.u_tiles * a.k_tiles;
+    if (blocks >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     if (p->dtype == OFFT_C2C_F64)
-        hipLaunchKernelGGL(route_kernel<double2>, dim3(blocks), dim3(kRouteThreads), 0, s, r);
+        hipLaunchKernelGGL(pack_kernel<double2>, dim3((unsigned)blocks), dim3(kPackThreads), 0, s, a);
     else
-        hipLaunchKernelGGL(route_kernel<float2>, dim3(blocks), dim3(kRouteThreads), 0, s, r);
+        hipLaunchKernelGGL(pack_kernel<float2>, dim3((unsigned)blocks), dim3(kPackThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+// Unpack of process d's O_out lines from the receive array into `to`; src
+// >= 0: the chunk from that process only.
+static hipError_t launch_unpack(const offt_plan_s* p, const Exchange& ex, int d, int src, void* to, hipStream_t s) {
+    const DistState* ds = p->dist;
+    GatherArgs a = ex.gather;
+    a.recv = ds->recv;
+    a.to = to;
+    a.dst = d;
+    a.src_only = src;
+    a.line_begin = ds->line_start[ex.out_order][d];
+    a.line_end = ds->line_start[ex.out_order][d + 1];
+    const int64_t lines = a.line_end - a.line_begin;
+    if (lines <= 0) return hipSuccess;
+    constexpr int kWaves = kGatherThreads / 64;
+    const unsigned blocks = (unsigned)std::min<int64_t>((lines + kWaves - 1) / kWaves, kGatherMaxBlocks);
+    if (p->dtype == OFFT_C2C_F64)
+        hipLaunchKernelGGL(gather_kernel<double2>, dim3(blocks), dim3(kGatherThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(gather_kernel<float2>, dim3(blocks), dim3(kGatherThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -275,17 +343,30 @@ static hipError_t launch_copies(const offt_plan_s* p, const Exchange& ex, const 
 }
 
 // One exchange with the plan's method: pack every process's chunks, run the
-// method's copies and waits, unpack into `to` (the global O_out array).
+// method's copies and waits, unpack into `to` (the global O_out array;
+// `from` and `to` are different arrays).
 static int run_exchange(const offt_plan_s* p, const Exchange& ex, int method, const void* from, void* to,
                         hipStream_t s) {
     DistState* ds = p->dist;
     const int np = ds->np;
-    for (int sp = 0; sp < np; ++sp)
-        if (launch_route(p, ex, sp, -1, false, from, ds->send, s) != hipSuccess) return OFFT_ERR_HIP;
+    const size_t es = elem_size(p->dtype);
+    for (int sp = 0; sp < np; ++sp) {
+        // the own chunk: into the receive array, or straight into O_out
+        void* self = ex.direct[sp] ? static_cast<char*>(to) + ds->line_start[ex.out_order][sp] * ex.gather.nf * es
+                                   : static_cast<char*>(ds->recv) + ex.rdispl[(size_t)sp * np + sp] * es;
+        if (launch_pack(p, ex, sp, from, self, s) != hipSuccess) return OFFT_ERR_HIP;
+    }
     const auto& L = ex.launches[method];
     auto unpack_all = [&]() -> int {
-        for (int sp = 0; sp < np; ++sp)
-            if (launch_route(p, ex, sp, -1, true, ds->recv, to, s) != hipSuccess) return OFFT_ERR_HIP;
+        for (int d = 0; d < np; ++d)
+            if (!ex.direct[d] && launch_unpack(p, ex, d, -1, to, s) != hipSuccess) return OFFT_ERR_HIP;
+        return OFFT_SUCCESS;
+    };
+    // own chunks that are not already in place
+    auto unpack_own = [&]() -> int {
+        for (int d = 0; d < np; ++d)
+            if (!ex.direct[d] && ex.count[(size_t)d * np + d] && launch_unpack(p, ex, d, d, to, s) != hipSuccess)
+                return OFFT_ERR_HIP;
         return OFFT_SUCCESS;
     };
     // the communication stream starts after the packs
@@ -301,23 +382,26 @@ static int run_exchange(const offt_plan_s* p, const Exchange& ex, int method, co
         return unpack_all();
     }
     if (method == OFFT_COMM_SENDRECV) {
-        // Np steps, each a blocking exchange with one partner; the received
-        // chunk is unpacked before the next step
+        // Np - 1 steps after the own chunk, each a blocking exchange with one
+        // partner; the received chunk is unpacked before the next step
+        int rc = unpack_own();
         for (const auto& l : L) {
+            if (rc) return rc;
             if (launch_copies(p, ex, l, s) != hipSuccess) return OFFT_ERR_HIP;
             for (int sp = 0; sp < np; ++sp) {
                 const int d = (sp + l.dst) % np;
-                if (ex.count[(size_t)sp * np + d] &&
-                    launch_route(p, ex, sp, d, true, ds->recv, to, s) != hipSuccess)
+                if (sp != d && ex.count[(size_t)sp * np + d] && launch_unpack(p, ex, d, sp, to, s) != hipSuccess)
                     return OFFT_ERR_HIP;
             }
         }
-        return OFFT_SUCCESS;
+        return rc;
     }
     const bool some = method == OFFT_COMM_ISEND_WAITSOME || method == OFFT_COMM_ISEND_WAITSOME_BLOCK;
     const bool block = method == OFFT_COMM_ISEND_WAITALL_BLOCK || method == OFFT_COMM_ISEND_WAITSOME_BLOCK;
     std::vector<int> ends = block ? ex.group_end[method] : std::vector<int>{(int)L.size()};
     int rc = fork();
+    // Waitsome: the own chunks are complete once packed
+    if (rc == OFFT_SUCCESS && some) rc = unpack_own();
     int first = 0;
     for (int g = 0; g < (int)ends.size() && rc == OFFT_SUCCESS; ++g) {
         // the group's sends and receives are posted at once on the
@@ -333,7 +417,7 @@ static int run_exchange(const offt_plan_s* p, const Exchange& ex, int method, co
             for (int i = first; i < ends[g] && rc == OFFT_SUCCESS; ++i) {
                 const auto& l = L[i];
                 if (hipStreamWaitEvent(s, ds->ev_chunk[(size_t)l.src * np + l.dst], 0) != hipSuccess ||
-                    launch_route(p, ex, l.src, l.dst, true, ds->recv, to, s) != hipSuccess)
+                    launch_unpack(p, ex, l.dst, l.src, to, s) != hipSuccess)
                     rc = OFFT_ERR_HIP;
             }
             // the next group is posted once this one is complete
@@ -416,25 +500,28 @@ int exec_dist(const offt_plan_s* p, int dir, int steps, const void* in, void* ou
     const int ord[3] = {bwd ? kCba : kAbc, kCab, bwd ? kAbc : kCba};
     const Exchange* ex = bwd ? ds->bwd : ds->fwd;
     void* work = ds->work;
+    if (in == work || out == work) return OFFT_ERR_INVALID_ARG;
     // a partial backward flow ends with its data still conjugated
     auto done = [&](int rc) { return rc == OFFT_SUCCESS && bwd && steps < 5 ? conj_in_place(p, out, N, s) : rc; };
-    int rc = OFFT_SUCCESS;
-    // step 1: lines of the first order, in -> (work, or out when it is the last step)
-    void* t1 = steps == 1 ? out : work;
-    rc = run_lines(p, ord[0], in, t1, bwd, 0, 1.0, s);
+    // buffers: each exchange goes from one of out / work to the other (the
+    // pack cannot run in place), chosen so that the last step ends in out
+    void* b1 = (steps == 1 || steps == 4) ? out : work;   // after step 1
+    void* b2 = b1 == work ? out : work;                   // after steps 2 and 3
+    void* b3 = b2 == work ? out : work;                   // after step 4
+    // step 1: lines of the first order
+    int rc = run_lines(p, ord[0], in, b1, bwd, 0, 1.0, s);
     if (rc || steps == 1) return done(rc);
-    // step 2: exchange to the middle order, into work (or out)
-    void* t2 = steps <= 3 ? out : work;
-    rc = run_exchange(p, ex[0], method, work, t2, s);
+    // step 2: exchange to the middle order
+    rc = run_exchange(p, ex[0], method, b1, b2, s);
     if (rc || steps == 2) return done(rc);
     // step 3: lines of the middle order, in place
-    rc = run_lines(p, ord[1], t2, t2, 0, 0, 1.0, s);
+    rc = run_lines(p, ord[1], b2, b2, 0, 0, 1.0, s);
     if (rc || steps == 3) return done(rc);
-    // step 4: exchange to the last order, into out
-    rc = run_exchange(p, ex[1], method, work, out, s);
+    // step 4: exchange to the last order
+    rc = run_exchange(p, ex[1], method, b2, b3, s);
     if (rc || steps == 4) return done(rc);
-    // step 5: lines of the last order, in place
-    return run_lines(p, ord[2], out, out, 0, bwd, scale, s);
+    // step 5: lines of the last order, into out
+    return run_lines(p, ord[2], b3, out, 0, bwd, scale, s);
 }
 
 // Time of one forward flow with `method` (1 warm-up + reps timed runs,

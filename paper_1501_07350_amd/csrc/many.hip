@@ -15,6 +15,7 @@
 
 #include "../../include/offt.h"
 #include "many_device.hpp"
+#include "many_tables.hpp"
 #include "offt_internal.h"
 #include "plan_impl.h"
 #include "selector.h"
@@ -30,7 +31,6 @@ __global__ void many_reset_kernel(unsigned* counters, int n) {
     for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) counters[i] = 0u;
 }
 
-constexpr int kManyThreads = 512;          // workgroup size of the persistent kernel
 constexpr int kManySpinLimit = 1 << 22;    // polls (~2 s) before a wait gives up and flags an error
 constexpr int64_t kAlignBytes = 256;       // every grid starts on a 256-byte boundary
 
@@ -69,6 +69,8 @@ struct ManyState {
     // level-synchronous persistent form: (level, case) groups and its graph
     ManyGroup* d_groups = nullptr;
     int* d_gseg = nullptr;
+    ManyRange* d_ranges = nullptr;
+    int ncases = 0;
     int sync_nblocks = 0;
     hipGraph_t sgraph = nullptr;
     hipGraphExec_t sgexec = nullptr;
@@ -135,119 +137,49 @@ static int dev_alloc(offt_plan_s* p, size_t bytes, void** out) {
     return OFFT_SUCCESS;
 }
 
-// LDS per workgroup of the batch executors: three fit in a CU's 160 KiB (the
-// level kernels' 65 registers allow three 512-thread workgroups per CU; on 64
-// uneven complex64 grids 52 KiB beat 80 KiB by 16% and 40 KiB by 2%)
-constexpr int64_t kManyLdsBudget = 52 * 1024;
-constexpr int kTilesPerItem = 4;
-
-// Tile width of a pass inside the batch executors: as many lines as fill the
-// kManyThreads threads, within the LDS budget (three workgroups per CU).
-static int many_logW(const PassPlan& pp, int dtype) {
-    const int64_t es = (int64_t)elem_size(dtype);
-    int lw = 0;
-    while ((int64_t(2) << lw) * pp.k->tpl <= kManyThreads &&
-           tile_lds_elems(2 << lw, pp.L) * es <= std::min(kManyLdsBudget, lds_limit()))
-        ++lw;
-    return lw;
-}
 
 static int build_many(offt_plan_s* p, hipStream_t s) {
     ManyState* m = p->many;
     const int dtype = p->dtype;
     const size_t es = elem_size(dtype);
-    // segments: level-major, then grid order
-    std::vector<ManySeg> segs;
-    std::vector<int> seg_of(m->count * 3, -1);
-    size_t lds_max = 0;
     m->exec = pick_executor(m, dtype);
     m->persistent_ok = m->exec != nullptr;
     if (!m->exec) m->why_not = "an axis length outside the persistent executor's set {48,60,64,80,96,120,128,150,160}";
-    for (int lvl = 0; lvl < 3; ++lvl) {
-        for (int g = 0; g < m->count; ++g) {
-            ManyGrid& G = m->grids[g];
-            if (lvl >= G.ntuned) continue;
-            const PassPlan& pp = G.tuned[lvl];
-            ManySeg sg;
-            memset(&sg, 0, sizeof sg);
-            sg.elem_off = G.off;
-            sg.nlines = pp.M1 * pp.M2;
-            sg.M2 = pp.M2;
-            sg.tw = pp.tw;
-            sg.scale_bwd = p->normalize ? 1.0 / (double)(G.dims[0] * G.dims[1] * G.dims[2]) : 1.0;
-            sg.kid = m->exec ? find_case(m->exec, pp.k) : -1;
-            sg.logW = many_logW(pp, dtype);
-            sg.mode = pp.mode;
-            const int64_t W = int64_t(1) << sg.logW;
-            sg.ntiles = (int)((sg.nlines + W - 1) / W);
-            sg.tiles_per_item = kTilesPerItem;
-            sg.nitems = (sg.ntiles + kTilesPerItem - 1) / kTilesPerItem;
-            sg.first = lvl == 0;
-            sg.last = lvl == G.ntuned - 1;
-            sg.dep = lvl > 0 ? seg_of[(lvl - 1) * m->count + g] : -1;
-            seg_of[lvl * m->count + g] = (int)segs.size();
-            lds_max = std::max(lds_max, (size_t)tile_lds_elems((int)W, pp.L) * es);
-            segs.push_back(sg);
+    // segments, tiles and work items (many_tables.hpp, shared with the CPU
+    // emulation of the executors)
+    std::vector<ManyGridDesc> gd(m->count);
+    for (int g = 0; g < m->count; ++g) {
+        const ManyGrid& G = m->grids[g];
+        gd[g].elem_off = G.off;
+        gd[g].scale_bwd = p->normalize ? 1.0 / (double)(G.dims[0] * G.dims[1] * G.dims[2]) : 1.0;
+        for (int i = 0; i < G.ntuned; ++i) {
+            const PassPlan& pp = G.tuned[i];
+            gd[g].passes.push_back({pp.L, pp.M1 * pp.M2, pp.M2, pp.mode, pp.k->tpl,
+                                    m->exec ? find_case(m->exec, pp.k) : -1, pp.tw});
         }
     }
-    int64_t items = 0;
-    std::vector<int> seg_level;
-    for (int lvl = 0; lvl < 3; ++lvl)
-        for (int g = 0; g < m->count; ++g)
-            if (seg_of[lvl * m->count + g] >= 0) seg_level.push_back(lvl);
-    int64_t tiles = 0;
-    int lv = 0;
-    for (size_t i = 0; i < segs.size(); ++i) {
-        while (lv < seg_level[i]) {
-            ++lv;
-            m->level_begin[lv] = items;
-            m->level_tile_begin[lv] = tiles;
-        }
-        segs[i].item_base = items;
-        segs[i].tile_base = tiles;
-        items += segs[i].nitems;
-        tiles += segs[i].ntiles;
-    }
-    while (lv < 3) {
-        ++lv;
-        m->level_begin[lv] = items;
-        m->level_tile_begin[lv] = tiles;
+    ManyTables tab;
+    build_many_tables(gd, (int64_t)es, kManyThreads, std::min(kManyLdsBudget, lds_limit()), kTilesPerItem, &tab);
+    m->ncases = m->exec ? m->exec->ncases : 0;
+    if (m->exec) build_many_groups(&tab, m->ncases);
+    std::vector<ManySeg>& segs = tab.segs;
+    const int64_t items = tab.total_items;
+    const size_t lds_max = tab.lds_bytes;
+    for (int l = 0; l < 4; ++l) {
+        m->level_begin[l] = tab.level_begin[l];
+        m->level_tile_begin[l] = tab.level_tile_begin[l];
     }
     m->nseg = (int)segs.size();
     m->total_items = items;
     if (items >= (int64_t(1) << 31)) { m->persistent_ok = false; m->why_not = "too many work items"; }
     if (m->nseg == 0) return OFFT_SUCCESS;   // all grids 1x1x1: copies only
-    // (level, case) groups of the level-synchronous form: segments of each
-    // group in grid order, tiles numbered within the group, and per group the
-    // tiles of the earlier groups of its level (dealing continues across groups)
-    const int ncases = m->exec ? m->exec->ncases : 0;
-    std::vector<ManyGroup> groups((size_t)3 * ncases);
-    std::vector<int> gseg;
-    if (m->exec) {
-        for (int lvl = 0; lvl < 3; ++lvl) {
-            int64_t rot = 0;
-            for (int c = 0; c < ncases; ++c) {
-                ManyGroup& gr = groups[(size_t)lvl * ncases + c];
-                gr.seg_begin = (int)gseg.size();
-                gr.ntiles = 0;
-                gr.rot = rot;
-                for (size_t i = 0; i < segs.size(); ++i) {
-                    if (seg_level[i] != lvl || segs[i].kid != c) continue;
-                    segs[i].group_tile_base = gr.ntiles;
-                    gr.ntiles += segs[i].ntiles;
-                    gseg.push_back((int)i);
-                }
-                gr.seg_end = (int)gseg.size();
-                rot += gr.ntiles;
-            }
-        }
-    }
     void* d = nullptr;
     int rc = dev_alloc(p, sizeof(ManySeg) * segs.size(), &d);
     if (rc) return rc;
     m->d_segs = static_cast<ManySeg*>(d);
-    // counters: queue head, error flag, one per segment, two level barriers
-    const size_t ncnt = kManyCounterBase + segs.size() + 2;
+    // counters: queue head, error flag, one per segment, then the
+    // level-synchronous form's two level barriers and level queues
+    const size_t ncnt = kManyCounterBase + segs.size() + kManySyncCounters;
     rc = dev_alloc(p, sizeof(unsigned) * ncnt, &d);
     if (rc) return rc;
     m->d_counters = static_cast<unsigned*>(d);
@@ -255,17 +187,22 @@ static int build_many(offt_plan_s* p, hipStream_t s) {
             hipSuccess ||
         hipMemsetAsync(m->d_counters, 0, sizeof(unsigned) * ncnt, s) != hipSuccess)
         return OFFT_ERR_HIP;
-    if (!groups.empty()) {
-        rc = dev_alloc(p, sizeof(ManyGroup) * groups.size(), &d);
+    if (!tab.groups.empty()) {
+        rc = dev_alloc(p, sizeof(ManyGroup) * tab.groups.size(), &d);
         if (rc) return rc;
         m->d_groups = static_cast<ManyGroup*>(d);
-        rc = dev_alloc(p, sizeof(int) * std::max<size_t>(gseg.size(), 1), &d);
+        rc = dev_alloc(p, sizeof(int) * std::max<size_t>(tab.gseg.size(), 1), &d);
         if (rc) return rc;
         m->d_gseg = static_cast<int*>(d);
-        if (hipMemcpyAsync(m->d_groups, groups.data(), sizeof(ManyGroup) * groups.size(), hipMemcpyHostToDevice,
-                           s) != hipSuccess ||
-            (!gseg.empty() && hipMemcpyAsync(m->d_gseg, gseg.data(), sizeof(int) * gseg.size(),
-                                             hipMemcpyHostToDevice, s) != hipSuccess))
+        rc = dev_alloc(p, sizeof(ManyRange) * tab.ranges.size(), &d);
+        if (rc) return rc;
+        m->d_ranges = static_cast<ManyRange*>(d);
+        if (hipMemcpyAsync(m->d_groups, tab.groups.data(), sizeof(ManyGroup) * tab.groups.size(),
+                           hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(m->d_ranges, tab.ranges.data(), sizeof(ManyRange) * tab.ranges.size(),
+                           hipMemcpyHostToDevice, s) != hipSuccess ||
+            (!tab.gseg.empty() && hipMemcpyAsync(m->d_gseg, tab.gseg.data(), sizeof(int) * tab.gseg.size(),
+                                                 hipMemcpyHostToDevice, s) != hipSuccess))
             return OFFT_ERR_HIP;
     }
     if (!m->persistent_ok) return OFFT_SUCCESS;
@@ -386,13 +323,15 @@ static ManySyncArgs make_sync_args(const ManyState* m) {
     memset(&g, 0, sizeof g);
     g.groups = m->d_groups;
     g.gseg = m->d_gseg;
+    g.ranges = m->d_ranges;
     g.barrier = m->d_counters + kManyCounterBase + m->nseg;
-    g.ncases = m->exec->ncases;
+    g.queue = g.barrier + 2;
+    g.ncases = m->ncases;
     return g;
 }
 
 static int launch_sync(ManyState* m, const void* in, void* out, int dir, hipStream_t s) {
-    const int ncnt = kManyCounterBase + m->nseg + 2;
+    const int ncnt = kManyCounterBase + m->nseg + kManySyncCounters;
     hipLaunchKernelGGL(many_reset_kernel, dim3(1), dim3(256), 0, s, m->d_counters, ncnt);
     if (hipGetLastError() != hipSuccess) return OFFT_ERR_HIP;
     ManyArgs a = make_args(m, in, out, dir);
@@ -420,7 +359,7 @@ static int sync_graph_launch(ManyState* m, const void* in, void* out, int dir, h
     };
     if (!m->sgraph_ready) {
         if (hipGraphCreate(&m->sgraph, 0) != hipSuccess) return OFFT_ERR_HIP;
-        int ncnt = kManyCounterBase + m->nseg + 2;
+        int ncnt = kManyCounterBase + m->nseg + kManySyncCounters;
         unsigned* cnt = m->d_counters;
         void* rparams[] = {&cnt, &ncnt};
         hipKernelNodeParams rp;

@@ -1,0 +1,164 @@
+// many_tables.hpp -- host-side work-item tables of the uneven-batch
+// executors (many.hip): segments (one per grid and pass level), their tile
+// widths, tile and work-item numbering, level boundaries and the launch's
+// dynamic LDS.  Plain C++ over the device structs of many_device.hpp, so the
+// library and the CPU emulation of the executors build the same tables.
+#pragma once
+
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "many_device.hpp"
+
+namespace offt {
+
+constexpr int kManyThreads = 512;   // workgroup size of every executor kernel
+// LDS per workgroup of the executors: three fit in a CU's 160 KiB (the level
+// kernels' 65 registers allow three 512-thread workgroups per CU; on 64
+// uneven complex64 grids 52 KiB beat 80 KiB by 16% and 40 KiB by 2%)
+constexpr int64_t kManyLdsBudget = 52 * 1024;
+constexpr int kTilesPerItem = 4;    // tiles of one work item of the queue-based persistent kernel
+
+// One axis pass of one grid, as the executors see it.
+struct ManyPassDesc {
+    int L;                // line length
+    int64_t nlines;       // lines of the pass (M1 * M2)
+    int64_t M2;           // element stride of the axis
+    int mode;             // 0 contiguous lines, 1 strided lines
+    int tpl;              // threads per line of the kernel case
+    int kid;              // kernel case in the executor's dispatch table (-1: none)
+    const void* tw;       // twiddle table of L
+};
+
+struct ManyGridDesc {
+    int64_t elem_off;                   // element offset in the packed buffer
+    double scale_bwd;                   // scale of the last pass of a backward transform
+    std::vector<ManyPassDesc> passes;   // in pass order
+};
+
+struct ManyTables {
+    std::vector<ManySeg> segs;          // level-major, grid order within a level
+    int64_t level_begin[4] = {0, 0, 0, 0};        // work items of level l: [level_begin[l], level_begin[l+1])
+    int64_t level_tile_begin[4] = {0, 0, 0, 0};   // tiles of level l (level kernels and queues)
+    int64_t total_items = 0;
+    size_t lds_bytes = 0;               // dynamic LDS of the launch: the largest tile
+    std::vector<int> seg_level;         // pass level of each segment
+    // level-synchronous form: (level, case) groups of segments in grid order
+    // (build_many_groups), tiles numbered within a group
+    std::vector<ManyGroup> groups;      // [level * ncases + case]
+    std::vector<int> gseg;
+    std::vector<ManyRange> ranges;      // [(level * kXcds + x) * ncases + case]
+};
+
+// Counters of the level-synchronous form after the segment counters: two
+// level barriers, then one queue per level and XCD range.
+constexpr int kManySyncCounters = 2 + 3 * kXcds;
+
+// Tile width of a pass inside the executors: as many lines as fill `threads`
+// threads, within `lds_budget` bytes of LDS.
+inline int many_tile_logW(const ManyPassDesc& p, int64_t elem_bytes, int threads, int64_t lds_budget) {
+    int lw = 0;
+    while ((int64_t(2) << lw) * p.tpl <= threads && tile_lds_elems(2 << lw, p.L) * elem_bytes <= lds_budget) ++lw;
+    return lw;
+}
+
+inline void build_many_tables(const std::vector<ManyGridDesc>& grids, int64_t elem_bytes, int threads,
+                              int64_t lds_budget, int tiles_per_item, ManyTables* t) {
+    const int count = (int)grids.size();
+    std::vector<int> seg_of((size_t)count * 3, -1), seg_level;
+    t->segs.clear();
+    t->lds_bytes = 0;
+    for (int lvl = 0; lvl < 3; ++lvl) {
+        for (int g = 0; g < count; ++g) {
+            const ManyGridDesc& G = grids[g];
+            if (lvl >= (int)G.passes.size()) continue;
+            const ManyPassDesc& pp = G.passes[lvl];
+            ManySeg sg;
+            memset(&sg, 0, sizeof sg);
+            sg.elem_off = G.elem_off;
+            sg.nlines = pp.nlines;
+            sg.M2 = pp.M2;
+            sg.tw = pp.tw;
+            sg.scale_bwd = G.scale_bwd;
+            sg.kid = pp.kid;
+            sg.logW = many_tile_logW(pp, elem_bytes, threads, lds_budget);
+            sg.mode = pp.mode;
+            const int64_t W = int64_t(1) << sg.logW;
+            sg.ntiles = (int)((sg.nlines + W - 1) / W);
+            sg.tiles_per_item = tiles_per_item;
+            sg.nitems = (sg.ntiles + tiles_per_item - 1) / tiles_per_item;
+            sg.first = lvl == 0;
+            sg.last = lvl == (int)G.passes.size() - 1;
+            sg.dep = lvl > 0 ? seg_of[(size_t)(lvl - 1) * count + g] : -1;
+            seg_of[(size_t)lvl * count + g] = (int)t->segs.size();
+            seg_level.push_back(lvl);
+            t->lds_bytes = std::max(t->lds_bytes, (size_t)(tile_lds_elems((int)W, pp.L) * elem_bytes));
+            t->segs.push_back(sg);
+        }
+    }
+    int64_t items = 0, tiles = 0;
+    int lv = 0;
+    for (int l = 0; l < 4; ++l) t->level_begin[l] = t->level_tile_begin[l] = 0;
+    for (size_t i = 0; i < t->segs.size(); ++i) {
+        while (lv < seg_level[i]) {
+            ++lv;
+            t->level_begin[lv] = items;
+            t->level_tile_begin[lv] = tiles;
+        }
+        t->segs[i].item_base = items;
+        t->segs[i].tile_base = tiles;
+        items += t->segs[i].nitems;
+        tiles += t->segs[i].ntiles;
+    }
+    while (lv < 3) {
+        ++lv;
+        t->level_begin[lv] = items;
+        t->level_tile_begin[lv] = tiles;
+    }
+    t->total_items = items;
+    t->seg_level = seg_level;
+}
+
+// The (level, case) groups of the level-synchronous form over `ncases`
+// kernel cases: each group's segments in grid order, group_tile_base of each
+// segment its first tile within the group; and the level queues' ranges:
+// range x of a level takes the x-th of kXcds near-equal shares of every
+// group's tiles, case after case, in items of kSyncTilesPerPop tiles.
+inline void build_many_groups(ManyTables* t, int ncases) {
+    t->groups.assign((size_t)3 * ncases, ManyGroup{0, 0, 0});
+    t->gseg.clear();
+    for (int lvl = 0; lvl < 3; ++lvl) {
+        for (int c = 0; c < ncases; ++c) {
+            ManyGroup& gr = t->groups[(size_t)lvl * ncases + c];
+            gr.seg_begin = (int)t->gseg.size();
+            gr.ntiles = 0;
+            for (size_t i = 0; i < t->segs.size(); ++i) {
+                if (t->seg_level[i] != lvl || t->segs[i].kid != c) continue;
+                t->segs[i].group_tile_base = gr.ntiles;
+                gr.ntiles += t->segs[i].ntiles;
+                t->gseg.push_back((int)i);
+            }
+            gr.seg_end = (int)t->gseg.size();
+        }
+    }
+    t->ranges.assign((size_t)3 * kXcds * ncases, ManyRange{0, 0, 0, 0});
+    for (int lvl = 0; lvl < 3; ++lvl) {
+        for (int x = 0; x < kXcds; ++x) {
+            int64_t item = 0;
+            for (int c = 0; c < ncases; ++c) {
+                const int64_t n = t->groups[(size_t)lvl * ncases + c].ntiles;
+                ManyRange& r = t->ranges[((size_t)lvl * kXcds + x) * ncases + c];
+                r.tile_begin = n * x / kXcds;
+                r.tile_end = n * (x + 1) / kXcds;
+                r.item_begin = item;
+                item += (r.tile_end - r.tile_begin + kSyncTilesPerPop - 1) / kSyncTilesPerPop;
+                r.item_end = item;
+            }
+        }
+    }
+}
+
+}  // namespace offt

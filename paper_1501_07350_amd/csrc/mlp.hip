@@ -275,7 +275,8 @@ int offt_mlp_forward(offt_mlp_t m, const float* X, const int32_t* idx, int B, fl
     if (!m || !X || !y || B < 1) { set_error(OFFT_ERR_INVALID_ARG); return OFFT_ERR_INVALID_ARG; }
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t lds = sizeof(float) * (m->D + 2 * m->H);
-    // in chunks of max_batch so the activation buffers are never needed here
+    // one workgroup per row, at most 65535 workgroups per launch; the forward
+    // pass alone keeps no activations
     for (int b0 = 0; b0 < B; b0 += 65535) {
         const int nb = std::min(65535, B - b0);
         hipLaunchKernelGGL(mlp_forward_kernel, dim3(nb), dim3(m->H), lds, s, m->params,

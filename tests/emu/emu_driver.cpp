@@ -6,13 +6,17 @@
 //       plain stores) over a [M1][L][M2] view of synthetic data, tile by tile
 //       with W*TPL threads each (strided lines with LDS exchanges in 2^logP
 //       parts when M2 > 1); prints the forward-transformed data as text
-//   emu_driver many <dtype> <nwg> <threads> <nseg> <segments...> <total>
-//       the persistent loop over a segment table, run by nwg workgroups at
-//       once: each workgroup is a forked process of `threads` CPU threads;
-//       buffers and counters live in shared memory
-//   emu_driver sync <dtype> <nwg> <threads> <nseg> <segments + level...> <total>
-//       the level-synchronous persistent body (grid barriers between levels)
-//       over the batch executor's cases, nwg workgroups at once
+//   emu_driver many <dtype> <nwg> <ngrids> <grids...> <total> [<seg> <dep>]
+//       the persistent loop over the segment table the library builds
+//       (many_tables.hpp) for the grids' passes, run by nwg workgroups at
+//       once: each workgroup is a forked process of kManyThreads CPU
+//       threads with exactly the launch's dynamic LDS; buffers and counters
+//       live in shared memory.  Each grid: <elem_off> <npass>, then per pass
+//       <L> <kid> <mode> <nlines> <M2> <tpl>.  The optional <seg> <dep>
+//       makes segment seg wait for segment dep instead.
+//   emu_driver sync <dtype> <nwg> <ngrids> <grids...> <total>
+//       the level-synchronous persistent body (tile queue per level, grid
+//       barriers between levels) over the batch executor's cases
 //   emu_driver route <Na> <Nb> <Nc> <np> <in_order> <out_order> <per_chunk>
 //       one exchange of the distributed flow with the library's own tables
 //       (dist_tables.hpp) and exchange code (dist_device.hpp): every
@@ -37,6 +41,7 @@
 
 #include "fft_device.hpp"
 #include "many_device.hpp"
+#include "many_tables.hpp"
 #include "dist_device.hpp"
 #include "dist_tables.hpp"
 #include "emu_cases.inc"
@@ -80,68 +85,65 @@ static bool run_block(int threads, const std::function<void(int)>& fn) {
 
 template <typename V>
 static int do_many(int argc, char** argv, bool sync) {
-    // many|sync <dtype> <nwg> <threads> <nseg> then per segment:
-    //   L kid logW mode nlines M2 ntiles first last dep elem_off tiles_per_item [level (sync)]
-    // then <total_elems>
     int k = 3;
     const int nwg = atoi(argv[k++]);
-    const int threads = atoi(argv[k++]);
-    const int nseg = atoi(argv[k++]);
-    std::vector<ManySeg> segs(nseg);
-    std::vector<int> seg_level(nseg, 0);
-    std::vector<std::vector<V>> tws(nseg);
-    int64_t items = 0;
-    size_t lds_elems = 0;
-    for (int s = 0; s < nseg; ++s) {
-        ManySeg& g = segs[s];
-        memset(&g, 0, sizeof g);
-        const int L = atoi(argv[k++]);
-        g.kid = atoi(argv[k++]);
-        g.logW = atoi(argv[k++]);
-        g.mode = atoi(argv[k++]);
-        g.nlines = atoll(argv[k++]);
-        g.M2 = atoll(argv[k++]);
-        g.ntiles = atoi(argv[k++]);
-        g.first = atoi(argv[k++]);
-        g.last = atoi(argv[k++]);
-        g.dep = atoi(argv[k++]);
-        g.elem_off = atoll(argv[k++]);
-        g.tiles_per_item = atoi(argv[k++]);
-        if (sync) seg_level[s] = atoi(argv[k++]);
-        g.nitems = (g.ntiles + g.tiles_per_item - 1) / g.tiles_per_item;
-        g.scale_bwd = 1.0;
-        g.item_base = items;
-        items += g.nitems;
-        twiddles(tws[s], L);
-        g.tw = tws[s].data();
-        lds_elems = std::max(lds_elems, (size_t)tile_lds_elems(1 << g.logW, L));
-    }
-    const int64_t total = atoll(argv[k++]);
-    // (level, case) groups of the level-synchronous form, built as the library does
-    // as many cases as the executor has (the kernel walks all of them)
-    int ncases = sync ? EmuSync<V>::ncases : 0;
-    for (const ManySeg& g : segs) ncases = std::max(ncases, g.kid + 1);
-    std::vector<ManyGroup> groups((size_t)3 * ncases);
-    std::vector<int> gseg;
-    for (int lvl = 0; lvl < 3; ++lvl) {
-        int64_t rot = 0;
-        for (int c = 0; c < ncases; ++c) {
-            ManyGroup& gr = groups[(size_t)lvl * ncases + c];
-            gr.seg_begin = (int)gseg.size();
-            gr.ntiles = 0;
-            gr.rot = rot;
-            for (int i = 0; i < nseg; ++i) {
-                if (seg_level[i] != lvl || segs[i].kid != c) continue;
-                segs[i].group_tile_base = gr.ntiles;
-                gr.ntiles += segs[i].ntiles;
-                gseg.push_back(i);
-            }
-            gr.seg_end = (int)gseg.size();
-            rot += gr.ntiles;
+    const int ngrids = atoi(argv[k++]);
+    std::vector<ManyGridDesc> gd(ngrids);
+    std::vector<std::vector<V>> tws;
+    tws.reserve(64);
+    for (int g = 0; g < ngrids; ++g) {
+        gd[g].elem_off = atoll(argv[k++]);
+        gd[g].scale_bwd = 1.0;
+        const int npass = atoi(argv[k++]);
+        for (int i = 0; i < npass; ++i) {
+            ManyPassDesc d;
+            d.L = atoi(argv[k++]);
+            d.kid = atoi(argv[k++]);
+            d.mode = atoi(argv[k++]);
+            d.nlines = atoll(argv[k++]);
+            d.M2 = atoll(argv[k++]);
+            d.tpl = atoi(argv[k++]);
+            tws.emplace_back();
+            twiddles(tws.back(), d.L);
+            d.tw = nullptr;
+            gd[g].passes.push_back(d);
         }
     }
-    // shared between the workgroup processes: buffers, counters, two level barriers
-    const size_t bytes = sizeof(V) * 2 * (size_t)total + sizeof(unsigned) * (kManyCounterBase + nseg + 2);
+    const int64_t total = atoll(argv[k++]);
+    // the library's own tables and launch LDS (no slack: AddressSanitizer
+    // flags any access beyond what the GPU launch gets)
+    ManyTables tab;
+    build_many_tables(gd, (int64_t)sizeof(V), kManyThreads, kManyLdsBudget, kTilesPerItem, &tab);
+    const int ncases = sync ? EmuSync<V>::ncases : 0;
+    if (sync) build_many_groups(&tab, ncases);
+    std::vector<ManySeg>& segs = tab.segs;
+    const int nseg = (int)segs.size();
+    {
+        // twiddle tables: segments follow the level-major order of the table
+        std::vector<const void*> tw_of;
+        size_t t = 0;
+        std::vector<std::vector<const void*>> per_grid(ngrids);
+        for (int g = 0; g < ngrids; ++g)
+            for (size_t i = 0; i < gd[g].passes.size(); ++i) per_grid[g].push_back(tws[t++].data());
+        int s2 = 0;
+        for (int lvl = 0; lvl < 3; ++lvl)
+            for (int g = 0; g < ngrids; ++g)
+                if (lvl < (int)gd[g].passes.size()) segs[s2++].tw = per_grid[g][lvl];
+    }
+    int64_t waiting_items = 0;
+    if (k + 1 < argc) {   // a dependency made unmet on purpose
+        const int sgi = atoi(argv[k]);
+        if (sgi < 0 || sgi >= (int)segs.size()) return 2;
+        segs[sgi].dep = atoi(argv[k + 1]);
+        waiting_items = tab.total_items - segs[sgi].item_base;
+    }
+    const size_t lds_elems = tab.lds_bytes / sizeof(V);
+    const int64_t items = tab.total_items;
+    const int threads = kManyThreads;
+    // shared between the workgroup processes: buffers, counters, two level
+    // barriers, the level queues (one per level and XCD range)
+    const int ncnt = kManyCounterBase + nseg + kManySyncCounters;
+    const size_t bytes = sizeof(V) * 2 * (size_t)total + sizeof(unsigned) * ncnt;
     void* shm = mmap(nullptr, bytes, PROT_READ | PROT_WRITE, MAP_SHARED | MAP_ANONYMOUS, -1, 0);
     if (shm == MAP_FAILED) return 3;
     V* in = static_cast<V*>(shm);
@@ -152,12 +154,14 @@ static int do_many(int argc, char** argv, bool sync) {
         in[i].y = (decltype(in[i].y))std::cos(0.91 * (double)i);
         out[i].x = out[i].y = 0;
     }
-    for (int i = 0; i < kManyCounterBase + nseg + 2; ++i) counters[i] = 0u;
+    for (int i = 0; i < ncnt; ++i) counters[i] = 0u;
     ManySyncArgs sa;
     memset(&sa, 0, sizeof sa);
-    sa.groups = groups.data();
-    sa.gseg = gseg.data();
+    sa.groups = tab.groups.data();
+    sa.gseg = tab.gseg.data();
+    sa.ranges = tab.ranges.data();
     sa.barrier = counters + kManyCounterBase + nseg;
+    sa.queue = sa.barrier + 2;
     sa.ncases = ncases;
     gridDim.x = (unsigned)nwg;
     ManyArgs a;
@@ -182,14 +186,14 @@ static int do_many(int argc, char** argv, bool sync) {
         const pid_t pid = fork();
         if (pid == 0) {
             blockIdx.x = (unsigned)wg;
-            std::vector<V> lds(lds_elems + 64);
+            std::vector<V> lds(lds_elems);
             const bool okc = run_block(threads, [&](int) { body(lds.data()); });
             _exit(okc ? 0 : 1);
         }
         kids.push_back(pid);
     }
     blockIdx.x = 0;
-    std::vector<V> lds(lds_elems + 64);
+    std::vector<V> lds(lds_elems);
     bool ok = run_block(threads, [&](int) { body(lds.data()); });
     for (pid_t pid : kids) {
         int st = 0;
@@ -197,7 +201,7 @@ static int do_many(int argc, char** argv, bool sync) {
         if (!WIFEXITED(st) || WEXITSTATUS(st) != 0) ok = false;
     }
     if (!ok || counters[1]) {
-        std::printf("FAIL barrier_ok=%d err=%u\n", (int)ok, counters[1]);
+        std::printf("FAIL barrier_ok=%d err=%u waiting_items=%lld\n", (int)ok, counters[1], (long long)waiting_items);
         return 1;
     }
     for (int l = 0; sync && l < 2; ++l)   // every workgroup arrived at both level barriers
@@ -281,6 +285,31 @@ static void run_grid(unsigned blocks, unsigned threads, const std::function<void
     }
 }
 
+// The pack kernel's body with its LDS tile (a static: shared by the
+// emulated threads of one workgroup).
+static void emu_pack(const PackArgs& a) {
+    __shared__ double2 tile[kPackTile][kPackTile + 1];
+    pack_tile<double2>(a, tile);
+}
+
+// Blocks one after the other, the threads of each concurrently with a
+// barrier; false if a block's threads passed different numbers of barriers.
+static bool run_grid_sync(unsigned blocks, unsigned threads, const std::function<void()>& body) {
+    gridDim.x = blocks;
+    blockDim.x = threads;
+    bool ok = true;
+    for (unsigned b = 0; b < blocks; ++b) {
+        blockIdx.x = b;
+        ok = run_block((int)threads, [&](int) { body(); }) && ok;
+    }
+    return ok;
+}
+
+// One exchange as dist.hip runs it: the library's tables (forward for the
+// chunk sizes and places, reverse for the positions), pack per process with
+// its own chunk into the receive array or straight into O_out, copies of the
+// other chunks, unpack of every process's lines (all chunks at once or chunk
+// by chunk).
 static int do_route(int argc, char** argv) {
     if (argc < 9) return 2;
     const int64_t dims[3] = {atoll(argv[2]), atoll(argv[3]), atoll(argv[4])};
@@ -291,8 +320,11 @@ static int do_route(int argc, char** argv) {
         st[o].resize(np + 1);
         dist_line_starts(dims, o, np, st[o].data());
     }
-    ExchangeTables t;
-    if (!build_exchange_tables(dims, np, in_order, out_order, st[in_order].data(), st[out_order].data(), &t)) {
+    const int64_t* is = st[in_order].data();
+    const int64_t* os = st[out_order].data();
+    ExchangeTables t, rev;
+    if (!build_exchange_tables(dims, np, in_order, out_order, is, os, &t) ||
+        !build_exchange_tables(dims, np, out_order, in_order, os, is, &rev)) {
         std::printf("FAIL tables\n");
         return 1;
     }
@@ -305,57 +337,85 @@ static int do_route(int argc, char** argv) {
         out[i].x = -1.0;
         out[i].y = 0.0;
     }
-    RouteArgs r;
-    memset(&r, 0, sizeof r);
-    for (int i = 0; i < 3; ++i) {
-        r.in_n[i] = t.in_n[i];
-        r.out_n[i] = t.out_n[i];
-        r.in_ax[i] = t.in_ax[i];
-        r.out_ax[i] = t.out_ax[i];
+    ReverseTables rt;
+    memset(&rt, 0, sizeof rt);
+    rt.klo = rev.klo.data();
+    rt.cnt = rev.cnt.data();
+    rt.pre = rev.pre.data();
+    rt.in_start = is;
+    rt.nm = rev.in_n[1];
+    rt.base_mul = rev.base_mul;
+    rt.step = rev.step;
+    rt.nq = rev.nq;
+    rt.q_slowest = rev.q_slowest;
+    const int u_axis = t.out_ax[2];
+    if (u_axis != t.in_ax[0] && u_axis != t.in_ax[1]) {
+        std::printf("FAIL axes\n");
+        return 1;
     }
-    r.sdispl = t.sdispl.data();
-    r.rdispl = t.rdispl.data();
-    r.klo = t.klo.data();
-    r.cnt = t.cnt.data();
-    r.pre = t.pre.data();
-    r.out_start = st[out_order].data();
-    r.base_mul = t.base_mul;
-    r.step = t.step;
-    r.nq = t.nq;
-    r.q_slowest = t.q_slowest;
-    r.np = np;
-    const unsigned blocks = 3;   // fewer blocks than lines: the grid-stride loop is exercised
+    bool ok = true;
+    std::vector<char> direct(np);
     for (int sp = 0; sp < np; ++sp) {
-        RouteArgs a = r;
+        direct[sp] = t.count[(size_t)sp * np + sp] == (os[sp + 1] - os[sp]) * t.out_n[2];
+        PackArgs a;
+        memset(&a, 0, sizeof a);
         a.from = in.data();
-        a.to = send.data();
+        a.send = send.data();
+        a.self = direct[sp] ? out.data() + os[sp] * t.out_n[2] : recv.data() + t.rdispl[(size_t)sp * np + sp];
+        a.sdispl = t.sdispl.data();
+        a.out_start = os;
+        a.rev = rt;
+        for (int i = 0; i < 3; ++i) {
+            a.in_n[i] = t.in_n[i];
+            a.out_n[i] = t.out_n[i];
+            a.in_ax[i] = t.in_ax[i];
+            a.out_ax[i] = t.out_ax[i];
+        }
+        a.u_slowest = u_axis == t.in_ax[0] ? 1 : 0;
+        a.np = np;
         a.src = sp;
-        a.dst_only = -1;
-        a.unpack = 0;
-        a.line_begin = st[in_order][sp];
-        a.line_end = st[in_order][sp + 1];
-        run_grid(blocks, kRouteThreads, [&] { route_lines<double2>(a); });
+        a.line_begin = is[sp];
+        a.line_end = is[sp + 1];
+        const int64_t nm = a.in_n[1];
+        const int64_t lo = a.line_begin / nm, hi = (a.line_end - 1) / nm + 1;
+        if (a.u_slowest) { a.u_lo = lo; a.u_n = hi - lo; a.v_lo = 0; a.v_n = nm; }
+        else { a.v_lo = lo; a.v_n = hi - lo; a.u_lo = 0; a.u_n = nm; }
+        a.u_tiles = (a.u_n + kPackTile - 1) / kPackTile;
+        a.k_tiles = (a.in_n[2] + kPackTile - 1) / kPackTile;
+        ok = run_grid_sync((unsigned)(a.v_n * a.u_tiles * a.k_tiles), kPackThreads, [&] { emu_pack(a); }) && ok;
     }
     for (int sp = 0; sp < np; ++sp)
         for (int d = 0; d < np; ++d) {
+            if (sp == d) continue;   // the own chunk is already in place
             CopyDesc c;
             c.from = t.sdispl[(size_t)sp * np + d];
             c.to = t.rdispl[(size_t)d * np + sp];
             c.n = t.count[(size_t)sp * np + d];
             if (c.n) run_grid(2, kCopyThreads, [&] { copy_chunk(send.data(), recv.data(), c); });
         }
-    for (int sp = 0; sp < np; ++sp)
-        for (int d = per_chunk ? 0 : -1; d < (per_chunk ? np : 0); ++d) {
-            RouteArgs a = r;
-            a.from = recv.data();
+    for (int d = 0; d < np; ++d) {
+        if (direct[d]) continue;
+        for (int sp = per_chunk ? 0 : -1; sp < (per_chunk ? np : 0); ++sp) {
+            GatherArgs a;
+            memset(&a, 0, sizeof a);
+            a.recv = recv.data();
             a.to = out.data();
-            a.src = sp;
-            a.dst_only = d;
-            a.unpack = 1;
-            a.line_begin = st[in_order][sp];
-            a.line_end = st[in_order][sp + 1];
-            run_grid(blocks, kRouteThreads, [&] { route_lines<double2>(a); });
+            a.rdispl = t.rdispl.data();
+            a.rev = rt;
+            a.nf = t.out_n[2];
+            a.line_begin = os[d];
+            a.line_end = os[d + 1];
+            a.np = np;
+            a.dst = d;
+            a.src_only = sp;
+            // fewer waves than lines: the line loop is exercised
+            run_grid(2, kGatherThreads, [&] { gather_lines<double2>(a); });
         }
+    }
+    if (!ok) {
+        std::printf("FAIL barrier\n");
+        return 1;
+    }
     std::printf("OK\n");
     for (int sp = 0; sp < np; ++sp) {
         for (int d = 0; d < np; ++d) std::printf("%lld ", (long long)t.count[(size_t)sp * np + d]);

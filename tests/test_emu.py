@@ -27,8 +27,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 EMU = os.path.join(HERE, "emu")
 CSRC = os.path.join(os.path.dirname(HERE), "paper_1501_07350_amd", "csrc")
 BUILD = os.path.join(EMU, "_build")
-THREADS = 512          # workgroup size of the persistent executor
-LDS_LIMIT = 160 * 1024  # gfx950 per-workgroup LDS
 
 
 def gen_kernels():
@@ -75,7 +73,9 @@ def emu_binary():
                                   for P in (1, 2, 4) if gk.splits(L, seq, P)])
             lines.append(f"      case {i}: {body} break;")
         lines.append("      default: break;\n    }\n  }\n};")
-    # the level-synchronous body over the batch executor's cases
+    # the level-synchronous body over the batch executor's cases (plain
+    # stores, each case's tiles in a loop of their own)
+    lines.insert(0, "template <typename V> struct EmuSync;")
     for vt, prec in (("double2", "f64"), ("float2", "f32")):
         names = []
         for i, (L, seq, tpl) in enumerate(gk.many_cases(prec, "batch")):
@@ -85,7 +85,6 @@ def emu_binary():
         lines.append(f"template <> struct EmuSync<{vt}> {{ static constexpr int ncases = {len(names)}; "
                      f"static void body(const ManyArgs& a, const ManySyncArgs& g, "
                      f"{vt}* lds) {{ many_sync_body<{vt}, {', '.join(names)}>(a, g, lds); }} }};")
-    lines.insert(0, "template <typename V> struct EmuSync;")
     with open(os.path.join(build, "emu_cases.inc"), "w") as f:
         f.write("namespace offt {\n" + "\n".join(lines) + "\n}\n")
     exe = os.path.join(build, "emu_driver")
@@ -164,23 +163,12 @@ def plan_passes(dims, dtype):
     return out
 
 
-def many_logW(p, es):
-    """Tile width inside the batch executors: fill THREADS threads within a
-    52 KiB LDS budget."""
-    lw = 0
-    while (2 << lw) * p["tpl"] <= THREADS and tile_lds_elems(2 << lw, p["L"]) * es <= min(52 * 1024, LDS_LIMIT):
-        lw += 1
-    return lw
-
-
-TILES_PER_ITEM = 4
-
-
-def segment_args(dims_list, dtype, which="all", levels=False):
-    """The persistent executor's segment table, built as the library does
-    (pass levels in order, grids in order within a level); `which` case set,
-    and with `levels` each segment's pass level appended (level-synchronous
-    form)."""
+def grid_args(dims_list, dtype, which="all"):
+    """Driver arguments of a batch: each grid's offset in the packed buffer
+    (256-byte aligned, as the library packs) and its heuristic passes with
+    their kernel cases; the driver builds the segment table with the
+    library's own code (many_tables.hpp).  Returns (args, offsets, total,
+    passes per grid)."""
     gk = gen_kernels()
     prec = "f64" if dtype == torch.complex128 else "f32"
     es = 16 if prec == "f64" else 8
@@ -192,27 +180,21 @@ def segment_args(dims_list, dtype, which="all", levels=False):
         off += int(np.prod(d))
         off = (off + align - 1) // align * align
     total = off
-    passes = [plan_passes(d, dtype) for d in dims_list]
-    segs, seg_of = [], {}
-    for lvl in range(3):
-        for g, ps in enumerate(passes):
-            if lvl >= len(ps):
-                continue
-            p = ps[lvl]
+    args = [str(len(dims_list))]
+    npass = []
+    for g, d in enumerate(dims_list):
+        ps = plan_passes(d, dtype)
+        npass.append(len(ps))
+        args += [str(offs[g]), str(len(ps))]
+        for p in ps:
             kid = cases.index((p["L"], p["seq"], p["tpl"]))
-            lw = many_logW(p, es)
-            nlines = p["M1"] * p["M2"]
-            ntiles = -(-nlines // (1 << lw))
-            dep = seg_of[(lvl - 1, g)] if lvl > 0 else -1
-            seg_of[(lvl, g)] = len(segs)
-            segs.append([p["L"], kid, lw, p["mode"], nlines, p["M2"], ntiles, int(lvl == 0),
-                         int(lvl == len(ps) - 1), dep, offs[g], TILES_PER_ITEM] + ([lvl] if levels else []))
-    args = [str(THREADS), str(len(segs))] + [str(v) for s in segs for v in s] + [str(total)]
-    return args, offs, total
+            args += [str(p["L"]), str(kid), str(p["mode"]), str(p["M1"] * p["M2"]), str(p["M2"]), str(p["tpl"])]
+    args.append(str(total))
+    return args, offs, total, npass
 
 
 def run_many(exe, dims_list, dtype, nwg=1, sync=False):
-    args, offs, total = segment_args(dims_list, dtype, "batch" if sync else "all", levels=sync)
+    args, offs, total, _ = grid_args(dims_list, dtype, "batch" if sync else "all")
     code = "0" if dtype == torch.complex128 else "1"
     r = subprocess.run([exe, "sync" if sync else "many", code, str(nwg)] + args, capture_output=True, text=True,
                        timeout=600)
@@ -253,32 +235,30 @@ def test_emulated_concurrent_workgroups_mixed_batch(emu_binary, nwg):
 
 
 def test_emulated_unmet_dependency_ends_within_one_spin_limit(emu_binary):
-    """A dependency that is never met (a segment made to wait on a grid's last
-    pass, which publishes nothing): the first wait gives up after its spin
-    limit and raises the error flag, and every later item then skips its wait
-    and its tile, so the loop ends after about one spin limit instead of one
-    per waiting item."""
+    """A dependency that is never met (the second pass of the largest grid
+    made to wait on a grid's last pass, which publishes nothing): the first
+    wait gives up after its spin limit and raises the error flag, and every
+    later item then skips its wait and its tile, so the loop ends after about
+    one spin limit instead of one per waiting item."""
     import time
-    args, _, _ = segment_args(MIXED, torch.complex64, "all")
-    nseg = int(args[1])
-    segs = [args[2 + 12 * s: 2 + 12 * (s + 1)] for s in range(nseg)]
-    last = next(s for s in range(nseg) if segs[s][8] == "1")
-    # the waiting segment with the most tiles, and its dependants
-    waiting = max((s for s in range(nseg) if segs[s][9] != "-1"), key=lambda s: int(segs[s][6]))
-    segs[waiting][9] = str(last)
-    nitems = sum(-(-int(segs[s][6]) // TILES_PER_ITEM) for s in range(nseg) if s >= waiting)
-    assert nitems >= 8
-    table = args[:2] + [v for sg in segs for v in sg] + args[2 + 12 * nseg:]
+    args, _, _, npass = grid_args(MIXED, torch.complex64, "all")
+    # segment order of the library's table: level-major, grid order within a level
+    order = [(lvl, g) for lvl in range(3) for g in range(len(MIXED)) if lvl < npass[g]]
+    big = MIXED.index((48, 60, 64))
+    waiting = order.index((1, big))
+    last = next(i for i, (lvl, g) in enumerate(order) if lvl == npass[g] - 1 and g != big)
     t0 = time.perf_counter()
     r = subprocess.run([emu_binary, "many", "1", "1"] + args, capture_output=True, text=True, timeout=600)
     t_normal = time.perf_counter() - t0
     assert r.returncode == 0, r.stdout[:300]
     spin = 20000   # polls of at least 20 us each in the emulation: >= 0.4 s per full wait
     t0 = time.perf_counter()
-    r = subprocess.run([emu_binary, "many", "1", "1"] + table, capture_output=True, text=True, timeout=600,
-                       env={**os.environ, "EMU_SPIN_LIMIT": str(spin)})
+    r = subprocess.run([emu_binary, "many", "1", "1"] + args + [str(waiting), str(last)], capture_output=True,
+                       text=True, timeout=600, env={**os.environ, "EMU_SPIN_LIMIT": str(spin)})
     t_unmet = time.perf_counter() - t0
     assert r.returncode == 1 and "err=1" in r.stdout, (r.stdout[:300], r.stderr[-2000:])
+    nitems = int(r.stdout.split("waiting_items=")[1].split()[0])
+    assert nitems >= 8
     # one full wait beyond the normal run; one wait per waiting item would add
     # at least nitems * 0.4 s
     assert t_unmet < t_normal + 0.5 * nitems * spin * 20e-6, (t_normal, t_unmet, nitems)
@@ -453,12 +433,13 @@ SYNC_DIMS = [(48, 1, 60), (1, 64, 1), (16 * 3, 60, 64), (80, 96, 1), (1, 1, 1), 
 
 
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
-@pytest.mark.parametrize("nwg", [1, 3])
+@pytest.mark.parametrize("nwg", [1, 3, 9])
 def test_emulated_level_synchronous_body(emu_binary, dtype, nwg):
-    """The level-synchronous persistent body: tiles dealt round-robin over nwg
-    workgroups (one process each), grid barriers between levels in shared
-    memory; every workgroup arrives at both barriers, no wait times out, and
-    every grid matches the oracle."""
+    """The level-synchronous persistent body: nwg workgroups (one process
+    each) take items from the per-level XCD-range queues (their own range
+    first, then the others'; 9 puts two workgroups on one range), grid
+    barriers between levels in shared memory; every workgroup arrives at both
+    barriers, no wait times out, and every grid matches the oracle."""
     dims = [tuple(min(v, 64) if v > 1 else 1 for v in d) for d in SYNC_DIMS]
     dims = [tuple(v if v in (1, 48, 60, 64) else 64 for v in d) for d in dims]
     run_many(emu_binary, dims, dtype, nwg=nwg, sync=True)
