@@ -178,6 +178,25 @@ int offt_exec_bwd(offt_plan_t p, const void* in, void* out, void* stream);
  * normalize outside {-1, 0, 1}. */
 int offt_exec_bwd_norm(offt_plan_t p, const void* in, void* out, int normalize, void* stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the forward
+ * (direction OFFT_FORWARD) or backward (OFFT_BACKWARD, scaled by
+ * 1/(Na Nb Nc) when normalize = 1) transform of `batch` grids of
+ * Na x Nb x Nc points, natural layout, with no plan object and no device
+ * allocation.  It runs the heuristic plan of offt_plan with the same kernels,
+ * so its results equal offt_exec_fwd / offt_exec_bwd of such a plan bit for
+ * bit.  The twiddle tables (one per distinct axis length, at most 3 of
+ * OFFT_MAX_AXIS complex values) live in a file-scope device array of 48 KiB
+ * that each GPU the library runs on holds until the process ends; every call
+ * rewrites them on `stream` before its passes, so calls that overlap on one
+ * GPU (on different streams) race and must not be issued.  Axis lengths as
+ * offt_plan (2/3/5-smooth, at most OFFT_MAX_AXIS: longer axes would not fit a
+ * table and are rejected with OFFT_ERR_UNSUPPORTED_SIZE).  Stream-ordered,
+ * never synchronises.  Errors: INVALID_ARG, UNSUPPORTED_SIZE, NO_DEVICE,
+ * HIP. */
+int offt_exec_noalloc(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch, int direction, int normalize,
+                      const void* in, void* out, void* stream);
+
 /* Number of axis passes of a plan (0..3: axes of length 1 need none), or a
  * negative code. */
 int offt_plan_passes(offt_plan_t p);
