@@ -61,8 +61,8 @@ constexpr int kGatherMaxBlocks = 16384;
 // The kernels of one exchange (device code in dist_device.hpp).
 template <typename V>
 __global__ void __launch_bounds__(kPackThreads) pack_kernel(PackArgs a) {
-    __shared__ V tile[kPackTile][kPackTile + 1];
-    pack_tile<V>(a, tile);
+    __shared__ PackShared<V> sh;
+    pack_tile<V>(a, sh);
 }
 
 template <typename V>

@@ -37,18 +37,20 @@ struct ReverseTables {
     int q_slowest;             // q = m / nm (1) or m % nm (0)
 };
 
+// Line indices and lengths fit 32 bits (at most 2^20 lines of a grid), so
+// the divisions by the middle length are 32-bit ones.
 __device__ __forceinline__ int64_t rev_q(const ReverseTables& t, int64_t m) {
-    return t.q_slowest ? m / t.nm : m % t.nm;
+    const uint32_t mm = (uint32_t)m, nm = (uint32_t)t.nm;
+    return t.q_slowest ? mm / nm : mm % nm;
 }
 
 // Elements that process proc owns on the O_out lines [0, m).
 __device__ __forceinline__ int64_t rev_prefix(const ReverseTables& t, int proc, int64_t m) {
     const int64_t* pre = t.pre + (int64_t)proc * (t.nq + 1);
-    if (t.q_slowest) {
-        const int64_t q = m / t.nm;
-        return t.nm * pre[q] + (m - q * t.nm) * (q < t.nq ? t.cnt[(int64_t)proc * t.nq + q] : 0);
-    }
-    return (m / t.nm) * pre[t.nq] + pre[m % t.nm];
+    const uint32_t mm = (uint32_t)m, nm = (uint32_t)t.nm;
+    const uint32_t q = mm / nm, r = mm - q * nm;
+    if (t.q_slowest) return t.nm * pre[q] + (int64_t)r * ((int)q < t.nq ? t.cnt[(int64_t)proc * t.nq + q] : 0);
+    return (int64_t)q * pre[t.nq] + pre[r];
 }
 
 __device__ __forceinline__ int dist_owner(const int64_t* start, int np, int64_t line) {
@@ -85,8 +87,17 @@ struct PackArgs {
     int np, src;
 };
 
+// LDS of one pack tile: the elements, and per tile column (one k) the place
+// of its first element's run in the chunk it goes to.
 template <typename V>
-__device__ __forceinline__ void pack_tile(const PackArgs& a, V (*tile)[kPackTile + 1]) {
+struct PackShared {
+    V tile[kPackTile][kPackTile + 1];
+    int64_t col_off[kPackTile];   // element offset of u = 0 in the column's destination array
+    int col_self[kPackTile];      // the column goes to src's own chunk
+};
+
+template <typename V>
+__device__ __forceinline__ void pack_tile(const PackArgs& a, PackShared<V>& sh) {
     const V* __restrict__ from = static_cast<const V*>(a.from);
     const int64_t nm = a.in_n[1], nf = a.in_n[2];
     const int64_t b = blockIdx.x;
@@ -100,26 +111,31 @@ __device__ __forceinline__ void pack_tile(const PackArgs& a, V (*tile)[kPackTile
     for (int r = row; r < kPackTile; r += kRows) {
         const int64_t u = u0 + r, k = k0 + lane;
         const int64_t l = a.u_slowest ? u * nm + v : v * nm + u;
-        if (u < a.u_lo + a.u_n && k < nf && l >= a.line_begin && l < a.line_end) tile[r][lane] = from[l * nf + k];
+        if (u < a.u_lo + a.u_n && k < nf && l >= a.line_begin && l < a.line_end) sh.tile[r][lane] = from[l * nf + k];
     }
-    __syncthreads();
-    // write: column c of the tile is k = k0 + c, lanes along u (O_out's k')
-    int64_t co[3];
-    for (int c = row; c < kPackTile; c += kRows) {
-        const int64_t k = k0 + c;
-        if (k >= nf) break;
+    // meanwhile, the first wavefront places the tile's columns: column k
+    // lies on one O_out line m (u is O_out's fastest axis), owned by d
+    if (threadIdx.x < kPackTile && k0 + threadIdx.x < nf) {
+        int64_t co[3];
         co[a.in_ax[a.u_slowest ? 1 : 0]] = v;
-        co[a.in_ax[2]] = k;
+        co[a.in_ax[2]] = k0 + threadIdx.x;
         co[a.in_ax[a.u_slowest ? 0 : 1]] = 0;
-        const int64_t m = co[a.out_ax[0]] * a.out_n[1] + co[a.out_ax[1]];   // O_out line (u does not enter)
+        const int64_t m = co[a.out_ax[0]] * a.out_n[1] + co[a.out_ax[1]];
         const int d = dist_owner(a.out_start, a.np, m);
         const int64_t q = rev_q(a.rev, m);
         const int64_t pos0 = rev_prefix(a.rev, a.src, m) - rev_prefix(a.rev, a.src, a.out_start[d]) -
                              a.rev.klo[(int64_t)a.src * a.rev.nq + q];
-        V* __restrict__ dst = d == a.src ? static_cast<V*>(a.self) : static_cast<V*>(a.send) + a.sdispl[a.src * a.np + d];
-        const int64_t u = u0 + lane;
-        const int64_t l = a.u_slowest ? u * nm + v : v * nm + u;
-        if (u < a.u_lo + a.u_n && l >= a.line_begin && l < a.line_end) dst[pos0 + u] = tile[lane][c];
+        sh.col_self[threadIdx.x] = d == a.src;
+        sh.col_off[threadIdx.x] = d == a.src ? pos0 : a.sdispl[a.src * a.np + d] + pos0;
+    }
+    __syncthreads();
+    // write: column c of the tile is k = k0 + c, lanes along u (O_out's k')
+    const int64_t u = u0 + lane;
+    const int64_t l = a.u_slowest ? u * nm + v : v * nm + u;
+    if (u >= a.u_lo + a.u_n || l < a.line_begin || l >= a.line_end) return;
+    for (int c = row; c < kPackTile && k0 + c < nf; c += kRows) {
+        V* __restrict__ dst = sh.col_self[c] ? static_cast<V*>(a.self) : static_cast<V*>(a.send);
+        dst[sh.col_off[c] + u] = sh.tile[lane][c];
     }
 }
 

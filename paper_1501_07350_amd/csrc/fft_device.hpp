@@ -517,6 +517,21 @@ template <bool COHERENT, typename V> __device__ __forceinline__ void store_elem_
 // element per line per lane).
 constexpr int kDirectRowMinTpl = 16;
 
+// The thread's index in one tile's code.  In a loop that runs tile after
+// tile over every kernel case (the level-synchronous batch executor) it is
+// made opaque with an empty asm, so that each case's per-thread index math
+// stays inside its tile instead of being hoisted out of the loop for all the
+// cases at once, where it would stay live across the loop and spill.
+#ifndef OFFT_OPAQUE_VGPR   // the CPU emulation of this header defines it away
+#define OFFT_OPAQUE_VGPR(x) asm volatile("" : "+v"(x))
+#endif
+template <bool OPAQUE>
+__device__ __forceinline__ int tile_thread_index() {
+    int tid = (int)threadIdx.x;
+    if constexpr (OPAQUE) OFFT_OPAQUE_VGPR(tid);
+    return tid;
+}
+
 // Device body of one axis pass for one tile of W = 2^logW lines starting at
 // line l0.  Threads: W * TPL.  lds: tile_lds_elems(W, L) elements.
 //   strided lines:     lanes walk the W lines (consecutive columns of a row),
@@ -526,13 +541,13 @@ constexpr int kDirectRowMinTpl = 16;
 //                      is staged through LDS as one contiguous block.
 // Threads beyond W*TPL (possible when a larger workgroup runs this tile, as in
 // the persistent batch executor) only take part in the barriers.
-template <typename V, bool COHERENT, int L, int TPL, int P, int... Rs>
+template <typename V, bool COHERENT, bool LOOPED, int L, int TPL, int P, int... Rs>
 __device__ __forceinline__ void pass_tile_impl(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
     using S = decltype(V{}.x);
     static_assert(RadixProduct<Rs...>::value == L, "radix sequence must multiply to L");
     constexpr int LP = line_pitch(L, P);
     const int W = 1 << a.logW;
-    const int tid = threadIdx.x;
+    const int tid = tile_thread_index<LOOPED>();
     const int64_t rem = a.nlines - l0;
     const int nl = rem < W ? (int)rem : W;
     const V* __restrict__ in = static_cast<const V*>(a.in);
@@ -752,21 +767,28 @@ __device__ __forceinline__ void pass_tile_transpose(const PassArgs& a, V* __rest
 // One tile of an axis pass with ordinary stores (stand-alone pass kernels).
 template <typename V, int L, int TPL, int... Rs>
 __device__ __forceinline__ void pass_tile(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
-    pass_tile_impl<V, false, L, TPL, 1, Rs...>(a, lds, l0);
+    pass_tile_impl<V, false, false, L, TPL, 1, Rs...>(a, lds, l0);
 }
 
 // One tile of a strided pass whose LDS exchanges run in P parts (stand-alone
 // pass kernels of lengths whose radix sequence allows it).
 template <typename V, int L, int TPL, int P, int... Rs>
 __device__ __forceinline__ void pass_tile_parts(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
-    pass_tile_impl<V, false, L, TPL, P, Rs...>(a, lds, l0);
+    pass_tile_impl<V, false, false, L, TPL, P, Rs...>(a, lds, l0);
 }
 
 // One tile with write-through stores (batch executors, whose tiles are read
 // by other workgroups of the same launch).
 template <typename V, int L, int TPL, int... Rs>
 __device__ __forceinline__ void pass_tile_coherent(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
-    pass_tile_impl<V, true, L, TPL, 1, Rs...>(a, lds, l0);
+    pass_tile_impl<V, true, false, L, TPL, 1, Rs...>(a, lds, l0);
+}
+
+// One tile with ordinary stores inside a loop over tiles of every kernel
+// case (the level-synchronous batch executor).
+template <typename V, int L, int TPL, int... Rs>
+__device__ __forceinline__ void pass_tile_looped(const PassArgs& a, V* __restrict__ lds, int64_t l0) {
+    pass_tile_impl<V, false, true, L, TPL, 1, Rs...>(a, lds, l0);
 }
 
 }  // namespace offt

@@ -239,6 +239,16 @@ def many_cases(prec, which="all"):
     return [e[:3] for e in entries(prec, parts=False) if keep(e[0])]
 
 
+# waves per SIMD the level-synchronous kernel is compiled for: 4, two
+# 512-thread workgroups per CU (128 registers).  Its loop runs every case's
+# tile code inline, which needs about 126 registers for complex64 (with the
+# opaque thread index; without it the hoisted index math spills); asked for
+# 6 waves (80 registers) it spills, and behind an out-of-line call (80
+# registers, no spills) each tile pays the call's stack traffic and ran
+# slower.
+SYNC_WAVES_PER_EU = {"f32": 4, "f64": 4}
+
+
 def emit_many(outdir):
     os.makedirs(outdir, exist_ok=True)
     files = []
@@ -297,27 +307,6 @@ def emit_many(outdir):
                 "    extern __shared__ __align__(16) unsigned char smem_raw[];",
                 f"    many_level_body<{vt}>(a, tile_begin, reinterpret_cast<{vt}*>(smem_raw), DispatchPlain_{name}{{}});",
                 "}",
-                # level-synchronous persistent kernel: one type per case, each
-                # case's tiles in a loop of their own (plain stores)
-                "namespace {",
-            ]
-            for i, (L, seq, tpl) in enumerate(cases):
-                rad = ", ".join(str(x) for x in seq)
-                lines.append(f"struct SyncCase{i}_{name} {{ static constexpr int kid = {i}; "
-                             f"static __device__ __forceinline__ void tile(const PassArgs& p, {vt}* lds, int64_t l0) "
-                             f"{{ pass_tile<{vt}, {L}, {tpl}, {rad}>(p, lds, l0); }} }};")
-            case_types = ", ".join(f"SyncCase{i}_{name}" for i in range(len(cases)))
-            lines += [
-                "}  // namespace",
-                # complex64: two 512-thread workgroups per CU (4 waves per
-                # SIMD, <= 128 registers; the cases fit without spilling);
-                # complex128 keeps what its cases need
-                f"__global__ void __launch_bounds__(512) "
-                + ("__attribute__((amdgpu_waves_per_eu(4))) " if prec == "f32" else "")
-                + f"many_sync_kernel_{name}(ManyArgs a, ManySyncArgs g) {{",
-                "    extern __shared__ __align__(16) unsigned char smem_raw[];",
-                f"    many_sync_body<{vt}, {case_types}>(a, g, reinterpret_cast<{vt}*>(smem_raw));",
-                "}",
                 f"static const ManyCase cases_{name}[] = {{",
             ]
             for L, seq, tpl in cases:
@@ -328,8 +317,7 @@ def emit_many(outdir):
                 f"extern const ManyExecutor g_many_{name};",
                 f"const ManyExecutor g_many_{name} = {{\"{ex}\", {dcode}, cases_{name}, {len(cases)}, "
                 f"reinterpret_cast<const void*>(&many_kernel_{name}), "
-                f"reinterpret_cast<const void*>(&many_level_kernel_{name}), "
-                f"reinterpret_cast<const void*>(&many_sync_kernel_{name})}};",
+                f"reinterpret_cast<const void*>(&many_level_kernel_{name})}};",
                 "}  // namespace offt",
             ]
             path = os.path.join(outdir, f"many_{name}.hip")
@@ -338,9 +326,58 @@ def emit_many(outdir):
                 with open(path, "w") as f:
                     f.write(text)
             files.append(path)
+            # level-synchronous persistent kernel: the plain tile code inlined
+            # into its loop, each tile's thread index opaque
+            sl = [
+                "// generated by gen_kernels.py -- do not edit",
+                '#include "offt_internal.h"',
+                '#include "many_device.hpp"',
+                "namespace offt {",
+                "namespace {",
+                f"__device__ __forceinline__ void dispatch_looped_{name}(int kid, const PassArgs& a, {vt}* lds, int64_t l0) {{",
+                "    switch (kid) {",
+            ]
+            for i, (L, seq, tpl) in enumerate(cases):
+                rad = ", ".join(str(x) for x in seq)
+                sl.append(f"        case {i}: pass_tile_looped<{vt}, {L}, {tpl}, {rad}>(a, lds, l0); break;")
+            sl += [
+                "        default: break;",
+                "    }",
+                "}",
+                f"struct DispatchLooped_{name} {{",
+                f"    __device__ __forceinline__ void operator()(int kid, const PassArgs& a, {vt}* lds, int64_t l0) const {{",
+                f"        dispatch_looped_{name}(kid, a, lds, l0);",
+                "    }",
+                "};",
+                "}  // namespace",
+                f"__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu({SYNC_WAVES_PER_EU[prec]}))) "
+                f"many_sync_kernel_{name}(ManyArgs a, ManySyncArgs g) {{",
+                "    extern __shared__ __align__(16) unsigned char smem_raw[];",
+                f"    many_sync_body<{vt}>(a, g, reinterpret_cast<{vt}*>(smem_raw), DispatchLooped_{name}{{}});",
+                "}",
+                f"const void* many_sync_kernel_{name}_address() {{",
+                f"    return reinterpret_cast<const void*>(&many_sync_kernel_{name});",
+                "}",
+                "}  // namespace offt",
+            ]
+            spath = os.path.join(outdir, f"many_sync_{name}.hip")
+            stext = "\n".join(sl) + "\n"
+            if not os.path.exists(spath) or open(spath).read() != stext:
+                with open(spath, "w") as f:
+                    f.write(stext)
+            files.append(spath)
     inc = [f"extern const ManyExecutor g_many_{ex}_{prec};" for prec in ("f64", "f32") for ex, _ in EXECUTORS]
     inc.append("#define OFFT_MANY_EXECUTORS_F64 " + ", ".join(f"&g_many_{ex}_f64" for ex, _ in EXECUTORS))
     inc.append("#define OFFT_MANY_EXECUTORS_F32 " + ", ".join(f"&g_many_{ex}_f32" for ex, _ in EXECUTORS))
+    # the level-synchronous kernels live in files of their own (their looped
+    # tile code and register budget would otherwise change the code of the
+    # level kernels); their addresses are looked up through these functions
+    inc += [f"const void* many_sync_kernel_{ex}_{prec}_address();" for prec in ("f64", "f32") for ex, _ in EXECUTORS]
+    inc.append("inline const void* many_sync_kernel(const ManyExecutor* e) {")
+    for prec in ("f64", "f32"):
+        for ex, _ in EXECUTORS:
+            inc.append(f"    if (e == &g_many_{ex}_{prec}) return many_sync_kernel_{ex}_{prec}_address();")
+    inc += ["    return nullptr;", "}"]
     text = "\n".join(inc) + "\n"
     path = os.path.join(outdir, "many_executors.inc")
     if not os.path.exists(path) or open(path).read() != text:

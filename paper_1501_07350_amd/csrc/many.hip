@@ -66,11 +66,8 @@ struct ManyState {
     hipGraphNode_t node_many = nullptr;
     ManyArgs gargs{};
     bool graph_ready = false;
-    // level-synchronous persistent form: (level, case) groups and its graph
-    ManyGroup* d_groups = nullptr;
-    int* d_gseg = nullptr;
-    ManyRange* d_ranges = nullptr;
-    int ncases = 0;
+    int* d_tile_seg = nullptr;   // segment of every tile (level kernels, level-synchronous form)
+    // level-synchronous persistent form and its graph
     int sync_nblocks = 0;
     hipGraph_t sgraph = nullptr;
     hipGraphExec_t sgexec = nullptr;
@@ -160,8 +157,6 @@ static int build_many(offt_plan_s* p, hipStream_t s) {
     }
     ManyTables tab;
     build_many_tables(gd, (int64_t)es, kManyThreads, std::min(kManyLdsBudget, lds_limit()), kTilesPerItem, &tab);
-    m->ncases = m->exec ? m->exec->ncases : 0;
-    if (m->exec) build_many_groups(&tab, m->ncases);
     std::vector<ManySeg>& segs = tab.segs;
     const int64_t items = tab.total_items;
     const size_t lds_max = tab.lds_bytes;
@@ -177,9 +172,15 @@ static int build_many(offt_plan_s* p, hipStream_t s) {
     int rc = dev_alloc(p, sizeof(ManySeg) * segs.size(), &d);
     if (rc) return rc;
     m->d_segs = static_cast<ManySeg*>(d);
+    rc = dev_alloc(p, sizeof(int) * std::max<size_t>(tab.tile_seg.size(), 1), &d);
+    if (rc) return rc;
+    m->d_tile_seg = static_cast<int*>(d);
+    if (!tab.tile_seg.empty() && hipMemcpyAsync(m->d_tile_seg, tab.tile_seg.data(), sizeof(int) * tab.tile_seg.size(),
+                                                hipMemcpyHostToDevice, s) != hipSuccess)
+        return OFFT_ERR_HIP;
     // counters: queue head, error flag, one per segment, then the
-    // level-synchronous form's two level barriers and level queues
-    const size_t ncnt = kManyCounterBase + segs.size() + kManySyncCounters;
+    // level-synchronous form's two level barriers
+    const size_t ncnt = many_sync_base((int64_t)segs.size()) + kManySyncCounters;
     rc = dev_alloc(p, sizeof(unsigned) * ncnt, &d);
     if (rc) return rc;
     m->d_counters = static_cast<unsigned*>(d);
@@ -187,24 +188,6 @@ static int build_many(offt_plan_s* p, hipStream_t s) {
             hipSuccess ||
         hipMemsetAsync(m->d_counters, 0, sizeof(unsigned) * ncnt, s) != hipSuccess)
         return OFFT_ERR_HIP;
-    if (!tab.groups.empty()) {
-        rc = dev_alloc(p, sizeof(ManyGroup) * tab.groups.size(), &d);
-        if (rc) return rc;
-        m->d_groups = static_cast<ManyGroup*>(d);
-        rc = dev_alloc(p, sizeof(int) * std::max<size_t>(tab.gseg.size(), 1), &d);
-        if (rc) return rc;
-        m->d_gseg = static_cast<int*>(d);
-        rc = dev_alloc(p, sizeof(ManyRange) * tab.ranges.size(), &d);
-        if (rc) return rc;
-        m->d_ranges = static_cast<ManyRange*>(d);
-        if (hipMemcpyAsync(m->d_groups, tab.groups.data(), sizeof(ManyGroup) * tab.groups.size(),
-                           hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipMemcpyAsync(m->d_ranges, tab.ranges.data(), sizeof(ManyRange) * tab.ranges.size(),
-                           hipMemcpyHostToDevice, s) != hipSuccess ||
-            (!tab.gseg.empty() && hipMemcpyAsync(m->d_gseg, tab.gseg.data(), sizeof(int) * tab.gseg.size(),
-                                                 hipMemcpyHostToDevice, s) != hipSuccess))
-            return OFFT_ERR_HIP;
-    }
     if (!m->persistent_ok) return OFFT_SUCCESS;
     // occupancy-sized persistent grid
     m->kernel = m->exec->kernel;
@@ -222,11 +205,11 @@ static int build_many(offt_plan_s* p, hipStream_t s) {
     // the level-synchronous kernel: every workgroup resident (its grid barrier
     // waits for all of them), so exactly what fits the device at once
     if (m->lds > 65536 &&
-        hipFuncSetAttribute(m->exec->sync_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->lds) !=
+        hipFuncSetAttribute(many_sync_kernel(m->exec), hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->lds) !=
             hipSuccess)
         return OFFT_ERR_HIP;
     int sync_per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&sync_per_cu, m->exec->sync_kernel, kManyThreads, m->lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&sync_per_cu, many_sync_kernel(m->exec), kManyThreads, m->lds) !=
         hipSuccess)
         return OFFT_ERR_HIP;
     m->sync_nblocks = std::max(sync_per_cu, 1) * cus;
@@ -239,6 +222,7 @@ static ManyArgs make_args(const ManyState* m, const void* in, void* out, int dir
     a.in = in;
     a.out = out;
     a.segs = m->d_segs;
+    a.tile_seg = m->d_tile_seg;
     a.counters = m->d_counters;
     a.total_items = m->total_items;
     a.nseg = m->nseg;
@@ -321,23 +305,19 @@ static int launch_persistent(ManyState* m, const void* in, void* out, int dir, h
 static ManySyncArgs make_sync_args(const ManyState* m) {
     ManySyncArgs g;
     memset(&g, 0, sizeof g);
-    g.groups = m->d_groups;
-    g.gseg = m->d_gseg;
-    g.ranges = m->d_ranges;
-    g.barrier = m->d_counters + kManyCounterBase + m->nseg;
-    g.queue = g.barrier + 2;
-    g.ncases = m->ncases;
+    for (int l = 0; l < 4; ++l) g.level_tile_begin[l] = m->level_tile_begin[l];
+    g.barrier = m->d_counters + many_sync_base(m->nseg);
     return g;
 }
 
 static int launch_sync(ManyState* m, const void* in, void* out, int dir, hipStream_t s) {
-    const int ncnt = kManyCounterBase + m->nseg + kManySyncCounters;
+    const int ncnt = (int)(many_sync_base(m->nseg) + kManySyncCounters);
     hipLaunchKernelGGL(many_reset_kernel, dim3(1), dim3(256), 0, s, m->d_counters, ncnt);
     if (hipGetLastError() != hipSuccess) return OFFT_ERR_HIP;
     ManyArgs a = make_args(m, in, out, dir);
     ManySyncArgs g = make_sync_args(m);
     void* params[] = {&a, &g};
-    if (hipLaunchKernel(m->exec->sync_kernel, dim3(m->sync_nblocks), dim3(kManyThreads), params, m->lds, s) !=
+    if (hipLaunchKernel(many_sync_kernel(m->exec), dim3(m->sync_nblocks), dim3(kManyThreads), params, m->lds, s) !=
         hipSuccess)
         return OFFT_ERR_HIP;
     return OFFT_SUCCESS;
@@ -351,7 +331,7 @@ static int sync_graph_launch(ManyState* m, const void* in, void* out, int dir, h
         memset(kp, 0, sizeof *kp);
         params[0] = &m->sargs;
         params[1] = &g;
-        kp->func = const_cast<void*>(m->exec->sync_kernel);
+        kp->func = const_cast<void*>(many_sync_kernel(m->exec));
         kp->gridDim = dim3(m->sync_nblocks);
         kp->blockDim = dim3(kManyThreads);
         kp->sharedMemBytes = (unsigned)m->lds;
@@ -359,7 +339,7 @@ static int sync_graph_launch(ManyState* m, const void* in, void* out, int dir, h
     };
     if (!m->sgraph_ready) {
         if (hipGraphCreate(&m->sgraph, 0) != hipSuccess) return OFFT_ERR_HIP;
-        int ncnt = kManyCounterBase + m->nseg + kManySyncCounters;
+        int ncnt = (int)(many_sync_base(m->nseg) + kManySyncCounters);
         unsigned* cnt = m->d_counters;
         void* rparams[] = {&cnt, &ncnt};
         hipKernelNodeParams rp;

@@ -41,7 +41,6 @@ struct ManySeg {
     int64_t M2;          // element stride of the pass axis
     int64_t item_base;   // first work item of the segment (items, not tiles)
     int64_t tile_base;   // first tile of the segment in the level kernels' tile numbering
-    int64_t group_tile_base;   // first tile of the segment within its (level, case) group
     const void* tw;      // twiddle table of the pass length
     double scale_bwd;    // scale of the grid's last pass in a backward transform
     int kid;             // kernel case in the executor's dispatch table
@@ -59,6 +58,7 @@ struct ManyArgs {
     const void* in;
     void* out;
     const ManySeg* segs;
+    const int* tile_seg; // [tile]: segment of each tile of the level kernels' numbering
     unsigned* counters;  // [0] queue head, [1] error flag, [2 + s] items done in segment s
     int64_t total_items;
     int nseg;
@@ -190,18 +190,6 @@ __device__ __forceinline__ void many_body(const ManyArgs& a, V* __restrict__ lds
     }
 }
 
-// Segment of tile `tile` in the level kernels' numbering: the last segment
-// with tile_base <= tile.
-__device__ __forceinline__ int find_segment_by_tile(const ManySeg* segs, int nseg, int64_t tile) {
-    int lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (segs[mid].tile_base <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 // Non-persistent form: one workgroup per tile of tiles
 // [tile_begin, tile_begin + gridDim.x), all of one pass level, so the kernel
 // boundary between levels orders the passes and no counters are used.
@@ -209,95 +197,35 @@ template <typename V, typename Dispatch>
 __device__ __forceinline__ void many_level_body(const ManyArgs& a, int64_t tile_begin, V* __restrict__ lds,
                                                 const Dispatch& dispatch) {
     const int64_t tile = tile_begin + (int64_t)blockIdx.x;
-    const int seg = find_segment_by_tile(a.segs, a.nseg, tile);
+    const int seg = a.tile_seg[tile];
     const ManySeg sg = a.segs[seg];
     const PassArgs p = segment_pass_args<V>(a, sg);
     dispatch(sg.kid, p, lds, (tile - sg.tile_base) << sg.logW);
 }
 
 // ---- level-synchronous persistent form ------------------------------------
-// One launch of gridDim.x workgroups, all resident.  Pass level by pass
-// level the workgroups take the level's tiles from queues, then meet at a
-// grid barrier after each level.  A level's tiles are split into kXcds
-// ranges, one queue counter each: range x holds, case after case, the x-th
-// share of every (level, kernel case) group's tiles (the group's segments in
-// grid order), cut into items of kSyncTilesPerPop consecutive tiles of one
-// case.  A workgroup pops items from the range of its own XCD (workgroups go
-// to the XCDs round-robin in launch order), then from the others'.  Item
-// numbers only grow, so a workgroup walks the cases in order, each case's
-// items in a loop of its own: the case's code is inlined without a loop
-// around a switch over all cases (whose hoisted values would all stay live),
-// and a range costs one pop per item plus one that finds it empty.  The next
-// item is popped before the current one runs, so the atomic's round trip
-// overlaps the tile's loads.  Tiles use plain stores; the barrier makes them
-// visible across XCDs: every thread waits for its stores, then one thread
-// releases at agent scope (L2 write-back), arrives, waits for all
-// workgroups, and acquires (L2 invalidate).  A barrier wait gives up after
-// spin_limit polls and raises the error flag, so the grid always drains even
-// if not every workgroup is resident (the results are then invalid and
-// offt_many_status says so).
-constexpr int kSyncTilesPerPop = 4;
-
-struct ManyGroup {
-    int seg_begin;       // [seg_begin, seg_end) into ManySyncArgs::gseg
-    int seg_end;
-    int64_t ntiles;      // tiles of the group
-};
-
-// The items of one (level, XCD range, case): items [item_begin, item_end) of
-// the range's queue cover the group's tiles [tile_begin, tile_end).
-struct ManyRange {
-    int64_t item_begin;
-    int64_t item_end;
-    int64_t tile_begin;
-    int64_t tile_end;
-};
+// One launch of gridDim.x workgroups, all resident (sized from the
+// occupancy of the kernel, three per CU).  Pass level by pass level each
+// workgroup runs the level's tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+// of the level kernels' numbering -- the order in which the hardware would
+// hand the level kernel's workgroups out -- and the workgroups meet at a grid
+// barrier after each level.  No atomics are taken per tile: device-scope
+// atomics serialise on their address, and a shared tile queue costs more
+// than the imbalance it removes (consecutive tiles come from one segment, so
+// a round-robin deal gives every workgroup near-equal work).  The tile code
+// is one out-of-line call, so the loop keeps only its own few values live.
+// Tiles use plain stores; the barrier makes them visible across XCDs: every
+// thread waits for its stores, then one thread releases at agent scope (L2
+// write-back), arrives, waits for all workgroups, and acquires (L2
+// invalidate).  A barrier wait gives up after spin_limit polls and raises
+// the error flag, so the grid always drains even if not every workgroup is
+// resident (the results are then invalid and offt_many_status says so).
+constexpr int kManySyncStride = 64;   // the two barrier counters 256 bytes apart
 
 struct ManySyncArgs {
-    const ManyGroup* groups;   // [level * ncases + case]
-    const int* gseg;           // segment indices, grouped by (level, case), grid order within a group
-    const ManyRange* ranges;   // [(level * kXcds + x) * ncases + case]
-    unsigned* queue;           // [level * kXcds + x]: items taken from range x (zeroed)
-    unsigned* barrier;         // one arrival counter per level boundary (zeroed before the launch)
-    int ncases;
-    int pad_;
+    int64_t level_tile_begin[4];   // tiles of level l: [level_tile_begin[l], level_tile_begin[l + 1])
+    unsigned* barrier;             // [l * kManySyncStride]: arrivals at level boundary l (zeroed before the launch)
 };
-
-// Items of case kid in range `rg` while the workgroup's current item `*item`
-// (the same in every thread) falls in them; pops the next one from `queue`.
-template <typename V, typename TileFn>
-__device__ __forceinline__ void many_sync_case(const ManyArgs& a, const ManySyncArgs& g, int lvl, int kid,
-                                               const ManyRange* rg, unsigned* queue, int64_t* item,
-                                               int64_t* s_next, TileFn&& tile) {
-    if (kid >= g.ncases) return;   // a table of fewer cases than the kernel's: nothing to run
-    const ManyRange r = rg[kid];
-    if (*item >= r.item_end) return;
-    const ManyGroup gr = g.groups[lvl * g.ncases + kid];
-    while (*item < r.item_end) {
-        unsigned next = 0;
-        if (threadIdx.x == 0)
-            next = __hip_atomic_fetch_add(queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int64_t t0 = r.tile_begin + (*item - r.item_begin) * kSyncTilesPerPop;
-        const int64_t t1 = t0 + kSyncTilesPerPop < r.tile_end ? t0 + kSyncTilesPerPop : r.tile_end;
-        for (int64_t t = t0; t < t1; ++t) {
-            // segment of group tile t: the last with group_tile_base <= t
-            int lo = gr.seg_begin, hi = gr.seg_end - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (a.segs[g.gseg[mid]].group_tile_base <= t) lo = mid;
-                else hi = mid - 1;
-            }
-            const ManySeg sg = a.segs[g.gseg[lo]];
-            const PassArgs p = segment_pass_args<V>(a, sg);
-            if (t > t0) __syncthreads();   // the previous tile is done with LDS
-            tile(p, (t - sg.group_tile_base) << sg.logW);
-        }
-        __syncthreads();   // the tiles are done with LDS and every thread has read the broadcast slot
-        if (threadIdx.x == 0) *s_next = (int64_t)next;
-        __syncthreads();
-        *item = *s_next;
-    }
-}
 
 __device__ __forceinline__ void many_grid_barrier(const ManyArgs& a, unsigned* counter) {
     wait_own_stores();
@@ -311,40 +239,18 @@ __device__ __forceinline__ void many_grid_barrier(const ManyArgs& a, unsigned* c
     __syncthreads();
 }
 
-// Every range of one level, the workgroup's own XCD's first, each range's
-// cases in case order.  Case types provide `static constexpr int kid` and
-// `static void tile(const PassArgs&, V* lds, int64_t l0)`.
-template <typename V, typename... Cases>
-__device__ __forceinline__ void many_sync_level(const ManyArgs& a, const ManySyncArgs& g, int lvl, V* __restrict__ lds,
-                                                int64_t* s_next) {
-    const int own = (int)(blockIdx.x % kXcds);
-    for (int v = 0; v < kXcds; ++v) {
-        const int x = (own + v) % kXcds;
-        const ManyRange* rg = g.ranges + (int64_t)(lvl * kXcds + x) * g.ncases;
-        if (g.ncases == 0 || rg[g.ncases - 1].item_end == 0) continue;   // an empty range: no pop
-        unsigned* queue = g.queue + lvl * kXcds + x;
-        __syncthreads();   // every thread has read the broadcast slot
-        if (threadIdx.x == 0)
-            *s_next = (int64_t)__hip_atomic_fetch_add(queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        int64_t item = *s_next;
-        (many_sync_case<V>(a, g, lvl, Cases::kid, rg, queue, &item, s_next,
-                           [&](const PassArgs& p, int64_t l0) { Cases::tile(p, lds, l0); }),
-         ...);
+template <typename V, typename Dispatch>
+__device__ __forceinline__ void many_sync_body(const ManyArgs& a, const ManySyncArgs& g, V* __restrict__ lds,
+                                               const Dispatch& dispatch) {
+    for (int lvl = 0; lvl < 3; ++lvl) {
+        for (int64_t t = g.level_tile_begin[lvl] + blockIdx.x; t < g.level_tile_begin[lvl + 1]; t += gridDim.x) {
+            const ManySeg sg = a.segs[a.tile_seg[t]];
+            const PassArgs p = segment_pass_args<V>(a, sg);
+            __syncthreads();   // the previous tile is done with LDS
+            dispatch(sg.kid, p, lds, (t - sg.tile_base) << sg.logW);
+        }
+        if (lvl < 2) many_grid_barrier(a, g.barrier + lvl * kManySyncStride);
     }
-}
-
-// The whole transform of the batch: three levels, two grid barriers (the
-// levels written out, so that no value is kept live from one level's loops
-// into the next).
-template <typename V, typename... Cases>
-__device__ __forceinline__ void many_sync_body(const ManyArgs& a, const ManySyncArgs& g, V* __restrict__ lds) {
-    __shared__ int64_t s_next;
-    many_sync_level<V, Cases...>(a, g, 0, lds, &s_next);
-    many_grid_barrier(a, g.barrier + 0);
-    many_sync_level<V, Cases...>(a, g, 1, lds, &s_next);
-    many_grid_barrier(a, g.barrier + 1);
-    many_sync_level<V, Cases...>(a, g, 2, lds, &s_next);
 }
 
 }  // namespace offt

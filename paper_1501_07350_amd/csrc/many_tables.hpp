@@ -42,20 +42,19 @@ struct ManyGridDesc {
 struct ManyTables {
     std::vector<ManySeg> segs;          // level-major, grid order within a level
     int64_t level_begin[4] = {0, 0, 0, 0};        // work items of level l: [level_begin[l], level_begin[l+1])
-    int64_t level_tile_begin[4] = {0, 0, 0, 0};   // tiles of level l (level kernels and queues)
+    int64_t level_tile_begin[4] = {0, 0, 0, 0};   // tiles of level l (level kernels, level-synchronous form)
     int64_t total_items = 0;
     size_t lds_bytes = 0;               // dynamic LDS of the launch: the largest tile
     std::vector<int> seg_level;         // pass level of each segment
-    // level-synchronous form: (level, case) groups of segments in grid order
-    // (build_many_groups), tiles numbered within a group
-    std::vector<ManyGroup> groups;      // [level * ncases + case]
-    std::vector<int> gseg;
-    std::vector<ManyRange> ranges;      // [(level * kXcds + x) * ncases + case]
+    std::vector<int> tile_seg;          // [tile]: segment of each tile (level kernels' numbering)
 };
 
-// Counters of the level-synchronous form after the segment counters: two
-// level barriers, then one queue per level and XCD range.
-constexpr int kManySyncCounters = 2 + 3 * kXcds;
+// Counters of the level-synchronous form, after the segment counters from a
+// 256-byte boundary on: its two level barriers, each alone in 256 bytes.
+constexpr int kManySyncCounters = 2 * kManySyncStride;
+inline int64_t many_sync_base(int64_t nseg) {
+    return (kManyCounterBase + nseg + kManySyncStride - 1) / kManySyncStride * kManySyncStride;
+}
 
 // Tile width of a pass inside the executors: as many lines as fill `threads`
 // threads, within `lds_budget` bytes of LDS.
@@ -118,47 +117,13 @@ inline void build_many_tables(const std::vector<ManyGridDesc>& grids, int64_t el
         t->level_begin[lv] = items;
         t->level_tile_begin[lv] = tiles;
     }
+    // segment of every tile of the level kernels' numbering
+    t->tile_seg.assign((size_t)tiles, 0);
+    for (size_t i = 0; i < t->segs.size(); ++i)
+        std::fill(t->tile_seg.begin() + t->segs[i].tile_base,
+                  t->tile_seg.begin() + t->segs[i].tile_base + t->segs[i].ntiles, (int)i);
     t->total_items = items;
     t->seg_level = seg_level;
-}
-
-// The (level, case) groups of the level-synchronous form over `ncases`
-// kernel cases: each group's segments in grid order, group_tile_base of each
-// segment its first tile within the group; and the level queues' ranges:
-// range x of a level takes the x-th of kXcds near-equal shares of every
-// group's tiles, case after case, in items of kSyncTilesPerPop tiles.
-inline void build_many_groups(ManyTables* t, int ncases) {
-    t->groups.assign((size_t)3 * ncases, ManyGroup{0, 0, 0});
-    t->gseg.clear();
-    for (int lvl = 0; lvl < 3; ++lvl) {
-        for (int c = 0; c < ncases; ++c) {
-            ManyGroup& gr = t->groups[(size_t)lvl * ncases + c];
-            gr.seg_begin = (int)t->gseg.size();
-            gr.ntiles = 0;
-            for (size_t i = 0; i < t->segs.size(); ++i) {
-                if (t->seg_level[i] != lvl || t->segs[i].kid != c) continue;
-                t->segs[i].group_tile_base = gr.ntiles;
-                gr.ntiles += t->segs[i].ntiles;
-                t->gseg.push_back((int)i);
-            }
-            gr.seg_end = (int)t->gseg.size();
-        }
-    }
-    t->ranges.assign((size_t)3 * kXcds * ncases, ManyRange{0, 0, 0, 0});
-    for (int lvl = 0; lvl < 3; ++lvl) {
-        for (int x = 0; x < kXcds; ++x) {
-            int64_t item = 0;
-            for (int c = 0; c < ncases; ++c) {
-                const int64_t n = t->groups[(size_t)lvl * ncases + c].ntiles;
-                ManyRange& r = t->ranges[((size_t)lvl * kXcds + x) * ncases + c];
-                r.tile_begin = n * x / kXcds;
-                r.tile_end = n * (x + 1) / kXcds;
-                r.item_begin = item;
-                item += (r.tile_end - r.tile_begin + kSyncTilesPerPop - 1) / kSyncTilesPerPop;
-                r.item_end = item;
-            }
-        }
-    }
 }
 
 }  // namespace offt

@@ -52,7 +52,6 @@ struct ManyExecutor {
     int ncases;
     const void* kernel;        // persistent kernel (ManyArgs)
     const void* level_kernel;  // one tile per workgroup (ManyArgs, int64_t tile_begin)
-    const void* sync_kernel;   // level-synchronous persistent kernel (ManyArgs, ManySyncArgs)
 };
 
 // Registry of all compiled pass kernels (generated tables).

@@ -15,8 +15,11 @@
 //       <L> <kid> <mode> <nlines> <M2> <tpl>.  The optional <seg> <dep>
 //       makes segment seg wait for segment dep instead.
 //   emu_driver sync <dtype> <nwg> <ngrids> <grids...> <total>
-//       the level-synchronous persistent body (tile queue per level, grid
-//       barriers between levels) over the batch executor's cases
+//       the level-synchronous persistent body (each level's tiles dealt
+//       round-robin, grid barriers between levels) over the batch
+//       executor's cases
+//   emu_driver levels <dtype> <nwg> <ngrids> <grids...> <total>
+//       the level kernels' body, one workgroup per tile, level after level
 //   emu_driver route <Na> <Nb> <Nc> <np> <in_order> <out_order> <per_chunk>
 //       one exchange of the distributed flow with the library's own tables
 //       (dist_tables.hpp) and exchange code (dist_device.hpp): every
@@ -84,7 +87,7 @@ static bool run_block(int threads, const std::function<void(int)>& fn) {
 }
 
 template <typename V>
-static int do_many(int argc, char** argv, bool sync) {
+static int do_many(int argc, char** argv, bool sync, bool levels = false) {
     int k = 3;
     const int nwg = atoi(argv[k++]);
     const int ngrids = atoi(argv[k++]);
@@ -114,8 +117,6 @@ static int do_many(int argc, char** argv, bool sync) {
     // flags any access beyond what the GPU launch gets)
     ManyTables tab;
     build_many_tables(gd, (int64_t)sizeof(V), kManyThreads, kManyLdsBudget, kTilesPerItem, &tab);
-    const int ncases = sync ? EmuSync<V>::ncases : 0;
-    if (sync) build_many_groups(&tab, ncases);
     std::vector<ManySeg>& segs = tab.segs;
     const int nseg = (int)segs.size();
     {
@@ -141,8 +142,8 @@ static int do_many(int argc, char** argv, bool sync) {
     const int64_t items = tab.total_items;
     const int threads = kManyThreads;
     // shared between the workgroup processes: buffers, counters, two level
-    // barriers, the level queues (one per level and XCD range)
-    const int ncnt = kManyCounterBase + nseg + kManySyncCounters;
+    // barriers of the level-synchronous form
+    const int ncnt = (int)(many_sync_base(nseg) + kManySyncCounters);
     const size_t bytes = sizeof(V) * 2 * (size_t)total + sizeof(unsigned) * ncnt;
     void* shm = mmap(nullptr, bytes, PROT_READ | PROT_WRITE, MAP_SHARED | MAP_ANONYMOUS, -1, 0);
     if (shm == MAP_FAILED) return 3;
@@ -157,18 +158,15 @@ static int do_many(int argc, char** argv, bool sync) {
     for (int i = 0; i < ncnt; ++i) counters[i] = 0u;
     ManySyncArgs sa;
     memset(&sa, 0, sizeof sa);
-    sa.groups = tab.groups.data();
-    sa.gseg = tab.gseg.data();
-    sa.ranges = tab.ranges.data();
-    sa.barrier = counters + kManyCounterBase + nseg;
-    sa.queue = sa.barrier + 2;
-    sa.ncases = ncases;
+    for (int l = 0; l < 4; ++l) sa.level_tile_begin[l] = tab.level_tile_begin[l];
+    sa.barrier = counters + many_sync_base(nseg);
     gridDim.x = (unsigned)nwg;
     ManyArgs a;
     memset(&a, 0, sizeof a);
     a.in = in;
     a.out = out;
     a.segs = segs.data();
+    a.tile_seg = tab.tile_seg.data();
     a.counters = counters;
     a.total_items = items;
     a.nseg = nseg;
@@ -178,9 +176,31 @@ static int do_many(int argc, char** argv, bool sync) {
     a.spin_limit = getenv("EMU_SPIN_LIMIT") ? atoi(getenv("EMU_SPIN_LIMIT")) : 1 << 22;
     blockDim.x = threads;
     auto body = [&](V* lds) {
-        if (sync) EmuSync<V>::body(a, sa, lds);
+        if (sync) many_sync_body<V>(a, sa, lds, EmuLevelDispatch<V>{});
         else many_body<V>(a, lds, EmuDispatch<V>{});
     };
+    if (levels) {
+        // one workgroup per tile, the levels one after the other
+        std::vector<V> lds(lds_elems);
+        bool okl = true;
+        for (int l = 0; l < 3; ++l) {
+            const int64_t begin = tab.level_tile_begin[l];
+            gridDim.x = (unsigned)(tab.level_tile_begin[l + 1] - begin);
+            for (unsigned b = 0; b < gridDim.x; ++b) {
+                blockIdx.x = b;
+                okl = run_block(threads, [&](int) {
+                    many_level_body<V>(a, begin, lds.data(), EmuLevelDispatch<V>{});
+                }) && okl;
+            }
+        }
+        if (!okl) {
+            std::printf("FAIL barrier\n");
+            return 1;
+        }
+        std::printf("OK %lld tiles\n", (long long)tab.level_tile_begin[3]);
+        for (int64_t i = 0; i < total; ++i) std::printf("%.17g %.17g\n", (double)out[i].x, (double)out[i].y);
+        return 0;
+    }
     std::vector<pid_t> kids;
     for (int wg = 1; wg < nwg; ++wg) {
         const pid_t pid = fork();
@@ -205,8 +225,8 @@ static int do_many(int argc, char** argv, bool sync) {
         return 1;
     }
     for (int l = 0; sync && l < 2; ++l)   // every workgroup arrived at both level barriers
-        if (counters[kManyCounterBase + nseg + l] != (unsigned)nwg) {
-            std::printf("FAIL barrier %d arrivals %u of %d\n", l, counters[kManyCounterBase + nseg + l], nwg);
+        if (sa.barrier[l * kManySyncStride] != (unsigned)nwg) {
+            std::printf("FAIL barrier %d arrivals %u of %d\n", l, sa.barrier[l * kManySyncStride], nwg);
             return 1;
         }
     for (int s = 0; !sync && s < nseg; ++s)   // a grid's last pass publishes nothing
@@ -288,8 +308,8 @@ static void run_grid(unsigned blocks, unsigned threads, const std::function<void
 // The pack kernel's body with its LDS tile (a static: shared by the
 // emulated threads of one workgroup).
 static void emu_pack(const PackArgs& a) {
-    __shared__ double2 tile[kPackTile][kPackTile + 1];
-    pack_tile<double2>(a, tile);
+    __shared__ PackShared<double2> sh;
+    pack_tile<double2>(a, sh);
 }
 
 // Blocks one after the other, the threads of each concurrently with a
@@ -432,6 +452,8 @@ int main(int argc, char** argv) {
     const int dtype = atoi(argv[2]);
     if (mode == "many") return dtype == 0 ? do_many<double2>(argc, argv, false) : do_many<float2>(argc, argv, false);
     if (mode == "sync") return dtype == 0 ? do_many<double2>(argc, argv, true) : do_many<float2>(argc, argv, true);
+    if (mode == "levels")
+        return dtype == 0 ? do_many<double2>(argc, argv, false, true) : do_many<float2>(argc, argv, false, true);
     if (mode == "pass") return dtype == 0 ? do_pass<double2>(argc, argv) : do_pass<float2>(argc, argv);
     return 2;
 }

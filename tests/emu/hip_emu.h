@@ -71,6 +71,8 @@ inline void __syncthreads() {
 #define __builtin_amdgcn_fence(o, scope) __atomic_thread_fence(o)
 #define __builtin_amdgcn_s_sleep(n) std::this_thread::sleep_for(std::chrono::microseconds(20))
 #define __builtin_amdgcn_s_waitcnt(n) ((void)0)
+// A value made opaque to the device compiler's loop hoisting: nothing to do on the host.
+#define OFFT_OPAQUE_VGPR(x) ((void)(x))
 // One emulated thread per wavefront: a wave-uniform value is the thread's own.
 #define __builtin_amdgcn_readfirstlane(x) (x)
 

@@ -9,11 +9,12 @@ test.  The persistent batch loop runs as a single workgroup, which takes the
 work items in order, so every dependency is met by construction; the check is
 on the tile code, the barrier structure and the bookkeeping.
 """
+import fcntl
+import hashlib
 import importlib.util
 import os
 import shutil
 import subprocess
-import tempfile
 
 import numpy as np
 import pytest
@@ -47,11 +48,11 @@ def plain_cases(gk, prec):
 
 @pytest.fixture(scope="module")
 def emu_binary():
-    # one build folder per test process, so that parallel workers never run a
-    # driver another worker is still writing
+    # the driver is built once per content (generated cases, driver, device
+    # headers, command) into BUILD/<hash>; parallel test processes wait on a
+    # lock for the one that builds it
     gk = gen_kernels()
     os.makedirs(BUILD, exist_ok=True)
-    build = tempfile.mkdtemp(prefix=f"pid{os.getpid()}_", dir=BUILD)
     lines = ["template <typename V> struct EmuDispatch;"]
     for vt, prec in (("double2", "f64"), ("float2", "f32")):
         lines.append(f"template <> struct EmuDispatch<{vt}> {{")
@@ -73,27 +74,44 @@ def emu_binary():
                                   for P in (1, 2, 4) if gk.splits(L, seq, P)])
             lines.append(f"      case {i}: {body} break;")
         lines.append("      default: break;\n    }\n  }\n};")
-    # the level-synchronous body over the batch executor's cases (plain
-    # stores, each case's tiles in a loop of their own)
-    lines.insert(0, "template <typename V> struct EmuSync;")
+    # the level kernels' and the level-synchronous form's dispatch over the
+    # batch executor's cases (plain stores)
+    lines.insert(0, "template <typename V> struct EmuLevelDispatch;")
     for vt, prec in (("double2", "f64"), ("float2", "f32")):
-        names = []
+        lines.append(f"template <> struct EmuLevelDispatch<{vt}> {{")
+        lines.append(f"  void operator()(int kid, const PassArgs& a, {vt}* lds, int64_t l0) const {{")
+        lines.append("    switch (kid) {")
         for i, (L, seq, tpl) in enumerate(gk.many_cases(prec, "batch")):
-            names.append(f"EmuSyncCase{i}_{prec}")
-            lines.append(f"struct {names[-1]} {{ static constexpr int kid = {i}; static void tile(const PassArgs& p, "
-                         f"{vt}* lds, int64_t l0) {{ pass_tile<{vt}, {L}, {tpl}, {', '.join(map(str, seq))}>(p, lds, l0); }} }};")
-        lines.append(f"template <> struct EmuSync<{vt}> {{ static constexpr int ncases = {len(names)}; "
-                     f"static void body(const ManyArgs& a, const ManySyncArgs& g, "
-                     f"{vt}* lds) {{ many_sync_body<{vt}, {', '.join(names)}>(a, g, lds); }} }};")
-    with open(os.path.join(build, "emu_cases.inc"), "w") as f:
-        f.write("namespace offt {\n" + "\n".join(lines) + "\n}\n")
+            lines.append(f"      case {i}: pass_tile<{vt}, {L}, {tpl}, {', '.join(map(str, seq))}>(a, lds, l0); break;")
+        lines.append("      default: break;\n    }\n  }\n};")
+    cases_text = "namespace offt {\n" + "\n".join(lines) + "\n}\n"
+    flags = ["-std=c++17", "-O1", "-g", "-pthread", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
+    h = hashlib.sha256(cases_text.encode() + " ".join(flags).encode())
+    for d in (EMU, CSRC):
+        for name in sorted(os.listdir(d)):
+            if name.endswith((".h", ".hpp", ".cpp")):
+                with open(os.path.join(d, name), "rb") as f:
+                    h.update(name.encode() + f.read())
+    build = os.path.join(BUILD, h.hexdigest()[:16])
     exe = os.path.join(build, "emu_driver")
-    cmd = ["g++", "-std=c++17", "-O1", "-g", "-pthread", "-fsanitize=address,undefined",
-           "-fno-sanitize-recover=undefined", "-I", EMU, "-I", build, "-I", CSRC,
-           os.path.join(EMU, "emu_driver.cpp"), "-o", exe]
-    subprocess.run(cmd, check=True)
+    with open(os.path.join(BUILD, "lock"), "w") as lk:
+        fcntl.flock(lk, fcntl.LOCK_EX)
+        try:
+            if not os.path.exists(exe):
+                # drivers of older sources are not needed any more
+                for old in os.listdir(BUILD):
+                    if old != "lock" and os.path.isdir(os.path.join(BUILD, old)):
+                        shutil.rmtree(os.path.join(BUILD, old), ignore_errors=True)
+                os.makedirs(build, exist_ok=True)
+                with open(os.path.join(build, "emu_cases.inc"), "w") as f:
+                    f.write(cases_text)
+                cmd = ["g++"] + flags + ["-I", EMU, "-I", build, "-I", CSRC, os.path.join(EMU, "emu_driver.cpp"),
+                                         "-o", exe + ".tmp"]
+                subprocess.run(cmd, check=True)
+                os.replace(exe + ".tmp", exe)
+        finally:
+            fcntl.flock(lk, fcntl.LOCK_UN)
     yield exe
-    shutil.rmtree(build, ignore_errors=True)
 
 
 ORDER_NAMES = ["abc", "cab", "cba"]
@@ -193,11 +211,11 @@ def grid_args(dims_list, dtype, which="all"):
     return args, offs, total, npass
 
 
-def run_many(exe, dims_list, dtype, nwg=1, sync=False):
-    args, offs, total, _ = grid_args(dims_list, dtype, "batch" if sync else "all")
+def run_many(exe, dims_list, dtype, nwg=1, sync=False, levels=False):
+    args, offs, total, _ = grid_args(dims_list, dtype, "batch" if (sync or levels) else "all")
     code = "0" if dtype == torch.complex128 else "1"
-    r = subprocess.run([exe, "sync" if sync else "many", code, str(nwg)] + args, capture_output=True, text=True,
-                       timeout=600)
+    mode = "levels" if levels else "sync" if sync else "many"
+    r = subprocess.run([exe, mode, code, str(nwg)] + args, capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, (r.stdout[:500], r.stderr[-3000:])
     lines = r.stdout.splitlines()
     assert lines[0].startswith("OK"), lines[0]
@@ -436,10 +454,19 @@ SYNC_DIMS = [(48, 1, 60), (1, 64, 1), (16 * 3, 60, 64), (80, 96, 1), (1, 1, 1), 
 @pytest.mark.parametrize("nwg", [1, 3, 9])
 def test_emulated_level_synchronous_body(emu_binary, dtype, nwg):
     """The level-synchronous persistent body: nwg workgroups (one process
-    each) take items from the per-level XCD-range queues (their own range
-    first, then the others'; 9 puts two workgroups on one range), grid
-    barriers between levels in shared memory; every workgroup arrives at both
-    barriers, no wait times out, and every grid matches the oracle."""
+    each) take the level's tiles round-robin, grid barriers between levels in
+    shared memory; every workgroup arrives at both barriers, no wait times
+    out, and every grid matches the oracle."""
     dims = [tuple(min(v, 64) if v > 1 else 1 for v in d) for d in SYNC_DIMS]
     dims = [tuple(v if v in (1, 48, 60, 64) else 64 for v in d) for d in dims]
     run_many(emu_binary, dims, dtype, nwg=nwg, sync=True)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
+def test_emulated_level_kernels(emu_binary, dtype):
+    """The level kernels' body: one workgroup per tile, each finding its
+    segment in the library's tile table, level after level; every grid
+    matches the oracle."""
+    dims = [tuple(min(v, 64) if v > 1 else 1 for v in d) for d in SYNC_DIMS]
+    dims = [tuple(v if v in (1, 48, 60, 64) else 64 for v in d) for d in dims]
+    run_many(emu_binary, dims, dtype, levels=True)
