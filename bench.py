@@ -677,13 +677,33 @@ def summarize_stats(d: str, log: str, command: str, n: int, steps: int, warmup: 
             x = disp[k]
             dur.setdefault((r, i), ([], x["Kernel_Name"])).__getitem__(0).append(
                 (int(x["End_Timestamp"]) - int(x["Start_Timestamp"])) / 1e3)
+    # the copy of each pass's accesses (offt_copy_pass), run after each
+    # transform: per run, per pass, warmup + steps dispatches
+    copies = [r for r in trace if "copy_pattern_kernel" in r["Kernel_Name"]]
+    cdur = {}
+    k = 0
+    for r, (_, _, plan) in enumerate(runs):
+        for i in range(len(pass_keys(plan))):
+            for st in range(warmup + steps):
+                if k < len(copies) and st >= warmup:
+                    x = copies[k]
+                    cdur.setdefault((r, i), []).append((int(x["End_Timestamp"]) - int(x["Start_Timestamp"])) / 1e3)
+                k += 1
+    if k != len(copies):
+        raise RuntimeError(f"expected {k} copy dispatches, the trace holds {len(copies)}")
+    es = {"complex128": 16, "complex64": 8}
     lines.append("")
-    lines.append("# per-pass mean duration over the timed steps (from the dispatch trace)")
+    lines.append("# per-pass mean duration over the timed steps (from the dispatch trace), and the copy kernel")
+    lines.append("# of the same pass (its tiles, threads, tile order and access mode, no arithmetic)")
     for r, (tag, label, plan) in enumerate(runs):
         lines.append(f"{n}^3 {label}, plan {plan}")
+        nbytes = 2 * n ** 3 * es[label]
         for i, key in enumerate(pass_keys(plan)):
             v, name = dur[(r, i)]
-            lines.append(f"  pass {i} {key:<18} mean {sum(v)/len(v):9.2f} us over {len(v)} dispatches  {name[:100]}")
+            pm = sum(v) / len(v)
+            cm = sum(cdur[(r, i)]) / len(cdur[(r, i)])
+            lines.append(f"  pass {i} {key:<18} mean {pm:9.2f} us ({nbytes / (pm * 1e3):7.1f} GB/s), copy {cm:9.2f} us "
+                         f"({nbytes / (cm * 1e3):7.1f} GB/s), of copy {cm / pm:6.3f}  {name[:100]}")
     return "\n".join(lines) + "\n"
 
 

@@ -268,9 +268,9 @@ int offt_twiddles(int64_t n, int dtype, void* host_out);
  * o->tune = OFFT_TUNE_EXHAUSTIVE each distinct grid shape gets its own tuned
  * plan.  Execution (offt_exec_many and its default forms below) runs every
  * (grid, axis pass, tile) work item of the batch in one of several launch
- * forms: one kernel per pass level replayed from a HIP graph (the default,
- * fastest measured), one persistent kernel replayed from a graph, or each
- * grid's passes as separate launches.  Grids stay in natural order
+ * forms: one kernel per pass level, the three replayed from one HIP graph
+ * (the default, fastest measured), one persistent kernel replayed from a
+ * graph, or each grid's passes as separate launches.  Grids stay in natural order
  * (o->layout other than NATURAL is OFFT_ERR_INVALID_ARG).  Errors as
  * offt_plan_ex. */
 offt_plan_t offt_plan_many(int count, const int64_t* dims, int dtype, const offt_opts* o);
@@ -293,9 +293,9 @@ int64_t offt_many_offset(offt_plan_t p, int i);
  *    3  LEVELS: the same kernels launched directly;
  *    5  SYNC_GRAPH: one level-synchronous persistent kernel, after a counter
  *       reset, replayed from a HIP graph: one resident workgroup per slot the
- *       device has, each level's tiles dealt round-robin, a grid barrier
- *       between levels (each case's tiles in a loop of their own, plain
- *       stores, one L2 write-back and invalidate per workgroup per barrier);
+ *       device has, each level's tiles dealt round-robin in the level
+ *       kernels' order, a grid barrier between levels (plain stores, one L2
+ *       write-back and invalidate per workgroup per barrier);
  *    4  SYNC: the same two kernels launched directly;
  *   -1  SEPARATE_HEURISTIC: every grid's passes as ordinary launches with the
  *       heuristic plans;

@@ -100,3 +100,36 @@ def test_reversed_trace_summary(tmp_path):
     assert passes[11][2] == "a=8/8" and passes[11][3] == "(T)"
     assert [float(p[-4]) for p in passes[:3]] == [1.0, 1.1, 1.2]
     assert float(passes[23][-4]) == 8.2
+
+
+def test_stats_summary_with_copy_kernels(tmp_path):
+    """Per-pass means of a headline run from the dispatch trace: the
+    transform's passes, then each pass's copy kernel, per timed plan."""
+    steps, warmup, n = 2, 1, 8
+    p64, p32 = "order=cba;a=8/8;b=8/8/x;c=8/8", "order=abc;a=8/8;b=8/8;c=8/8"
+    log = tmp_path / "stats.log"
+    log.write_text("noise\n" + __import__("json").dumps({"plan": p64, "f32": {"plan": p32}}) + "\n")
+    d = []
+    for scale in (1, 2):                                   # complex128 run, then complex64
+        for st in range(warmup + steps):
+            d += [("offt::fft_pass_kernel<...>", (90_000 if st < warmup else 1_000 * (i + 1) * scale), 10)
+                  for i in range(3)]
+        for i in range(3):
+            d += [("offt::copy_pattern_kernel<...>", (70_000 if st < warmup else 500 * (i + 1) * scale), 10)
+                  for st in range(warmup + steps)]
+    write_trace(str(tmp_path / "run" / "run_kernel_trace.csv"), d)
+    with open(tmp_path / "run" / "run_kernel_stats.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs", "MinNs", "MaxNs",
+                                          "Percentage"])
+        w.writeheader()
+        w.writerow({"Name": "offt::fft_pass_kernel<...>", "Calls": 18, "TotalDurationNs": 1, "AverageNs": 1,
+                    "MinNs": 1, "MaxNs": 1, "Percentage": 100})
+    txt = load_bench().summarize_stats(str(tmp_path), str(log), "cmd", n, steps, warmup)
+    passes = [l.split() for l in txt.splitlines() if l.startswith("  pass")]
+    assert [float(p[4]) for p in passes] == [1.0, 2.0, 3.0, 2.0, 4.0, 6.0]
+    # copy kernels at half the pass time: "of copy" 0.5
+    assert [float(p[p.index("copy") + 1]) for p in passes] == [0.5, 1.0, 1.5, 1.0, 2.0, 3.0]
+    assert all(float(p[p.index("of") + 2]) == 0.5 for p in passes)
+    # 2 * 512 points * 16 bytes in 1 us = 16.4 GB/s; the copy in 0.5 us, 32.8
+    first = [l for l in txt.splitlines() if l.startswith("  pass")][0]
+    assert "16.4 GB/s" in first and "32.8 GB/s" in first
