@@ -707,6 +707,18 @@ def summarize_stats(d: str, log: str, command: str, n: int, steps: int, warmup: 
     return "\n".join(lines) + "\n"
 
 
+def summarize_kernels(d: str, command: str, title: str, top: int = 20) -> str:
+    """The kernel-statistics table of one rocprofv3 --stats run (the largest
+    total time first)."""
+    rows = _read_csv(_find(d, "kernel_stats.csv"))
+    lines = [f"# rocprofv3 kernel statistics: {title}", f"# command: {command}",
+             f"{'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total%':>7}  kernel"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:top]:
+        lines.append(f"{int(r['Calls']):>6} {float(r['AverageNs'])/1e3:>10.2f} {float(r['MinNs'])/1e3:>10.2f} "
+                     f"{float(r['MaxNs'])/1e3:>10.2f} {float(r['Percentage']):>7.2f}  {r['Name'][:150]}")
+    return "\n".join(lines) + "\n"
+
+
 def summarize_batch(d: str, command: str, steps: int, warmup: int) -> str:
     """Kernel-trace figures of the uneven-batch executors from one
     `--batch-only` run: per executor family, dispatches and mean duration;
@@ -1006,6 +1018,9 @@ def main():
                     help="time only the 4- and 5-axis grids (to profile their passes)")
     ap.add_argument("--summarize-nd", nargs=2, metavar=("DIR", "LOG"),
                     help="reduce a rocprofv3 --kernel-trace run of --nd-only")
+    ap.add_argument("--summarize-kernels", metavar="DIR",
+                    help="reduce a rocprofv3 --stats run to its kernel table (with --title)")
+    ap.add_argument("--title", default="", help="title of a --summarize-kernels table")
     ap.add_argument("--summarize-batch", metavar="DIR",
                     help="reduce a rocprofv3 --kernel-trace run of --batch-only")
     ap.add_argument("--configs", action="store_true",
@@ -1033,6 +1048,10 @@ def main():
         return
     if args.summarize_nd:
         txt = summarize_nd(args.summarize_nd[0], args.summarize_nd[1], args.command, args.steps, args.warmup)
+        open(args.out, "w").write(txt) if args.out else print(txt)
+        return
+    if args.summarize_kernels:
+        txt = summarize_kernels(args.summarize_kernels, args.command, args.title)
         open(args.out, "w").write(txt) if args.out else print(txt)
         return
     if args.summarize_batch:

@@ -1,9 +1,9 @@
 """Parity at the full workload sizes, against the full recursive oracle (O3)
 element by element: 256^3 and 512^3 complex128, 512^3 and 1024^3 complex64.
 
-Each size runs the heuristic plan and the tuned plans the benchmark times
-(the plan-cache entries for 512^3, the recorded tuned plan for 1024^3), in the
-benchmark's launch configuration: the passes launched one by one with
+Each size runs the heuristic plan and the tuned plan the benchmark times
+(the plan-cache entry of that size and precision), in the benchmark's launch
+configuration: the passes launched one by one with
 offt_exec_pass, out of place, on torch's current stream.  The error is the
 relative L2 norm over the whole grid (tolerance 1e-12 for binary64,
 2e-6 * log2(N) for binary32); the worst element error relative to the largest
@@ -25,8 +25,6 @@ pytestmark = pytest.mark.gpu
 C128, C64 = torch.complex128, torch.complex64
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PLAN_CACHE = os.path.join(ROOT, "paper_1501_07350_amd", "data", "plan_cache_mi355x.txt")
-# tuned 1024^3 complex64 plan recorded by the exhaustive tuner on MI355X
-TUNED_1024_C64 = "order=bca;a=32x32/32/p2/x;b=32x32/32/p2/x;c=16x8x8/2"
 
 
 def cached_plan(n, dtype):
@@ -96,6 +94,12 @@ def test_256_complex128_heuristic():
     check_full(256, C128)
 
 
+def test_256_complex128_tuned_cached_plan():
+    plan = cached_plan(256, C128)
+    assert plan, "plan cache has no 256^3 complex128 entry"
+    check_full(256, C128, plan)
+
+
 def test_512_complex128_heuristic():
     check_full(512, C128)
 
@@ -122,6 +126,8 @@ def test_1024_complex64_heuristic():
 
 
 @pytest.mark.timeout(900)
-def test_1024_complex64_tuned_plan():
-    check_full(1024, C64, TUNED_1024_C64)
+def test_1024_complex64_tuned_cached_plan():
+    plan = cached_plan(1024, C64)
+    assert plan, "plan cache has no 1024^3 complex64 entry"
+    check_full(1024, C64, plan)
     _REF.clear()
