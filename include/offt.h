@@ -340,10 +340,12 @@ int offt_many_status(offt_plan_t p);
  * reverse with the conjugate roots of unity.  in == out is allowed.
  *
  * A transpose packs each process's elements into one chunk per destination
- * (in the sender's local order), copies the chunks between the processes'
+ * (each chunk in the destination's order, a process's own chunk straight to
+ * its place), copies the chunks that change process between the processes'
  * send and receive slices, and unpacks them into the destination's local
- * array.  The copies follow one of the six communication methods of
- * Sec. 3.2.1 (OFFT_COMM_*):
+ * array (when a process receives only from itself its pack writes that
+ * array directly).  The copies follow one of the six communication methods
+ * of Sec. 3.2.1 (OFFT_COMM_*):
  *   ISEND_WAITALL        every chunk posted at once as its own copy on a
  *                        communication stream, then one wait for all, then
  *                        the unpacks;
@@ -358,10 +360,10 @@ int offt_many_status(offt_plan_t p);
  *                        the others are still in flight;
  *   ISEND_WAITSOME_BLOCK the same per group of block_size destinations, the
  *                        next group posted once the current one is unpacked;
- *   SENDRECV             nprocs steps: at step i every process sends to
- *                        process myid + i and receives from myid - i (mod
- *                        nprocs), the received chunk unpacked before the
- *                        next step.
+ *   SENDRECV             nprocs - 1 steps after the own chunk: at step i
+ *                        every process sends to process myid + i and
+ *                        receives from myid - i (mod nprocs), the received
+ *                        chunk unpacked before the next step.
  * OFFT_COMM_AUTO times every method at plan time on the plan's stream (one
  * warm-up and o->reps timed forward transforms each, minimum of two, median
  * of more) and keeps the fastest, ties to the lower id: the paper's
