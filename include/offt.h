@@ -461,8 +461,9 @@ int64_t offt_transpose_volume(int64_t n1, int64_t n2, int64_t n3, int64_t np, in
  * per grid shape (the heuristic plan first; then other radix sequences and
  * tile widths per axis; then the heuristic with one axis's tile order
  * switched between launch order and XCD-contiguous order; then the other five
- * axis orders).  These calls expose that list for building and using the
- * learned selector. */
+ * axis orders; then the heuristic with one axis's access mode switched
+ * between streaming and cached grid data).  These calls expose that list for
+ * building and using the learned selector. */
 
 /* Length of one plan feature vector. */
 int offt_feature_dim(void);

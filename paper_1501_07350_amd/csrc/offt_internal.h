@@ -146,6 +146,9 @@ PlanChoice default_choice(int dtype, const int64_t dims[3]);
 PlanChoice default_choice_reversed(int dtype, const int64_t dims[3]);
 // Candidate plans for tuning (deterministic order, default first).
 std::vector<PlanChoice> candidate_choices(int dtype, const int64_t dims[3]);
+// The learned selector's candidate list: candidate_choices, then the
+// heuristic with one axis's access mode switched (selector.cpp).
+std::vector<PlanChoice> selector_candidates(int dtype, const int64_t dims[3], int64_t batch);
 // The heuristic pass over `lines` contiguous lines of length L (kernel, tile
 // width, access mode for grid data of grid_bytes), twiddles not attached.
 PassPlan contiguous_pass(int dtype, int L, int64_t lines, int64_t grid_bytes);

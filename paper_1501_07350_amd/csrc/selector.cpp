@@ -30,6 +30,22 @@ namespace offt {
 
 static const int kOrders[6][3] = {{2, 1, 0}, {2, 0, 1}, {1, 2, 0}, {1, 0, 2}, {0, 2, 1}, {0, 1, 2}};
 
+std::vector<PlanChoice> selector_candidates(int dtype, const int64_t dims[3], int64_t batch) {
+    std::vector<PlanChoice> out = candidate_choices(dtype, dims);
+    if (out.empty()) return out;
+    // the heuristic with one axis's access mode switched (streaming <->
+    // cached grid data; by default the mode follows the grid's size)
+    const PlanChoice base = out[0];
+    const int64_t bytes = dims[0] * dims[1] * dims[2] * batch * (int64_t)elem_size(dtype);
+    for (int ax = 0; ax < 3; ++ax) {
+        if (dims[ax] <= 1 || !base.k[ax]) continue;
+        PlanChoice c = base;
+        c.io[ax] = resolve_stream(base.io[ax], bytes) ? kIoCached : kIoStream;
+        out.push_back(c);
+    }
+    return out;
+}
+
 void plan_features(int dtype, const int64_t dims[3], int64_t batch, const PlanChoice& c, float* f) {
     for (int i = 0; i < kFeatureDim; ++i) f[i] = 0.f;
     const double N = (double)dims[0] * (double)dims[1] * (double)dims[2];
@@ -66,6 +82,8 @@ void plan_features(int dtype, const int64_t dims[3], int64_t batch, const PlanCh
         g[10] = (float)pos[ax] * 0.5f;
         g[12] = (float)std::log2((double)k->nparts);
         g[13] = (float)c.xcd[ax];
+        // the access mode the pass runs with (streaming or cached grid data)
+        g[14] = (float)resolve_stream(c.io[ax], (int64_t)(N * (double)batch) * (int64_t)elem_size(dtype));
     }
 }
 
@@ -145,7 +163,7 @@ int learned_choice(int dtype, const int64_t dims[3], int64_t batch, const char* 
         }
         w = it->second;
     }
-    const std::vector<PlanChoice> cands = candidate_choices(dtype, dims);
+    const std::vector<PlanChoice> cands = selector_candidates(dtype, dims, batch);
     if (cands.empty()) { *why = "no candidate plans"; return OFFT_ERR_UNSUPPORTED_SIZE; }
     std::vector<float> x(kFeatureDim);
     int best = -1;
@@ -175,7 +193,7 @@ int offt_candidates(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t batch
     const int rc = validate_dims(Na, Nb, Nc, dtype, batch);
     if (rc != OFFT_SUCCESS) { set_error(rc); return rc; }
     const int64_t dims[3] = {Na, Nb, Nc};
-    const std::vector<PlanChoice> cands = candidate_choices(dtype, dims);
+    const std::vector<PlanChoice> cands = selector_candidates(dtype, dims, batch);
     const int n = (int)cands.size();
     if (max < 0 || (max > 0 && (!plans || !features))) { set_error(OFFT_ERR_INVALID_ARG); return OFFT_ERR_INVALID_ARG; }
     size_t pos = 0;

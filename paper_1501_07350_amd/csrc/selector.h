@@ -17,7 +17,7 @@ namespace offt {
 // log2 threads per line, position in the pass order, count of radix-32
 // stages, log2 of the parts its LDS exchanges run in, XCD-contiguous tile
 // order.
-constexpr int kAxisFeatures = 14;
+constexpr int kAxisFeatures = 15;
 constexpr int kFeatureDim = 12 + 3 * kAxisFeatures;
 void plan_features(int dtype, const int64_t dims[3], int64_t batch, const PlanChoice& c, float* out);
 

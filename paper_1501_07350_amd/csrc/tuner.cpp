@@ -665,7 +665,7 @@ extern "C" int offt_tune_table(int64_t Na, int64_t Nb, int64_t Nc, int dtype, in
     tmp.dims[0] = Na; tmp.dims[1] = Nb; tmp.dims[2] = Nc;
     tmp.batch = batch;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const std::vector<PlanChoice> cands = candidate_choices(dtype, tmp.dims);
+    const std::vector<PlanChoice> cands = selector_candidates(dtype, tmp.dims, batch);
     for (int i = 0; i < std::min((int)cands.size(), max) && rc == OFFT_SUCCESS; ++i)
         rc = time_choice(&tmp, cands[i], tmp.dims, buf, buf, nullptr, s, reps, &times_ms[i]);
     (void)hipStreamSynchronize(s);

@@ -283,13 +283,14 @@ def evaluate_against_tuner(records, weights_path, count: int = 100, steps: int =
     rather than against the best of the selector's own candidate list: on the
     first `count` held-out grids, the learned plan, the heuristic plan and
     the exhaustively tuned plan are each timed as whole forward transforms
-    in the same session (one warm-up, median of `steps` runs, HIP events).
+    in the same session (one warm-up, then the median of `steps` samples, each
+    enough back-to-back executions to cover about 1 ms, HIP events).
     Also the tuner's own time per grid.  GPU."""
     import torch
 
     from . import Plan
 
-    def timed(plan, x, y):
+    def timed(plan, x, y, inner):
         h = int(torch.cuda.current_stream().cuda_stream)
         plan.exec_ptr(-1, x.data_ptr(), y.data_ptr(), h)
         ts = []
@@ -297,13 +298,14 @@ def evaluate_against_tuner(records, weights_path, count: int = 100, steps: int =
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-            plan.exec_ptr(-1, x.data_ptr(), y.data_ptr(), h)
+            for _ in range(inner):
+                plan.exec_ptr(-1, x.data_ptr(), y.data_ptr(), h)
             e1.record()
             torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
+            ts.append(e0.elapsed_time(e1) / inner)
         return float(np.median(ts))
 
-    reg_l, reg_h, tune_s = [], [], []
+    reg_l, reg_h, tune_s, per_grid = [], [], [], []
     for j, rec in enumerate(records[:count]):
         dims, bt = tuple(rec["dims"]), rec["batch"]
         dt = torch.complex128 if rec["dtype"] == 0 else torch.complex64
@@ -315,9 +317,14 @@ def evaluate_against_tuner(records, weights_path, count: int = 100, steps: int =
         tune_s.append(time.perf_counter() - t0)
         pl = Plan(dims, dtype=dt, batch=bt, tune="forced", forced_plan=learned)
         ph = Plan(dims, dtype=dt, batch=bt)
-        t_ex, t_l, t_h = timed(ex, x, y), timed(pl, x, y), timed(ph, x, y)
+        # back-to-back executions per timed sample, enough to cover ~1 ms, so
+        # that small grids are not timed at the resolution of one launch
+        inner = max(1, min(200, int(math.ceil(1.0 / max(timed(ex, x, y, 1), 1e-3)))))
+        t_ex, t_l, t_h = timed(ex, x, y, inner), timed(pl, x, y, inner), timed(ph, x, y, inner)
         reg_l.append(t_l / t_ex - 1.0)
         reg_h.append(t_h / t_ex - 1.0)
+        per_grid.append({"dims": list(dims), "batch": bt, "dtype": rec["dtype"], "ms_tuner": round(t_ex, 5),
+                         "ms_learned": round(t_l, 5), "ms_heuristic": round(t_h, 5)})
         for q in (ex, pl, ph):
             q.close()
         del x, y
@@ -330,7 +337,7 @@ def evaluate_against_tuner(records, weights_path, count: int = 100, steps: int =
         return {"mean": float(a.mean()), "median": float(np.median(a)), "p90": float(np.percentile(a, 90)),
                 "max": float(a.max()), "min": float(a.min())}
     return {"grids": len(reg_l), "regret_learned_vs_tuner": stats(reg_l), "regret_heuristic_vs_tuner": stats(reg_h),
-            "tuner_seconds_mean": float(np.mean(tune_s)),
+            "tuner_seconds_mean": float(np.mean(tune_s)), "per_grid": per_grid,
             "note": "negative regret: the plan was faster than the tuner's choice in this timing"}
 
 
