@@ -70,3 +70,25 @@ def test_learned_selector_gain_on_heldout_grids():
     assert ev["speedup_learned_over_heuristic_geomean"] > 1.0
     # ... at a tiny fraction of exhaustive tuning's cost
     assert ev["selection_us_mean"] * 1e-3 < 0.05 * ev["exhaustive_tuning_ms_mean"]
+
+
+def test_access_mode_candidates_and_feature():
+    """The candidate list ends with the heuristic plan with one axis's access
+    mode switched (cached for a grid above 256 MiB, where passes stream by
+    default; streaming below), and the per-axis access-mode feature follows
+    the mode the pass runs with."""
+    per_axis = 15
+    for dims, batch, dtype, suffix, default_mode in (((512, 512, 512), 1, 0, "/c", 1.0),
+                                                     ((64, 48, 60), 1, 1, "/s", 0.0)):
+        plans, feats = selector.candidates(dims, batch, dtype)
+        switched = [i for i, p in enumerate(plans) if suffix in p]
+        assert len(switched) == 3, plans
+        assert switched == list(range(len(plans) - 3, len(plans)))
+        mode = feats[:, 12 + per_axis - 1::per_axis]          # the mode feature of axes a, b, c
+        assert np.all(mode[0] == default_mode)
+        flipped = []
+        for i in switched:
+            f = np.flatnonzero(mode[i] != default_mode)
+            assert len(f) == 1, (plans[i], mode[i])
+            flipped.append(int(f[0]))
+        assert sorted(flipped) == [0, 1, 2]
