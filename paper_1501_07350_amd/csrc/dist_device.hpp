@@ -37,14 +37,15 @@ struct ReverseTables {
     int q_slowest;             // q = m / nm (1) or m % nm (0)
 };
 
-// Line indices and lengths fit 32 bits (at most 2^20 lines of a grid), so
-// the divisions by the middle length are 32-bit ones.
+// Line indices and lengths fit 32 bits (axes of at most 1024 points: at
+// most 2^20 lines), so the divisions by the middle length are 32-bit ones.
 __device__ __forceinline__ int64_t rev_q(const ReverseTables& t, int64_t m) {
     const uint32_t mm = (uint32_t)m, nm = (uint32_t)t.nm;
     return t.q_slowest ? mm / nm : mm % nm;
 }
 
-// Elements that process proc owns on the O_out lines [0, m).
+// Elements of the O_out lines [0, m) that come from process proc (the
+// process that owns them in O_in).
 __device__ __forceinline__ int64_t rev_prefix(const ReverseTables& t, int proc, int64_t m) {
     const int64_t* pre = t.pre + (int64_t)proc * (t.nq + 1);
     const uint32_t mm = (uint32_t)m, nm = (uint32_t)t.nm;
