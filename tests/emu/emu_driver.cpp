@@ -18,6 +18,9 @@
 //       the level-synchronous persistent body (each level's tiles dealt
 //       round-robin, grid barriers between levels) over the batch
 //       executor's cases
+//   emu_driver tables <dtype> <nwg> <ngrids> <grids...> <total>
+//       prints the segment, tile and level tables the library builds for the
+//       grids (many_tables.hpp), without running anything
 //   emu_driver levels <dtype> <nwg> <ngrids> <grids...> <total>
 //       the level kernels' body, one workgroup per tile, level after level
 //   emu_driver route <Na> <Nb> <Nc> <np> <in_order> <out_order> <per_chunk>
@@ -87,7 +90,7 @@ static bool run_block(int threads, const std::function<void(int)>& fn) {
 }
 
 template <typename V>
-static int do_many(int argc, char** argv, bool sync, bool levels = false) {
+static int do_many(int argc, char** argv, bool sync, bool levels = false, bool tables_only = false) {
     int k = 3;
     const int nwg = atoi(argv[k++]);
     const int ngrids = atoi(argv[k++]);
@@ -119,6 +122,22 @@ static int do_many(int argc, char** argv, bool sync, bool levels = false) {
     build_many_tables(gd, (int64_t)sizeof(V), kManyThreads, kManyLdsBudget, kTilesPerItem, &tab);
     std::vector<ManySeg>& segs = tab.segs;
     const int nseg = (int)segs.size();
+    if (tables_only) {
+        // the tables as the library builds them, one segment per line
+        std::printf("TABLES %d segments %lld items %lld tiles lds %zu threads %d tiles_per_item %d\n", nseg,
+                    (long long)tab.total_items, (long long)tab.level_tile_begin[3], tab.lds_bytes, kManyThreads,
+                    kTilesPerItem);
+        for (int i = 0; i < nseg; ++i) {
+            const ManySeg& sg = segs[i];
+            std::printf("%d %d %lld %lld %lld %d %d %d %d %d %d %d %d %lld %lld\n", i, tab.seg_level[i],
+                        (long long)sg.elem_off, (long long)sg.nlines, (long long)sg.M2, sg.kid, sg.logW, sg.mode,
+                        sg.ntiles, sg.nitems, sg.first, sg.last, sg.dep, (long long)sg.item_base,
+                        (long long)sg.tile_base);
+        }
+        for (int l = 0; l < 4; ++l) std::printf("level %d %lld %lld\n", l, (long long)tab.level_begin[l],
+                                                 (long long)tab.level_tile_begin[l]);
+        return 0;
+    }
     {
         // twiddle tables: segments follow the level-major order of the table
         std::vector<const void*> tw_of;
@@ -452,6 +471,9 @@ int main(int argc, char** argv) {
     const int dtype = atoi(argv[2]);
     if (mode == "many") return dtype == 0 ? do_many<double2>(argc, argv, false) : do_many<float2>(argc, argv, false);
     if (mode == "sync") return dtype == 0 ? do_many<double2>(argc, argv, true) : do_many<float2>(argc, argv, true);
+    if (mode == "tables")
+        return dtype == 0 ? do_many<double2>(argc, argv, false, false, true)
+                          : do_many<float2>(argc, argv, false, false, true);
     if (mode == "levels")
         return dtype == 0 ? do_many<double2>(argc, argv, false, true) : do_many<float2>(argc, argv, false, true);
     if (mode == "pass") return dtype == 0 ? do_pass<double2>(argc, argv) : do_pass<float2>(argc, argv);

@@ -240,6 +240,58 @@ def run_many(exe, dims_list, dtype, nwg=1, sync=False, levels=False):
 MIXED = [(2, 3, 5), (1, 1, 1), (9, 25, 27), (100, 4, 6), (48, 60, 64), (16, 1, 8), (5, 5, 5)]
 
 
+@pytest.mark.parametrize("which", ["all", "batch"])
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
+def test_library_tables_invariants(emu_binary, dtype, which):
+    """The segment table the library builds (many_tables.hpp, printed by the
+    driver without running anything) for the mixed batch that once stopped
+    and for the batch executor's lengths: every dependency is the same grid's
+    segment one level lower, which is not a last pass and publishes one count
+    per work item; first passes wait for nothing; every tile fits the
+    launch's LDS and the workgroup's threads; items and tiles are numbered
+    contiguously level by level."""
+    dims = MIXED if which == "all" else [tuple(v if v in (1, 48, 60, 64) else 64 for v in d) for d in SYNC_DIMS]
+    args, offs, total, npass = grid_args(dims, dtype, which)
+    code = "0" if dtype == torch.complex128 else "1"
+    r = subprocess.run([emu_binary, "tables", code, "1"] + args, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = r.stdout.splitlines()
+    head = lines[0].split()
+    assert head[0] == "TABLES"
+    nseg, items, tiles, lds, threads, per_item = (int(head[i]) for i in (1, 3, 5, 8, 10, 12))
+    segs = [list(map(int, ln.split())) for ln in lines[1:1 + nseg]]
+    levels = [list(map(int, ln.split()[2:])) for ln in lines[1 + nseg:]]
+    gk = gen_kernels()
+    prec = "f64" if dtype == torch.complex128 else "f32"
+    cases = gk.many_cases(prec, which)
+    es = 16 if prec == "f64" else 8
+    assert nseg == sum(npass)
+    item_next, tile_next = 0, 0
+    for (i, lvl, off, nlines, M2, kid, logW, mode, ntiles, nitems, first, last, dep, item_base, tile_base) in segs:
+        g = offs.index(off)
+        L, seq, tpl = cases[kid]
+        W = 1 << logW
+        assert W * tpl <= threads
+        assert tile_lds_elems(W, L) * es <= lds
+        assert ntiles == (nlines + W - 1) // W and nitems == (ntiles + per_item - 1) // per_item
+        assert first == (lvl == 0) and last == (lvl == npass[g] - 1)
+        if lvl == 0:
+            assert dep == -1
+        else:
+            d = segs[dep]
+            assert d[2] == off and d[1] == lvl - 1 and d[11] == 0   # same grid, one level lower, not a last pass
+        assert item_base == item_next and tile_base == tile_next   # contiguous, level-major order
+        item_next += nitems
+        tile_next += ntiles
+    assert item_next == items and tile_next == tiles
+    # level boundaries: the first item and tile of each level
+    for lvl in range(3):
+        first_seg = next((s for s in segs if s[1] == lvl), None)
+        if first_seg is not None:
+            assert levels[lvl] == [first_seg[13], first_seg[14]]
+    assert levels[3] == [items, tiles]
+
+
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
 def test_emulated_persistent_loop_mixed_batch(emu_binary, dtype):
     run_many(emu_binary, MIXED, dtype)
