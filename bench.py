@@ -431,7 +431,7 @@ def time_dist(n: int, dtype, steps: int, warmup: int, check: bool, nprocs=(2, 4,
 
 
 def time_small(steps: int, warmup: int, check: bool, n: int = 32):
-    """Config 1: one n^3 complex128 grid, forward then inverse with 1/N,
+    """One n^3 complex128 grid, forward then inverse with 1/N,
     latency per round trip with the pass kernels launched directly and
     replayed from a HIP graph (use_graph)."""
     import numpy as np
@@ -522,12 +522,12 @@ def cpu_baseline(n: int):
                       f"binary64, mean {dt:.2f} s each"}
 
 
-def configs_report(steps: int, warmup: int):
+def other_workloads_report(steps: int, warmup: int):
     """Every workload of the measurement plan besides the 512^3 headline:
-    config 1 (32^3 round trip), config 2 (256^3 complex128, forward error vs
-    the full oracle and round-trip error), config 3's 1024^3 complex64, and
-    the CPU oracle timed on this host (O1 brute force, O2 per-axis DFT, O3
-    recursive FFT; all cores and one thread)."""
+    the 32^3 complex128 round trip, 256^3 complex128 (forward error vs the
+    full oracle and round-trip error), 1024^3 complex64, and the CPU oracle
+    timed on this host (O1 brute force, O2 per-axis DFT, O3 recursive FFT;
+    all cores and one thread)."""
     import numpy as np
     import torch
 
@@ -541,7 +541,7 @@ def configs_report(steps: int, warmup: int):
     except (OSError, StopIteration):
         pass
     rep = {"cpu_model": cpu, "cores": oracle.max_threads()}
-    rep["config1"] = time_small(steps, warmup, True)
+    rep["round_trip_32cubed_c128"] = time_small(steps, warmup, True)
 
     def round_trip(n, dtype, check_full):
         shape = (n, n, n)
@@ -561,11 +561,11 @@ def configs_report(steps: int, warmup: int):
         return d
 
     r2 = time_transform(256, torch.complex128, steps, warmup, False, "exhaustive")
-    rep["config2"] = {"workload": "256x256x256 complex128", "ms": round(r2["ms"], 4),
+    rep["grid_256cubed_c128"] = {"workload": "256x256x256 complex128", "ms": round(r2["ms"], 4),
                       "gflops": round(r2["gflops"], 1), "eff_gbs": round(r2["eff_gbs"], 1),
                       "pass_ms": [round(v, 4) for v in r2["pass_ms"]], **round_trip(256, torch.complex128, True)}
     r3 = time_transform(1024, torch.complex64, steps, warmup, True, "exhaustive")
-    rep["config3_1024"] = {"workload": "1024x1024x1024 complex64", "ms": round(r3["ms"], 4),
+    rep["grid_1024cubed_c64"] = {"workload": "1024x1024x1024 complex64", "ms": round(r3["ms"], 4),
                            "gflops": round(r3["gflops"], 1), "eff_gbs": round(r3["eff_gbs"], 1),
                            "frac_of_peak_effective": round(r3["eff_gbs"] / PEAK_HBM_GBS, 4),
                            "pass_ms": [round(v, 4) for v in r3["pass_ms"]], "plan": r3["plan"],
@@ -1023,8 +1023,9 @@ def main():
     ap.add_argument("--title", default="", help="title of a --summarize-kernels table")
     ap.add_argument("--summarize-batch", metavar="DIR",
                     help="reduce a rocprofv3 --kernel-trace run of --batch-only")
-    ap.add_argument("--configs", action="store_true",
-                    help="report configs 1, 2 and 1024^3 of config 3, and the CPU oracle table, instead")
+    ap.add_argument("--other-workloads", action="store_true",
+                    help="report the 32^3 round trip, 256^3 complex128, 1024^3 complex64 and the CPU oracle table "
+                         "instead")
     ap.add_argument("--plan-cache", default=PLAN_CACHE,
                     help="plan cache of the tuned plans ('none': tune afresh without a cache)")
     ap.add_argument("--command", default="", help="profiling command recorded in the summary")
@@ -1073,8 +1074,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
-    if args.configs:
-        print(json.dumps(configs_report(args.steps, args.warmup)), flush=True)
+    if args.other_workloads:
+        print(json.dumps(other_workloads_report(args.steps, args.warmup)), flush=True)
         return
     if args.reversed_only:
         print(json.dumps({"reversed_output": reversed_runs(args.n, args.steps, args.warmup, not args.no_check)}),

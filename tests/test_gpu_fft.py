@@ -53,7 +53,7 @@ def ref3(xh, sign=oracle.FORWARD):
 
 
 # ------------------------------------------------------------ small workload ----
-def test_config1_32cubed_complex128_vs_brute_force():
+def test_32cubed_complex128_vs_brute_force():
     """32x32x32 complex128 forward vs the brute-force definition, then the
     inverse; round trip with 1/N."""
     plan, x, y = run((32, 32, 32), C128, normalize=True)

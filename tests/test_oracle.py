@@ -105,7 +105,7 @@ def test_fft3_vs_numpy_library_run(shape):
     assert oracle.rel_l2(oracle.fft3(x, oracle.BACKWARD), np.fft.ifftn(x) * x.size) <= TIGHT
 
 
-def test_brute_force_config1_vs_numpy():
+def test_brute_force_32cubed_vs_numpy():
     # 32^3 complex128, the small workload: brute force is the definition itself.
     x = synth.complex_grid((32, 32, 32), torch.complex128).numpy()
     y = oracle.dft3_brute(x)
