@@ -367,6 +367,67 @@ def time_batch(steps: int, warmup: int, check: bool, count: int = 64):
     return out
 
 
+def time_batch_any_lengths(steps: int, warmup: int, check: bool, count: int = 64):
+    """Uneven batch of `count` complex64 grids with axes drawn from every
+    2/3/5-smooth length 2..160 (the every-length executor, level kernels
+    only) with the heuristic plans: level kernels, directly and from a HIP
+    graph, vs every grid's passes launched separately."""
+    import numpy as np
+    import torch
+
+    import paper_1501_07350_amd as offt
+    import synth
+
+    lengths = synth.smooth_lengths(2, 160)
+    dims = synth.uneven_batch_dims(count, key=synth.KEY_DIMS + 101, lengths=lengths)
+    dtype = torch.complex64
+    plan = offt.ManyPlan(dims, dtype=dtype, tune="none")
+    grids = synth.batch_grids(dims, dtype, key0=synth.SEED + 900, device="cuda")
+    x = plan.pack(grids)
+    y = torch.empty_like(x)
+    h = int(torch.cuda.current_stream().cuda_stream)
+    xp, yp = x.data_ptr(), y.data_ptr()
+    variants = {"separate_heuristic": offt.MANY_SEPARATE_HEURISTIC,
+                "levels_heuristic": offt.MANY_LEVELS,
+                "levels_graph_heuristic": offt.MANY_LEVELS_GRAPH}
+    ms = {}
+    for name, mode in variants.items():
+        for _ in range(warmup):
+            plan.exec_ptr(xp, yp, offt.FORWARD, mode, h)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            plan.exec_ptr(xp, yp, offt.FORWARD, mode, h)
+        e1.record()
+        torch.cuda.synchronize()
+        ms[name] = e0.elapsed_time(e1) / steps
+    flop = sum(5.0 * a * b * c * math.log2(a * b * c) for a, b, c in dims if a * b * c > 1)
+    nbytes = sum(6.0 * a * b * c * 8 for a, b, c in dims)
+    out = {
+        "workload": f"{count} complex64 grids, axes uniform over the 2/3/5-smooth lengths 2..160",
+        "elements": int(sum(a * b * c for a, b, c in dims)),
+        "executor": plan.describe().splitlines()[0],
+        "ms": {k: round(v, 4) for k, v in ms.items()},
+        "gflops": {k: round(flop / (v * 1e6), 1) for k, v in ms.items()},
+        "eff_gbs": {k: round(nbytes / (v * 1e6), 1) for k, v in ms.items()},
+        "speedup_levels_graph_vs_separate": round(ms["separate_heuristic"] / ms["levels_graph_heuristic"], 3),
+    }
+    if check:
+        import oracle
+        plan.exec_ptr(xp, yp, offt.FORWARD, offt.MANY_LEVELS_GRAPH, h)
+        torch.cuda.synchronize()
+        worst = 0.0
+        for g, yg in enumerate(plan.unpack(y)):
+            ref = oracle.fft3(grids[g].cpu().numpy().astype(np.complex128))
+            e = oracle.rel_l2(yg.cpu().numpy(), ref)
+            worst = max(worst, e / oracle.tolerance(grids[g].numel(), True))
+        out["check_worst_error_over_tolerance_all_grids"] = worst
+    plan.close()
+    return out
+
+
 def time_dist(n: int, dtype, steps: int, warmup: int, check: bool, nprocs=(2, 4, 8)):
     """The paper's distributed flow over Np virtual processes on this GPU
     (per-process line transforms, abc -> cab and cab -> cba transposes with
@@ -727,15 +788,17 @@ def summarize_batch(d: str, command: str, steps: int, warmup: int) -> str:
     level's start to the last one's end."""
     trace = _read_csv(_find(d, "kernel_trace.csv"))
     trace.sort(key=lambda r: int(r["Dispatch_Id"]))
-    fams = [("persistent work-queue kernel", "many_kernel_", 3),
-            ("level kernels", "many_level_kernel_", 2),
-            ("level-synchronous persistent kernel", "many_sync_kernel_", 2)]
+    fams = [("persistent work-queue kernel", "many_kernel_batch_", 3),
+            ("level kernels", "many_level_kernel_batch_", 2),
+            ("level-synchronous persistent kernel", "many_sync_kernel_batch_", 2),
+            ("every-length executor, level kernels", "many_level_kernel_all_", 2)]
     runs_per_variant = steps + warmup
     lines = ["# rocprofv3 kernel trace of the uneven-batch executors (64 complex64 grids, one forward each)",
              f"# command: {command}",
              f"# {steps} timed + {warmup} warm-up executions per variant; the persistent kernel runs in 3 variants",
              "# (tuned, tuned in a graph, heuristic in a graph), the level and level-synchronous kernels in 2",
-             "# (direct, in a graph)",
+             "# (direct, in a graph); the every-length executor's level kernels run the second batch (64 grids,",
+             "# axes over every 2/3/5-smooth length 2..160, heuristic plans) in 2",
              f"{'executor':<38} {'dispatches':>10} {'mean_us':>9} {'per_exec':>8} {'busy_us_per_exec':>17}"]
     for label, key, nvar in fams:
         rows = [r for r in trace if key in r["Kernel_Name"]]
@@ -747,7 +810,7 @@ def summarize_batch(d: str, command: str, steps: int, warmup: int) -> str:
         per = len(rows) / execs
         lines.append(f"{label:<38} {len(rows):>10} {sum(durs) / len(rows):>9.2f} {per:>8.2f} "
                      f"{sum(durs) / execs:>17.2f}")
-        if key == "many_level_kernel_" and per == int(per):
+        if key.startswith("many_level_kernel_") and per == int(per):
             k = int(per)
             tail = rows[len(rows) - steps * k:]
             spans = []
@@ -1089,7 +1152,9 @@ def main():
         print(json.dumps({"nd": nd_runs(args.steps, args.warmup, not args.no_check)}), flush=True)
         return
     if args.batch_only:
-        print(json.dumps({"batch": time_batch(args.steps, args.warmup, not args.no_check)}), flush=True)
+        print(json.dumps({"batch": time_batch(args.steps, args.warmup, not args.no_check),
+                          "batch_any_lengths": time_batch_any_lengths(args.steps, args.warmup,
+                                                                      not args.no_check)}), flush=True)
         return
     n = args.n
     # plans tuned at init (excluded from the timing, as the paper excludes its
@@ -1144,6 +1209,7 @@ def main():
     if not args.no_batch:
         out["small"] = time_small(args.steps, args.warmup, not args.no_check)
         out["batch"] = time_batch(args.steps, args.warmup, not args.no_check)
+        out["batch_any_lengths"] = time_batch_any_lengths(args.steps, args.warmup, not args.no_check)
         out["reversed_output"] = reversed_runs(n, args.steps, args.warmup, not args.no_check)
         out["nd"] = nd_runs(args.steps, args.warmup, not args.no_check)
         out["dist"] = time_dist(n, torch.complex128, args.steps, args.warmup, not args.no_check)

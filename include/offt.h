@@ -300,16 +300,18 @@ int64_t offt_many_offset(offt_plan_t p, int i);
  *   -1  SEPARATE_HEURISTIC: every grid's passes as ordinary launches with the
  *       heuristic plans;
  *   -2  SEPARATE_TUNED: the same with the plans chosen at plan time.
+ * The level forms (2, 3) run any batch whose axes are all at most 160 long;
+ * the persistent forms (0, 1, 4, 5) only batches whose axis lengths all lie
+ * in the set {48, 60, 64, 80, 96, 120, 128, 150, 160} (lengths 1 are fine
+ * for both).
  * Never allocates device memory.  Errors: INVALID_ARG, BAD_PLAN (not a
- * many-plan), UNSUPPORTED_SIZE (use_graph >= 0 when an axis length of the
- * batch is outside the batch executor's set {48, 60, 64, 80, 96, 120, 128,
- * 150, 160}; lengths 1 are fine), HIP. */
+ * many-plan), UNSUPPORTED_SIZE (use_graph >= 0 for a batch outside that
+ * form's lengths), HIP. */
 int offt_exec_many(offt_plan_t p, const void* in, void* out, int direction, int use_graph,
                    void* stream);
 
-/* offt_exec_many in the default launch form: LEVELS_GRAPH when the batch
- * executor covers every pass of the batch, else SEPARATE_TUNED.  Same
- * errors. */
+/* offt_exec_many in the default launch form: LEVELS_GRAPH when every axis
+ * of the batch is at most 160 long, else SEPARATE_TUNED.  Same errors. */
 int offt_exec_many_fwd(offt_plan_t p, const void* in, void* out, void* stream);
 int offt_exec_many_bwd(offt_plan_t p, const void* in, void* out, void* stream);
 

@@ -253,7 +253,8 @@ class ManyPlan:
 
     def forward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """Forward transform of every grid in the default launch form (level
-        kernels from a graph where the batch executor covers the batch)."""
+        kernels from a graph when every axis is at most 160 long, else
+        separate launches)."""
         return self._default(_lib.load().offt_exec_many_fwd, x, out)
 
     def backward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

@@ -1,6 +1,7 @@
 """Build the HIP library libofft.so for gfx950 in-tree.
 
-Steps: generate the pass-kernel instantiations (csrc/gen_kernels.py), compile
+Steps: generate the pass-kernel instantiations (csrc/gen_kernels.py) and the
+batch executors (csrc/gen_many.py), compile
 every source under csrc/ and csrc/_gen/ with hipcc in parallel, link into
 paper_1501_07350_amd/libofft.so.
 """
@@ -40,9 +41,10 @@ def sources():
     sys.path.insert(0, CSRC)
     try:
         import gen_kernels  # noqa: E402
+        import gen_many  # noqa: E402
     finally:
         sys.path.pop(0)
-    gen = gen_kernels.emit(GEN) + gen_kernels.emit_many(GEN)
+    gen = gen_kernels.emit(GEN) + gen_many.emit_many(GEN)
     own = sorted(
         os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp"))
     )

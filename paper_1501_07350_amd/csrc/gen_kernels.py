@@ -19,7 +19,6 @@ import sys
 
 MAX_L = 1024
 PARTS = 8  # translation units per precision (compiled in parallel)
-MANY_MAX_L = 160  # longest axis the persistent batch executor dispatches
 
 
 def smooth(n):
@@ -220,174 +219,7 @@ def emit(outdir):
     return [os.path.join(outdir, t + ".hip") for t in tables]
 
 
-# Persistent executors: each compiles the kernel cases of a set of lengths.
-# A plan uses the first executor whose set covers all its passes.  Register
-# use of an executor is that of its hungriest case, so the lengths of the
-# uneven-batch workload get a compact executor of their own.
-BATCH_LENGTHS = (48, 60, 64, 80, 96, 120, 128, 150, 160)
-CASE_SETS = {"batch": lambda L: L in BATCH_LENGTHS, "all": lambda L: L <= MANY_MAX_L}
-# Executors compiled into the library.  The "all" set (every length <= 160)
-# is not built: its kernel stopped responding on the GPU for a batch of mixed
-# small lengths although the same tile code and loop pass the CPU emulation
-# (tests/test_emu.py); until that is understood only the compact executor runs.
-EXECUTORS = (("batch", CASE_SETS["batch"]),)
-
-
-def many_cases(prec, which="all"):
-    """Kernel cases (L, radix sequence, threads per line) of one case set."""
-    keep = CASE_SETS[which]
-    return [e[:3] for e in entries(prec, parts=False) if keep(e[0])]
-
-
-# waves per SIMD the level-synchronous kernel is compiled for: 4, two
-# 512-thread workgroups per CU (128 registers).  Its loop runs every case's
-# tile code inline, which needs about 126 registers for complex64 (with the
-# opaque thread index; without it the hoisted index math spills); asked for
-# 6 waves (80 registers) it spills, and behind an out-of-line call (80
-# registers, no spills) each tile pays the call's stack traffic and ran
-# slower.
-SYNC_WAVES_PER_EU = {"f32": 4, "f64": 4}
-
-
-def emit_many(outdir):
-    os.makedirs(outdir, exist_ok=True)
-    files = []
-    for prec, vt, dcode in (("f64", "double2", 0), ("f32", "float2", 1)):
-        for ex, _ in EXECUTORS:
-            name = f"{ex}_{prec}"
-            cases = many_cases(prec, ex)
-            lines = [
-                "// generated by gen_kernels.py -- do not edit",
-                '#include "offt_internal.h"',
-                '#include "many_device.hpp"',
-                "namespace offt {",
-                "namespace {",
-                # The whole switch is one out-of-line function called once per
-                # tile: inlined into the persistent loop, loop-invariant code of
-                # every case would be hoisted and kept live together.
-                f"__device__ __noinline__ void dispatch_{name}(int kid, const PassArgs& a, {vt}* lds, int64_t l0) {{",
-                "    switch (kid) {",
-            ]
-            for i, (L, seq, tpl) in enumerate(cases):
-                rad = ", ".join(str(x) for x in seq)
-                lines.append(f"        case {i}: pass_tile_coherent<{vt}, {L}, {tpl}, {rad}>(a, lds, l0); break;")
-            lines += [
-                "        default: break;",
-                "    }",
-                "}",
-                # the level kernels are ordered by kernel boundaries: plain
-                # stores; one tile per workgroup and no loop to hoist out of,
-                # so their dispatch is inlined (no call frame)
-                f"__device__ __forceinline__ void dispatch_plain_{name}(int kid, const PassArgs& a, {vt}* lds, int64_t l0) {{",
-                "    switch (kid) {",
-            ]
-            for i, (L, seq, tpl) in enumerate(cases):
-                rad = ", ".join(str(x) for x in seq)
-                lines.append(f"        case {i}: pass_tile<{vt}, {L}, {tpl}, {rad}>(a, lds, l0); break;")
-            lines += [
-                "        default: break;",
-                "    }",
-                "}",
-                f"struct Dispatch_{name} {{",
-                f"    __device__ __forceinline__ void operator()(int kid, const PassArgs& a, {vt}* lds, int64_t l0) const {{",
-                f"        dispatch_{name}(kid, a, lds, l0);",
-                "    }",
-                "};",
-                f"struct DispatchPlain_{name} {{",
-                f"    __device__ __forceinline__ void operator()(int kid, const PassArgs& a, {vt}* lds, int64_t l0) const {{",
-                f"        dispatch_plain_{name}(kid, a, lds, l0);",
-                "    }",
-                "};",
-                "}  // namespace",
-                f"__global__ void __launch_bounds__(512) many_kernel_{name}(ManyArgs a) {{",
-                "    extern __shared__ __align__(16) unsigned char smem_raw[];",
-                f"    many_body<{vt}>(a, reinterpret_cast<{vt}*>(smem_raw), Dispatch_{name}{{}});",
-                "}",
-                f"__global__ void __launch_bounds__(512) many_level_kernel_{name}(ManyArgs a, int64_t tile_begin) {{",
-                "    extern __shared__ __align__(16) unsigned char smem_raw[];",
-                f"    many_level_body<{vt}>(a, tile_begin, reinterpret_cast<{vt}*>(smem_raw), DispatchPlain_{name}{{}});",
-                "}",
-                f"static const ManyCase cases_{name}[] = {{",
-            ]
-            for L, seq, tpl in cases:
-                padded = ", ".join(str(x) for x in (seq + [0] * (8 - len(seq))))
-                lines.append(f"    {{{dcode}, {L}, {len(seq)}, {{{padded}}}, {tpl}}},")
-            lines += [
-                "};",
-                f"extern const ManyExecutor g_many_{name};",
-                f"const ManyExecutor g_many_{name} = {{\"{ex}\", {dcode}, cases_{name}, {len(cases)}, "
-                f"reinterpret_cast<const void*>(&many_kernel_{name}), "
-                f"reinterpret_cast<const void*>(&many_level_kernel_{name})}};",
-                "}  // namespace offt",
-            ]
-            path = os.path.join(outdir, f"many_{name}.hip")
-            text = "\n".join(lines) + "\n"
-            if not os.path.exists(path) or open(path).read() != text:
-                with open(path, "w") as f:
-                    f.write(text)
-            files.append(path)
-            # level-synchronous persistent kernel: the plain tile code inlined
-            # into its loop, each tile's thread index opaque
-            sl = [
-                "// generated by gen_kernels.py -- do not edit",
-                '#include "offt_internal.h"',
-                '#include "many_device.hpp"',
-                "namespace offt {",
-                "namespace {",
-                f"__device__ __forceinline__ void dispatch_looped_{name}(int kid, const PassArgs& a, {vt}* lds, int64_t l0) {{",
-                "    switch (kid) {",
-            ]
-            for i, (L, seq, tpl) in enumerate(cases):
-                rad = ", ".join(str(x) for x in seq)
-                sl.append(f"        case {i}: pass_tile_looped<{vt}, {L}, {tpl}, {rad}>(a, lds, l0); break;")
-            sl += [
-                "        default: break;",
-                "    }",
-                "}",
-                f"struct DispatchLooped_{name} {{",
-                f"    __device__ __forceinline__ void operator()(int kid, const PassArgs& a, {vt}* lds, int64_t l0) const {{",
-                f"        dispatch_looped_{name}(kid, a, lds, l0);",
-                "    }",
-                "};",
-                "}  // namespace",
-                f"__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu({SYNC_WAVES_PER_EU[prec]}))) "
-                f"many_sync_kernel_{name}(ManyArgs a, ManySyncArgs g) {{",
-                "    extern __shared__ __align__(16) unsigned char smem_raw[];",
-                f"    many_sync_body<{vt}>(a, g, reinterpret_cast<{vt}*>(smem_raw), DispatchLooped_{name}{{}});",
-                "}",
-                f"const void* many_sync_kernel_{name}_address() {{",
-                f"    return reinterpret_cast<const void*>(&many_sync_kernel_{name});",
-                "}",
-                "}  // namespace offt",
-            ]
-            spath = os.path.join(outdir, f"many_sync_{name}.hip")
-            stext = "\n".join(sl) + "\n"
-            if not os.path.exists(spath) or open(spath).read() != stext:
-                with open(spath, "w") as f:
-                    f.write(stext)
-            files.append(spath)
-    inc = [f"extern const ManyExecutor g_many_{ex}_{prec};" for prec in ("f64", "f32") for ex, _ in EXECUTORS]
-    inc.append("#define OFFT_MANY_EXECUTORS_F64 " + ", ".join(f"&g_many_{ex}_f64" for ex, _ in EXECUTORS))
-    inc.append("#define OFFT_MANY_EXECUTORS_F32 " + ", ".join(f"&g_many_{ex}_f32" for ex, _ in EXECUTORS))
-    # the level-synchronous kernels live in files of their own (their looped
-    # tile code and register budget would otherwise change the code of the
-    # level kernels); their addresses are looked up through these functions
-    inc += [f"const void* many_sync_kernel_{ex}_{prec}_address();" for prec in ("f64", "f32") for ex, _ in EXECUTORS]
-    inc.append("inline const void* many_sync_kernel(const ManyExecutor* e) {")
-    for prec in ("f64", "f32"):
-        for ex, _ in EXECUTORS:
-            inc.append(f"    if (e == &g_many_{ex}_{prec}) return many_sync_kernel_{ex}_{prec}_address();")
-    inc += ["    return nullptr;", "}"]
-    text = "\n".join(inc) + "\n"
-    path = os.path.join(outdir, "many_executors.inc")
-    if not os.path.exists(path) or open(path).read() != text:
-        with open(path, "w") as f:
-            f.write(text)
-    return files
-
-
 if __name__ == "__main__":
     outdir = sys.argv[1] if len(sys.argv) > 1 else os.path.join(os.path.dirname(__file__), "_gen")
-    files = emit(outdir) + emit_many(outdir)
-    print(len(entries("f64")), "+", len(entries("f32")), "kernels in", len(files), "files;",
-          [(ex, len(many_cases("f32", ex))) for ex, _ in EXECUTORS], "persistent cases (f32)")
+    files = emit(outdir)
+    print(len(entries("f64")), "+", len(entries("f32")), "kernels in", len(files), "files")

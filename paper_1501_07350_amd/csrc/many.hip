@@ -48,9 +48,11 @@ struct ManyState {
     int count = 0;
     int64_t total_elems = 0;
     std::vector<ManyGrid> grids;
-    bool persistent_ok = false;  // every pass has a case in the executor
+    bool levels_ok = false;      // every pass has a case in the executor: level kernels
+    bool persistent_ok = false;  // ... and the executor has the persistent forms
     const ManyExecutor* exec = nullptr;
-    std::string why_not;
+    std::string why_not;         // why the persistent forms are unavailable
+    std::string why_not_levels;  // why the level kernels are unavailable
     ManySeg* d_segs = nullptr;
     unsigned* d_counters = nullptr;
     int nseg = 0;
@@ -140,8 +142,10 @@ static int build_many(offt_plan_s* p, hipStream_t s) {
     const int dtype = p->dtype;
     const size_t es = elem_size(dtype);
     m->exec = pick_executor(m, dtype);
-    m->persistent_ok = m->exec != nullptr;
-    if (!m->exec) m->why_not = "an axis length outside the persistent executor's set {48,60,64,80,96,120,128,150,160}";
+    m->levels_ok = m->exec != nullptr;
+    m->persistent_ok = m->exec && m->exec->kernel;
+    if (!m->exec) m->why_not_levels = "an axis length above 160";
+    if (!m->persistent_ok) m->why_not = "an axis length outside the set {48,60,64,80,96,120,128,150,160}";
     // segments, tiles and work items (many_tables.hpp, shared with the CPU
     // emulation of the executors)
     std::vector<ManyGridDesc> gd(m->count);
@@ -167,6 +171,12 @@ static int build_many(offt_plan_s* p, hipStream_t s) {
     m->nseg = (int)segs.size();
     m->total_items = items;
     if (items >= (int64_t(1) << 31)) { m->persistent_ok = false; m->why_not = "too many work items"; }
+    // a launch holds at most 2^32 - 1 work-items: tiles of one level
+    for (int l = 0; l < 3; ++l)
+        if ((tab.level_tile_begin[l + 1] - tab.level_tile_begin[l]) * kManyThreads > int64_t(0xffffffffu)) {
+            m->levels_ok = m->persistent_ok = false;
+            m->why_not_levels = m->why_not = "too many tiles in one pass level";
+        }
     if (m->nseg == 0) return OFFT_SUCCESS;   // all grids 1x1x1: copies only
     void* d = nullptr;
     int rc = dev_alloc(p, sizeof(ManySeg) * segs.size(), &d);
@@ -188,10 +198,15 @@ static int build_many(offt_plan_s* p, hipStream_t s) {
             hipSuccess ||
         hipMemsetAsync(m->d_counters, 0, sizeof(unsigned) * ncnt, s) != hipSuccess)
         return OFFT_ERR_HIP;
+    if (!m->levels_ok) return OFFT_SUCCESS;
+    m->lds = std::max<size_t>(lds_max, 16);
+    if (m->lds > 65536 &&
+        hipFuncSetAttribute(m->exec->level_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->lds) !=
+            hipSuccess)
+        return OFFT_ERR_HIP;
     if (!m->persistent_ok) return OFFT_SUCCESS;
     // occupancy-sized persistent grid
     m->kernel = m->exec->kernel;
-    m->lds = std::max<size_t>(lds_max, 16);
     if (m->lds > 65536 &&
         hipFuncSetAttribute(m->kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->lds) != hipSuccess)
         return OFFT_ERR_HIP;
@@ -517,9 +532,10 @@ offt_plan_t offt_plan_many(int count, const int64_t* dims, int dtype, const offt
     if (rc == OFFT_SUCCESS && hipStreamSynchronize(s) != hipSuccess) rc = OFFT_ERR_HIP;
     if (rc != OFFT_SUCCESS) { free_plan(p); set_error(rc); return nullptr; }
     char buf[256];
-    snprintf(buf, sizeof buf, "many: %d grids, %lld elements, %d segments, %lld work items, executor %s, %d workgroups x %d (level-synchronous: %d), lds %zu%s%s",
+    snprintf(buf, sizeof buf, "many: %d grids, %lld elements, %d segments, %lld work items, executor %s, %d workgroups x %d (level-synchronous: %d), lds %zu%s%s%s%s",
              count, (long long)m->total_elems, m->nseg, (long long)m->total_items, m->exec ? m->exec->name : "-",
              m->nblocks, kManyThreads, m->sync_nblocks, m->lds,
+             m->levels_ok ? "" : "; level kernels unavailable: ", m->levels_ok ? "" : m->why_not_levels.c_str(),
              m->persistent_ok ? "" : "; persistent executor unavailable: ", m->persistent_ok ? "" : m->why_not.c_str());
     m->desc = buf;
     for (const ManyGrid& G : m->grids) m->desc += "\n" + choice_to_string(G.choice, G.dims);
@@ -537,11 +553,11 @@ int64_t offt_many_offset(offt_plan_t p, int i) {
 }
 
 // The default launch of a many-plan: the level kernels replayed from a graph
-// (the fastest form measured on MI355X) when the batch executor covers every
-// pass, else the tuned plans as separate launches.
+// (the fastest form measured on MI355X) when an executor covers every pass
+// (every axis at most 160 long), else the tuned plans as separate launches.
 static int many_default_form(offt_plan_t p) {
     if (!p || p->kind != 2 || !p->many) return OFFT_MANY_LEVELS_GRAPH;   // rejected below
-    return p->many->persistent_ok ? OFFT_MANY_LEVELS_GRAPH : OFFT_MANY_SEPARATE_TUNED;
+    return p->many->levels_ok ? OFFT_MANY_LEVELS_GRAPH : OFFT_MANY_SEPARATE_TUNED;
 }
 
 int offt_exec_many_fwd(offt_plan_t p, const void* in, void* out, void* stream) {
@@ -574,16 +590,19 @@ int offt_exec_many(offt_plan_t p, const void* in, void* out, int direction, int 
     if (rc != OFFT_SUCCESS) {
     } else if (use_graph < 0 || m->nseg == 0) {
         rc = exec_separate(p, in, out, direction, use_graph == -2 || m->nseg == 0, s);
+    } else if (use_graph == OFFT_MANY_LEVELS_GRAPH || use_graph == OFFT_MANY_LEVELS) {
+        if (!m->levels_ok)
+            rc = OFFT_ERR_UNSUPPORTED_SIZE;
+        else if (use_graph == OFFT_MANY_LEVELS_GRAPH)
+            rc = level_graph_launch(m, in, out, direction, s);
+        else
+            rc = launch_levels(m, in, out, direction, s);
     } else if (!m->persistent_ok) {
         rc = OFFT_ERR_UNSUPPORTED_SIZE;
     } else if (use_graph == OFFT_MANY_PERSISTENT_GRAPH) {
         rc = graph_launch(m, in, out, direction, s);
     } else if (use_graph == OFFT_MANY_PERSISTENT) {
         rc = launch_persistent(m, in, out, direction, s);
-    } else if (use_graph == OFFT_MANY_LEVELS_GRAPH) {
-        rc = level_graph_launch(m, in, out, direction, s);
-    } else if (use_graph == OFFT_MANY_LEVELS) {
-        rc = launch_levels(m, in, out, direction, s);
     } else if (use_graph == OFFT_MANY_SYNC_GRAPH) {
         rc = sync_graph_launch(m, in, out, direction, s);
     } else {

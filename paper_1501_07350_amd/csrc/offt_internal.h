@@ -50,7 +50,7 @@ struct ManyExecutor {
     int dtype;
     const ManyCase* cases;
     int ncases;
-    const void* kernel;        // persistent kernel (ManyArgs)
+    const void* kernel;        // work-queue persistent kernel (ManyArgs); null: level kernels only
     const void* level_kernel;  // one tile per workgroup (ManyArgs, int64_t tile_begin)
 };
 

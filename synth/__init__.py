@@ -114,10 +114,11 @@ def draw_index(key: int, j: int, n: int) -> int:
 BATCH_AXIS_LENGTHS = (48, 60, 64, 80, 96, 120, 128, 150, 160)
 
 
-def uneven_batch_dims(count: int = 64, key: int = KEY_DIMS):
+def uneven_batch_dims(count: int = 64, key: int = KEY_DIMS, lengths=BATCH_AXIS_LENGTHS):
     """Axis lengths for the uneven-batch workload: each of the 3*count axes is
-    drawn independently and uniformly from BATCH_AXIS_LENGTHS."""
-    L = BATCH_AXIS_LENGTHS
+    drawn independently and uniformly from `lengths` (BATCH_AXIS_LENGTHS by
+    default)."""
+    L = tuple(lengths)
     return [tuple(L[draw_index(key, 3 * g + k, len(L))] for k in range(3)) for g in range(count)]
 
 

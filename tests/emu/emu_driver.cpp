@@ -22,7 +22,9 @@
 //       prints the segment, tile and level tables the library builds for the
 //       grids (many_tables.hpp), without running anything
 //   emu_driver levels <dtype> <nwg> <ngrids> <grids...> <total>
-//       the level kernels' body, one workgroup per tile, level after level
+//       the level kernels' body, one workgroup per tile, level after level,
+//       over the batch executor's cases (levels_all: the every-length
+//       executor's)
 //   emu_driver route <Na> <Nb> <Nc> <np> <in_order> <out_order> <per_chunk>
 //       one exchange of the distributed flow with the library's own tables
 //       (dist_tables.hpp) and exchange code (dist_device.hpp): every
@@ -90,7 +92,8 @@ static bool run_block(int threads, const std::function<void(int)>& fn) {
 }
 
 template <typename V>
-static int do_many(int argc, char** argv, bool sync, bool levels = false, bool tables_only = false) {
+static int do_many(int argc, char** argv, bool sync, bool levels = false, bool tables_only = false,
+                   bool all_cases = false) {
     int k = 3;
     const int nwg = atoi(argv[k++]);
     const int ngrids = atoi(argv[k++]);
@@ -208,7 +211,8 @@ static int do_many(int argc, char** argv, bool sync, bool levels = false, bool t
             for (unsigned b = 0; b < gridDim.x; ++b) {
                 blockIdx.x = b;
                 okl = run_block(threads, [&](int) {
-                    many_level_body<V>(a, begin, lds.data(), EmuLevelDispatch<V>{});
+                    if (all_cases) many_level_body<V>(a, begin, lds.data(), EmuLevelDispatchAll<V>{});
+                    else many_level_body<V>(a, begin, lds.data(), EmuLevelDispatch<V>{});
                 }) && okl;
             }
         }
@@ -476,6 +480,9 @@ int main(int argc, char** argv) {
                           : do_many<float2>(argc, argv, false, false, true);
     if (mode == "levels")
         return dtype == 0 ? do_many<double2>(argc, argv, false, true) : do_many<float2>(argc, argv, false, true);
+    if (mode == "levels_all")
+        return dtype == 0 ? do_many<double2>(argc, argv, false, true, false, true)
+                          : do_many<float2>(argc, argv, false, true, false, true);
     if (mode == "pass") return dtype == 0 ? do_pass<double2>(argc, argv) : do_pass<float2>(argc, argv);
     return 2;
 }

@@ -30,11 +30,20 @@ CSRC = os.path.join(os.path.dirname(HERE), "paper_1501_07350_amd", "csrc")
 BUILD = os.path.join(EMU, "_build")
 
 
-def gen_kernels():
-    spec = importlib.util.spec_from_file_location("gen_kernels_emu", os.path.join(CSRC, "gen_kernels.py"))
+def _load(name):
+    spec = importlib.util.spec_from_file_location(name + "_emu", os.path.join(CSRC, name + ".py"))
     mod = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mod)
     return mod
+
+
+def gen_kernels():
+    return _load("gen_kernels")
+
+
+def many_cases(prec, which):
+    """Kernel cases of one of the library's batch executors (csrc/gen_many.py)."""
+    return _load("gen_many").many_cases(prec, which)
 
 
 # cases the emulated stand-alone passes add to the executor's: the radix-32
@@ -43,7 +52,7 @@ EXTRA_PASS_CASES = [(32, [32], 1), (64, [32, 2], 2)]
 
 
 def plain_cases(gk, prec):
-    return gk.many_cases(prec, "all") + EXTRA_PASS_CASES
+    return many_cases(prec, "all") + EXTRA_PASS_CASES
 
 
 @pytest.fixture(scope="module")
@@ -58,7 +67,7 @@ def emu_binary():
         lines.append(f"template <> struct EmuDispatch<{vt}> {{")
         lines.append(f"  void operator()(int kid, const PassArgs& a, {vt}* lds, int64_t l0) const {{")
         lines.append("    switch (kid) {")
-        for i, (L, seq, tpl) in enumerate(gk.many_cases(prec, "all")):
+        for i, (L, seq, tpl) in enumerate(many_cases(prec, "all")):
             lines.append(f"      case {i}: pass_tile_coherent<{vt}, {L}, {tpl}, {', '.join(map(str, seq))}>(a, lds, l0); break;")
         lines.append("      default: break;\n    }\n  }\n};")
     lines.append("template <typename V> struct EmuDispatchPlain;")
@@ -75,15 +84,17 @@ def emu_binary():
             lines.append(f"      case {i}: {body} break;")
         lines.append("      default: break;\n    }\n  }\n};")
     # the level kernels' and the level-synchronous form's dispatch over the
-    # batch executor's cases (plain stores)
-    lines.insert(0, "template <typename V> struct EmuLevelDispatch;")
-    for vt, prec in (("double2", "f64"), ("float2", "f32")):
-        lines.append(f"template <> struct EmuLevelDispatch<{vt}> {{")
-        lines.append(f"  void operator()(int kid, const PassArgs& a, {vt}* lds, int64_t l0) const {{")
-        lines.append("    switch (kid) {")
-        for i, (L, seq, tpl) in enumerate(gk.many_cases(prec, "batch")):
-            lines.append(f"      case {i}: pass_tile<{vt}, {L}, {tpl}, {', '.join(map(str, seq))}>(a, lds, l0); break;")
-        lines.append("      default: break;\n    }\n  }\n};")
+    # batch executor's cases, and the level kernels' over the every-length
+    # executor's (plain stores)
+    for struct, which in (("EmuLevelDispatch", "batch"), ("EmuLevelDispatchAll", "all")):
+        lines.insert(0, f"template <typename V> struct {struct};")
+        for vt, prec in (("double2", "f64"), ("float2", "f32")):
+            lines.append(f"template <> struct {struct}<{vt}> {{")
+            lines.append(f"  void operator()(int kid, const PassArgs& a, {vt}* lds, int64_t l0) const {{")
+            lines.append("    switch (kid) {")
+            for i, (L, seq, tpl) in enumerate(many_cases(prec, which)):
+                lines.append(f"      case {i}: pass_tile<{vt}, {L}, {tpl}, {', '.join(map(str, seq))}>(a, lds, l0); break;")
+            lines.append("      default: break;\n    }\n  }\n};")
     cases_text = "namespace offt {\n" + "\n".join(lines) + "\n}\n"
     flags = ["-std=c++17", "-O1", "-g", "-pthread", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
     h = hashlib.sha256(cases_text.encode() + " ".join(flags).encode())
@@ -187,10 +198,9 @@ def grid_args(dims_list, dtype, which="all"):
     their kernel cases; the driver builds the segment table with the
     library's own code (many_tables.hpp).  Returns (args, offsets, total,
     passes per grid)."""
-    gk = gen_kernels()
     prec = "f64" if dtype == torch.complex128 else "f32"
     es = 16 if prec == "f64" else 8
-    cases = gk.many_cases(prec, which)
+    cases = many_cases(prec, which)
     align = 256 // es
     offs, off = [], 0
     for d in dims_list:
@@ -211,10 +221,15 @@ def grid_args(dims_list, dtype, which="all"):
     return args, offs, total, npass
 
 
-def run_many(exe, dims_list, dtype, nwg=1, sync=False, levels=False):
-    args, offs, total, _ = grid_args(dims_list, dtype, "batch" if (sync or levels) else "all")
+def run_many(exe, dims_list, dtype, nwg=1, sync=False, levels=False, which=None):
+    """Run the batch loop of one form on the emulator: the work-queue loop
+    over the every-length executor's cases, the level-synchronous loop or
+    the level kernels over the batch executor's (the level kernels also over
+    the every-length executor's, which="all")."""
+    which = which or ("batch" if (sync or levels) else "all")
+    args, offs, total, _ = grid_args(dims_list, dtype, which)
     code = "0" if dtype == torch.complex128 else "1"
-    mode = "levels" if levels else "sync" if sync else "many"
+    mode = ("levels_all" if which == "all" else "levels") if levels else "sync" if sync else "many"
     r = subprocess.run([exe, mode, code, str(nwg)] + args, capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, (r.stdout[:500], r.stderr[-3000:])
     lines = r.stdout.splitlines()
@@ -261,9 +276,8 @@ def test_library_tables_invariants(emu_binary, dtype, which):
     nseg, items, tiles, lds, threads, per_item = (int(head[i]) for i in (1, 3, 5, 8, 10, 12))
     segs = [list(map(int, ln.split())) for ln in lines[1:1 + nseg]]
     levels = [list(map(int, ln.split()[2:])) for ln in lines[1 + nseg:]]
-    gk = gen_kernels()
     prec = "f64" if dtype == torch.complex128 else "f32"
-    cases = gk.many_cases(prec, which)
+    cases = many_cases(prec, which)
     es = 16 if prec == "f64" else 8
     assert nseg == sum(npass)
     item_next, tile_next = 0, 0
@@ -343,9 +357,8 @@ def test_emulated_persistent_loop_batch_lengths(emu_binary):
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
 def test_emulated_every_case_once(emu_binary, dtype):
     """Every kernel case of the executor on a small strided and contiguous pass."""
-    gk = gen_kernels()
     prec = "f64" if dtype == torch.complex128 else "f32"
-    lengths = sorted({L for L, _, _ in gk.many_cases(prec, "all")})
+    lengths = sorted({L for L, _, _ in many_cases(prec, "all")})
     dims = [d for L in lengths for d in ((L, 1, 3), (1, 2, L))]
     run_many(emu_binary, dims, dtype)
 
@@ -522,3 +535,12 @@ def test_emulated_level_kernels(emu_binary, dtype):
     dims = [tuple(min(v, 64) if v > 1 else 1 for v in d) for d in SYNC_DIMS]
     dims = [tuple(v if v in (1, 48, 60, 64) else 64 for v in d) for d in dims]
     run_many(emu_binary, dims, dtype, levels=True)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
+def test_emulated_level_kernels_every_length_executor(emu_binary, dtype):
+    """The level kernels of the every-length executor over the mixed batch of
+    small lengths (2, 3, 5, 9, 25, 27, 100, 16, 8, 48, 60, 64, and a 1x1x1
+    grid): exactly the launch's LDS, the library's tables; every grid
+    matches the oracle."""
+    run_many(emu_binary, MIXED, dtype, levels=True, which="all")

@@ -133,7 +133,7 @@ def test_mixed_small_batch_separate_launches(dtype):
     # lengths outside the persistent executor's set (2, 3, 5, 9, 25, 27, 100)
     # and a 1x1x1 grid: separate launches, normalised round trip, in place
     plan = offt.ManyPlan(MIXED, dtype=dtype, normalize_inverse=True)
-    assert "unavailable" in plan.describe()
+    assert "persistent executor unavailable" in plan.describe()
     grids, x = packed_input(plan, MIXED, dtype, key0=synth.SEED + 300)
     with pytest.raises(offt.OfftError) as ei:
         plan.execute(x, use_graph=1)
@@ -150,9 +150,72 @@ def test_mixed_small_batch_separate_launches(dtype):
         assert e <= oracle.tolerance(a.numel(), dtype == C64), (g, e)
 
 
-@pytest.mark.skip(reason="the persistent executor for every length <= 160 stopped responding on the GPU for "
-                         "this batch; its cause is not found (the tile code and loop pass the CPU emulation in "
-                         "tests/test_emu.py), so that executor is not built")
+@pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
+def test_mixed_small_batch_level_kernels(dtype):
+    """Lengths outside the persistent executor's set run on the level kernels
+    of the every-length executor: against the oracle, bit-identical to the
+    same plans as separate launches, as the default form, and an in-place
+    normalised round trip."""
+    plan = offt.ManyPlan(MIXED, dtype=dtype, normalize_inverse=True)
+    desc = plan.describe()
+    print(desc.splitlines()[0], flush=True)
+    assert "executor all" in desc and "level kernels unavailable" not in desc
+    grids, x = packed_input(plan, MIXED, dtype, key0=synth.SEED + 310)
+    y = plan.execute(x, use_graph=2)
+    y_levels = plan.execute(x, use_graph=3)
+    y_sep = plan.execute(x, use_graph=-2)
+    y_default = plan.forward(x)
+    torch.cuda.synchronize()
+    check_against_oracle(plan, grids, y, dtype)
+    assert same_grids(plan, y, y_levels)
+    assert same_grids(plan, y, y_sep)
+    assert same_grids(plan, y, y_default)
+    buf = y.clone()
+    plan.execute(buf, out=buf, use_graph=2, direction=offt.BACKWARD)
+    torch.cuda.synchronize()
+    for g, (a, b) in enumerate(zip(grids, plan.unpack(buf))):
+        e = oracle.rel_l2(b.cpu().numpy(), a.cpu().numpy())
+        assert e <= oracle.tolerance(a.numel(), dtype == C64), (g, e)
+
+
+def every_length_dims():
+    """Grids whose axes take every 2/3/5-smooth length from 2 to 160, three
+    lengths per grid, short and long lengths mixed."""
+    def smooth(n):
+        for q in (2, 3, 5):
+            while n % q == 0:
+                n //= q
+        return n == 1
+
+    lengths = [n for n in range(2, 161) if smooth(n)]
+    half = (len(lengths) + 1) // 2
+    short, long_ = lengths[:half], lengths[half:][::-1]
+    axes = [v for pair in zip(short, long_ + [1]) for v in pair]
+    axes += [1] * (-len(axes) % 3)
+    return [tuple(axes[i:i + 3]) for i in range(0, len(axes), 3)]
+
+
+@pytest.mark.parametrize("tune", ["none", "exhaustive"])
+def test_every_length_up_to_160_level_kernels(tune):
+    """Every length the every-length executor compiles, in heuristic and in
+    tuned plans, through the level kernels: against the oracle and bit for
+    bit against the same plans as separate launches."""
+    dims = every_length_dims()
+    plan = offt.ManyPlan(dims, dtype=C64, tune=tune)
+    print(plan.describe().splitlines()[0], flush=True)
+    assert "executor all" in plan.describe()
+    grids, x = packed_input(plan, dims, C64, key0=synth.SEED + 320)
+    y = plan.forward(x)
+    y_sep = plan.execute(x, use_graph=-2)
+    torch.cuda.synchronize()
+    assert same_grids(plan, y, y_sep)
+    check_against_oracle(plan, grids, y, C64)
+
+
+@pytest.mark.skip(reason="the work-queue persistent kernel of the executor for every length <= 160 stopped "
+                         "responding on the GPU for this batch; its cause is not found (the tile code and loop "
+                         "pass the CPU emulation in tests/test_emu.py), so that executor's persistent forms are "
+                         "not built")
 def test_mixed_small_batch_persistent_all_lengths():
     plan = offt.ManyPlan(MIXED, dtype=C64, normalize_inverse=True)
     grids, x = packed_input(plan, MIXED, C64, key0=synth.SEED + 300)
@@ -189,11 +252,12 @@ def test_batch_lengths_with_unit_axes_persistent():
 def test_long_axis_has_no_persistent_executor():
     dims = [(256, 4, 4), (8, 8, 8)]
     plan = offt.ManyPlan(dims, dtype=C64)
-    assert "unavailable" in plan.describe()
+    assert "level kernels unavailable" in plan.describe()
     grids, x = packed_input(plan, dims, C64)
-    with pytest.raises(offt.OfftError) as ei:
-        plan.execute(x, use_graph=1)
-    assert ei.value.code == -2
+    for form in (1, 2):
+        with pytest.raises(offt.OfftError) as ei:
+            plan.execute(x, use_graph=form)
+        assert ei.value.code == -2
     y = plan.execute(x, use_graph=-1)
     torch.cuda.synchronize()
     check_against_oracle(plan, grids, y, C64)
