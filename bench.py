@@ -69,6 +69,49 @@ def pass_keys(plan: str):
     return [f"{ax}={fields[ax]}" for ax in fields["order"]]
 
 
+def plan_slab(plan: str) -> int:
+    """Planes per slab of a plan string's slab schedule (";slab=S"), or 0."""
+    for f in plan.split("|")[0].strip().split(";"):
+        if f.startswith("slab="):
+            return int(f[5:])
+    return 0
+
+
+def pass_groups(plan: str):
+    """Pass indices timed together: each pass on its own, except that the
+    passes of a slab schedule (every pass after the first) form one group,
+    since they run interleaved slab by slab."""
+    npass = len(pass_keys(plan))
+    if plan_slab(plan) and npass > 1:
+        return [[0], list(range(1, npass))]
+    return [[i] for i in range(npass)]
+
+
+def pass_label(plan: str, i: int) -> str:
+    """Key "axis=spec" of pass i, with ";slab=S" for a pass of a slab schedule
+    (its access modes and cache behaviour differ from the whole-grid pass)."""
+    S = plan_slab(plan)
+    keys = pass_keys(plan)
+    return keys[i] + (f";slab={S}" if S and i > 0 else "")
+
+
+def group_key(plan: str, g) -> str:
+    keys = pass_keys(plan)
+    key = "+".join(keys[i] for i in g)
+    return key + (f";slab={plan_slab(plan)}" if len(g) > 1 else "")
+
+
+def pass_launches(plan: str, planes: int):
+    """Pass index of every kernel launch of one transform, in launch order
+    (`planes` = Na x batch: a slab schedule launches each of its passes once
+    per slab, slab after slab)."""
+    npass = len(pass_keys(plan))
+    S = plan_slab(plan)
+    if not S or npass < 2:
+        return list(range(npass))
+    return [0] + [i for _ in range(-(-planes // S)) for i in range(1, npass)]
+
+
 def load_traffic(tag: str, key: str):
     """Measured HBM bytes per launch of one pass (from rocprofv3 PMC runs),
     only if they were taken on the current kernel sources."""
@@ -97,28 +140,33 @@ def time_transform(n: int, dtype, steps: int, warmup: int, check: bool, tune: st
     plan = offt.Plan(shape, dtype=dtype, tune=tune, forced_plan=forced, cache_path=_cache(tune), reps=TUNE_REPS)
     plan_s = time.perf_counter() - t0
     npass = plan.npasses()
+    desc = plan.describe()
+    # each pass timed on its own, a slab schedule's passes as one group
+    # (launched as the transform launches them: interleaved slab by slab)
+    groups = pass_groups(desc)
+    ng = len(groups)
     stream = torch.cuda.current_stream()
     h = int(stream.cuda_stream)
     xp, yp = x.data_ptr(), y.data_ptr()
 
     def step():
-        for i in range(npass):
-            plan.exec_pass(i, offt.FORWARD, xp, yp, h)
+        for g in groups:
+            plan.exec_range(g[0], len(g), offt.FORWARD, xp, yp, h)
 
     for _ in range(warmup):
         step()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(npass + 1)] for _ in range(steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(ng + 1)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        for i in range(npass):
-            ev[k][i].record(stream)
-            plan.exec_pass(i, offt.FORWARD, xp, yp, h)
-        ev[k][npass].record(stream)
+        for j, g in enumerate(groups):
+            ev[k][j].record(stream)
+            plan.exec_range(g[0], len(g), offt.FORWARD, xp, yp, h)
+        ev[k][ng].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    pass_ms = [sum(ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(steps)) / steps for i in range(npass)]
-    total_ms = ev[0][0].elapsed_time(ev[steps - 1][npass])
+    pass_ms = [sum(ev[k][j].elapsed_time(ev[k][j + 1]) for k in range(steps)) / steps for j in range(ng)]
+    total_ms = ev[0][0].elapsed_time(ev[steps - 1][ng])
     ms = total_ms / steps
     N = x.numel()
     s = x.element_size()
@@ -153,9 +201,10 @@ def time_transform(n: int, dtype, steps: int, warmup: int, check: bool, tune: st
         "gflops": 5.0 * N * math.log2(N) / (ms * 1e6),
         "eff_gbs": 6.0 * N * s / (ms * 1e6),
         "wall_ms_per_step": 1e3 * wall / steps,
-        "plan": plan.describe(),
+        "plan": desc,
         "plan_seconds": plan_s,
         "pass_ms": pass_ms,
+        "groups": groups,
         "pass_bytes": 2 * N * s,
         "copy_ms": copy_ms,
     }
@@ -535,8 +584,12 @@ def time_small(steps: int, warmup: int, check: bool, n: int = 32):
 
 
 def roofline(res, tag):
-    i = max(range(len(res["pass_ms"])), key=lambda j: res["pass_ms"][j])
-    dur_ms = res["pass_ms"][i]
+    """The dominant kernel: the slowest pass that runs as one launch over the
+    whole grid (the passes of a slab schedule run as one launch per slab)."""
+    groups = res["groups"]
+    j = max((j for j in range(len(groups)) if len(groups[j]) == 1), key=lambda j: res["pass_ms"][j])
+    i = groups[j][0]
+    dur_ms = res["pass_ms"][j]
     achieved = res["pass_bytes"] / (dur_ms * 1e6)
     key = pass_keys(res["plan"])[i]
     copy_gbs = res["pass_bytes"] / (res["copy_ms"][i] * 1e6)
@@ -547,13 +600,16 @@ def roofline(res, tag):
 
 
 def copy_ceilings(res):
-    """Per pass: the copy of the pass's own access pattern (GB/s of the
-    algorithmic bytes) and the pass's rate as a fraction of it."""
+    """Per pass (per group of a slab schedule): the copy of the pass's own
+    access pattern over the whole grid (GB/s of the algorithmic bytes) and
+    the pass's rate as a fraction of it."""
     out = []
-    for key, pm, cm in zip(pass_keys(res["plan"]), res["pass_ms"], res["copy_ms"]):
-        g = res["pass_bytes"] / (cm * 1e6)
-        out.append({"pass": key, "copy_ms": round(cm, 4), "copy_gbs": round(g, 1),
-                    "pass_gbs": round(res["pass_bytes"] / (pm * 1e6), 1), "frac_of_copy": round(cm / pm, 4)})
+    for g, pm in zip(res["groups"], res["pass_ms"]):
+        cm = sum(res["copy_ms"][i] for i in g)
+        nbytes = res["pass_bytes"] * len(g)
+        out.append({"pass": group_key(res["plan"], g), "copy_ms": round(cm, 4),
+                    "copy_gbs": round(nbytes / (cm * 1e6), 1), "pass_gbs": round(nbytes / (pm * 1e6), 1),
+                    "frac_of_copy": round(cm / pm, 4)})
     return out
 
 
@@ -707,18 +763,25 @@ def _profiled_runs(log: str, n: int):
     return runs
 
 
-def _pass_dispatches(names, runs, steps, warmup):
+def _pass_dispatches(names, runs, steps, warmup, planes):
     """Split the fft_pass_kernel dispatches (in dispatch order) into
-    runs x steps x passes; yields (run index, pass index, step, position)."""
+    runs x steps x passes (a pass of a slab schedule has one dispatch per
+    slab); yields (run index, pass index, step, position)."""
     k = 0
     for r, (_, _, plan) in enumerate(runs):
-        npass = len(pass_keys(plan))
+        seq = pass_launches(plan, planes)
         for st in range(steps + warmup):
-            for i in range(npass):
+            for i in seq:
                 yield r, i, st, k
                 k += 1
     if k != len(names):
         raise RuntimeError(f"expected {k} pass dispatches, the trace holds {len(names)}")
+
+
+def _per_step(items):
+    """{(run, pass): {step: summed value}} -> {(run, pass): mean over steps}
+    (a pass of a slab schedule sums its slabs' dispatches)."""
+    return {key: sum(v.values()) / len(v) for key, v in items.items()}
 
 
 def summarize_stats(d: str, log: str, command: str, n: int, steps: int, warmup: int) -> str:
@@ -732,12 +795,14 @@ def summarize_stats(d: str, log: str, command: str, n: int, steps: int, warmup: 
     trace = _read_csv(_find(d, "kernel_trace.csv"))
     trace.sort(key=lambda r: int(r["Dispatch_Id"]))
     disp = [r for r in trace if "fft_pass_kernel" in r["Kernel_Name"]]
-    dur = {}
-    for r, i, st, k in _pass_dispatches(disp, runs, steps, warmup):
+    dur, kname = {}, {}
+    for r, i, st, k in _pass_dispatches(disp, runs, steps, warmup, n):
         if st >= warmup:
             x = disp[k]
-            dur.setdefault((r, i), ([], x["Kernel_Name"])).__getitem__(0).append(
-                (int(x["End_Timestamp"]) - int(x["Start_Timestamp"])) / 1e3)
+            kname[(r, i)] = x["Kernel_Name"]
+            steps_d = dur.setdefault((r, i), {})
+            steps_d[st] = steps_d.get(st, 0.0) + (int(x["End_Timestamp"]) - int(x["Start_Timestamp"])) / 1e3
+    dur = _per_step(dur)
     # the copy of each pass's accesses (offt_copy_pass), run after each
     # transform: per run, per pass, warmup + steps dispatches
     copies = [r for r in trace if "copy_pattern_kernel" in r["Kernel_Name"]]
@@ -754,14 +819,15 @@ def summarize_stats(d: str, log: str, command: str, n: int, steps: int, warmup: 
         raise RuntimeError(f"expected {k} copy dispatches, the trace holds {len(copies)}")
     es = {"complex128": 16, "complex64": 8}
     lines.append("")
-    lines.append("# per-pass mean duration over the timed steps (from the dispatch trace), and the copy kernel")
-    lines.append("# of the same pass (its tiles, threads, tile order and access mode, no arithmetic)")
+    lines.append("# per-pass mean duration over the timed steps (from the dispatch trace; a pass of a slab")
+    lines.append("# schedule summed over its slabs' dispatches), and the copy kernel of the same pass over the")
+    lines.append("# whole grid (its tiles, threads, tile order and access mode, no arithmetic)")
     for r, (tag, label, plan) in enumerate(runs):
         lines.append(f"{n}^3 {label}, plan {plan}")
         nbytes = 2 * n ** 3 * es[label]
-        for i, key in enumerate(pass_keys(plan)):
-            v, name = dur[(r, i)]
-            pm = sum(v) / len(v)
+        for i in range(len(pass_keys(plan))):
+            key = pass_label(plan, i)
+            pm, name = dur[(r, i)], kname[(r, i)]
             cm = sum(cdur[(r, i)]) / len(cdur[(r, i)])
             lines.append(f"  pass {i} {key:<18} mean {pm:9.2f} us ({nbytes / (pm * 1e3):7.1f} GB/s), copy {cm:9.2f} us "
                          f"({nbytes / (cm * 1e3):7.1f} GB/s), of copy {cm / pm:6.3f}  {name[:100]}")
@@ -962,15 +1028,16 @@ def summarize_sq(d: str, log: str, command: str, n: int, steps: int, warmup: int
     if len(durs) != len(idx):
         raise RuntimeError(f"{len(idx)} counter dispatches but {len(durs)} traced pass dispatches")
     acc = {}
-    for r, i, st, k in _pass_dispatches(idx, runs, steps, warmup):
+    for r, i, st, k in _pass_dispatches(idx, runs, steps, warmup, n):
         if st < warmup:
             continue
         a = acc.setdefault((r, i), {c: 0.0 for c in SQ_COUNTERS + ["us"]})
         for c in SQ_COUNTERS:
             a[c] += vals[c][idx[k]][1]
         a["us"] += durs[k]
-        a["n"] = a.get("n", 0) + 1
-    lines = ["# rocprofv3 SQ / GRBM counters per axis pass (mean per dispatch over the timed steps)",
+        a.setdefault("steps", set()).add(st)
+    lines = ["# rocprofv3 SQ / GRBM counters per axis pass (per pass and step, averaged over the timed steps;",
+             "# a pass of a slab schedule summed over its slabs' dispatches)",
              f"# command: {command}",
              "# valu% = 100*SQ_ACTIVE_INST_VALU/CU_NUM/GRBM_GUI_ACTIVE (rocprofv3 VALUBusy); lds% the same with",
              "# SQ_ACTIVE_INST_LDS; conflict% = 100*SQ_LDS_BANK_CONFLICT/GRBM_GUI_ACTIVE/CU_NUM (LDSBankConflict);",
@@ -981,9 +1048,10 @@ def summarize_sq(d: str, log: str, command: str, n: int, steps: int, warmup: int
              f"{'valu/pt':>8} {'lds/pt':>7} {'vmem/pt':>8} {'waves':>8}"]
     for r, (tag, label, plan) in enumerate(runs):
         N = n ** 3
-        for i, key in enumerate(pass_keys(plan)):
+        for i in range(len(pass_keys(plan))):
+            key = pass_label(plan, i)
             a = acc[(r, i)]
-            m = {c: a[c] / a["n"] for c in SQ_COUNTERS + ["us"]}
+            m = {c: a[c] / len(a["steps"]) for c in SQ_COUNTERS + ["us"]}
             g = m["GRBM_GUI_ACTIVE"] / XCD_NUM
             lines.append(
                 f"{n}^3 c{label[7:]:<5} {key:<18} {m['us']:8.1f} {g / m['us'] / 1e3:5.2f} "
@@ -1011,7 +1079,8 @@ def summarize_pmc(fetch_dir: str, write_dir: str, log: str, n: int, steps: int, 
             out["command"] = command + "; merged with the earlier sessions' passes on the same kernel sources"
     except (OSError, ValueError):
         pass
-    text = [f"# HBM traffic per dispatch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE",
+    text = [f"# HBM traffic per pass from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (a pass of a slab schedule",
+            "# summed over its slabs' dispatches)",
             f"# command: {command}"]
     acc = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
@@ -1023,15 +1092,15 @@ def summarize_pmc(fetch_dir: str, write_dir: str, log: str, n: int, steps: int, 
         text.append(f"{counter}: calibration copy of {CALIB_BYTES} B in and out counted {calib_kib:.0f} KiB "
                     f"-> factor {factor:.4f}")
         vals = {}
-        for r, i, st, k in _pass_dispatches(passes, runs, steps, warmup):
+        for r, i, st, k in _pass_dispatches(passes, runs, steps, warmup, n):
             if st >= warmup:
-                vals.setdefault((r, i), []).append(passes[k][1])
-        for (r, i), v in sorted(vals.items()):
+                per = vals.setdefault((r, i), {})
+                per[st] = per.get(st, 0.0) + passes[k][1]
+        for (r, i), kib in sorted(_per_step(vals).items()):
             tag, label, plan = runs[r]
-            key = pass_keys(plan)[i]
-            kib = sum(v) / len(v)
+            key = pass_label(plan, i)
             acc.setdefault((tag, key), {})[counter] = kib * 1024.0 * factor
-            text.append(f"{tag} {key:<18} {counter}: {kib:.0f} KiB/dispatch -> {kib*1024*factor/1e9:.4f} GB scaled")
+            text.append(f"{tag} {key:<18} {counter}: {kib:.0f} KiB/pass -> {kib*1024*factor/1e9:.4f} GB scaled")
     for (tag, key), c in sorted(acc.items()):
         s = 16 if tag.endswith("f64") else 8
         alg = 2 * n ** 3 * s

@@ -203,14 +203,27 @@ int offt_plan_passes(offt_plan_t p);
 
 /* Launch only axis pass i (0-based, plan order) of the forward
  * (direction = OFFT_FORWARD) or backward (OFFT_BACKWARD) transform.  Launching
- * passes 0..n-1 in order on one stream with the same in/out is exactly
- * offt_exec_fwd / offt_exec_bwd (pass 0 reads `in`, later passes work in place
- * on `out`; in REVERSED layouts the passes route through the plan's
- * workspace exactly as exec does); it exists so that each pass can be timed
- * on its own.
+ * passes 0..n-1 in order on one stream with the same in/out gives exactly
+ * the result of offt_exec_fwd / offt_exec_bwd (pass 0 reads `in`, later
+ * passes work in place on `out`; in REVERSED layouts the passes route
+ * through the plan's workspace exactly as exec does; a pass of a slab
+ * schedule runs here over all its slabs, one launch per slab, where exec
+ * interleaves the passes slab by slab); it exists so that each pass can be
+ * timed on its own.
  * Errors: INVALID_ARG (NULL plan/pointer, i out of range, bad direction),
  * BAD_PLAN, HIP. */
 int offt_exec_pass(offt_plan_t p, int i, int direction, const void* in, void* out, void* stream);
+
+/* Launch passes first .. first+count-1 (plan order) exactly as offt_exec_fwd /
+ * offt_exec_bwd launches them: same buffers, conjugation and scaling as
+ * offt_exec_pass, and the passes of a slab schedule (offt_plan_describe's
+ * ";slab=S") interleaved slab by slab.  A range covering every pass is
+ * offt_exec_fwd / offt_exec_bwd; ranges launched back to back give the same
+ * result.  It exists so that the pass over a and the slab schedule after it
+ * can be timed apart.  Errors: INVALID_ARG (NULL plan/pointer, count < 1,
+ * range outside 0..passes-1, bad direction), BAD_PLAN, HIP. */
+int offt_exec_range(offt_plan_t p, int first, int count, int direction, const void* in, void* out,
+                    void* stream);
 
 /* Copy of axis pass i's memory accesses, the measured ceiling of that pass:
  * the pass's tiles (lines per workgroup, threads, tile order, grid-data
@@ -228,7 +241,14 @@ int offt_destroy(offt_plan_t p);
 
 /* Plan string (axis order, radix sequence, tile width and pass mode of each
  * axis pass) written NUL-terminated into buf[0..n).  Returns the length of the
- * full string, or a negative code; the string is truncated if n is too small. */
+ * full string, or a negative code; the string is truncated if n is too small.
+ * A trailing ";slab=S" marks a slab schedule: the pass over a runs first over
+ * the whole grid, then the passes over b and c run S planes (Nb x Nc, counted
+ * over the batch) at a time, both passes of one slab before the next slab,
+ * so that a slab's second pass finds the first one's output in the
+ * Infinity Cache (natural layout only; the exhaustive tuner tries it for
+ * grids above 512 MiB).  Every element goes through the same arithmetic as
+ * without it: results are bit-identical to the plan without ";slab=". */
 int offt_plan_describe(offt_plan_t p, char* buf, size_t n);
 
 /* Bytes of device memory the plan owns (twiddle tables, scratch). */

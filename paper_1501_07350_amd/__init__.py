@@ -165,6 +165,21 @@ class Plan:
                                               ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream)),
                    "exec_pass")
 
+    def exec_range(self, first: int, count: int, direction: int, in_ptr: int, out_ptr: int,
+                   stream: int = 0) -> None:
+        """Launch passes first..first+count-1 as exec does (a slab schedule's
+        passes interleaved slab by slab)."""
+        _lib.check(_lib.load().offt_exec_range(self._h, int(first), int(count), int(direction),
+                                               ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
+                                               ctypes.c_void_p(stream)), "exec_range")
+
+    def slab(self) -> int:
+        """Planes per slab of the plan's slab schedule, or 0."""
+        for field in self.describe().split("|")[0].split(";"):
+            if field.startswith("slab="):
+                return int(field[5:])
+        return 0
+
     def copy_pass(self, i: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
         """The copy of pass i's memory accesses (its measured ceiling)."""
         _lib.check(_lib.load().offt_copy_pass(self._h, int(i), ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),

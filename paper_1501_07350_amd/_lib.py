@@ -89,6 +89,7 @@ SIGNATURES = {
     "offt_destroy": (_ci, [_vp]),
     "offt_plan_passes": (_ci, [_vp]),
     "offt_exec_pass": (_ci, [_vp, _ci, _ci, _vp, _vp, _vp]),
+    "offt_exec_range": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, _vp]),
     "offt_copy_pass": (_ci, [_vp, _ci, _vp, _vp, _vp]),
     "offt_exec_noalloc": (_ci, [_i64, _i64, _i64, _ci, _i64, _ci, _ci, _vp, _vp, _vp]),
     "offt_plan_describe": (_ci, [_vp, ctypes.c_char_p, ctypes.c_size_t]),

@@ -95,8 +95,9 @@ const PassPlan* dir_passes(const offt_plan_s* p, int dir) {
 }
 
 int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const void* in, void* out,
-                void* work, int dir, hipStream_t s, int normalize) {
+                void* work, int dir, hipStream_t s, int normalize, int i0, int i1) {
     const int64_t N = p->grid_elems();
+    if (i1 < 0) i1 = npass;
     if (npass == 0) {
         if (in != out) {
             const size_t bytes = (size_t)(N * p->batch) * elem_size(p->dtype);
@@ -106,15 +107,39 @@ int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const v
         return OFFT_SUCCESS;
     }
     const bool bwd = dir > 0;
-    for (int i = 0; i < npass; ++i) {
+    const int norm = normalize < 0 ? p->normalize : normalize;
+    const size_t es = elem_size(p->dtype);
+    // pass i (whole grid, or the planes of one slab at element offset off)
+    auto launch = [&](int i, const PassPlan& q, int64_t off) {
         const bool last = i == npass - 1;
-        const int norm = normalize < 0 ? p->normalize : normalize;
         const double scale = (bwd && last && norm) ? 1.0 / (double)N : 1.0;
         const void* src = nullptr;
         void* dst = nullptr;
         if (!pass_io(passes, npass, i, in, out, work, &src, &dst)) return OFFT_ERR_BAD_PLAN;
-        if (launch_pass(passes[i], src, dst, bwd && i == 0, bwd && last, scale, s) != hipSuccess)
+        if (launch_pass(q, static_cast<const char*>(src) + off * es, static_cast<char*>(dst) + off * es,
+                        bwd && i == 0, bwd && last, scale, s) != hipSuccess)
             return OFFT_ERR_HIP;
+        return OFFT_SUCCESS;
+    };
+    // passes before the slab schedule (all of them without one) over the
+    // whole grid, then the slab schedule: every remaining pass of one slab
+    // before the next slab
+    const int first_slab = slab_start(passes, npass);
+    for (int i = i0; i < std::min(i1, first_slab); ++i) {
+        const int rc = launch(i, passes[i], 0);
+        if (rc != OFFT_SUCCESS) return rc;
+    }
+    const int j0 = std::max(i0, first_slab);
+    if (j0 >= i1) return OFFT_SUCCESS;
+    const PassPlan& sp = passes[first_slab];
+    for (int64_t p0 = 0; p0 < sp.planes; p0 += sp.slab) {
+        const int64_t np = std::min(sp.slab, sp.planes - p0);
+        for (int i = j0; i < i1; ++i) {
+            int64_t off = 0;
+            const PassPlan q = slab_pass(passes[i], p0, np, &off);
+            const int rc = launch(i, q, off);
+            if (rc != OFFT_SUCCESS) return rc;
+        }
     }
     return OFFT_SUCCESS;
 }
@@ -469,19 +494,25 @@ int offt_exec_pass(offt_plan_t p, int i, int direction, const void* in, void* ou
     }
     if (p->kind != 1 && p->kind != 3) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
     if (i < 0 || i >= p->npass) { set_error(OFFT_ERR_INVALID_ARG); return OFFT_ERR_INVALID_ARG; }
-    const int64_t N = p->grid_elems();
-    const bool bwd = direction == OFFT_BACKWARD;
-    const bool last = i == p->npass - 1;
-    const double scale = (bwd && last && p->normalize) ? 1.0 / (double)N : 1.0;
-    const PassPlan* ps = dir_passes(p, direction);
-    const void* src = nullptr;
-    void* dst = nullptr;
-    int rc = OFFT_SUCCESS;
-    if (!pass_io(ps, p->npass, i, in, out, p->work, &src, &dst))
-        rc = OFFT_ERR_BAD_PLAN;
-    else if (launch_pass(ps[i], src, dst, bwd && i == 0, bwd && last, scale, static_cast<hipStream_t>(stream)) !=
-             hipSuccess)
-        rc = OFFT_ERR_HIP;
+    const int rc = exec_passes(p, dir_passes(p, direction), p->npass, in, out, p->work, direction,
+                               static_cast<hipStream_t>(stream), -1, i, i + 1);
+    set_error(rc);
+    return rc;
+}
+
+int offt_exec_range(offt_plan_t p, int first, int count, int direction, const void* in, void* out,
+                    void* stream) {
+    if (!p || !in || !out || (direction != OFFT_FORWARD && direction != OFFT_BACKWARD)) {
+        set_error(OFFT_ERR_INVALID_ARG);
+        return OFFT_ERR_INVALID_ARG;
+    }
+    if (p->kind != 1 && p->kind != 3) { set_error(OFFT_ERR_BAD_PLAN); return OFFT_ERR_BAD_PLAN; }
+    if (first < 0 || count < 1 || first > p->npass - count) {
+        set_error(OFFT_ERR_INVALID_ARG);
+        return OFFT_ERR_INVALID_ARG;
+    }
+    const int rc = exec_passes(p, dir_passes(p, direction), p->npass, in, out, p->work, direction,
+                               static_cast<hipStream_t>(stream), -1, first, first + count);
     set_error(rc);
     return rc;
 }

@@ -71,7 +71,19 @@ struct PassPlan {
     int xcd = 0;               // tiles in contiguous runs per XCD (PassArgs::xcd_remap)
     int stream = 0;            // streaming loads and stores (PassArgs::stream_io)
     const void* tw;            // device twiddle table for L
+    // Slab schedule (PlanChoice::slab): a pass over axis b or c after the
+    // whole-grid pass over a runs on `slab` planes (Nb x Nc) at a time, every
+    // such pass of one slab before the next slab.  0: the whole grid at once.
+    int64_t slab = 0;
+    int64_t planes = 0;        // planes the pass covers (batch * Na)
+    int64_t plane_elems = 0;   // elements of one plane (Nb * Nc)
 };
+
+// Pass p restricted to planes [p0, p0 + np) of a slab schedule; *elem_off
+// receives the element offset of plane p0.
+PassPlan slab_pass(const PassPlan& p, int64_t p0, int64_t np, int64_t* elem_off);
+// Index of the first pass of a list that runs slab by slab, or n.
+int slab_start(const PassPlan* ps, int n);
 
 // Grid-data access mode of a pass (plan choices, plan-string suffix):
 // kIoAuto streams when the batch of grids exceeds kStreamMinBytes (it then
@@ -97,7 +109,15 @@ struct PlanChoice {
     // writes strided lines of the cba grid (mode 2).  Passes before it see
     // the abc grid, passes after it the cba grid.
     int tax = -1;
+    // Slab schedule: 0, or the number of planes (Nb x Nc, counted over the
+    // batch) per slab.  Requires natural output order (tax < 0) and the pass
+    // over a first; the passes over b and c then run slab by slab (plan
+    // string ";slab=S"), so that a slab's second pass finds the first pass's
+    // output in the Infinity Cache.
+    int64_t slab = 0;
 };
+// Whether a choice's slab schedule fits its grid (see PlanChoice::slab).
+bool slab_fits(const PlanChoice& c, const int64_t dims[3]);
 
 // Where an axis pass of a choice runs: on the input's (abc) grid, on the
 // reversed (cba) grid, or as the transposing pass between them.

@@ -66,9 +66,12 @@ int set_choice_b(offt_plan_s* p, const PlanChoice& c, hipStream_t s);
 // The passes a direction runs (the backward list differs for reversed layouts).
 const PassPlan* dir_passes(const offt_plan_s* p, int dir);
 void reversed_dims(const int64_t dims[3], int64_t out[3]);
-// normalize: -1 the plan's normalize_inverse, else 0 / 1 for this call
+// normalize: -1 the plan's normalize_inverse, else 0 / 1 for this call.
+// Passes [i0, i1) of the list (i1 < 0: to the end) as the whole transform
+// runs them: buffers, conjugation and scaling by their place in the list, a
+// slab schedule's passes interleaved slab by slab.
 int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const void* in, void* out,
-                void* work, int dir, hipStream_t s, int normalize = -1);
+                void* work, int dir, hipStream_t s, int normalize = -1, int i0 = 0, int i1 = -1);
 void free_plan(offt_plan_s* p);
 
 // Tuning (tuner.cpp): fills *choice for EXHAUSTIVE / LEARNED modes.

@@ -517,7 +517,38 @@ std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]) {
         os << ";" << kAxisName[ax] << "=";
         axis_to_string(os, c.k[ax], c.logW[ax], dims[ax], c.xcd[ax], c.io[ax]);
     }
+    if (c.slab > 0) os << ";slab=" << c.slab;
     return os.str();
+}
+
+bool slab_fits(const PlanChoice& c, const int64_t dims[3]) {
+    return c.slab == 0 || (c.slab > 0 && c.tax < 0 && c.order[0] == 0 && dims[0] > 1 && dims[1] * dims[2] > 1);
+}
+
+// Planes per slab from a plan string: a decimal count of 1 to 2^40.
+static bool parse_slab(const std::string& val, int64_t* out) {
+    if (val.empty() || val.size() > 13) return false;
+    int64_t v = 0;
+    for (char ch : val) {
+        if (ch < '0' || ch > '9') return false;
+        v = v * 10 + (ch - '0');
+    }
+    if (v < 1 || v > (int64_t(1) << 40)) return false;
+    *out = v;
+    return true;
+}
+
+PassPlan slab_pass(const PassPlan& p, int64_t p0, int64_t np, int64_t* elem_off) {
+    PassPlan q = p;
+    q.M1 = p.M1 / p.planes * np;
+    *elem_off = p0 * p.plane_elems;
+    return q;
+}
+
+int slab_start(const PassPlan* ps, int n) {
+    for (int i = 0; i < n; ++i)
+        if (ps[i].slab > 0) return i;
+    return n;
 }
 
 bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanChoice* out, bool check_fit) {
@@ -540,6 +571,8 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
             if (val == "a") c.tax = 0;
             else if (val == "c") c.tax = 2;
             else return false;
+        } else if (key == "slab") {
+            if (!parse_slab(val, &c.slab)) return false;
         } else if (key.size() == 1 && key[0] >= 'a' && key[0] <= 'c') {
             const int ax = key[0] - 'a';
             if (dims[ax] <= 1) {
@@ -553,6 +586,7 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
     }
     if (!have_order) return false;
     if (c.tax >= 0 && (!reversal_moves_data(dims) || dims[c.tax] <= 1)) return false;
+    if (!slab_fits(c, dims)) return false;
     // axes the string leaves out take the heuristic's kernel for their geometry
     assign_default_kernels(c, dtype, dims);
     for (int ax = 0; ax < 3; ++ax) {
@@ -693,6 +727,20 @@ int build_passes(const PlanChoice& c, const int64_t dims[3], int64_t batch, Pass
         const int ax = c.order[i];
         if (dims[ax] <= 1) continue;
         out[n++] = make_pass(dims, batch, ax, axis_geom(c, ax), c.k[ax], c.logW[ax], c.xcd[ax], c.io[ax]);
+    }
+    if (c.slab > 0 && slab_fits(c, dims)) {
+        // every pass after the one over a, on slabs of planes; access modes
+        // resolved for one slab's bytes (it may stay cached between them)
+        const int64_t planes = batch * dims[0], plane_elems = dims[1] * dims[2];
+        const int64_t slab = std::min(c.slab, planes);
+        for (int i = 1; i < n; ++i) {
+            out[i].slab = slab;
+            out[i].planes = planes;
+            out[i].plane_elems = plane_elems;
+            if (out[i].k)
+                out[i].stream = resolve_stream(c.io[out[i].axis],
+                                               slab * plane_elems * (int64_t)elem_size(out[i].k->dtype));
+        }
     }
     return n;
 }

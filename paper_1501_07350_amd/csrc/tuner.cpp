@@ -368,6 +368,34 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
         ++*timed;
         if (rc == OFFT_SUCCESS && ms < 0.99f * win_ms) { win_ms = ms; winner = c; }
     }
+    // slab schedules of grids larger than twice the Infinity Cache: the pass
+    // over a first, then the winner's kernels for b and c slab by slab, in
+    // both orders, with slabs of 64, 128 and 256 MiB (their passes' access
+    // modes resolved per slab); kept when more than 1% faster
+    const int64_t plane_bytes = dims[1] * dims[2] * (int64_t)elem_size(p->dtype);
+    const int64_t planes = dims[0] * p->batch;
+    if (!rev && winner.tax < 0 && dims[0] > 1 && dims[1] * dims[2] > 1 && grid_bytes > 2 * kStreamMinBytes) {
+        const PlanChoice base = winner;
+        for (int bc = 0; bc < 2 && rc == OFFT_SUCCESS; ++bc) {
+            PlanChoice ord = base;
+            ord.order[0] = 0;
+            ord.order[1] = bc ? 2 : 1;
+            ord.order[2] = bc ? 1 : 2;
+            ord.io[1] = ord.io[2] = kIoAuto;
+            int64_t last = 0;
+            for (int64_t mib : {64, 128, 256}) {
+                const int64_t slab = std::max<int64_t>(1, (mib << 20) / plane_bytes);
+                if (slab >= planes || slab == last || rc != OFFT_SUCCESS) continue;
+                last = slab;
+                PlanChoice c = ord;
+                c.slab = slab;
+                float ms = 0.f;
+                rc = time_choice(p, c, dims, B.src, B.buf, B.work, s, o.reps, &ms);
+                ++*timed;
+                if (rc == OFFT_SUCCESS && ms < 0.99f * win_ms) { win_ms = ms; winner = c; }
+            }
+        }
+    }
     if (rc != OFFT_SUCCESS) return rc;
     *choice = winner;
     *win_ms_out = win_ms;

@@ -95,6 +95,8 @@ def test_exec_rejects_null_handles():
     assert lib.offt_plan_describe(None, None, 0) == _lib.ERR_INVALID_ARG
     assert lib.offt_workspace_bytes(None) == _lib.ERR_INVALID_ARG
     assert lib.offt_exec_many(None, None, None, -1, 1, None) < 0
+    assert lib.offt_exec_pass(None, 0, -1, None, None, None) == _lib.ERR_INVALID_ARG
+    assert lib.offt_exec_range(None, 0, 1, -1, None, None, None) == _lib.ERR_INVALID_ARG
     assert lib.offt_many_offset(None, 0) < 0
 
 

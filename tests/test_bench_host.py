@@ -133,3 +133,49 @@ def test_stats_summary_with_copy_kernels(tmp_path):
     # 2 * 512 points * 16 bytes in 1 us = 16.4 GB/s; the copy in 0.5 us, 32.8
     first = [l for l in txt.splitlines() if l.startswith("  pass")][0]
     assert "16.4 GB/s" in first and "32.8 GB/s" in first
+
+
+def test_stats_summary_with_slab_schedule(tmp_path):
+    """A slab schedule launches its passes once per slab, slab after slab:
+    per pass and step the slabs' dispatches are summed."""
+    b = load_bench()
+    steps, warmup, n = 2, 1, 8
+    p64, p32 = "order=abc;a=8/8;b=8/8;c=8/8", "order=abc;a=8/8;b=8/8;c=8/8;slab=3"
+    assert b.pass_launches(p32, n) == [0, 1, 2, 1, 2, 1, 2]        # slabs of 3, 3 and 2 planes
+    assert b.pass_launches(p64, n) == [0, 1, 2]
+    assert b.pass_groups(p32) == [[0], [1, 2]] and b.pass_groups(p64) == [[0], [1], [2]]
+    assert b.group_key(p32, [1, 2]) == "b=8/8+c=8/8;slab=3"
+    assert b.pass_label(p32, 0) == "a=8/8" and b.pass_label(p32, 2) == "c=8/8;slab=3"
+    log = tmp_path / "stats.log"
+    log.write_text(__import__("json").dumps({"plan": p64, "f32": {"plan": p32}}) + "\n")
+    d = []
+    for plan in (p64, p32):
+        for st in range(warmup + steps):
+            for i in b.pass_launches(plan, n):
+                slabbed = b.plan_slab(plan) and i > 0
+                d.append(("offt::fft_pass_kernel<...>", 90_000 if st < warmup else (300 if slabbed else 1_000), 10))
+        for i in range(3):
+            d += [("offt::copy_pattern_kernel<...>", 500, 10) for _ in range(warmup + steps)]
+    write_trace(str(tmp_path / "run" / "run_kernel_trace.csv"), d)
+    with open(tmp_path / "run" / "run_kernel_stats.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs", "MinNs", "MaxNs",
+                                          "Percentage"])
+        w.writeheader()
+        w.writerow({"Name": "offt::fft_pass_kernel<...>", "Calls": 30, "TotalDurationNs": 1, "AverageNs": 1,
+                    "MinNs": 1, "MaxNs": 1, "Percentage": 100})
+    txt = b.summarize_stats(str(tmp_path), str(log), "cmd", n, steps, warmup)
+    passes = [l.split() for l in txt.splitlines() if l.startswith("  pass")]
+    assert [float(p[4]) for p in passes] == [1.0, 1.0, 1.0, 1.0, 0.9, 0.9]
+    assert [p[2] for p in passes][3:] == ["a=8/8", "b=8/8;slab=3", "c=8/8;slab=3"]
+
+
+def test_roofline_and_copy_ceilings_of_a_slab_schedule():
+    b = load_bench()
+    res = {"plan": "order=abc;a=8/8;b=8/8;c=8/8;slab=3", "groups": [[0], [1, 2]], "pass_ms": [1.0, 1.5],
+           "copy_ms": [0.8, 0.6, 0.6], "pass_bytes": 10 ** 9}
+    r = b.roofline(res, "8_f32")
+    # the slab group takes longer, but the dominant single-launch kernel is pass a
+    assert r["kernel"] == "a=8/8" and r["kernel_ms"] == 1.0 and r["achieved"] == 1000.0
+    c = b.copy_ceilings(res)
+    assert [x["pass"] for x in c] == ["a=8/8", "b=8/8+c=8/8;slab=3"]
+    assert c[1]["copy_ms"] == 1.2 and c[1]["pass_gbs"] == round(2e9 / 1.5e6, 1) and c[1]["frac_of_copy"] == 0.8

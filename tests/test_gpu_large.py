@@ -3,8 +3,9 @@ element by element: 256^3 and 512^3 complex128, 512^3 and 1024^3 complex64.
 
 Each size runs the heuristic plan and the tuned plan the benchmark times
 (the plan-cache entry of that size and precision), in the benchmark's launch
-configuration: the passes launched one by one with
-offt_exec_pass, out of place, on torch's current stream.  The error is the
+configuration: the passes launched one by one with offt_exec_range (the
+passes of a slab schedule as one range), out of place, on torch's current
+stream, and compared bit for bit with the whole-transform call.  The error is the
 relative L2 norm over the whole grid (tolerance 1e-12 for binary64,
 2e-6 * log2(N) for binary32); the worst element error relative to the largest
 reference magnitude is printed beside it.  The normalised round trip is
@@ -55,10 +56,13 @@ def reference(n, dtype):
 
 
 def run_passes(plan, direction, x, y):
-    """The benchmark's launch configuration: each pass on its own, x -> y."""
+    """The benchmark's launch configuration, x -> y: each pass on its own,
+    the passes of a slab schedule as one range (interleaved slab by slab)."""
     h = int(torch.cuda.current_stream().cuda_stream)
-    for i in range(plan.npasses()):
-        plan.exec_pass(i, direction, x.data_ptr(), y.data_ptr(), h)
+    n = plan.npasses()
+    groups = [[0], list(range(1, n))] if plan.slab() and n > 1 else [[i] for i in range(n)]
+    for g in groups:
+        plan.exec_range(g[0], len(g), direction, x.data_ptr(), y.data_ptr(), h)
 
 
 def max_rel(a, b):
@@ -72,6 +76,9 @@ def check_full(n, dtype, forced=None):
     print(f"case {n}^3 {dtype} plan {plan.describe()}", flush=True)
     y = torch.empty_like(x)
     run_passes(plan, offt.FORWARD, x, y)
+    torch.cuda.synchronize()
+    # the whole-transform call gives the same bits
+    assert torch.equal(plan.forward(x), y)
     torch.cuda.synchronize()
     yh = y.cpu().numpy().astype(np.complex128)
     tol = oracle.tolerance(x.numel(), dtype == C64)

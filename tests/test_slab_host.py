@@ -1,0 +1,56 @@
+"""Plan strings of the slab schedule (";slab=S"): parsed, written back in
+canonical form, and rejected where the schedule does not fit (no GPU)."""
+import pytest
+import torch
+
+import paper_1501_07350_amd as offt
+
+C128, C64 = torch.complex128, torch.complex64
+PLAN = "order=abc;a=16x16x2/16/p2;b=16x16x2/16/p2/x;c=8x8x8/2"
+
+
+@pytest.mark.parametrize("slab,canonical", [("64", "64"), ("1", "1"), ("0064", "64"), ("4096", "4096")])
+def test_slab_round_trip(slab, canonical):
+    s = offt.plan_string((512, 512, 512), C128, "natural", f"{PLAN};slab={slab}")
+    assert s == f"{PLAN};slab={canonical}"
+    # the slab field may stand anywhere in the string
+    t = offt.plan_string((512, 512, 512), C128, "natural", f"slab={slab};{PLAN}")
+    assert t == s
+
+
+def test_plan_without_slab_has_none():
+    assert "slab" not in offt.plan_string((512, 512, 512), C128, "natural", PLAN)
+    assert "slab" not in offt.default_plan_string((512, 512, 512), C128)
+
+
+@pytest.mark.parametrize("shape,plan", [
+    ((512, 512, 512), PLAN.replace("order=abc", "order=bac") + ";slab=64"),    # pass over a not first
+    ((512, 512, 512), PLAN.replace("order=abc", "order=cba") + ";slab=64"),
+    ((512, 512, 512), PLAN + ";slab=0"),
+    ((512, 512, 512), PLAN + ";slab=-4"),
+    ((512, 512, 512), PLAN + ";slab="),
+    ((512, 512, 512), PLAN + ";slab=6x"),
+    ((512, 512, 512), PLAN + ";slab=99999999999999"),
+    ((1, 512, 512), "order=abc;a=1;b=16x16x2/16/p2/x;c=8x8x8/2;slab=4"),        # no pass over a
+    ((512, 1, 1), "order=abc;a=16x16x2/16/p2;b=1;c=1;slab=4"),                 # nothing after it
+])
+def test_unusable_slab_plans_rejected(shape, plan):
+    with pytest.raises(offt.OfftError) as e:
+        offt.plan_string(shape, C128, "natural", plan)
+    assert e.value.code == -6
+
+
+def test_slab_not_in_reversed_layout():
+    s = offt.plan_string((64, 48, 30), C64, "cba")
+    fwd, bwd = s.split("|")
+    with pytest.raises(offt.OfftError) as e:
+        offt.plan_string((64, 48, 30), C64, "cba", f"{fwd};slab=4|{bwd}")
+    assert e.value.code == -6
+
+
+def test_slab_with_unit_axis_b_or_c():
+    # one of b and c of length 1: the schedule covers the remaining pass
+    base = offt.default_plan_string((64, 1, 30), C64)
+    order = dict(f.split("=", 1) for f in base.split(";"))["order"]
+    plan = base.replace(f"order={order}", "order=a" + order.replace("a", "")) + ";slab=8"
+    assert offt.plan_string((64, 1, 30), C64, "natural", plan) == plan
