@@ -103,3 +103,31 @@ def test_range_rejects_bad_arguments():
         with pytest.raises(offt.OfftError) as e:
             plan.exec_range(first, count, offt.FORWARD, x.data_ptr(), x.data_ptr())
         assert e.value.code == -1
+
+
+def test_tuner_on_a_grid_above_512_mib():
+    """The exhaustive tuner on a 640 MiB complex64 grid (where it also tries
+    slab schedules): whatever it keeps matches the oracle on sampled lines,
+    and its whole-transform call equals its ranges launched one by one."""
+    shape = (320, 512, 512)
+    x = synth.complex_grid(shape, C64, device="cuda")
+    plan = offt.Plan(shape, dtype=C64, tune="exhaustive")
+    print(f"tuned: {plan.describe()}", flush=True)
+    y = plan.forward(x)
+    n = plan.npasses()
+    groups = [[0], list(range(1, n))] if plan.slab() else [[i] for i in range(n)]
+    y2 = torch.empty_like(x)
+    h = int(torch.cuda.current_stream().cuda_stream)
+    for g in groups:
+        plan.exec_range(g[0], len(g), offt.FORWARD, x.data_ptr(), y2.data_ptr(), h)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y2)
+    xh = x.cpu().numpy().astype(np.complex128)
+    yh = y.cpu().numpy()
+    got, ref = [], []
+    for ka, kb in ((0, 0), (7, 301), (319, 511)):
+        got.append(yh[ka, kb].astype(np.complex128))
+        ref.append(oracle.dft3_line(xh, ka, kb))
+    e = oracle.rel_l2(np.concatenate(got), np.concatenate(ref))
+    assert e <= oracle.tolerance(x.numel(), True), e
+    plan.close()
