@@ -961,8 +961,9 @@ def summarize_nd(d: str, log: str, command: str, steps: int, warmup: int) -> str
     trace.sort(key=lambda r: int(r["Dispatch_Id"]))
     disp = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace
             if "fft_pass_kernel" in r["Kernel_Name"]]
-    lines = ["# rocprofv3 kernel trace of the 4- and 5-axis transforms: mean duration per pass dispatch over",
-             "# the timed transforms; GB/s = algorithmic 2*N*s bytes per pass / duration",
+    lines = ["# rocprofv3 kernel trace of the 4- and 5-axis transforms: mean duration per pass over the timed",
+             "# transforms (a pass of a slab schedule summed over its slabs' dispatches); GB/s = algorithmic",
+             "# 2*N*s bytes per pass / duration",
              f"# command: {command}"]
     k = 0
     for r in res:
@@ -974,19 +975,23 @@ def summarize_nd(d: str, log: str, command: str, steps: int, warmup: int) -> str
             order = fields["order"]
             lines.append(f"{'x'.join(map(str, r['shape']))} {r['dtype']} {name} plan {plan}: "
                          f"{r[name]['ms'] * 1e3:.1f} us per transform (HIP events)")
-            per = [[] for _ in order]
+            # a slab schedule launches its later passes once per slab: per pass
+            # and transform, the slabs' dispatches are summed
+            per = [[0.0] * steps for _ in order]
+            seq = pass_launches(plan, r["shape"][0])
             for st in range(warmup + steps):
-                for i in range(len(order)):
+                for i in seq:
                     if k >= len(disp):
                         raise RuntimeError(f"the trace holds {len(disp)} pass dispatches, fewer than expected")
                     if st >= warmup:
-                        per[i].append(disp[k])
+                        per[i][st - warmup] += disp[k]
                     k += 1
             total = 0.0
             for i, ax in enumerate(order):
                 m = sum(per[i]) / len(per[i])
                 total += m
-                lines.append(f"  pass {i} {ax}={fields[ax]:<14} {m:9.2f} us  {2.0 * N * s / (m * 1e3):7.1f} GB/s")
+                label = pass_label(plan, i)
+                lines.append(f"  pass {i} {label:<16} {m:9.2f} us  {2.0 * N * s / (m * 1e3):7.1f} GB/s")
             lines.append(f"  summed pass time {total:.1f} us")
     if k != len(disp):
         raise RuntimeError(f"expected {k} pass dispatches, the trace holds {len(disp)}")

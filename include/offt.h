@@ -147,9 +147,12 @@ offt_plan_t offt_plan_ex(int64_t Na, int64_t Nb, int64_t Nc, int dtype, int64_t 
  *              first; OFFT_TUNE_EXHAUSTIVE times every kernel and tile width
  *              of each axis, then every order of the passes (up to 5! = 120,
  *              the GPU counterpart of the paper's search over transpose
- *              orders); OFFT_TUNE_LEARNED falls back to it.  Plan strings
- *              name the axes a..e ("order=edcba;a=...;...;e=...").  The layout
- *              must be OFFT_LAYOUT_NATURAL.
+ *              orders), and above 512 MiB slab schedules (the pass over a
+ *              first, the others on blocks of the trailing axes, as
+ *              ";slab=S" of offt_plan_describe); OFFT_TUNE_LEARNED falls back
+ *              to it.  Plan strings name the axes a..e
+ *              ("order=edcba;a=...;...;e=...").  The layout must be
+ *              OFFT_LAYOUT_NATURAL.
  * Executed, described and destroyed with the same calls as offt_plan.
  * Errors as offt_plan_ex. */
 #define OFFT_MAX_DIMS 5

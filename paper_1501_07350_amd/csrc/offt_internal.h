@@ -145,7 +145,12 @@ struct NdChoice {
     int logW[kMaxDims];
     int xcd[kMaxDims] = {0, 0, 0, 0, 0};
     int io[kMaxDims] = {0, 0, 0, 0, 0};
+    // slab schedule as PlanChoice::slab: the pass over the first axis first,
+    // then every other pass on `slab` blocks (of the product of the other
+    // axes) at a time; 0: none
+    int64_t slab = 0;
 };
+bool nd_slab_fits(const NdChoice& c, const int64_t* dims);
 PassPlan make_pass_nd(int ndim, const int64_t* dims, int64_t batch, int ax, const KernelEntry* k, int logW,
                       int xcd = 0, int io = kIoAuto);
 NdChoice default_choice_nd(int dtype, int ndim, const int64_t* dims);

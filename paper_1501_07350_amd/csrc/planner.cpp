@@ -663,7 +663,14 @@ std::string nd_choice_to_string(const NdChoice& c, const int64_t* dims) {
         os << ";" << kAxisName[ax] << "=";
         axis_to_string(os, c.k[ax], c.logW[ax], dims[ax], c.xcd[ax], c.io[ax]);
     }
+    if (c.slab > 0) os << ";slab=" << c.slab;
     return os.str();
+}
+
+bool nd_slab_fits(const NdChoice& c, const int64_t* dims) {
+    int64_t rest = 1;
+    for (int ax = 1; ax < c.ndim; ++ax) rest *= dims[ax];
+    return c.slab == 0 || (c.slab > 0 && c.ndim >= 2 && c.order[0] == 0 && dims[0] > 1 && rest > 1);
 }
 
 bool nd_choice_from_string(const char* s, int dtype, int ndim, const int64_t* dims, NdChoice* out,
@@ -682,6 +689,8 @@ bool nd_choice_from_string(const char* s, int dtype, int ndim, const int64_t* di
         if (key == "order") {
             if (!parse_order(val, ndim, c.order)) return false;
             have_order = true;
+        } else if (key == "slab") {
+            if (!parse_slab(val, &c.slab)) return false;
         } else if (key.size() == 1 && key[0] >= 'a' && key[0] < 'a' + ndim) {
             const int ax = key[0] - 'a';
             if (dims[ax] <= 1) {
@@ -693,7 +702,7 @@ bool nd_choice_from_string(const char* s, int dtype, int ndim, const int64_t* di
             return false;
         }
     }
-    if (!have_order) return false;
+    if (!have_order || !nd_slab_fits(c, dims)) return false;
     for (int ax = 0; ax < ndim; ++ax) {
         if (!spec[ax].given) continue;
         const bool strided = make_pass_nd(ndim, dims, 1, ax, nullptr, 0).M2 > 1;
@@ -711,6 +720,26 @@ bool nd_choice_from_string(const char* s, int dtype, int ndim, const int64_t* di
     return true;
 }
 
+static int64_t grid_elems_nd(int ndim, const int64_t* dims) {
+    int64_t n = 1;
+    for (int i = 0; i < ndim; ++i) n *= dims[i];
+    return n;
+}
+
+// Every pass after the first on slabs of `slab` planes (blocks of
+// plane_elems elements, `planes` of them); access modes resolved for one
+// slab's bytes (it may stay cached between the passes).
+static void set_slab(PassPlan* out, int n, int64_t planes, int64_t plane_elems, int64_t slab_planes, const int* io) {
+    const int64_t slab = std::min(slab_planes, planes);
+    for (int i = 1; i < n; ++i) {
+        out[i].slab = slab;
+        out[i].planes = planes;
+        out[i].plane_elems = plane_elems;
+        if (out[i].k)
+            out[i].stream = resolve_stream(io[out[i].axis], slab * plane_elems * (int64_t)elem_size(out[i].k->dtype));
+    }
+}
+
 int build_passes_nd(const NdChoice& c, const int64_t* dims, int64_t batch, PassPlan* out) {
     int n = 0;
     for (int i = 0; i < c.ndim; ++i) {
@@ -718,6 +747,8 @@ int build_passes_nd(const NdChoice& c, const int64_t* dims, int64_t batch, PassP
         if (dims[ax] <= 1) continue;
         out[n++] = make_pass_nd(c.ndim, dims, batch, ax, c.k[ax], c.logW[ax], c.xcd[ax], c.io[ax]);
     }
+    if (c.slab > 0 && nd_slab_fits(c, dims))
+        set_slab(out, n, batch * dims[0], dims[0] > 0 ? grid_elems_nd(c.ndim, dims) / dims[0] : 0, c.slab, c.io);
     return n;
 }
 
@@ -728,20 +759,7 @@ int build_passes(const PlanChoice& c, const int64_t dims[3], int64_t batch, Pass
         if (dims[ax] <= 1) continue;
         out[n++] = make_pass(dims, batch, ax, axis_geom(c, ax), c.k[ax], c.logW[ax], c.xcd[ax], c.io[ax]);
     }
-    if (c.slab > 0 && slab_fits(c, dims)) {
-        // every pass after the one over a, on slabs of planes; access modes
-        // resolved for one slab's bytes (it may stay cached between them)
-        const int64_t planes = batch * dims[0], plane_elems = dims[1] * dims[2];
-        const int64_t slab = std::min(c.slab, planes);
-        for (int i = 1; i < n; ++i) {
-            out[i].slab = slab;
-            out[i].planes = planes;
-            out[i].plane_elems = plane_elems;
-            if (out[i].k)
-                out[i].stream = resolve_stream(c.io[out[i].axis],
-                                               slab * plane_elems * (int64_t)elem_size(out[i].k->dtype));
-        }
-    }
+    if (c.slab > 0 && slab_fits(c, dims)) set_slab(out, n, batch * dims[0], dims[1] * dims[2], c.slab, c.io);
     return n;
 }
 

@@ -643,6 +643,43 @@ static int exhaustive_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice, f
         ++*timed;
         if (rc == OFFT_SUCCESS && ms < wms) { wms = ms; winner = c; }
     }
+    // slab schedules of grids larger than twice the Infinity Cache, as for
+    // three axes: the pass over the first axis first, then the other passes
+    // slab by slab, in the winner's order or from the contiguous axis down,
+    // with slabs of 64, 128 and 256 MiB; kept when more than 1% faster
+    int64_t rest = 1;
+    for (int ax = 1; ax < D; ++ax) rest *= dims[ax];
+    const int64_t es = (int64_t)elem_size(p->dtype);
+    const int64_t planes = dims[0] * p->batch;
+    if (D >= 2 && dims[0] > 1 && rest > 1 && nelem * es > 2 * kStreamMinBytes) {
+        const NdChoice top = winner;
+        for (int variant = 0; variant < 2 && rc == OFFT_SUCCESS; ++variant) {
+            NdChoice ord = top;
+            int pos = 0;
+            ord.order[pos++] = 0;
+            if (variant == 0) {
+                for (int i = 0; i < D; ++i)
+                    if (top.order[i] != 0) ord.order[pos++] = top.order[i];
+            } else {
+                for (int ax = D - 1; ax >= 1; --ax) ord.order[pos++] = ax;
+            }
+            for (int ax = 1; ax < D; ++ax) ord.io[ax] = kIoAuto;
+            int64_t last = 0;
+            for (int64_t mib : {64, 128, 256}) {
+                const int64_t slab = std::max<int64_t>(1, (mib << 20) / (rest * es));
+                if (slab >= planes || slab == last || rc != OFFT_SUCCESS) continue;
+                last = slab;
+                NdChoice c = ord;
+                c.slab = slab;
+                PassPlan passes[kMaxDims];
+                const int n = build_passes_nd(c, dims, p->batch, passes);
+                float ms = 0.f;
+                rc = time_passes(p, passes, n, nelem, src, buf, nullptr, s, o.reps, &ms);
+                ++*timed;
+                if (rc == OFFT_SUCCESS && ms < 0.99f * wms) { wms = ms; winner = c; }
+            }
+        }
+    }
     (void)hipStreamSynchronize(s);
     (void)hipFree(buf);
     if (src != buf) (void)hipFree(src);

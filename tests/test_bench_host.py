@@ -73,6 +73,31 @@ def test_nd_trace_summary(tmp_path):
     assert "summed pass time 10.0 us" in txt and "summed pass time 20.0 us" in txt
 
 
+def test_nd_trace_summary_with_slab_schedule(tmp_path):
+    """A 4-axis slab schedule: the pass over a once, then b, c, d once per
+    slab (8 planes in slabs of 3: three slabs)."""
+    b = load_bench()
+    steps, warmup = 2, 1
+    plan = "order=adcb;a=8/8;b=8/8;c=8/8;d=8/8;slab=3"
+    res = [{"shape": [8, 8, 8, 8], "dtype": "f32", "tuned": {"ms": 0.01, "plan": plan},
+            "heuristic": {"ms": 0.02, "plan": "order=dcba;a=8/8;b=8/8;c=8/8;d=8/8"}}]
+    log = tmp_path / "nd.log"
+    log.write_text(__import__("json").dumps({"nd": res}) + "\n")
+    d = []
+    for p in (plan, res[0]["heuristic"]["plan"]):
+        for st in range(warmup + steps):
+            d += [("offt::fft_pass_kernel<...>", 50_000 if st < warmup else (100 * (i + 1) if b.plan_slab(p) and i
+                                                                            else 1_000), 10)
+                  for i in b.pass_launches(p, 8)]
+    write_trace(str(tmp_path / "run" / "run_kernel_trace.csv"), d)
+    txt = b.summarize_nd(str(tmp_path), str(log), "cmd", steps, warmup)
+    passes = [l.split() for l in txt.splitlines() if l.startswith("  pass")]
+    assert [p[2] for p in passes[:4]] == ["a=8/8", "d=8/8;slab=3", "c=8/8;slab=3", "b=8/8;slab=3"]
+    # three slabs of 0.2, 0.3 and 0.4 us per pass
+    assert [float(p[3]) for p in passes[:4]] == [1.0, 0.6, 0.9, 1.2]
+    assert [float(p[3]) for p in passes[4:]] == [1.0, 1.0, 1.0, 1.0]
+
+
 def test_reversed_trace_summary(tmp_path):
     steps, warmup, n = 2, 1, 8
     nat = "order=bca;a=8/8;b=8/8/x;c=8/8"

@@ -13,6 +13,7 @@ import torch
 import oracle
 import paper_1501_07350_amd as offt
 import synth
+from oracle import ndim
 
 pytestmark = pytest.mark.gpu
 
@@ -131,3 +132,40 @@ def test_tuner_on_a_grid_above_512_mib():
     e = oracle.rel_l2(np.concatenate(got), np.concatenate(ref))
     assert e <= oracle.tolerance(x.numel(), True), e
     plan.close()
+
+
+# grids of 4 and 5 axes: (shape, batch, blocks of the trailing axes per slab)
+ND_CASES = [((12, 8, 6, 10), 1, 5), ((6, 4, 5, 3, 8), 2, 4), ((10, 1, 6, 8), 1, 3), ((9, 6, 4, 10), 3, 2)]
+
+
+def nd_plans(shape, dtype, S):
+    base = offt.plan_string_nd(shape, dtype)
+    order = dict(f.split("=", 1) for f in base.split(";"))["order"]
+    plain = base.replace(f"order={order}", "order=a" + order.replace("a", ""))
+    return plain, f"{plain};slab={S}"
+
+
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("shape,batch,S", ND_CASES, ids=lambda v: str(v))
+def test_nd_slab_schedule_bit_identical_and_vs_oracle(shape, batch, S, dtype):
+    plain, slab = nd_plans(shape, dtype, S)
+    print(f"case {shape} batch {batch} {dtype}: {slab}", flush=True)
+    full = ((batch,) if batch > 1 else ()) + tuple(shape)
+    x = synth.complex_grid(full, dtype, device="cuda")
+    p0 = offt.Plan(shape, dtype=dtype, batch=batch, tune="forced", forced_plan=plain, normalize_inverse=True)
+    p1 = offt.Plan(shape, dtype=dtype, batch=batch, tune="forced", forced_plan=slab, normalize_inverse=True)
+    assert p0.slab() == 0 and p1.slab() == S
+    y0 = p0.forward(x)
+    y1 = p1.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+    xh = x.cpu().numpy().astype(np.complex128)
+    ref = ndim.fftn_batch(xh, len(shape)) if batch > 1 else ndim.fftn(xh)
+    tol = oracle.tolerance(int(np.prod(shape)), dtype == C64)
+    assert oracle.rel_l2(y1.cpu().numpy(), ref) <= tol
+    z1 = y1.clone()
+    p1.backward(z1, out=z1)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(z1.cpu().numpy(), xh) <= tol
+    p0.close()
+    p1.close()

@@ -54,3 +54,33 @@ def test_slab_with_unit_axis_b_or_c():
     order = dict(f.split("=", 1) for f in base.split(";"))["order"]
     plan = base.replace(f"order={order}", "order=a" + order.replace("a", "")) + ";slab=8"
     assert offt.plan_string((64, 1, 30), C64, "natural", plan) == plan
+
+
+def nd_with_first_axis_first(shape, dtype):
+    base = offt.plan_string_nd(shape, dtype)
+    order = dict(f.split("=", 1) for f in base.split(";"))["order"]
+    return base.replace(f"order={order}", "order=a" + order.replace("a", ""))
+
+
+@pytest.mark.parametrize("shape", [(16, 8, 6, 10), (6, 4, 5, 3, 8)])
+def test_nd_slab_round_trip(shape):
+    plan = nd_with_first_axis_first(shape, C64) + ";slab=3"
+    assert offt.plan_string_nd(shape, C64, plan) == plan
+    assert "slab" not in offt.plan_string_nd(shape, C64)
+
+
+def test_nd_slab_needs_first_axis_first():
+    shape = (16, 8, 6, 10)
+    base = offt.plan_string_nd(shape, C64)          # heuristic order: last axis first
+    assert not base.split(";")[0].endswith("=a") and "order=a" not in base
+    with pytest.raises(offt.OfftError) as e:
+        offt.plan_string_nd(shape, C64, base + ";slab=3")
+    assert e.value.code == -6
+
+
+@pytest.mark.parametrize("slab", ["0", "-1", "", "x"])
+def test_nd_bad_slab_rejected(slab):
+    shape = (16, 8, 6, 10)
+    with pytest.raises(offt.OfftError) as e:
+        offt.plan_string_nd(shape, C64, nd_with_first_axis_first(shape, C64) + f";slab={slab}")
+    assert e.value.code == -6
