@@ -175,6 +175,43 @@ def test_128_4_complex64_sampled_points():
     assert e_pts <= t and e_rt <= t
 
 
+def cached_nd_plan(shape, dtype):
+    """Plan-cache entry of a grid (the tuned plan the benchmark times)."""
+    import os
+    path = os.path.join(os.path.dirname(offt.__file__), "data", "plan_cache_mi355x.txt")
+    key = f"dtype={0 if dtype == C128 else 1} dims={'x'.join(map(str, shape))} batch=1 "
+    for line in open(path):
+        head, plan, _ = line.rstrip("\n").split("\t")
+        if head.startswith(key) and "layout=" not in head:
+            return plan
+    return None
+
+
+@pytest.mark.parametrize("shape,dtype", [((128, 128, 128, 128), C64), ((128, 128, 128, 128), C128),
+                                         ((48, 48, 48, 48, 48), C64)], ids=["128^4-c64", "128^4-c128", "48^5-c64"])
+def test_cached_tuned_plans_full_oracle(shape, dtype):
+    """The tuned plans the benchmark times (plan cache, slab schedules
+    included), through the whole-transform call, against the full oracle at
+    every point; the normalised round trip."""
+    plan_s = cached_nd_plan(shape, dtype)
+    assert plan_s is not None
+    print(f"case {shape} {dtype} {plan_s}", flush=True)
+    x = gen(shape, dtype)
+    plan = offt.Plan(shape, dtype=dtype, tune="forced", forced_plan=plan_s, normalize_inverse=True)
+    assert plan.describe() == plan_s
+    y = plan.forward(x)
+    torch.cuda.synchronize()
+    xh = host(x)
+    t = tol(x.numel(), dtype)
+    e = oracle.rel_l2(host(y), ndim.fftn(xh))
+    z = plan.backward(y)
+    torch.cuda.synchronize()
+    e_rt = oracle.rel_l2(host(z), xh)
+    print(f"{shape} {dtype}: full {e:.2e} roundtrip {e_rt:.2e}", flush=True)
+    plan.close()
+    assert e <= t and e_rt <= t
+
+
 @pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
 def test_longest_axes_in_4_and_5_axis_grids(dtype):
     """Axes of 1024 points (exchanges in parts on the strided ones) inside 4-
