@@ -395,6 +395,30 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
                 if (rc == OFFT_SUCCESS && ms < 0.99f * win_ms) { win_ms = ms; winner = c; }
             }
         }
+        // a kept schedule, its slab passes refined in place: each of b and c
+        // with its other fast kernel and with the other tile order (what a
+        // pass finds in the cache, and how many tiles a slab holds, differ
+        // from the whole-grid passes they were ranked on)
+        for (int ax = 1; ax < 3 && winner.slab > 0 && rc == OFFT_SUCCESS; ++ax) {
+            if (dims[ax] <= 1) continue;
+            const int g = axis_geom(winner, ax);
+            for (int variant = 0; variant < 2 && rc == OFFT_SUCCESS; ++variant) {
+                PlanChoice c = winner;
+                if (variant == 0) {
+                    const int other = best_k[ax][g][0] == winner.k[ax] && best_lw[ax][g][0] == winner.logW[ax] ? 1 : 0;
+                    if (!best_k[ax][g][other]) continue;
+                    c.k[ax] = best_k[ax][g][other];
+                    c.logW[ax] = best_lw[ax][g][other];
+                    c.xcd[ax] = best_x[ax][g][other];
+                } else {
+                    c.xcd[ax] = !winner.xcd[ax];
+                }
+                float ms = 0.f;
+                rc = time_choice(p, c, dims, B.src, B.buf, B.work, s, o.reps, &ms);
+                ++*timed;
+                if (rc == OFFT_SUCCESS && ms < 0.99f * win_ms) { win_ms = ms; winner = c; }
+            }
+        }
     }
     if (rc != OFFT_SUCCESS) return rc;
     *choice = winner;
