@@ -64,9 +64,10 @@ def kernel_source_hash() -> str:
 def pass_keys(plan: str):
     """Per-pass keys "axis=spec" of a plan string such as
     order=bca;a=16x16x2/16;b=16x16x2/16;c=16x16x2/2 (pass i transforms the
-    axis order[i])."""
-    fields = dict(f.split("=", 1) for f in plan.strip().split(";"))
-    return [f"{ax}={fields[ax]}" for ax in fields["order"]]
+    i-th axis of the order that is longer than 1; an axis of length 1, spec
+    "1", has no pass)."""
+    fields = dict(f.split("=", 1) for f in plan.split("|")[0].strip().split(";"))
+    return [f"{ax}={fields[ax]}" for ax in fields["order"] if fields[ax] != "1"]
 
 
 def plan_slab(plan: str) -> int:
@@ -977,7 +978,8 @@ def summarize_nd(d: str, log: str, command: str, steps: int, warmup: int) -> str
                          f"{r[name]['ms'] * 1e3:.1f} us per transform (HIP events)")
             # a slab schedule launches its later passes once per slab: per pass
             # and transform, the slabs' dispatches are summed
-            per = [[0.0] * steps for _ in order]
+            npass = len(pass_keys(plan))
+            per = [[0.0] * steps for _ in range(npass)]
             seq = pass_launches(plan, r["shape"][0])
             for st in range(warmup + steps):
                 for i in seq:
@@ -987,7 +989,7 @@ def summarize_nd(d: str, log: str, command: str, steps: int, warmup: int) -> str
                         per[i][st - warmup] += disp[k]
                     k += 1
             total = 0.0
-            for i, ax in enumerate(order):
+            for i in range(npass):
                 m = sum(per[i]) / len(per[i])
                 total += m
                 label = pass_label(plan, i)
