@@ -972,8 +972,6 @@ def summarize_nd(d: str, log: str, command: str, steps: int, warmup: int) -> str
         s = 16 if r["dtype"] == "f64" else 8
         for name in ("tuned", "heuristic"):
             plan = r[name]["plan"]
-            fields = dict(f.split("=", 1) for f in plan.split(";"))
-            order = fields["order"]
             lines.append(f"{'x'.join(map(str, r['shape']))} {r['dtype']} {name} plan {plan}: "
                          f"{r[name]['ms'] * 1e3:.1f} us per transform (HIP events)")
             # a slab schedule launches its later passes once per slab: per pass
