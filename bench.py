@@ -70,18 +70,26 @@ def pass_keys(plan: str):
     return [f"{ax}={fields[ax]}" for ax in fields["order"] if fields[ax] != "1"]
 
 
-def plan_slab(plan: str) -> int:
-    """Planes per slab of a plan string's slab schedule (";slab=S"), or 0."""
+def plan_schedule(plan: str):
+    """("slab", planes per slab), ("col", columns per block) or (None, 0)
+    for a plan string's block schedule (";slab=S" or ";col=W")."""
     for f in plan.split("|")[0].strip().split(";"):
-        if f.startswith("slab="):
-            return int(f[5:])
-    return 0
+        for key in ("slab", "col"):
+            if f.startswith(key + "="):
+                return key, int(f[len(key) + 1:])
+    return None, 0
+
+
+def plan_slab(plan: str) -> int:
+    """Planes per slab or columns per block of a plan string's block
+    schedule, or 0."""
+    return plan_schedule(plan)[1]
 
 
 def pass_groups(plan: str):
     """Pass indices timed together: each pass on its own, except that the
-    passes of a slab schedule (every pass after the first) form one group,
-    since they run interleaved slab by slab."""
+    passes of a slab or column-block schedule (every pass after the first)
+    form one group, since they run interleaved block by block."""
     npass = len(pass_keys(plan))
     if plan_slab(plan) and npass > 1:
         return [[0], list(range(1, npass))]
@@ -91,26 +99,29 @@ def pass_groups(plan: str):
 def pass_label(plan: str, i: int) -> str:
     """Key "axis=spec" of pass i, with ";slab=S" for a pass of a slab schedule
     (its access modes and cache behaviour differ from the whole-grid pass)."""
-    S = plan_slab(plan)
+    kind, size = plan_schedule(plan)
     keys = pass_keys(plan)
-    return keys[i] + (f";slab={S}" if S and i > 0 else "")
+    return keys[i] + (f";{kind}={size}" if kind and i > 0 else "")
 
 
 def group_key(plan: str, g) -> str:
     keys = pass_keys(plan)
+    kind, size = plan_schedule(plan)
     key = "+".join(keys[i] for i in g)
-    return key + (f";slab={plan_slab(plan)}" if len(g) > 1 else "")
+    return key + (f";{kind}={size}" if len(g) > 1 else "")
 
 
-def pass_launches(plan: str, planes: int):
+def pass_launches(plan: str, planes: int, ncols: int | None = None):
     """Pass index of every kernel launch of one transform, in launch order
-    (`planes` = Na x batch: a slab schedule launches each of its passes once
-    per slab, slab after slab)."""
+    (`planes` = Na x batch, `ncols` = Nc, by default `planes`: a slab or
+    column-block schedule launches each of its passes once per block, block
+    after block)."""
     npass = len(pass_keys(plan))
-    S = plan_slab(plan)
-    if not S or npass < 2:
+    kind, size = plan_schedule(plan)
+    if not kind or npass < 2:
         return list(range(npass))
-    return [0] + [i for _ in range(-(-planes // S)) for i in range(1, npass)]
+    nblocks = -(-planes // size) if kind == "slab" else (ncols or planes) // size
+    return [0] + [i for _ in range(nblocks) for i in range(1, npass)]
 
 
 def load_traffic(tag: str, key: str):

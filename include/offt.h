@@ -209,18 +209,18 @@ int offt_plan_passes(offt_plan_t p);
  * passes 0..n-1 in order on one stream with the same in/out gives exactly
  * the result of offt_exec_fwd / offt_exec_bwd (pass 0 reads `in`, later
  * passes work in place on `out`; in REVERSED layouts the passes route
- * through the plan's workspace exactly as exec does; a pass of a slab
- * schedule runs here over all its slabs, one launch per slab, where exec
- * interleaves the passes slab by slab); it exists so that each pass can be
- * timed on its own.
+ * through the plan's workspace exactly as exec does; a pass of a slab or
+ * column-block schedule runs here over all its blocks, one launch per block,
+ * where exec interleaves the passes block by block); it exists so that each
+ * pass can be timed on its own.
  * Errors: INVALID_ARG (NULL plan/pointer, i out of range, bad direction),
  * BAD_PLAN, HIP. */
 int offt_exec_pass(offt_plan_t p, int i, int direction, const void* in, void* out, void* stream);
 
 /* Launch passes first .. first+count-1 (plan order) exactly as offt_exec_fwd /
  * offt_exec_bwd launches them: same buffers, conjugation and scaling as
- * offt_exec_pass, and the passes of a slab schedule (offt_plan_describe's
- * ";slab=S") interleaved slab by slab.  A range covering every pass is
+ * offt_exec_pass, and the passes of a slab or column-block schedule
+ * (offt_plan_describe's ";slab=S", ";col=W") interleaved block by block.  A range covering every pass is
  * offt_exec_fwd / offt_exec_bwd; ranges launched back to back give the same
  * result.  It exists so that the pass over a and the slab schedule after it
  * can be timed apart.  Errors: INVALID_ARG (NULL plan/pointer, count < 1,
@@ -250,8 +250,12 @@ int offt_destroy(offt_plan_t p);
  * over the batch) at a time, both passes of one slab before the next slab,
  * so that a slab's second pass finds the first one's output in the
  * Infinity Cache (natural layout only; the exhaustive tuner tries it for
- * grids above 512 MiB).  Every element goes through the same arithmetic as
- * without it: results are bit-identical to the plan without ";slab=". */
+ * grids above 512 MiB).  A trailing ";col=W" marks the column-block
+ * schedule instead: the pass over c first over the whole grid, then the
+ * passes over b and a on blocks of W consecutive columns c (W a power of two
+ * dividing Nc and at least their tile widths).  Every element goes through
+ * the same arithmetic as without either: results are bit-identical to the
+ * plan without ";slab=" or ";col=". */
 int offt_plan_describe(offt_plan_t p, char* buf, size_t n);
 
 /* Bytes of device memory the plan owns (twiddle tables, scratch). */

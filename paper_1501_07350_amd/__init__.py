@@ -173,12 +173,28 @@ class Plan:
                                                ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
                                                ctypes.c_void_p(stream)), "exec_range")
 
+    def _schedule_field(self, key: str) -> int:
+        for field in self.describe().split("|")[0].split(";"):
+            if field.startswith(key + "="):
+                return int(field[len(key) + 1:])
+        return 0
+
     def slab(self) -> int:
         """Planes per slab of the plan's slab schedule, or 0."""
-        for field in self.describe().split("|")[0].split(";"):
-            if field.startswith("slab="):
-                return int(field[5:])
-        return 0
+        return self._schedule_field("slab")
+
+    def col(self) -> int:
+        """Columns per block of the plan's column-block schedule, or 0."""
+        return self._schedule_field("col")
+
+    def pass_groups(self):
+        """Passes as exec launches them: each on its own, except that the
+        passes after the first of a slab or column-block schedule run
+        interleaved block by block (launch such a group with exec_range)."""
+        n = self.npasses()
+        if (self.slab() or self.col()) and n > 1:
+            return [[0], list(range(1, n))]
+        return [[i] for i in range(n)]
 
     def copy_pass(self, i: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
         """The copy of pass i's memory accesses (its measured ceiling)."""

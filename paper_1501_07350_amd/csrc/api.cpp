@@ -132,6 +132,16 @@ int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const v
     const int j0 = std::max(i0, first_slab);
     if (j0 >= i1) return OFFT_SUCCESS;
     const PassPlan& sp = passes[first_slab];
+    if (sp.col > 0) {
+        // column blocks: every remaining pass of one block before the next
+        for (int64_t c0 = 0; c0 < sp.ncol; c0 += sp.col) {
+            for (int i = j0; i < i1; ++i) {
+                const int rc = launch(i, col_pass(passes[i], c0), 0);
+                if (rc != OFFT_SUCCESS) return rc;
+            }
+        }
+        return OFFT_SUCCESS;
+    }
     for (int64_t p0 = 0; p0 < sp.planes; p0 += sp.slab) {
         const int64_t np = std::min(sp.slab, sp.planes - p0);
         for (int i = j0; i < i1; ++i) {

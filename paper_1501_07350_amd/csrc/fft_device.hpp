@@ -412,8 +412,16 @@ struct PassArgs {
     const void* in;
     void* out;
     const void* tw;     // W_L^m, m < L, in the pass precision
-    int64_t nlines;     // M1 * M2
+    int64_t nlines;     // M1 * M2 (M1 * lpm for a column block)
     int64_t M2;         // element stride of the axis (1: contiguous lines)
+    // strided lines (mode 1): lines per m1, and a column block: with
+    // blk_logw >= 0, line v of an m1 lies at
+    // m2 = (v >> blk_logw) * blk_ld + blk_off + (v & (2^blk_logw - 1)),
+    // the lines of 2^blk_logw consecutive columns out of every blk_ld
+    // (without a block, lpm == M2 and m2 = v)
+    int64_t lpm;
+    int64_t blk_ld, blk_off;
+    int blk_logw;
     int64_t X, Y;       // transposing passes: line m1*M2 + m2 is the contiguous row
                         // m1*M2 + (m2 mod X)*Y + m2 div X of the other buffer
     int logW;           // log2 of lines per workgroup
@@ -570,7 +578,10 @@ __device__ __forceinline__ void pass_tile_impl(const PassArgs& a, V* __restrict_
         const int t = tid >> a.logW;
         const bool ok = active && w < nl;
         const int64_t l = l0 + (ok ? w : 0);   // rows beyond the tail read line l0, store nothing
-        const int64_t m1 = l / a.M2, m2 = l - m1 * a.M2;
+        const int64_t m1 = l / a.lpm, v = l - m1 * a.lpm;
+        const int64_t m2 = a.blk_logw < 0 ? v
+                                          : (v >> a.blk_logw) * a.blk_ld + a.blk_off +
+                                                (v & ((int64_t(1) << a.blk_logw) - 1));
         const int64_t base = m1 * (int64_t)L * a.M2 + m2;
         const int64_t M2 = a.M2;
         const V* g = in + base;

@@ -110,6 +110,10 @@ __device__ __forceinline__ PassArgs segment_pass_args(const ManyArgs& a, const M
     p.tw = sg.tw;
     p.nlines = sg.nlines;
     p.M2 = sg.M2;
+    p.lpm = sg.M2;
+    p.blk_ld = 0;
+    p.blk_off = 0;
+    p.blk_logw = -1;
     p.logW = sg.logW;
     p.mode = sg.mode;
     p.X = 1;

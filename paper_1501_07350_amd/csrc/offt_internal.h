@@ -77,12 +77,26 @@ struct PassPlan {
     int64_t slab = 0;
     int64_t planes = 0;        // planes the pass covers (batch * Na)
     int64_t plane_elems = 0;   // elements of one plane (Nb * Nc)
+    // Column-block schedule (PlanChoice::col): a strided pass over a or b
+    // after the whole-grid pass over c runs on blocks of `col` consecutive
+    // columns c (out of ncol = Nc), every such pass of one block before the
+    // next block.  0: the whole grid at once.
+    int64_t col = 0;
+    int64_t ncol = 0;
+    // a strided pass restricted to one column block (PassArgs): lines per
+    // m1 (0: M2), log2 of the block width (-1: none), row length, first column
+    int64_t lpm = 0;
+    int blk_logw = -1;
+    int64_t blk_ld = 0, blk_off = 0;
 };
 
 // Pass p restricted to planes [p0, p0 + np) of a slab schedule; *elem_off
 // receives the element offset of plane p0.
 PassPlan slab_pass(const PassPlan& p, int64_t p0, int64_t np, int64_t* elem_off);
-// Index of the first pass of a list that runs slab by slab, or n.
+// Pass p restricted to the column block starting at column c0.
+PassPlan col_pass(const PassPlan& p, int64_t c0);
+// Index of the first pass of a list that runs block by block (slab or column
+// schedule), or n.
 int slab_start(const PassPlan* ps, int n);
 
 // Grid-data access mode of a pass (plan choices, plan-string suffix):
@@ -115,9 +129,18 @@ struct PlanChoice {
     // string ";slab=S"), so that a slab's second pass finds the first pass's
     // output in the Infinity Cache.
     int64_t slab = 0;
+    // Column-block schedule: 0, or the number of columns c per block (a power
+    // of two dividing Nc).  Requires natural output order and the pass over
+    // c first; the passes over b and a then run block by block (plan string
+    // ";col=W"), so that a block's second pass finds the first pass's output
+    // in the Infinity Cache.  At most one of slab and col is set.
+    int64_t col = 0;
 };
-// Whether a choice's slab schedule fits its grid (see PlanChoice::slab).
+// Whether a choice's slab or column schedule fits its grid (see
+// PlanChoice::slab, PlanChoice::col); with check_tiles, also that every
+// blocked pass's tile width divides the block.
 bool slab_fits(const PlanChoice& c, const int64_t dims[3]);
+bool col_fits(const PlanChoice& c, const int64_t dims[3], bool check_tiles);
 
 // Where an axis pass of a choice runs: on the input's (abc) grid, on the
 // reversed (cba) grid, or as the transposing pass between them.

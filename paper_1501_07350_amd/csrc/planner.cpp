@@ -518,11 +518,27 @@ std::string choice_to_string(const PlanChoice& c, const int64_t dims[3]) {
         axis_to_string(os, c.k[ax], c.logW[ax], dims[ax], c.xcd[ax], c.io[ax]);
     }
     if (c.slab > 0) os << ";slab=" << c.slab;
+    if (c.col > 0) os << ";col=" << c.col;
     return os.str();
 }
 
 bool slab_fits(const PlanChoice& c, const int64_t dims[3]) {
-    return c.slab == 0 || (c.slab > 0 && c.tax < 0 && c.order[0] == 0 && dims[0] > 1 && dims[1] * dims[2] > 1);
+    return c.slab == 0 || (c.slab > 0 && c.col == 0 && c.tax < 0 && c.order[0] == 0 && dims[0] > 1 &&
+                           dims[1] * dims[2] > 1);
+}
+
+bool col_fits(const PlanChoice& c, const int64_t dims[3], bool check_tiles) {
+    if (c.col == 0) return true;
+    const int64_t w = c.col;
+    if (w < 1 || (w & (w - 1)) || c.slab != 0 || c.tax >= 0 || c.order[0] != 2 || dims[2] <= 1 ||
+        dims[0] * dims[1] <= 1 || dims[2] % w != 0 || w >= dims[2])
+        return false;
+    // every blocked pass takes whole tiles of one block row: W lines of one
+    // m1 are W consecutive columns
+    if (check_tiles)
+        for (int ax = 0; ax < 2; ++ax)
+            if (dims[ax] > 1 && (!c.k[ax] || (int64_t(1) << c.logW[ax]) > w)) return false;
+    return true;
 }
 
 // Planes per slab from a plan string: a decimal count of 1 to 2^40.
@@ -545,9 +561,20 @@ PassPlan slab_pass(const PassPlan& p, int64_t p0, int64_t np, int64_t* elem_off)
     return q;
 }
 
+PassPlan col_pass(const PassPlan& p, int64_t c0) {
+    PassPlan q = p;
+    int lw = 0;
+    while ((int64_t(1) << lw) < p.col) ++lw;
+    q.blk_logw = lw;
+    q.blk_ld = p.ncol;
+    q.blk_off = c0;
+    q.lpm = p.M2 / p.ncol * p.col;   // rows of the m1 (M2 / Nc of them) times the block's columns
+    return q;
+}
+
 int slab_start(const PassPlan* ps, int n) {
     for (int i = 0; i < n; ++i)
-        if (ps[i].slab > 0) return i;
+        if (ps[i].slab > 0 || ps[i].col > 0) return i;
     return n;
 }
 
@@ -573,6 +600,8 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
             else return false;
         } else if (key == "slab") {
             if (!parse_slab(val, &c.slab)) return false;
+        } else if (key == "col") {
+            if (!parse_slab(val, &c.col)) return false;
         } else if (key.size() == 1 && key[0] >= 'a' && key[0] <= 'c') {
             const int ax = key[0] - 'a';
             if (dims[ax] <= 1) {
@@ -586,7 +615,7 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
     }
     if (!have_order) return false;
     if (c.tax >= 0 && (!reversal_moves_data(dims) || dims[c.tax] <= 1)) return false;
-    if (!slab_fits(c, dims)) return false;
+    if (!slab_fits(c, dims) || !col_fits(c, dims, false)) return false;
     // axes the string leaves out take the heuristic's kernel for their geometry
     assign_default_kernels(c, dtype, dims);
     for (int ax = 0; ax < 3; ++ax) {
@@ -604,6 +633,7 @@ bool choice_from_string(const char* s, int dtype, const int64_t dims[3], PlanCho
         c.xcd[ax] = sp.xcd;
         c.io[ax] = sp.io;
     }
+    if (!col_fits(c, dims, true)) return false;
     *out = c;
     return true;
 }
@@ -760,6 +790,17 @@ int build_passes(const PlanChoice& c, const int64_t dims[3], int64_t batch, Pass
         out[n++] = make_pass(dims, batch, ax, axis_geom(c, ax), c.k[ax], c.logW[ax], c.xcd[ax], c.io[ax]);
     }
     if (c.slab > 0 && slab_fits(c, dims)) set_slab(out, n, batch * dims[0], dims[1] * dims[2], c.slab, c.io);
+    if (c.col > 0 && col_fits(c, dims, true)) {
+        // every pass after the one over c, on blocks of columns; access modes
+        // resolved for one block's bytes
+        for (int i = 1; i < n; ++i) {
+            out[i].col = c.col;
+            out[i].ncol = dims[2];
+            if (out[i].k)
+                out[i].stream = resolve_stream(c.io[out[i].axis], batch * dims[0] * dims[1] * c.col *
+                                                                      (int64_t)elem_size(out[i].k->dtype));
+        }
+    }
     return n;
 }
 
@@ -769,8 +810,12 @@ hipError_t launch_pass(const PassPlan& p, const void* in, void* out, int conj_in
     a.in = in;
     a.out = out;
     a.tw = p.tw;
-    a.nlines = p.M1 * p.M2;
+    a.lpm = p.lpm > 0 ? p.lpm : p.M2;
+    a.nlines = p.M1 * a.lpm;
     a.M2 = p.M2;
+    a.blk_logw = p.blk_logw;
+    a.blk_ld = p.blk_ld;
+    a.blk_off = p.blk_off;
     a.X = p.X;
     a.Y = p.Y;
     a.logW = p.logW;

@@ -368,10 +368,11 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
         ++*timed;
         if (rc == OFFT_SUCCESS && ms < 0.99f * win_ms) { win_ms = ms; winner = c; }
     }
-    // slab schedules of grids larger than twice the Infinity Cache: the pass
-    // over a first, then the winner's kernels for b and c slab by slab, in
-    // both orders, with slabs of 64, 128 and 256 MiB (their passes' access
-    // modes resolved per slab); kept when more than 1% faster
+    // slab and column-block schedules of grids larger than twice the
+    // Infinity Cache: the pass over a first, then the winner's kernels for b
+    // and c slab by slab, in both orders, with slabs of 64, 128 and 256 MiB
+    // (their passes' access modes resolved per slab); kept when more than 1%
+    // faster
     const int64_t plane_bytes = dims[1] * dims[2] * (int64_t)elem_size(p->dtype);
     const int64_t planes = dims[0] * p->batch;
     if (!rev && winner.tax < 0 && dims[0] > 1 && dims[1] * dims[2] > 1 && grid_bytes > 2 * kStreamMinBytes) {
@@ -395,12 +396,39 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
                 if (rc == OFFT_SUCCESS && ms < 0.99f * win_ms) { win_ms = ms; winner = c; }
             }
         }
+        // column-block schedules: the pass over c first over the whole grid,
+        // then the winner's kernels for b and a on blocks of columns of 64,
+        // 128 and 256 MiB, in both orders (the tile widths of both must fit a
+        // block)
+        const int64_t colum_bytes = dims[0] * dims[1] * p->batch * (int64_t)elem_size(p->dtype);
+        for (int ba = 0; ba < 2 && rc == OFFT_SUCCESS; ++ba) {
+            PlanChoice ord = base;
+            ord.slab = 0;
+            ord.order[0] = 2;
+            ord.order[1] = ba ? 0 : 1;
+            ord.order[2] = ba ? 1 : 0;
+            ord.io[0] = ord.io[1] = kIoAuto;
+            int64_t last = 0;
+            for (int64_t mib : {64, 128, 256}) {
+                int64_t w = 1;
+                while (w * 2 * colum_bytes <= (mib << 20)) w *= 2;
+                if (w == last || rc != OFFT_SUCCESS) continue;
+                last = w;
+                PlanChoice c = ord;
+                c.col = w;
+                if (!col_fits(c, dims, true)) continue;
+                float ms = 0.f;
+                rc = time_choice(p, c, dims, B.src, B.buf, B.work, s, o.reps, &ms);
+                ++*timed;
+                if (rc == OFFT_SUCCESS && ms < 0.99f * win_ms) { win_ms = ms; winner = c; }
+            }
+        }
         // a kept schedule, its slab passes refined in place: each of b and c
         // with its other fast kernel and with the other tile order (what a
         // pass finds in the cache, and how many tiles a slab holds, differ
         // from the whole-grid passes they were ranked on)
-        for (int ax = 1; ax < 3 && winner.slab > 0 && rc == OFFT_SUCCESS; ++ax) {
-            if (dims[ax] <= 1) continue;
+        for (int ax = 0; ax < 3 && (winner.slab > 0 || winner.col > 0) && rc == OFFT_SUCCESS; ++ax) {
+            if (dims[ax] <= 1 || ax == (winner.slab > 0 ? 0 : 2)) continue;   // the whole-grid pass
             const int g = axis_geom(winner, ax);
             for (int variant = 0; variant < 2 && rc == OFFT_SUCCESS; ++variant) {
                 PlanChoice c = winner;
@@ -413,6 +441,7 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
                 } else {
                     c.xcd[ax] = !winner.xcd[ax];
                 }
+                if (!col_fits(c, dims, true)) continue;
                 float ms = 0.f;
                 rc = time_choice(p, c, dims, B.src, B.buf, B.work, s, o.reps, &ms);
                 ++*timed;

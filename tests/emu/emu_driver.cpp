@@ -5,7 +5,8 @@
 //       one stand-alone axis pass (kernel case kid of the executor's table,
 //       plain stores) over a [M1][L][M2] view of synthetic data, tile by tile
 //       with W*TPL threads each (strided lines with LDS exchanges in 2^logP
-//       parts when M2 > 1); prints the forward-transformed data as text
+//       parts when M2 > 1); prints the forward-transformed data as text.
+//       EMU_BLK="logw ld off" restricts a strided pass to one column block.
 //   emu_driver many <dtype> <nwg> <ngrids> <grids...> <total> [<seg> <dep>]
 //       the persistent loop over the segment table the library builds
 //       (many_tables.hpp) for the grids' passes, run by nwg workgroups at
@@ -290,6 +291,22 @@ static int do_pass(int argc, char** argv) {
     a.tw = tw.data();
     a.nlines = M1 * M2;
     a.M2 = M2;
+    a.lpm = M2;
+    a.blk_logw = -1;
+    // EMU_BLK="logw ld off": a strided pass restricted to the column block of
+    // 2^logw columns starting at column off of every row of ld columns
+    if (const char* blk = getenv("EMU_BLK")) {
+        int lw = -1;
+        long long ld = 0, off = 0;
+        if (sscanf(blk, "%d %lld %lld", &lw, &ld, &off) != 3 || lw < 0 || ld < 1 || M2 % ld != 0 ||
+            off + (1LL << lw) > ld || tmode != 0)
+            return 2;
+        a.blk_logw = lw;
+        a.blk_ld = ld;
+        a.blk_off = off;
+        a.lpm = M2 / ld * (1LL << lw);
+        a.nlines = M1 * a.lpm;
+    }
     a.logW = logW;
     a.mode = tmode ? tmode : (M2 > 1 ? 1 : 0);
     a.X = X;

@@ -389,6 +389,37 @@ def run_pass(exe, dtype, L, seq, tpl, M1, M2, logW, logP):
     assert worst <= oracle.tolerance(L, dtype == torch.complex64), worst
 
 
+def run_pass_block(exe, dtype, L, seq, tpl, M1, M2, logW, logP, logw, ld, off):
+    """A strided pass restricted to one column block (2^logw columns from
+    `off` in every row of `ld` columns): the block's lines match the naive
+    DFT, every other element is left untouched (zero)."""
+    gk = gen_kernels()
+    prec = "f64" if dtype == torch.complex128 else "f32"
+    kid = plain_cases(gk, prec).index((L, seq, tpl))
+    code = "0" if dtype == torch.complex128 else "1"
+    args = [exe, "pass", code] + [str(v) for v in (kid, L, M1, M2, logW, logP, tpl)]
+    env = dict(os.environ, EMU_BLK=f"{logw} {ld} {off}")
+    r = subprocess.run(args, capture_output=True, text=True, timeout=600, env=env)
+    assert r.returncode == 0, (r.stdout[:500], r.stderr[-3000:])
+    lines = r.stdout.splitlines()
+    assert lines[0].startswith("OK"), lines[0]
+    vals = np.array([[float(a) for a in ln.split()] for ln in lines[1:]])
+    out = (vals[:, 0] + 1j * vals[:, 1]).reshape(M1, L, M2)
+    i = np.arange(M1 * L * M2)
+    x = np.sin(0.37 * i + 0.1) + 1j * np.cos(0.91 * i)
+    if dtype == torch.complex64:
+        x = x.astype(np.complex64).astype(np.complex128)
+    x = x.reshape(M1, L, M2)
+    m2 = np.arange(M2)
+    inside = ((m2 % ld) >= off) & ((m2 % ld) < off + (1 << logw))
+    lines_in = x[:, :, inside].transpose(0, 2, 1).reshape(-1, L)
+    want = oracle.fft1_lines(lines_in, method=0)
+    got = out[:, :, inside].transpose(0, 2, 1).reshape(-1, L)
+    worst = max(oracle.rel_l2(got[k], want[k]) for k in range(got.shape[0]))
+    assert worst <= oracle.tolerance(L, dtype == torch.complex64), worst
+    assert not np.any(out[:, :, ~inside]), "elements outside the block were written"
+
+
 def run_tpass(exe, dtype, L, seq, tpl, M1, X, Y, logW, mode, logP=0):
     """One transposing pass through the emulated tile code: line l = m1*M2 + m2
     (M2 = X*Y) is strided in the [M1][L][M2] view and the contiguous row
@@ -544,3 +575,20 @@ def test_emulated_level_kernels_every_length_executor(emu_binary, dtype):
     grid): exactly the launch's LDS, the library's tables; every grid
     matches the oracle."""
     run_many(emu_binary, MIXED, dtype, levels=True, which="all")
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
+@pytest.mark.parametrize("case", [
+    # (L, seq, tpl, M1, M2, logW, logP, logw, ld, off): a pass along a over 6 rows
+    # of 32 columns, blocks of 8 and 16; a pass along b (M2 = ld); a 2-part exchange
+    (16, [16], 1, 1, 6 * 32, 3, 0, 3, 32, 16),
+    (16, [16], 1, 1, 6 * 32, 2, 0, 4, 32, 0),
+    (12, [4, 3], 3, 3, 32, 3, 0, 4, 32, 16),
+    (64, [8, 8], 8, 2, 3 * 16, 2, 1, 3, 16, 8),
+], ids=lambda v: str(v))
+def test_emulated_column_block_pass(emu_binary, dtype, case):
+    """The column-block addressing of strided passes (the column-block
+    schedule): only the block's lines are transformed, each exactly."""
+    L, seq, tpl, M1, M2, logW, logP, logw, ld, off = case
+    assert (1 << logW) <= (1 << logw) and M2 % ld == 0 and off + (1 << logw) <= ld
+    run_pass_block(emu_binary, dtype, L, seq, tpl, M1, M2, logW, logP, logw, ld, off)

@@ -59,9 +59,7 @@ def run_passes(plan, direction, x, y):
     """The benchmark's launch configuration, x -> y: each pass on its own,
     the passes of a slab schedule as one range (interleaved slab by slab)."""
     h = int(torch.cuda.current_stream().cuda_stream)
-    n = plan.npasses()
-    groups = [[0], list(range(1, n))] if plan.slab() and n > 1 else [[i] for i in range(n)]
-    for g in groups:
+    for g in plan.pass_groups():
         plan.exec_range(g[0], len(g), direction, x.data_ptr(), y.data_ptr(), h)
 
 

@@ -115,11 +115,9 @@ def test_tuner_on_a_grid_above_512_mib():
     plan = offt.Plan(shape, dtype=C64, tune="exhaustive")
     print(f"tuned: {plan.describe()}", flush=True)
     y = plan.forward(x)
-    n = plan.npasses()
-    groups = [[0], list(range(1, n))] if plan.slab() else [[i] for i in range(n)]
     y2 = torch.empty_like(x)
     h = int(torch.cuda.current_stream().cuda_stream)
-    for g in groups:
+    for g in plan.pass_groups():
         plan.exec_range(g[0], len(g), offt.FORWARD, x.data_ptr(), y2.data_ptr(), h)
     torch.cuda.synchronize()
     assert torch.equal(y, y2)
@@ -167,5 +165,61 @@ def test_nd_slab_schedule_bit_identical_and_vs_oracle(shape, batch, S, dtype):
     p1.backward(z1, out=z1)
     torch.cuda.synchronize()
     assert oracle.rel_l2(z1.cpu().numpy(), xh) <= tol
+    p0.close()
+    p1.close()
+
+
+# column-block schedules: (shape, batch, columns per block)
+COL_CASES = [((24, 20, 32), 1, 16), ((24, 20, 32), 2, 8), ((16, 12, 64), 1, 32), ((12, 1, 32), 2, 8),
+             ((1, 12, 32), 1, 8), ((40, 48, 64), 1, 16)]
+
+
+def col_plans(shape, dtype, w):
+    """The heuristic plan with the pass over c first and the strided tiles
+    at most w columns wide, without and with blocks of w columns."""
+    base = offt.default_plan_string(shape, dtype)
+    fields = [f.split("=", 1) for f in base.split(";")]
+    out = []
+    for k, v in fields:
+        if k == "order":
+            v = "c" + v.replace("c", "")
+        elif k in ("a", "b") and v != "1":
+            parts = v.split("/")
+            parts[1] = str(min(int(parts[1]), w))
+            v = "/".join(parts)
+        out.append(f"{k}={v}")
+    plain = ";".join(out)
+    return plain, f"{plain};col={w}"
+
+
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+@pytest.mark.parametrize("shape,batch,w", COL_CASES, ids=lambda v: str(v))
+def test_column_block_schedule_bit_identical_and_vs_oracle(shape, batch, w, dtype):
+    plain, blocked = col_plans(shape, dtype, w)
+    print(f"case {shape} batch {batch} {dtype}: {blocked}", flush=True)
+    full = ((batch,) if batch > 1 else ()) + tuple(shape)
+    x = synth.complex_grid(full, dtype, device="cuda")
+    p0 = offt.Plan(shape, dtype=dtype, batch=batch, tune="forced", forced_plan=plain, normalize_inverse=True)
+    p1 = offt.Plan(shape, dtype=dtype, batch=batch, tune="forced", forced_plan=blocked, normalize_inverse=True)
+    assert p0.col() == 0 and p1.col() == w
+    y0 = p0.forward(x)
+    y1 = p1.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+    ref = oracle_forward(x, shape, batch)
+    tol = oracle.tolerance(int(np.prod(shape)), dtype == C64)
+    assert oracle.rel_l2(y1.cpu().numpy().reshape(ref.shape), ref) <= tol
+    h = int(torch.cuda.current_stream().cuda_stream)
+    y2 = torch.empty_like(x)
+    for i in range(p1.npasses()):
+        p1.exec_pass(i, offt.FORWARD, x.data_ptr(), y2.data_ptr(), h)
+    y3 = torch.empty_like(x)
+    for g in p1.pass_groups():
+        p1.exec_range(g[0], len(g), offt.FORWARD, x.data_ptr(), y3.data_ptr(), h)
+    z1 = y1.clone()
+    p1.backward(z1, out=z1)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2) and torch.equal(y1, y3)
+    assert oracle.rel_l2(z1.cpu().numpy(), x.cpu().numpy()) <= tol
     p0.close()
     p1.close()

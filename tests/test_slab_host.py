@@ -84,3 +84,39 @@ def test_nd_bad_slab_rejected(slab):
     with pytest.raises(offt.OfftError) as e:
         offt.plan_string_nd(shape, C64, nd_with_first_axis_first(shape, C64) + f";slab={slab}")
     assert e.value.code == -6
+
+
+PLAN_C = "order=cba;a=16x16x2/16/p2;b=16x16x2/16/p2/x;c=8x8x8/2"
+
+
+@pytest.mark.parametrize("order", ["cba", "cab"])
+@pytest.mark.parametrize("col", ["16", "64", "256"])
+def test_column_block_round_trip(order, col):
+    plan = PLAN_C.replace("order=cba", f"order={order}") + f";col={col}"
+    assert offt.plan_string((512, 512, 512), C128, "natural", plan) == plan
+
+
+@pytest.mark.parametrize("plan", [
+    PLAN_C.replace("order=cba", "order=acb") + ";col=64",   # pass over c not first
+    PLAN_C + ";col=48",                                     # not a power of two
+    PLAN_C + ";col=512",                                    # the whole row
+    PLAN_C + ";col=8",                                      # narrower than the 16-column tiles
+    PLAN_C + ";col=0",
+    PLAN_C + ";col=64;slab=4",                              # both schedules
+])
+def test_unusable_column_block_plans_rejected(plan):
+    with pytest.raises(offt.OfftError) as e:
+        offt.plan_string((512, 512, 512), C128, "natural", plan)
+    assert e.value.code == -6
+
+
+def test_column_block_not_on_a_ragged_row():
+    # 48 columns split into blocks of 16 but not of 32; the strided tiles are
+    # 16 columns wide
+    plan = "order=cba;a=16x4/16/x;b=8x5/16/x;c=4x4x3/16"
+    assert offt.plan_string((64, 40, 48), C64, "natural", plan + ";col=16") == plan + ";col=16"
+    with pytest.raises(offt.OfftError):
+        offt.plan_string((64, 40, 48), C64, "natural", plan + ";col=32")
+    # tiles of 32 columns do not fit blocks of 16
+    with pytest.raises(offt.OfftError):
+        offt.plan_string((64, 40, 48), C64, "natural", plan.replace("/16/x", "/32/x") + ";col=16")
