@@ -423,14 +423,17 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
                 if (rc == OFFT_SUCCESS && ms < 0.99f * win_ms) { win_ms = ms; winner = c; }
             }
         }
-        // a kept schedule, its slab passes refined in place: each of b and c
-        // with its other fast kernel and with the other tile order (what a
-        // pass finds in the cache, and how many tiles a slab holds, differ
-        // from the whole-grid passes they were ranked on)
+        // a kept schedule, its blocked passes refined in place: each with its
+        // other fast kernel, with the other tile order and with the other
+        // access mode (what a pass finds in the cache, how many tiles a block
+        // holds and what its stores leave in the cache for the next block
+        // differ from the whole-grid passes they were ranked on)
+        const int64_t block_bytes = winner.slab > 0 ? std::min(winner.slab, planes) * plane_bytes
+                                                    : winner.col * colum_bytes;
         for (int ax = 0; ax < 3 && (winner.slab > 0 || winner.col > 0) && rc == OFFT_SUCCESS; ++ax) {
             if (dims[ax] <= 1 || ax == (winner.slab > 0 ? 0 : 2)) continue;   // the whole-grid pass
             const int g = axis_geom(winner, ax);
-            for (int variant = 0; variant < 2 && rc == OFFT_SUCCESS; ++variant) {
+            for (int variant = 0; variant < 3 && rc == OFFT_SUCCESS; ++variant) {
                 PlanChoice c = winner;
                 if (variant == 0) {
                     const int other = best_k[ax][g][0] == winner.k[ax] && best_lw[ax][g][0] == winner.logW[ax] ? 1 : 0;
@@ -438,8 +441,10 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
                     c.k[ax] = best_k[ax][g][other];
                     c.logW[ax] = best_lw[ax][g][other];
                     c.xcd[ax] = best_x[ax][g][other];
-                } else {
+                } else if (variant == 1) {
                     c.xcd[ax] = !winner.xcd[ax];
+                } else {
+                    c.io[ax] = resolve_stream(winner.io[ax], block_bytes) ? kIoCached : kIoStream;
                 }
                 if (!col_fits(c, dims, true)) continue;
                 float ms = 0.f;
