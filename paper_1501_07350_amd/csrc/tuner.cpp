@@ -737,6 +737,21 @@ static int exhaustive_nd(offt_plan_s* p, const offt_opts& o, NdChoice* choice, f
                 if (rc == OFFT_SUCCESS && ms < 0.99f * wms) { wms = ms; winner = c; }
             }
         }
+        // a kept schedule: each blocked pass with the other access mode
+        // (streaming stores of a block's last passes leave the cache to the
+        // next block)
+        const int64_t block_bytes = std::min(winner.slab, planes) * rest * es;
+        for (int ax = 1; ax < D && winner.slab > 0 && rc == OFFT_SUCCESS; ++ax) {
+            if (dims[ax] <= 1) continue;
+            NdChoice c = winner;
+            c.io[ax] = resolve_stream(winner.io[ax], block_bytes) ? kIoCached : kIoStream;
+            PassPlan passes[kMaxDims];
+            const int n = build_passes_nd(c, dims, p->batch, passes);
+            float ms = 0.f;
+            rc = time_passes(p, passes, n, nelem, src, buf, nullptr, s, o.reps, &ms);
+            ++*timed;
+            if (rc == OFFT_SUCCESS && ms < 0.99f * wms) { wms = ms; winner = c; }
+        }
     }
     (void)hipStreamSynchronize(s);
     (void)hipFree(buf);
