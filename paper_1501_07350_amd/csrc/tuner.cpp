@@ -202,6 +202,10 @@ struct TuneBuffers {
 // heuristic plan and the six pass orders (times the transposing axes) with
 // every combination of those kernels are timed as whole transforms.  Ties
 // keep the earlier candidate (the heuristic's kernels and order come first).
+// kernels per blocked pass tried in a kept block schedule (its axis's
+// fastest over the whole grid)
+constexpr size_t kBlockKernels = 6;
+
 static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dims[3], bool reversed,
                            const TuneBuffers& B, PlanChoice* choice, float* win_ms_out, int* timed) {
     hipStream_t s = static_cast<hipStream_t>(o.stream);
@@ -222,6 +226,11 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
     int best_lw[3][3][2] = {};
     int best_x[3][3][2] = {};   // XCD-contiguous tile order
     int best_io[3][3][2] = {};  // grid-data access mode (kIoAuto unless a forced mode was faster)
+    // every (kernel, width) timed on the input's geometry, fastest first: a
+    // pass of a block schedule runs from the Infinity Cache, where kernels
+    // rank differently than over the whole grid
+    struct Ranked { float ms; const KernelEntry* k; int lw; };
+    std::vector<Ranked> ranked[3];
     int rc = OFFT_SUCCESS;
     for (int ax = 0; ax < 3 && rc == OFFT_SUCCESS; ++ax) {
         if (dims[ax] <= 1) continue;
@@ -261,6 +270,7 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
                     rc = time_pass(p, make_pass(dims, p->batch, ax, g, k, lw), B.buf, B.work, s, o.reps, &ms);
                     ++*timed;
                     if (rc != OFFT_SUCCESS) break;
+                    if (g == kGeomNatural) ranked[ax].push_back({ms, k, lw});
                     if (ms < best_ms[0]) {
                         best_ms[1] = best_ms[0];
                         best_k[ax][g][1] = best_k[ax][g][0];
@@ -433,9 +443,18 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
         for (int ax = 0; ax < 3 && (winner.slab > 0 || winner.col > 0) && rc == OFFT_SUCCESS; ++ax) {
             if (dims[ax] <= 1 || ax == (winner.slab > 0 ? 0 : 2)) continue;   // the whole-grid pass
             const int g = axis_geom(winner, ax);
-            for (int variant = 0; variant < 3 && rc == OFFT_SUCCESS; ++variant) {
+            std::stable_sort(ranked[ax].begin(), ranked[ax].end(),
+                             [](const Ranked& x, const Ranked& y) { return x.ms < y.ms; });
+            const int nk = (int)std::min<size_t>(ranked[ax].size(), kBlockKernels);
+            for (int variant = -nk; variant < 3 && rc == OFFT_SUCCESS; ++variant) {
                 PlanChoice c = winner;
-                if (variant == 0) {
+                if (variant < 0) {
+                    // one of the axis's fastest whole-grid kernels, the winner's own aside
+                    const Ranked& r = ranked[ax][nk + variant];
+                    if (r.k == winner.k[ax] && r.lw == winner.logW[ax]) continue;
+                    c.k[ax] = r.k;
+                    c.logW[ax] = r.lw;
+                } else if (variant == 0) {
                     const int other = best_k[ax][g][0] == winner.k[ax] && best_lw[ax][g][0] == winner.logW[ax] ? 1 : 0;
                     if (!best_k[ax][g][other]) continue;
                     c.k[ax] = best_k[ax][g][other];
