@@ -109,7 +109,8 @@ int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const v
     const bool bwd = dir > 0;
     const int norm = normalize < 0 ? p->normalize : normalize;
     const size_t es = elem_size(p->dtype);
-    // pass i (whole grid, or the planes of one slab at element offset off)
+    // pass i (whole grid, the planes of one slab at element offset off, or
+    // one column block)
     auto launch = [&](int i, const PassPlan& q, int64_t off) {
         const bool last = i == npass - 1;
         const double scale = (bwd && last && norm) ? 1.0 / (double)N : 1.0;
@@ -121,9 +122,9 @@ int exec_passes(const offt_plan_s* p, const PassPlan* passes, int npass, const v
             return OFFT_ERR_HIP;
         return OFFT_SUCCESS;
     };
-    // passes before the slab schedule (all of them without one) over the
-    // whole grid, then the slab schedule: every remaining pass of one slab
-    // before the next slab
+    // passes before the block schedule (all of them without one) over the
+    // whole grid, then the schedule: every remaining pass of one slab (or
+    // column block) before the next
     const int first_slab = slab_start(passes, npass);
     for (int i = i0; i < std::min(i1, first_slab); ++i) {
         const int rc = launch(i, passes[i], 0);
