@@ -352,8 +352,9 @@ def nd_runs(steps: int, warmup: int, check: bool):
 
 def time_batch(steps: int, warmup: int, check: bool, count: int = 64):
     """Uneven batch of `count` complex64 grids (axes drawn from
-    {48,...,160}): every launch form of the batch executor (the level kernels,
-    the default, replayed from a HIP graph; the level-synchronous and the
+    {48,...,160}): every launch form of the batch executor (the level kernels
+    replayed from a HIP graph, the default, also grouped by
+    Infinity-Cache-sized groups of grids; the level-synchronous and the
     work-queue persistent kernels) vs every grid's passes launched separately
     on the same stream."""
     import numpy as np
@@ -381,6 +382,7 @@ def time_batch(steps: int, warmup: int, check: bool, count: int = 64):
         "graph_heuristic": (heur, offt.MANY_PERSISTENT_GRAPH),
         "levels_tuned": (tuned, offt.MANY_LEVELS),
         "levels_graph_tuned": (tuned, offt.MANY_LEVELS_GRAPH),
+        "levels_grouped_graph_tuned": (tuned, offt.MANY_LEVELS_GROUPED_GRAPH),
         "sync_tuned": (tuned, offt.MANY_SYNC),
         "sync_graph_tuned": (tuned, offt.MANY_SYNC_GRAPH),
     }
@@ -412,6 +414,8 @@ def time_batch(steps: int, warmup: int, check: bool, count: int = 64):
         # the library's default form (offt_exec_many_fwd) and the fastest
         # single-kernel form; every form's time is in "ms"
         "default_form": "levels_graph_tuned",
+        "speedup_levels_grouped_graph_tuned_vs_separate_heuristic": round(
+            ms["separate_heuristic"] / ms["levels_grouped_graph_tuned"], 3),
         "speedup_levels_graph_tuned_vs_separate_heuristic": round(
             ms["separate_heuristic"] / ms["levels_graph_tuned"], 3),
         "speedup_sync_graph_tuned_vs_separate_heuristic": round(ms["separate_heuristic"] / ms["sync_graph_tuned"], 3),
@@ -453,7 +457,8 @@ def time_batch_any_lengths(steps: int, warmup: int, check: bool, count: int = 64
     xp, yp = x.data_ptr(), y.data_ptr()
     variants = {"separate_heuristic": offt.MANY_SEPARATE_HEURISTIC,
                 "levels_heuristic": offt.MANY_LEVELS,
-                "levels_graph_heuristic": offt.MANY_LEVELS_GRAPH}
+                "levels_graph_heuristic": offt.MANY_LEVELS_GRAPH,
+                "levels_grouped_graph_heuristic": offt.MANY_LEVELS_GROUPED_GRAPH}
     ms = {}
     for name, mode in variants.items():
         for _ in range(warmup):
@@ -863,35 +868,38 @@ def summarize_kernels(d: str, command: str, title: str, top: int = 20) -> str:
 
 def summarize_batch(d: str, command: str, steps: int, warmup: int) -> str:
     """Kernel-trace figures of the uneven-batch executors from one
-    `--batch-only` run: per executor family, dispatches and mean duration;
-    per execution, the summed kernel time, and for the level kernels replayed
-    from the graph (the last `steps` executions) the span from the first
-    level's start to the last one's end."""
+    `--batch-only` run: per executor form, dispatches and mean duration; per
+    execution, the summed kernel time, and for the forms replayed from a
+    graph (the last `steps` executions) the span from the first kernel's
+    start to the last one's end."""
     trace = _read_csv(_find(d, "kernel_trace.csv"))
     trace.sort(key=lambda r: int(r["Dispatch_Id"]))
-    fams = [("persistent work-queue kernel", "many_kernel_batch_", 3),
-            ("level kernels", "many_level_kernel_batch_", 2),
-            ("level-synchronous persistent kernel", "many_sync_kernel_batch_", 2),
-            ("every-length executor, level kernels", "many_level_kernel_all_", 2)]
-    runs_per_variant = steps + warmup
+    runs = steps + warmup
+
+    def rows_of(key):
+        return [r for r in trace if key in r["Kernel_Name"]]
+
+    def dur(r):
+        return (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+
     lines = ["# rocprofv3 kernel trace of the uneven-batch executors (64 complex64 grids, one forward each)",
              f"# command: {command}",
-             f"# {steps} timed + {warmup} warm-up executions per variant; the persistent kernel runs in 3 variants",
-             "# (tuned, tuned in a graph, heuristic in a graph), the level and level-synchronous kernels in 2",
-             "# (direct, in a graph); the every-length executor's level kernels run the second batch (64 grids,",
-             "# axes over every 2/3/5-smooth length 2..160, heuristic plans) in 2",
-             f"{'executor':<38} {'dispatches':>10} {'mean_us':>9} {'per_exec':>8} {'busy_us_per_exec':>17}"]
-    for label, key, nvar in fams:
-        rows = [r for r in trace if key in r["Kernel_Name"]]
+             f"# {steps} timed + {warmup} warm-up executions per form, in the order the bench runs them: the",
+             "# persistent kernel (tuned, tuned in a graph, heuristic in a graph), the level kernels (direct, in a",
+             "# graph, grouped in a graph), the level-synchronous kernel (direct, in a graph); the every-length",
+             "# executor's level kernels run the second batch (64 grids, axes over every 2/3/5-smooth length",
+             "# 2..160, heuristic plans: direct, in a graph, grouped in a graph)",
+             f"{'form':<46} {'dispatches':>10} {'mean_us':>9} {'per_exec':>8} {'busy_us_per_exec':>17}"]
+
+    def report(label, rows, execs, graph):
         if not rows:
-            lines.append(f"{label:<38} {'none traced':>10}")
-            continue
-        durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows]
-        execs = nvar * runs_per_variant
+            lines.append(f"{label:<46} {'none traced':>10}")
+            return
+        durs = [dur(r) for r in rows]
         per = len(rows) / execs
-        lines.append(f"{label:<38} {len(rows):>10} {sum(durs) / len(rows):>9.2f} {per:>8.2f} "
+        lines.append(f"{label:<46} {len(rows):>10} {sum(durs) / len(rows):>9.2f} {per:>8.2f} "
                      f"{sum(durs) / execs:>17.2f}")
-        if key.startswith("many_level_kernel_") and per == int(per):
+        if graph and per == int(per):
             k = int(per)
             tail = rows[len(rows) - steps * k:]
             spans = []
@@ -899,9 +907,20 @@ def summarize_batch(d: str, command: str, steps: int, warmup: int) -> str:
                 grp = tail[e * k:(e + 1) * k]
                 spans.append((max(int(r["End_Timestamp"]) for r in grp)
                               - min(int(r["Start_Timestamp"]) for r in grp)) / 1e3)
-            busy = sum((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tail) / steps
-            lines.append(f"  graph replays: {k} level kernels per execution, span first start to last end "
+            busy = sum(dur(r) for r in tail) / steps
+            lines.append(f"  graph replays: {k} kernels per execution, span first start to last end "
                          f"{sum(spans) / len(spans):.2f} us (min {min(spans):.2f}), summed kernel time {busy:.2f} us")
+
+    report("persistent work-queue kernel", rows_of("many_kernel_batch_"), 3 * runs, False)
+    for label, key in (("", "many_level_kernel_batch_"), ("every-length executor, ", "many_level_kernel_all_")):
+        rows = rows_of(key)
+        # direct and graph forms: 3 level kernels per execution; the grouped
+        # graph: 3 per group, the rest
+        n3 = 3 * runs
+        report(f"{label}level kernels, direct", rows[:n3], runs, False)
+        report(f"{label}level kernels, graph", rows[n3:2 * n3], runs, True)
+        report(f"{label}level kernels, grouped graph", rows[2 * n3:], runs, True)
+    report("level-synchronous persistent kernel", rows_of("many_sync_kernel_batch_"), 2 * runs, False)
     return "\n".join(lines) + "\n"
 
 

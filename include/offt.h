@@ -318,6 +318,12 @@ int64_t offt_many_offset(offt_plan_t p, int i);
  *       all second, then all third), one workgroup per tile, replayed from a
  *       HIP graph built on the first call;
  *    3  LEVELS: the same kernels launched directly;
+ *    6  LEVELS_GROUPED_GRAPH: the level kernels group by group: consecutive
+ *       grids in groups of at most 192 MiB of grid data (a larger grid
+ *       alone), each group's levels one after the other before the next
+ *       group's, so that a group's later levels read what its earlier ones
+ *       wrote from the 256 MB Infinity Cache; replayed from a HIP graph built
+ *       on the first call;
  *    5  SYNC_GRAPH: one level-synchronous persistent kernel, after a counter
  *       reset, replayed from a HIP graph: one resident workgroup per slot the
  *       device has, each level's tiles dealt round-robin in the level
@@ -327,7 +333,7 @@ int64_t offt_many_offset(offt_plan_t p, int i);
  *   -1  SEPARATE_HEURISTIC: every grid's passes as ordinary launches with the
  *       heuristic plans;
  *   -2  SEPARATE_TUNED: the same with the plans chosen at plan time.
- * The level forms (2, 3) run any batch whose axes are all at most 160 long;
+ * The level forms (2, 3, 6) run any batch whose axes are all at most 160 long;
  * the persistent forms (0, 1, 4, 5) only batches whose axis lengths all lie
  * in the set {48, 60, 64, 80, 96, 120, 128, 150, 160} (lengths 1 are fine
  * for both).
@@ -573,6 +579,7 @@ int offt_mlp_adam(offt_mlp_t m, const float* grad, float lr, float beta1, float 
 #define OFFT_MANY_LEVELS 3
 #define OFFT_MANY_SYNC 4
 #define OFFT_MANY_SYNC_GRAPH 5
+#define OFFT_MANY_LEVELS_GROUPED_GRAPH 6
 
 #define OFFT_FORWARD (-1)
 #define OFFT_BACKWARD (+1)

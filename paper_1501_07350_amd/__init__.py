@@ -17,7 +17,8 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (BACKWARD, C2C_F32, C2C_F64, COMM_METHODS, FORWARD, MANY_LEVELS, MANY_LEVELS_GRAPH, MANY_PERSISTENT,
+from ._lib import (BACKWARD, C2C_F32, C2C_F64, COMM_METHODS, FORWARD, MANY_LEVELS, MANY_LEVELS_GRAPH,
+                   MANY_LEVELS_GROUPED_GRAPH, MANY_PERSISTENT,
                    MANY_PERSISTENT_GRAPH, MANY_SEPARATE_HEURISTIC, MANY_SEPARATE_TUNED, MANY_SYNC, MANY_SYNC_GRAPH,
                    LAYOUT_NATURAL, LAYOUT_REVERSED, MAX_AXIS, OfftError,
                    TUNE_EXHAUSTIVE, TUNE_FORCED, TUNE_LEARNED, TUNE_NONE)

@@ -40,6 +40,7 @@ MANY_LEVELS_GRAPH = 2
 MANY_LEVELS = 3
 MANY_SYNC = 4
 MANY_SYNC_GRAPH = 5
+MANY_LEVELS_GROUPED_GRAPH = 6
 MAX_AXIS = 1024
 MAX_DIMS = 5
 

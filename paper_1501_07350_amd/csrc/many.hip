@@ -32,6 +32,10 @@ __global__ void many_reset_kernel(unsigned* counters, int n) {
 }
 
 constexpr int kManySpinLimit = 1 << 22;    // polls (~2 s) before a wait gives up and flags an error
+// grid data per group of the grouped level schedule: three quarters of the
+// 256 MB Infinity Cache (on 64 uneven complex64 grids of 552 MB, groups of
+// at most 192 MiB beat 128 and 256 MiB)
+constexpr int64_t kManyGroupBytes = int64_t(192) << 20;
 constexpr int64_t kAlignBytes = 256;       // every grid starts on a 256-byte boundary
 
 struct ManyGrid {
@@ -84,6 +88,15 @@ struct ManyState {
     int64_t lbegin[3] = {0, 0, 0};
     int nlevels = 0;
     bool lgraph_ready = false;
+    // grouped level schedule: tile map, ranges (3 per group) and its graph
+    ManyGroups groups;
+    int* d_tile_map = nullptr;
+    hipGraph_t ggraph = nullptr;
+    hipGraphExec_t ggexec = nullptr;
+    std::vector<hipGraphNode_t> gnodes;
+    std::vector<int64_t> gbegin;
+    ManyArgs ggargs{};
+    bool ggraph_ready = false;
     std::string desc;
 };
 
@@ -120,6 +133,8 @@ void release_many(offt_plan_s* p) {
     if (m->lgraph) (void)hipGraphDestroy(m->lgraph);
     if (m->sgexec) (void)hipGraphExecDestroy(m->sgexec);
     if (m->sgraph) (void)hipGraphDestroy(m->sgraph);
+    if (m->ggexec) (void)hipGraphExecDestroy(m->ggexec);
+    if (m->ggraph) (void)hipGraphDestroy(m->ggraph);
     delete m;
     p->many = nullptr;
 }
@@ -199,6 +214,16 @@ static int build_many(offt_plan_s* p, hipStream_t s) {
         hipMemsetAsync(m->d_counters, 0, sizeof(unsigned) * ncnt, s) != hipSuccess)
         return OFFT_ERR_HIP;
     if (!m->levels_ok) return OFFT_SUCCESS;
+    // grouped level schedule: the level kernels' tiles group by group
+    build_many_groups(gd, tab, (int64_t)es, kManyGroupBytes, &m->groups);
+    if (!m->groups.map.empty()) {
+        rc = dev_alloc(p, sizeof(int) * m->groups.map.size(), &d);
+        if (rc) return rc;
+        m->d_tile_map = static_cast<int*>(d);
+        if (hipMemcpyAsync(m->d_tile_map, m->groups.map.data(), sizeof(int) * m->groups.map.size(),
+                           hipMemcpyHostToDevice, s) != hipSuccess)
+            return OFFT_ERR_HIP;
+    }
     m->lds = std::max<size_t>(lds_max, 16);
     if (m->lds > 65536 &&
         hipFuncSetAttribute(m->exec->level_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)m->lds) !=
@@ -303,6 +328,56 @@ static int level_graph_launch(ManyState* m, const void* in, void* out, int dir, 
         }
     }
     if (hipGraphLaunch(m->lgexec, s) != hipSuccess) return OFFT_ERR_HIP;
+    return OFFT_SUCCESS;
+}
+
+// Graph of the grouped level schedule: for each group of grids its non-empty
+// levels, all chained (one group's levels before the next group's); later
+// calls with other buffers or direction update the nodes' arguments.
+static int grouped_graph_launch(ManyState* m, const void* in, void* out, int dir, hipStream_t s) {
+    ManyArgs a = make_args(m, in, out, dir);
+    a.tile_map = m->d_tile_map;
+    const int nr = 3 * m->groups.groups;
+    auto node_params = [&](int r, hipKernelNodeParams* kp, void** params) {
+        memset(kp, 0, sizeof *kp);
+        params[0] = &m->ggargs;
+        params[1] = &m->gbegin[r];
+        kp->func = const_cast<void*>(m->exec->level_kernel);
+        kp->gridDim = dim3((unsigned)(m->groups.ranges[r + 1] - m->groups.ranges[r]));
+        kp->blockDim = dim3(kManyThreads);
+        kp->sharedMemBytes = (unsigned)m->lds;
+        kp->kernelParams = params;
+    };
+    if (!m->ggraph_ready) {
+        if (hipGraphCreate(&m->ggraph, 0) != hipSuccess) return OFFT_ERR_HIP;
+        m->ggargs = a;
+        m->gbegin.assign((size_t)nr, 0);
+        m->gnodes.assign((size_t)nr, nullptr);
+        hipGraphNode_t prev = nullptr;
+        for (int r = 0; r < nr; ++r) {
+            m->gbegin[r] = m->groups.ranges[r];
+            if (m->groups.ranges[r + 1] <= m->groups.ranges[r]) continue;
+            hipKernelNodeParams kp;
+            void* params[2];
+            node_params(r, &kp, params);
+            if (hipGraphAddKernelNode(&m->gnodes[r], m->ggraph, prev ? &prev : nullptr, prev ? 1 : 0, &kp) !=
+                hipSuccess)
+                return OFFT_ERR_HIP;
+            prev = m->gnodes[r];
+        }
+        if (hipGraphInstantiate(&m->ggexec, m->ggraph, nullptr, nullptr, 0) != hipSuccess) return OFFT_ERR_HIP;
+        m->ggraph_ready = true;
+    } else if (memcmp(&a, &m->ggargs, sizeof a) != 0) {
+        m->ggargs = a;
+        for (int r = 0; r < nr; ++r) {
+            if (!m->gnodes[r]) continue;
+            hipKernelNodeParams kp;
+            void* params[2];
+            node_params(r, &kp, params);
+            if (hipGraphExecKernelNodeSetParams(m->ggexec, m->gnodes[r], &kp) != hipSuccess) return OFFT_ERR_HIP;
+        }
+    }
+    if (hipGraphLaunch(m->ggexec, s) != hipSuccess) return OFFT_ERR_HIP;
     return OFFT_SUCCESS;
 }
 
@@ -531,10 +606,10 @@ offt_plan_t offt_plan_many(int count, const int64_t* dims, int dtype, const offt
     if (rc == OFFT_SUCCESS) rc = build_many(p, s);
     if (rc == OFFT_SUCCESS && hipStreamSynchronize(s) != hipSuccess) rc = OFFT_ERR_HIP;
     if (rc != OFFT_SUCCESS) { free_plan(p); set_error(rc); return nullptr; }
-    char buf[256];
-    snprintf(buf, sizeof buf, "many: %d grids, %lld elements, %d segments, %lld work items, executor %s, %d workgroups x %d (level-synchronous: %d), lds %zu%s%s%s%s",
+    char buf[512];
+    snprintf(buf, sizeof buf, "many: %d grids, %lld elements, %d segments, %lld work items, executor %s, %d workgroups x %d (level-synchronous: %d), lds %zu, %d level groups%s%s%s%s",
              count, (long long)m->total_elems, m->nseg, (long long)m->total_items, m->exec ? m->exec->name : "-",
-             m->nblocks, kManyThreads, m->sync_nblocks, m->lds,
+             m->nblocks, kManyThreads, m->sync_nblocks, m->lds, m->groups.groups,
              m->levels_ok ? "" : "; level kernels unavailable: ", m->levels_ok ? "" : m->why_not_levels.c_str(),
              m->persistent_ok ? "" : "; persistent executor unavailable: ", m->persistent_ok ? "" : m->why_not.c_str());
     m->desc = buf;
@@ -552,9 +627,10 @@ int64_t offt_many_offset(offt_plan_t p, int i) {
     return i == m->count ? m->total_elems : m->grids[i].off;
 }
 
-// The default launch of a many-plan: the level kernels replayed from a graph
-// (the fastest form measured on MI355X) when an executor covers every pass
-// (every axis at most 160 long), else the tuned plans as separate launches.
+// The default launch of a many-plan: the level kernels replayed from a
+// graph (with the grouped schedule, the fastest forms measured on MI355X)
+// when an executor covers every pass (every axis at most 160 long), else the
+// tuned plans as separate launches.
 static int many_default_form(offt_plan_t p) {
     if (!p || p->kind != 2 || !p->many) return OFFT_MANY_LEVELS_GRAPH;   // rejected below
     return p->many->levels_ok ? OFFT_MANY_LEVELS_GRAPH : OFFT_MANY_SEPARATE_TUNED;
@@ -570,7 +646,7 @@ int offt_exec_many_bwd(offt_plan_t p, const void* in, void* out, void* stream) {
 
 int offt_exec_many(offt_plan_t p, const void* in, void* out, int direction, int use_graph, void* stream) {
     if (!p || !in || !out || (direction != OFFT_FORWARD && direction != OFFT_BACKWARD) || use_graph < -2 ||
-        use_graph > OFFT_MANY_SYNC_GRAPH) {
+        use_graph > OFFT_MANY_LEVELS_GROUPED_GRAPH) {
         set_error(OFFT_ERR_INVALID_ARG);
         return OFFT_ERR_INVALID_ARG;
     }
@@ -590,11 +666,14 @@ int offt_exec_many(offt_plan_t p, const void* in, void* out, int direction, int 
     if (rc != OFFT_SUCCESS) {
     } else if (use_graph < 0 || m->nseg == 0) {
         rc = exec_separate(p, in, out, direction, use_graph == -2 || m->nseg == 0, s);
-    } else if (use_graph == OFFT_MANY_LEVELS_GRAPH || use_graph == OFFT_MANY_LEVELS) {
+    } else if (use_graph == OFFT_MANY_LEVELS_GRAPH || use_graph == OFFT_MANY_LEVELS ||
+               use_graph == OFFT_MANY_LEVELS_GROUPED_GRAPH) {
         if (!m->levels_ok)
             rc = OFFT_ERR_UNSUPPORTED_SIZE;
         else if (use_graph == OFFT_MANY_LEVELS_GRAPH)
             rc = level_graph_launch(m, in, out, direction, s);
+        else if (use_graph == OFFT_MANY_LEVELS_GROUPED_GRAPH)
+            rc = grouped_graph_launch(m, in, out, direction, s);
         else
             rc = launch_levels(m, in, out, direction, s);
     } else if (!m->persistent_ok) {

@@ -59,6 +59,7 @@ struct ManyArgs {
     void* out;
     const ManySeg* segs;
     const int* tile_seg; // [tile]: segment of each tile of the level kernels' numbering
+    const int* tile_map; // level kernels: launch position -> tile number (grouped schedule), or null
     unsigned* counters;  // [0] queue head, [1] error flag, [2 + s] items done in segment s
     int64_t total_items;
     int nseg;
@@ -196,11 +197,14 @@ __device__ __forceinline__ void many_body(const ManyArgs& a, V* __restrict__ lds
 
 // Non-persistent form: one workgroup per tile of tiles
 // [tile_begin, tile_begin + gridDim.x), all of one pass level, so the kernel
-// boundary between levels orders the passes and no counters are used.
+// boundary between levels orders the passes and no counters are used.  With
+// a tile map (grouped schedule) the launch covers map positions instead,
+// the tiles of one level of one group of grids.
 template <typename V, typename Dispatch>
 __device__ __forceinline__ void many_level_body(const ManyArgs& a, int64_t tile_begin, V* __restrict__ lds,
                                                 const Dispatch& dispatch) {
-    const int64_t tile = tile_begin + (int64_t)blockIdx.x;
+    const int64_t pos = tile_begin + (int64_t)blockIdx.x;
+    const int64_t tile = a.tile_map ? (int64_t)a.tile_map[pos] : pos;
     const int seg = a.tile_seg[tile];
     const ManySeg sg = a.segs[seg];
     const PassArgs p = segment_pass_args<V>(a, sg);

@@ -126,4 +126,60 @@ inline void build_many_tables(const std::vector<ManyGridDesc>& grids, int64_t el
     t->seg_level = seg_level;
 }
 
+// Grouped level schedule: consecutive grids in groups of at most
+// `group_bytes` of grid data (a larger grid alone), and per group its three
+// pass levels, so that a group's later levels find the earlier ones' output
+// in the Infinity Cache.  `map` lists the level kernels' tile numbers group
+// by group and level by level; range r = 3 g + l of `ranges` is
+// [ranges[r], ranges[r + 1]) of `map`.
+struct ManyGroups {
+    std::vector<int> map;
+    std::vector<int64_t> ranges;   // 3 * groups + 1 entries
+    int groups = 0;
+};
+
+inline void build_many_groups(const std::vector<ManyGridDesc>& grids, const ManyTables& t, int64_t elem_bytes,
+                              int64_t group_bytes, ManyGroups* out) {
+    const int count = (int)grids.size();
+    // group of every grid, in grid order
+    std::vector<int> group_of(count, 0);
+    int g = 0;
+    int64_t bytes = 0;
+    for (int i = 0; i < count; ++i) {
+        // the grid's points: its first pass covers them all (lines x length)
+        const int64_t n = grids[i].passes.empty() ? 0 : grids[i].passes[0].nlines * grids[i].passes[0].L;
+        const int64_t b = n * elem_bytes;
+        if (bytes > 0 && bytes + b > group_bytes) {
+            ++g;
+            bytes = 0;
+        }
+        group_of[i] = g;
+        bytes += b;
+    }
+    out->groups = count ? g + 1 : 0;
+    // segments of each (group, level), in the tables' order (grid order
+    // within a level); a segment's grid is found by its element offset
+    std::vector<int> seg_grid(t.segs.size(), 0);
+    {
+        int gi = 0;
+        for (size_t s = 0; s < t.segs.size(); ++s) {
+            if (s > 0 && t.seg_level[s] != t.seg_level[s - 1]) gi = 0;
+            while (gi < count && grids[gi].elem_off != t.segs[s].elem_off) ++gi;
+            seg_grid[s] = gi < count ? gi : count - 1;
+        }
+    }
+    out->map.clear();
+    out->ranges.assign((size_t)3 * out->groups + 1, 0);
+    for (int gr = 0; gr < out->groups; ++gr) {
+        for (int lvl = 0; lvl < 3; ++lvl) {
+            out->ranges[(size_t)3 * gr + lvl] = (int64_t)out->map.size();
+            for (size_t s = 0; s < t.segs.size(); ++s) {
+                if (t.seg_level[s] != lvl || group_of[seg_grid[s]] != gr) continue;
+                for (int k = 0; k < t.segs[s].ntiles; ++k) out->map.push_back((int)(t.segs[s].tile_base + k));
+            }
+        }
+    }
+    out->ranges[(size_t)3 * out->groups] = (int64_t)out->map.size();
+}
+
 }  // namespace offt

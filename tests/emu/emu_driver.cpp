@@ -203,12 +203,24 @@ static int do_many(int argc, char** argv, bool sync, bool levels = false, bool t
         else many_body<V>(a, lds, EmuDispatch<V>{});
     };
     if (levels) {
-        // one workgroup per tile, the levels one after the other
+        // one workgroup per tile, the levels one after the other; with
+        // EMU_GROUP_BYTES the grouped schedule of the library's own builder
+        // (each group's levels before the next group's, through the tile map)
         std::vector<V> lds(lds_elems);
         bool okl = true;
-        for (int l = 0; l < 3; ++l) {
-            const int64_t begin = tab.level_tile_begin[l];
-            gridDim.x = (unsigned)(tab.level_tile_begin[l + 1] - begin);
+        std::vector<int64_t> ranges;
+        ManyGroups grp;
+        if (const char* gb = getenv("EMU_GROUP_BYTES")) {
+            build_many_groups(gd, tab, (int64_t)sizeof(V), atoll(gb), &grp);
+            a.tile_map = grp.map.data();
+            ranges = grp.ranges;
+            std::printf("GROUPS %d\n", grp.groups);
+        } else {
+            ranges.assign(tab.level_tile_begin, tab.level_tile_begin + 4);
+        }
+        for (size_t r = 0; r + 1 < ranges.size(); ++r) {
+            const int64_t begin = ranges[r];
+            gridDim.x = (unsigned)(ranges[r + 1] - begin);
             for (unsigned b = 0; b < gridDim.x; ++b) {
                 blockIdx.x = b;
                 okl = run_block(threads, [&](int) {

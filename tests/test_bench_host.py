@@ -28,25 +28,33 @@ def write_trace(path, dispatches):
 
 def test_batch_trace_summary(tmp_path):
     steps, warmup = 3, 1
+    runs = steps + warmup
     d = []
-    for _ in range(3 * (steps + warmup)):          # persistent kernel, three variants
+    for _ in range(3 * runs):                        # persistent kernel, three variants
         d += [("fft_pass_kernel<tuner>", 1_000, 100), ("offt::many_kernel_batch_f32(offt::ManyArgs)", 900_000, 100)]
+    lvl = "offt::many_level_kernel_batch_f32(offt::ManyArgs, long)"
     for v in range(2):                               # level kernels, direct then graph
-        for _ in range(steps + warmup):
-            d += [("offt::many_level_kernel_batch_f32(offt::ManyArgs, long)", 100_000 * (k + 1), 2_000 * v)
-                  for k in range(3)]
-    for _ in range(2 * (steps + warmup)):
+        for _ in range(runs):
+            d += [(lvl, 100_000 * (k + 1), 2_000 * v) for k in range(3)]
+    for _ in range(runs):                            # grouped graph: 2 groups of 3 levels
+        d += [(lvl, 50_000, 1_000) for _ in range(6)]
+    for _ in range(2 * runs):
         d.append(("offt::many_sync_kernel_batch_f32(offt::ManyArgs, offt::ManySyncArgs)", 700_000, 100))
     write_trace(str(tmp_path / "run" / "run_kernel_trace.csv"), d)
     txt = load_bench().summarize_batch(str(tmp_path), "cmd", steps, warmup)
-    rows = {l[:38].strip(): l[38:].split() for l in txt.splitlines() if not l.startswith("#")}
+    rows = {l[:46].strip(): l[46:].split() for l in txt.splitlines() if not l.startswith(("#", " "))}
     assert rows["persistent work-queue kernel"] == ["12", "900.00", "1.00", "900.00"]
-    assert rows["level kernels"] == ["24", "200.00", "3.00", "600.00"]
+    assert rows["level kernels, direct"] == ["12", "200.00", "3.00", "600.00"]
+    assert rows["level kernels, graph"] == ["12", "200.00", "3.00", "600.00"]
+    assert rows["level kernels, grouped graph"] == ["24", "50.00", "6.00", "300.00"]
     assert rows["level-synchronous persistent kernel"] == ["8", "700.00", "1.00", "700.00"]
-    # graph replays: 3 kernels of 100, 200 and 300 us with 2 us between them
-    replay = [l for l in txt.splitlines() if "graph replays" in l][0]
-    assert "3 level kernels per execution" in replay
-    assert "span first start to last end 604.00 us" in replay and "summed kernel time 600.00 us" in replay
+    assert rows["every-length executor, level kernels, direct"] == ["none", "traced"]
+    replays = [l for l in txt.splitlines() if "graph replays" in l]
+    # level graph: 3 kernels of 100, 200 and 300 us with 2 us between them
+    assert "3 kernels per execution" in replays[0]
+    assert "span first start to last end 604.00 us" in replays[0] and "summed kernel time 600.00 us" in replays[0]
+    # grouped graph: 6 kernels of 50 us with 1 us between them
+    assert "6 kernels per execution" in replays[1] and "span first start to last end 305.00 us" in replays[1]
 
 
 def test_nd_trace_summary(tmp_path):

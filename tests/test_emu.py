@@ -221,7 +221,7 @@ def grid_args(dims_list, dtype, which="all"):
     return args, offs, total, npass
 
 
-def run_many(exe, dims_list, dtype, nwg=1, sync=False, levels=False, which=None):
+def run_many(exe, dims_list, dtype, nwg=1, sync=False, levels=False, which=None, group_bytes=None):
     """Run the batch loop of one form on the emulator: the work-queue loop
     over the every-length executor's cases, the level-synchronous loop or
     the level kernels over the batch executor's (the level kernels also over
@@ -230,9 +230,14 @@ def run_many(exe, dims_list, dtype, nwg=1, sync=False, levels=False, which=None)
     args, offs, total, _ = grid_args(dims_list, dtype, which)
     code = "0" if dtype == torch.complex128 else "1"
     mode = ("levels_all" if which == "all" else "levels") if levels else "sync" if sync else "many"
-    r = subprocess.run([exe, mode, code, str(nwg)] + args, capture_output=True, text=True, timeout=600)
+    env = dict(os.environ, EMU_GROUP_BYTES=str(group_bytes)) if group_bytes else None
+    r = subprocess.run([exe, mode, code, str(nwg)] + args, capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0, (r.stdout[:500], r.stderr[-3000:])
     lines = r.stdout.splitlines()
+    if group_bytes:
+        assert lines[0].startswith("GROUPS"), lines[0]
+        groups = int(lines[0].split()[1])
+        lines = lines[1:]
     assert lines[0].startswith("OK"), lines[0]
     vals = np.array([[float(a) for a in ln.split()] for ln in lines[1:]])
     out = vals[:, 0] + 1j * vals[:, 1]
@@ -250,6 +255,7 @@ def run_many(exe, dims_list, dtype, nwg=1, sync=False, levels=False, which=None)
         y = out[offs[g]:offs[g] + n].reshape(d)
         e = oracle.rel_l2(y, oracle.fft3(x))
         assert e <= oracle.tolerance(n, dtype == torch.complex64), (d, e)
+    return groups if group_bytes else None
 
 
 MIXED = [(2, 3, 5), (1, 1, 1), (9, 25, 27), (100, 4, 6), (48, 60, 64), (16, 1, 8), (5, 5, 5)]
@@ -592,3 +598,19 @@ def test_emulated_column_block_pass(emu_binary, dtype, case):
     L, seq, tpl, M1, M2, logW, logP, logw, ld, off = case
     assert (1 << logW) <= (1 << logw) and M2 % ld == 0 and off + (1 << logw) <= ld
     run_pass_block(emu_binary, dtype, L, seq, tpl, M1, M2, logW, logP, logw, ld, off)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128], ids=["c64", "c128"])
+@pytest.mark.parametrize("group_bytes", [1, 300_000, 10 ** 12])
+def test_emulated_grouped_level_schedule(emu_binary, dtype, group_bytes):
+    """The grouped level schedule with the library's own group builder: the
+    level kernels' body over each (group, level) range of the tile map, one
+    group after the other -- one grid per group, a few grids per group, one
+    group -- every grid matches the oracle."""
+    dims = MIXED
+    groups = run_many(emu_binary, dims, dtype, levels=True, which="all", group_bytes=group_bytes)
+    ngrids = sum(1 for d in dims if int(np.prod(d)) > 1)
+    if group_bytes == 1:
+        assert groups >= ngrids
+    if group_bytes == 10 ** 12:
+        assert groups == 1

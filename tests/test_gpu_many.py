@@ -72,16 +72,19 @@ def test_uneven_batch_64_grids_persistent_graph_vs_oracle_and_separate():
 
 def test_uneven_batch_64_grids_tuned_every_launch_form_vs_oracle():
     """The benchmark's timed forms: exhaustively tuned per-grid plans, run as
-    the level graph, the level-synchronous graph, the queue-based persistent
-    graph and separate launches; every one of the 64 grids against O3."""
+    the grouped level graph, the level graph (the default), the
+    level-synchronous graph, the queue-based persistent graph and separate
+    launches; every one of the 64 grids against O3."""
     dims = synth.uneven_batch_dims(64)
     plan = offt.ManyPlan(dims, dtype=C64, tune="exhaustive")
     print(plan.describe().splitlines()[0], flush=True)
     grids, x = packed_input(plan, dims, C64)
     refs = [oracle.fft3(g.cpu().numpy().astype(np.complex128)) for g in grids]
     first = None
-    for form in (offt.MANY_LEVELS_GRAPH, offt.MANY_SYNC_GRAPH, offt.MANY_PERSISTENT_GRAPH, offt.MANY_LEVELS,
-                 offt.MANY_SYNC, offt.MANY_PERSISTENT, offt.MANY_SEPARATE_TUNED):
+    assert "3 level groups" in plan.describe()     # 552 MB of grids in groups of at most 192 MiB
+    for form in (offt.MANY_LEVELS_GROUPED_GRAPH, offt.MANY_LEVELS_GRAPH, offt.MANY_SYNC_GRAPH,
+                 offt.MANY_PERSISTENT_GRAPH, offt.MANY_LEVELS, offt.MANY_SYNC, offt.MANY_PERSISTENT,
+                 offt.MANY_SEPARATE_TUNED):
         print(f"form {form}", flush=True)
         y = plan.execute(x, use_graph=form)
         torch.cuda.synchronize()
@@ -91,7 +94,7 @@ def test_uneven_batch_64_grids_tuned_every_launch_form_vs_oracle():
         if first is None:
             first = y
         else:
-            assert same_grids(plan, first, y), f"form {form} differs from the level graph"
+            assert same_grids(plan, first, y), f"form {form} differs from the grouped level graph"
 
 
 def test_graph_replays_match_eager_with_work_between():
@@ -280,17 +283,19 @@ def test_tuned_batch_plans_are_valid():
 
 
 def test_default_launch_form():
-    """offt_exec_many_fwd / _bwd: the level kernels from a graph where the
-    batch executor covers the batch (bit-identical to use_graph=2), the tuned
-    separate launches where it does not; backward round trip with 1/N."""
+    """offt_exec_many_fwd / _bwd: the level kernels from a graph where an
+    executor covers the batch (bit-identical to use_graph=2 and to the
+    grouped graph, 6), the tuned separate launches where it does not;
+    backward round trip with 1/N."""
     dims = synth.uneven_batch_dims(8, key=synth.KEY_DIMS + 23)
     plan = offt.ManyPlan(dims, dtype=C64, normalize_inverse=True)
     grids, x = packed_input(plan, dims, C64, key0=synth.SEED + 700)
     y = plan.forward(x)
     y2 = plan.execute(x, use_graph=2)
+    y6 = plan.execute(x, use_graph=6)
     z = plan.backward(y)
     torch.cuda.synchronize()
-    assert same_grids(plan, y, y2)
+    assert same_grids(plan, y, y2) and same_grids(plan, y, y6)
     check_against_oracle(plan, grids, y, C64)
     for g, (a, b) in enumerate(zip(grids, plan.unpack(z))):
         assert oracle.rel_l2(b.cpu().numpy(), a.cpu().numpy()) <= oracle.tolerance(a.numel(), True), g
@@ -302,3 +307,28 @@ def test_default_launch_form():
     torch.cuda.synchronize()
     assert same_grids(lplan, y, y2)
     check_against_oracle(lplan, grids, y, C64)
+
+
+def test_grouped_level_graph_many_groups():
+    """24 complex128 grids of 128-160 points per axis (about 1.1 GiB, 42-53
+    MiB each, so groups of a few grids under 192 MiB): the grouped graph
+    equals the level graph bit for bit, every grid matches the oracle, and a
+    call in place in the backward direction updates the graph."""
+    lens = (128, 144, 150, 160)
+    dims = [(lens[g % 4], lens[(g + 1) % 4], lens[(g + 3) % 4]) for g in range(24)]
+    plan = offt.ManyPlan(dims, dtype=C128, normalize_inverse=True)
+    ng = int(plan.describe().split(" level groups")[0].rsplit(" ", 1)[1])
+    print(plan.describe().splitlines()[0], flush=True)
+    assert ng >= 3
+    grids, x = packed_input(plan, dims, C128, key0=synth.SEED + 800)
+    y6 = plan.execute(x, use_graph=6)
+    y2 = plan.execute(x, use_graph=2)
+    torch.cuda.synchronize()
+    assert same_grids(plan, y6, y2)
+    check_against_oracle(plan, grids, y6, C128)
+    buf = y6.clone()
+    plan.execute(buf, out=buf, use_graph=6, direction=offt.BACKWARD)
+    torch.cuda.synchronize()
+    for g, (a, b) in enumerate(zip(grids, plan.unpack(buf))):
+        e = oracle.rel_l2(b.cpu().numpy(), a.cpu().numpy())
+        assert e <= oracle.tolerance(a.numel(), False), (g, e)
