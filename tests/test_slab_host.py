@@ -120,3 +120,25 @@ def test_column_block_not_on_a_ragged_row():
     # tiles of 32 columns do not fit blocks of 16
     with pytest.raises(offt.OfftError):
         offt.plan_string((64, 40, 48), C64, "natural", plan.replace("/16/x", "/32/x") + ";col=16")
+
+
+def test_every_plan_cache_entry_parses():
+    """Every entry of the committed plan cache names compiled kernels and a
+    schedule that fits its grid, and is written in canonical form (no
+    device needed; tile sizes are checked against the device at plan time)."""
+    import os
+    path = os.path.join(os.path.dirname(offt.__file__), "data", "plan_cache_mi355x.txt")
+    n = 0
+    for line in open(path):
+        head, plan, ms = line.rstrip("\n").split("\t")
+        fields = dict(f.split("=", 1) for f in head.split())
+        dims = tuple(int(v) for v in fields["dims"].split("x"))
+        dtype = C128 if fields["dtype"] == "0" else C64
+        assert float(ms) > 0
+        if len(dims) == 3:
+            layout = "cba" if fields.get("layout") == "cba" else "natural"
+            assert offt.plan_string(dims, dtype, layout, plan) == plan, line
+        else:
+            assert offt.plan_string_nd(dims, dtype, plan) == plan, line
+        n += 1
+    assert n >= 10
