@@ -952,23 +952,26 @@ def summarize_reversed(d: str, log: str, command: str, n: int, steps: int, warmu
             halves = res[dt][name]["plan"].split("|")
             for direction, half in (("fwd", halves[0]), ("bwd", halves[-1])):
                 fields = dict(f.split("=", 1) for f in half.split(";"))
-                order = fields["order"]
                 ev = res[dt][name][f"{direction}_ms"]
                 lines.append(f"{n}^3 {dt} {name} {direction} plan {half}: {ev * 1e3:.1f} us per transform (HIP events)")
-                per = [[] for _ in order]
+                # a natural plan with a block schedule launches its later
+                # passes once per block: per pass and transform, summed
+                keys = pass_keys(half)
+                per = [[0.0] * steps for _ in keys]
                 for st in range(warmup + steps):
-                    for i in range(len(order)):
+                    for i in pass_launches(half, n):
                         if k >= len(disp):
                             raise RuntimeError(f"the trace holds {len(disp)} pass dispatches, fewer than expected")
                         if st >= warmup:
-                            per[i].append(disp[k])
+                            per[i][st - warmup] += disp[k]
                         k += 1
                 total = 0.0
-                for i, ax in enumerate(order):
+                for i, key in enumerate(keys):
                     m = sum(per[i]) / len(per[i])
                     total += m
+                    ax = key.split("=", 1)[0]
                     tag = " (T)" if fields.get("rev") == ax else ""
-                    lines.append(f"  pass {i} {ax}={fields[ax] + tag:<20} {m:9.2f} us  "
+                    lines.append(f"  pass {i} {pass_label(half, i) + tag:<22} {m:9.2f} us  "
                                  f"{2.0 * N * s_b / (m * 1e3):7.1f} GB/s")
                 lines.append(f"  summed pass time {total:.1f} us")
     if k != len(disp):

@@ -135,6 +135,35 @@ def test_reversed_trace_summary(tmp_path):
     assert float(passes[23][-4]) == 8.2
 
 
+def test_reversed_trace_summary_with_slab_natural_plan(tmp_path):
+    """The natural plan beside the reversed one may run a slab schedule: its
+    later passes are summed over their slabs."""
+    b = load_bench()
+    steps, warmup, n = 2, 1, 8
+    nat = "order=acb;a=8/8;b=8/8/x;c=8/8;slab=4"
+    rev = "order=cba;rev=a;a=8/8;b=8/8/x;c=8/8|order=bca;rev=a;a=8/8;b=8/8;c=8/8"
+    res = {"workload": "w"}
+    for dt in ("f64", "f32"):
+        res[dt] = {"natural": {"fwd_ms": 0.006, "bwd_ms": 0.006, "plan": nat},
+                   "reversed": {"fwd_ms": 0.007, "bwd_ms": 0.008, "plan": rev}}
+    log = tmp_path / "rev.log"
+    log.write_text(__import__("json").dumps({"reversed_output": res}) + "\n")
+    d = []
+    for run in range(8):
+        plan = nat if run % 4 < 2 else rev.split("|")[run % 2]
+        for st in range(warmup + steps):
+            for i in b.pass_launches(plan, n):
+                slabbed = b.plan_slab(plan) and i > 0
+                d.append(("offt::fft_pass_kernel<...>", 99_000 if st < warmup else (250 if slabbed else 1_000), 10))
+    write_trace(str(tmp_path / "run" / "run_kernel_trace.csv"), d)
+    txt = b.summarize_reversed(str(tmp_path), str(log), "cmd", n, steps, warmup)
+    passes = [l.split() for l in txt.splitlines() if l.startswith("  pass")]
+    assert len(passes) == 24
+    assert [p[2] for p in passes[:3]] == ["a=8/8", "c=8/8;slab=4", "b=8/8/x;slab=4"]
+    # two slabs of 0.25 us per slab pass
+    assert [float(p[3]) for p in passes[:3]] == [1.0, 0.5, 0.5]
+
+
 def test_stats_summary_with_copy_kernels(tmp_path):
     """Per-pass means of a headline run from the dispatch trace: the
     transform's passes, then each pass's copy kernel, per timed plan."""
