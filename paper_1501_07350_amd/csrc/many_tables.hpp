@@ -165,7 +165,9 @@ inline void build_many_groups(const std::vector<ManyGridDesc>& grids, const Many
         for (size_t s = 0; s < t.segs.size(); ++s) {
             if (s > 0 && t.seg_level[s] != t.seg_level[s - 1]) gi = 0;
             while (gi < count && grids[gi].elem_off != t.segs[s].elem_off) ++gi;
-            seg_grid[s] = gi < count ? gi : count - 1;
+            // every segment belongs to a grid of the list (grid order within
+            // a level); a miss would leave the segment out of every group
+            seg_grid[s] = gi < count ? gi : -1;
         }
     }
     out->map.clear();
@@ -174,7 +176,7 @@ inline void build_many_groups(const std::vector<ManyGridDesc>& grids, const Many
         for (int lvl = 0; lvl < 3; ++lvl) {
             out->ranges[(size_t)3 * gr + lvl] = (int64_t)out->map.size();
             for (size_t s = 0; s < t.segs.size(); ++s) {
-                if (t.seg_level[s] != lvl || group_of[seg_grid[s]] != gr) continue;
+                if (t.seg_level[s] != lvl || seg_grid[s] < 0 || group_of[seg_grid[s]] != gr) continue;
                 for (int k = 0; k < t.segs[s].ntiles; ++k) out->map.push_back((int)(t.segs[s].tile_base + k));
             }
         }

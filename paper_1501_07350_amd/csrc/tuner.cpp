@@ -410,7 +410,7 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
         // then the winner's kernels for b and a on blocks of columns of 64,
         // 128 and 256 MiB, in both orders (the tile widths of both must fit a
         // block)
-        const int64_t colum_bytes = dims[0] * dims[1] * p->batch * (int64_t)elem_size(p->dtype);
+        const int64_t column_bytes = dims[0] * dims[1] * p->batch * (int64_t)elem_size(p->dtype);
         for (int ba = 0; ba < 2 && rc == OFFT_SUCCESS; ++ba) {
             PlanChoice ord = base;
             ord.slab = 0;
@@ -421,7 +421,7 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
             int64_t last = 0;
             for (int64_t mib : {64, 128, 256}) {
                 int64_t w = 1;
-                while (w * 2 * colum_bytes <= (mib << 20)) w *= 2;
+                while (w * 2 * column_bytes <= (mib << 20)) w *= 2;
                 if (w == last || rc != OFFT_SUCCESS) continue;
                 last = w;
                 PlanChoice c = ord;
@@ -439,7 +439,7 @@ static int exhaustive_dims(offt_plan_s* p, const offt_opts& o, const int64_t dim
         // holds and what its stores leave in the cache for the next block
         // differ from the whole-grid passes they were ranked on)
         const int64_t block_bytes = winner.slab > 0 ? std::min(winner.slab, planes) * plane_bytes
-                                                    : winner.col * colum_bytes;
+                                                    : winner.col * column_bytes;
         for (int ax = 0; ax < 3 && (winner.slab > 0 || winner.col > 0) && rc == OFFT_SUCCESS; ++ax) {
             if (dims[ax] <= 1 || ax == (winner.slab > 0 ? 0 : 2)) continue;   // the whole-grid pass
             const int g = axis_geom(winner, ax);
