@@ -11,6 +11,7 @@ Tolerances as for the natural order (relative L2: 1e-12 complex128,
 2e-6 log2 N complex64).
 """
 import itertools
+import os
 
 import numpy as np
 import pytest
@@ -24,6 +25,8 @@ from oracle import layout
 pytestmark = pytest.mark.gpu
 
 C128, C64 = torch.complex128, torch.complex64
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PLAN_CACHE = os.path.join(ROOT, "paper_1501_07350_amd", "data", "plan_cache_mi355x.txt")
 
 
 def tol(n, dtype):
@@ -183,9 +186,10 @@ def test_workspace_and_one_axis_grids():
 
 @pytest.mark.parametrize("n,dtype", [(512, C128), (512, C64)], ids=["512-c128", "512-c64"])
 def test_full_size_sampled_lines(n, dtype):
-    """512^3 in the benchmark's launch configuration (heuristic reversed plan,
-    out of place): sampled lines from the definition, Parseval and the
-    normalised round trip."""
+    """512^3 with the heuristic reversed plan, out of place (the benchmark's
+    tuned reversed plans are checked against the whole O3 transform in
+    test_512_cached_reversed_plan_full_oracle): sampled lines from the
+    definition, Parseval and the normalised round trip."""
     shape = (n, n, n)
     print(f"case {shape} {dtype} cba", flush=True)
     x = synth.complex_grid(shape, dtype, device="cuda")
@@ -208,6 +212,52 @@ def test_full_size_sampled_lines(n, dtype):
     print(f"{shape} {dtype} cba: lines {e_lines:.2e} parseval {e_pars:.2e} roundtrip {e_rt:.2e} "
           f"plan {plan.describe()}", flush=True)
     assert e_lines <= t and e_pars <= t and e_rt <= t
+
+
+def cached_reversed_plan(n, dtype):
+    """Reversed-order (cba) plan-cache entry of an n^3 grid, batch 1: the
+    forward and backward plan strings joined by '|'."""
+    code = 0 if dtype == C128 else 1
+    key = f"dtype={code} dims={n}x{n}x{n} batch=1 "
+    with open(PLAN_CACHE) as f:
+        for line in f:
+            head, plan, _ = line.rstrip("\n").split("\t")
+            if head.startswith(key) and "layout=cba" in head:
+                return plan
+    return None
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+def test_512_cached_reversed_plan_full_oracle(dtype):
+    """512^3 with the tuned reversed-order plans of the plan cache (those the
+    benchmark's reversed-output runs time): the whole forward output against
+    the O3 transform delivered in cba order, element by element, and the
+    backward transform of it against the whole input (normalised)."""
+    n = 512
+    shape = (n, n, n)
+    plan_str = cached_reversed_plan(n, dtype)
+    assert plan_str, "plan cache has no 512^3 reversed-order entry"
+    print(f"case {shape} {dtype} cba cached plan {plan_str}", flush=True)
+    x = synth.complex_grid(shape, dtype, device="cuda")
+    plan = offt.Plan(shape, dtype=dtype, layout="cba", tune="forced", forced_plan=plan_str,
+                     normalize_inverse=True)
+    y = plan.forward(x)
+    torch.cuda.synchronize()
+    t = tol(x.numel(), dtype)
+    xh = host(x)
+    yh = host(y)
+    ref = layout.fft3_reversed(xh)
+    e_fwd = oracle.rel_l2(yh, ref)
+    e_max = float(np.max(np.abs(yh - ref)) / np.max(np.abs(ref)))
+    del yh, ref
+    z = plan.backward(y)
+    torch.cuda.synchronize()
+    e_rt = oracle.rel_l2(host(z), xh)
+    print(f"{shape} {dtype} cba cached: forward {e_fwd:.2e} (max element {e_max:.2e}) round trip {e_rt:.2e} "
+          f"tol {t:.1e} plan {plan.describe()}", flush=True)
+    plan.close()
+    assert e_fwd <= t and e_rt <= t
 
 
 @pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
